@@ -1,0 +1,307 @@
+"""Python side of the CPU FP64 reference (TEST INFRASTRUCTURE ONLY).
+
+Thin numpy wrappers around ``oracle.c`` plus the leapfrog step, written in the order the
+method takes its steps.  Brute-force O(N^2) neighbours; use ``targets`` to sample large
+sets.  Every array is float64 (or int64 for indices) in caller order unless stated.
+
+Parity pins: tests/test_oracle_pins.py.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "oracle.c")
+_LIB = os.path.join(_HERE, "liboracle.so")
+
+_d = ctypes.POINTER(ctypes.c_double)
+_i64 = ctypes.POINTER(ctypes.c_int64)
+_i32 = ctypes.POINTER(ctypes.c_int32)
+_u64 = ctypes.POINTER(ctypes.c_uint64)
+I64, I32, DBL = ctypes.c_int64, ctypes.c_int32, ctypes.c_double
+
+
+def build(force: bool = True) -> str:
+    """Compile oracle.c with gcc (no FMA contraction, OpenMP)."""
+    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+        tmp = _LIB + ".tmp"
+        subprocess.check_call(["gcc", "-O2", "-ffp-contract=off", "-fopenmp", "-shared", "-fPIC",
+                               "-o", tmp, _SRC, "-lm"])
+        os.replace(tmp, _LIB)
+    return _LIB
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB):
+            build(force=False)
+        L = ctypes.CDLL(_LIB)
+        L.orc_keys.argtypes = [I64, _d, _d, _d, I32, _i64, _d, _u64]
+        L.orc_order.argtypes = [I64, _u64, _i64]
+        L.orc_octree.argtypes = [I64, _u64, ctypes.c_int, ctypes.c_int, I64, _u64, _i32, _i32, _i64, _i64]
+        L.orc_octree.restype = I64
+        L.orc_nbr_count.argtypes = [I64, _d, _d, _d, _d, _i32, I64, _i64, _i64]
+        L.orc_nbr_fill.argtypes = [I64, _d, _d, _d, _d, _i32, I64, _i64, _i64, _i64]
+        L.orc_w.argtypes = [DBL]
+        L.orc_w.restype = DBL
+        L.orc_dw_over_q.argtypes = [DBL]
+        L.orc_dw_over_q.restype = DBL
+        L.orc_density.argtypes = [_d, _d, _d, _d, _d, _d, DBL, DBL, I64, _i64, _i64, _i64, _d, _d, _d, _d]
+        L.orc_forces.argtypes = [_d] * 11 + [DBL, DBL, DBL, I64, _i64, _i64, _i64] + [_d] * 6
+        L.orc_gravity_direct.argtypes = [I64, _d, _d, _d, _d, DBL, DBL, I64, _i64, _d, _d, _d, _d]
+        L.orc_moments.argtypes = [I64, I64, _i64, _d, _d, _d, _d, _d]
+        L.orc_quad_field.argtypes = [_d, DBL, DBL, DBL, DBL, DBL, _d, _d]
+        L.orc_tree_gravity.argtypes = ([I64, I64, _i32, _i32, _i64, _i64, _d, _d, _d, _d, DBL, DBL, DBL, DBL,
+                                        I64, _i64, _i64, _d, _d, _d, _d])
+        L.orc_bbox.argtypes = [I64, I64, _d, _d, _d, _d]
+        L.orc_scale.argtypes = [_d, ctypes.c_int]
+        L.orc_scale.restype = DBL
+        _lib = L
+    return _lib
+
+
+def _p(a, t=_d):
+    return None if a is None else a.ctypes.data_as(t)
+
+
+def _f64(a):
+    return np.ascontiguousarray(a, dtype=np.float64)
+
+
+def _ii(a):
+    return None if a is None else np.ascontiguousarray(a, dtype=np.int64)
+
+
+# ---------------------------------------------------------------------------------------
+# Keys, order, tree (Sec. 2.1 "Tree topology", Fig. 1)
+
+def keys(x, y, z, seg_offsets=None, box=None):
+    x, y, z = _f64(x), _f64(y), _f64(z)
+    n = x.size
+    out = np.empty(n, dtype=np.uint64)
+    nseg = 1 if seg_offsets is None else len(seg_offsets) - 1
+    so = _ii(seg_offsets)
+    bx = None if box is None else _f64(box)
+    lib().orc_keys(n, _p(x), _p(y), _p(z), nseg, _p(so, _i64), _p(bx), _p(out, _u64))
+    return out
+
+
+def order(k):
+    k = np.ascontiguousarray(k, dtype=np.uint64)
+    out = np.empty(k.size, dtype=np.int64)
+    lib().orc_order(k.size, _p(k, _u64), _p(out, _i64))
+    return out
+
+
+def octree(sorted_keys, leaf_cap, min_level=0):
+    """Pre-order node list: dict of arrays key, level, leaf, start, count."""
+    k = np.ascontiguousarray(sorted_keys, dtype=np.uint64)
+    n = k.size
+    cap = max(64, 2 * n + 22 * (n // max(1, leaf_cap + 1) + 1) + 64)
+    nkey = np.empty(cap, np.uint64)
+    nlev = np.empty(cap, np.int32)
+    nleaf = np.empty(cap, np.int32)
+    nst = np.empty(cap, np.int64)
+    ncnt = np.empty(cap, np.int64)
+    m = lib().orc_octree(n, _p(k, _u64), int(leaf_cap), int(min_level), cap, _p(nkey, _u64), _p(nlev, _i32),
+                         _p(nleaf, _i32), _p(nst, _i64), _p(ncnt, _i64))
+    if m < 0:
+        raise RuntimeError("octree capacity exceeded")
+    return dict(key=nkey[:m], level=nlev[:m], leaf=nleaf[:m].astype(bool), start=nst[:m], count=ncnt[:m])
+
+
+def bbox(x, y, z):
+    out = np.empty(6)
+    x, y, z = _f64(x), _f64(y), _f64(z)
+    lib().orc_bbox(0, x.size, _p(x), _p(y), _p(z), _p(out))
+    return out
+
+
+def scale(box6, bits):
+    b = _f64(box6)
+    return lib().orc_scale(_p(b), int(bits))
+
+
+# ---------------------------------------------------------------------------------------
+# Neighbours: brute force, lists sorted by caller index, self included
+
+def seg_ids(n, seg_offsets):
+    if seg_offsets is None or len(seg_offsets) <= 2:
+        return None
+    s = np.empty(n, np.int32)
+    for i in range(len(seg_offsets) - 1):
+        s[seg_offsets[i]:seg_offsets[i + 1]] = i
+    return s
+
+
+def neighbors(x, y, z, h, targets=None, seg=None):
+    """CSR (offsets int64[ntgt+1], idx int64[nnz]) of the neighbour sets of the targets."""
+    x, y, z, h = _f64(x), _f64(y), _f64(z), _f64(h)
+    n = x.size
+    tg = _ii(targets)
+    nt = n if tg is None else tg.size
+    sg = None if seg is None else np.ascontiguousarray(seg, dtype=np.int32)
+    cnt = np.empty(nt, np.int64)
+    lib().orc_nbr_count(n, _p(x), _p(y), _p(z), _p(h), _p(sg, _i32), nt, _p(tg, _i64), _p(cnt, _i64))
+    off = np.zeros(nt + 1, np.int64)
+    np.cumsum(cnt, out=off[1:])
+    idx = np.empty(int(off[-1]), np.int64)
+    lib().orc_nbr_fill(n, _p(x), _p(y), _p(z), _p(h), _p(sg, _i32), nt, _p(tg, _i64), _p(off, _i64),
+                       _p(idx, _i64))
+    return off, idx
+
+
+# ---------------------------------------------------------------------------------------
+# Density + EOS (eq. (7), (9)); forces (eq. (5), (6)); gravity (eq. (10))
+
+def w(q):
+    return lib().orc_w(float(q))
+
+
+def dw_over_q(q):
+    return lib().orc_dw_over_q(float(q))
+
+
+def density(ps_or_arrays, csr, gamma=5.0 / 3.0, h_coeff=1.2, targets=None):
+    """Returns rho, P, c, h_next indexed by target."""
+    x, y, z, h, m, u = (_f64(ps_or_arrays[k]) for k in ("x", "y", "z", "h", "m", "u"))
+    off, idx = csr
+    tg = _ii(targets)
+    nt = x.size if tg is None else tg.size
+    rho, P, c, hn = (np.empty(nt) for _ in range(4))
+    lib().orc_density(_p(x), _p(y), _p(z), _p(h), _p(m), _p(u), gamma, h_coeff, nt, _p(tg, _i64),
+                      _p(_ii(off), _i64), _p(_ii(idx), _i64), _p(rho), _p(P), _p(c), _p(hn))
+    return rho, P, c, hn
+
+
+def forces(ps_or_arrays, rho, P, c, csr, alpha=1.0, beta=2.0, eps_av=0.01, targets=None, vel=None):
+    """Returns ax, ay, az, dudt, Sa, Su indexed by target.  rho, P, c indexed by particle.
+    vel: optional (vx, vy, vz) overriding the state's velocities (the KDK predictor)."""
+    x, y, z, h, m = (_f64(ps_or_arrays[k]) for k in ("x", "y", "z", "h", "m"))
+    vx, vy, vz = (_f64(v) for v in (vel if vel is not None else
+                                     (ps_or_arrays["vx"], ps_or_arrays["vy"], ps_or_arrays["vz"])))
+    rho, P, c = _f64(rho), _f64(P), _f64(c)
+    off, idx = csr
+    tg = _ii(targets)
+    nt = x.size if tg is None else tg.size
+    out = [np.empty(nt) for _ in range(6)]
+    lib().orc_forces(_p(x), _p(y), _p(z), _p(vx), _p(vy), _p(vz), _p(h), _p(m), _p(rho), _p(P), _p(c),
+                     alpha, beta, eps_av, nt, _p(tg, _i64), _p(_ii(off), _i64), _p(_ii(idx), _i64),
+                     *[_p(o) for o in out])
+    return tuple(out)
+
+
+def gravity_direct(x, y, z, m, G=1.0, eps=0.0, targets=None):
+    x, y, z, m = _f64(x), _f64(y), _f64(z), _f64(m)
+    tg = _ii(targets)
+    nt = x.size if tg is None else tg.size
+    gx, gy, gz, phi = (np.empty(nt) for _ in range(4))
+    lib().orc_gravity_direct(x.size, _p(x), _p(y), _p(z), _p(m), G, eps, nt, _p(tg, _i64), _p(gx), _p(gy),
+                             _p(gz), _p(phi))
+    return gx, gy, gz, phi
+
+
+def moments(x, y, z, m, idx=None):
+    x, y, z, m = _f64(x), _f64(y), _f64(z), _f64(m)
+    out = np.empty(10)
+    ii = _ii(idx)
+    k = x.size if ii is None else ii.size
+    lib().orc_moments(0, k, _p(ii, _i64), _p(x), _p(y), _p(z), _p(m), _p(out))
+    return out
+
+
+def quad_field(mom10, p, G=1.0, eps=0.0):
+    mo = _f64(mom10)
+    g = np.empty(3)
+    phi = np.empty(1)
+    lib().orc_quad_field(_p(mo), float(p[0]), float(p[1]), float(p[2]), G, eps, _p(g), _p(phi))
+    return g, float(phi[0])
+
+
+def tree_gravity(xs, ys, zs, ms, tree, L, theta, G, eps, gstart, gcount):
+    """Tree gravity over particles already in sorted order; tree from octree()."""
+    xs, ys, zs, ms = _f64(xs), _f64(ys), _f64(zs), _f64(ms)
+    n = xs.size
+    lev = np.ascontiguousarray(tree["level"], np.int32)
+    leaf = np.ascontiguousarray(tree["leaf"], np.int32)
+    st, ct = _ii(tree["start"]), _ii(tree["count"])
+    gs, gc = _ii(gstart), _ii(gcount)
+    gx, gy, gz, phi = (np.empty(n) for _ in range(4))
+    lib().orc_tree_gravity(n, lev.size, _p(lev, _i32), _p(leaf, _i32), _p(st, _i64), _p(ct, _i64), _p(xs), _p(ys),
+                           _p(zs), _p(ms), L, theta, G, eps, gs.size, _p(gs, _i64), _p(gc, _i64), _p(gx), _p(gy),
+                           _p(gz), _p(phi))
+    return gx, gy, gz, phi
+
+
+# ---------------------------------------------------------------------------------------
+# Leapfrog (kick-drift-kick) with velocity and energy predictors, lagged adaptive h
+
+class Params:
+    def __init__(self, gamma=5.0 / 3.0, alpha=1.0, beta=2.0, eps_av=0.01, h_coeff=1.2, adaptive_h=False,
+                 G=0.0, soft_eps=0.0):
+        self.gamma, self.alpha, self.beta, self.eps_av = gamma, alpha, beta, eps_av
+        self.h_coeff, self.adaptive_h, self.G, self.soft_eps = h_coeff, adaptive_h, G, soft_eps
+
+
+def accelerations(st: dict, prm: Params, vel=None, u=None, seg=None):
+    """Hydro (+ direct gravity) accelerations for the whole set.  Returns
+    (ax, ay, az, dudt, rho, P, c, h_next).  u overrides the state's energy in the EOS."""
+    csr = neighbors(st["x"], st["y"], st["z"], st["h"], seg=seg)
+    d = dict(st)
+    if u is not None:
+        d["u"] = u
+    rho, P, c, hn = density(d, csr, prm.gamma, prm.h_coeff)
+    ax, ay, az, du, _, _ = forces(d, rho, P, c, csr, prm.alpha, prm.beta, prm.eps_av, vel=vel)
+    if prm.G != 0.0:
+        gx, gy, gz, _ = gravity_direct(st["x"], st["y"], st["z"], st["m"], prm.G, prm.soft_eps)
+        ax, ay, az = ax + gx, ay + gy, az + gz
+    return ax, ay, az, du, rho, P, c, hn
+
+
+def prime(st: dict, prm: Params, seg=None):
+    """Accelerations at t = 0 and, for adaptive h, h <- h_coeff (m / rho)^(1/3)."""
+    st = {k: np.array(v, dtype=np.float64) for k, v in st.items()}
+    ax, ay, az, du, rho, P, c, hn = accelerations(st, prm, seg=seg)
+    st.update(ax=ax, ay=ay, az=az, dudt=du)
+    if prm.adaptive_h:
+        st["h"] = hn
+    return st
+
+
+def kdk_step(st: dict, dt: float, prm: Params, seg=None):
+    """One step from a primed state (dict with x..u, ax, ay, az, dudt)."""
+    s = {k: np.array(v, dtype=np.float64) for k, v in st.items()}
+    half = 0.5 * dt
+    vhx, vhy, vhz = s["vx"] + half * s["ax"], s["vy"] + half * s["ay"], s["vz"] + half * s["az"]
+    uh = s["u"] + half * s["dudt"]
+    s["x"], s["y"], s["z"] = s["x"] + dt * vhx, s["y"] + dt * vhy, s["z"] + dt * vhz
+    vpx, vpy, vpz = vhx + half * s["ax"], vhy + half * s["ay"], vhz + half * s["az"]
+    up = uh + half * s["dudt"]
+    ax, ay, az, du, rho, P, c, hn = accelerations(s, prm, vel=(vpx, vpy, vpz), u=up, seg=seg)
+    s["vx"], s["vy"], s["vz"] = vhx + half * ax, vhy + half * ay, vhz + half * az
+    s["u"] = uh + half * du
+    s.update(ax=ax, ay=ay, az=az, dudt=du, rho=rho)
+    if prm.adaptive_h:
+        s["h"] = hn
+    return s
+
+
+def diagnostics(st: dict, phi=None):
+    """[Px, Py, Pz, Lx, Ly, Lz, Ekin, Eth, Egrav] summed over all particles."""
+    m = st["m"]
+    v = np.stack([st["vx"], st["vy"], st["vz"]])
+    r = np.stack([st["x"], st["y"], st["z"]])
+    P = (m * v).sum(axis=1)
+    L = (m * np.cross(r.T, v.T).T).sum(axis=1)
+    ek = 0.5 * (m * (v * v).sum(axis=0)).sum()
+    eth = (m * st["u"]).sum()
+    eg = 0.0 if phi is None else 0.5 * (m * phi).sum()
+    return np.array([*P, *L, ek, eth, eg])
