@@ -1,0 +1,155 @@
+#!/usr/bin/env python3
+"""Benchmark: pair interactions/s (density + force) and steps/s of the SPH + octree hot path
+on one MI355X, FP64 and FP32-compensated, on the 3D Sod-type tube workload.
+
+Workload: 987,840 particles in [0,1] x [0,0.1]^2 (two lattices with spacing ratio 2:1:
+rho = 1, P = 1 left; rho = 0.125, P = 0.1 right), gamma = 5/3, adaptive h = 1.2 (m/rho)^(1/3),
+Monaghan viscosity alpha = 1, beta = 2, kick-drift-kick leapfrog at dt = 0.25 min(h/c).
+One benchmark step = one full leapfrog step: bounding box, keys, radix sort, reorder,
+octree + moments, neighbour lists, density + EOS, forces, kicks.  Inputs are resident in
+HBM before the timed region.
+
+value = (density pairs + force pairs per step) * steps / wall time of the timed steps (FP64).
+The FP32C form, per-kernel event timings, the roofline of the dominant kernel and a CPU
+reference baseline are reported in the same JSON line.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+FP64_PEAK_TFLOPS = 78.6     # MI355X FP64 vector, 256 CU x 64 lanes x 2 flop x 2.4 GHz
+HBM_PEAK_GBS = 8000.0
+
+# Algorithmic operation counts per true pair (see the design notes): one flop per IEEE
+# add, subtract, multiply, divide, square root or comparison in the definition.
+FLOP_DENS_PAIR = 23
+FLOP_FORCE_PAIR = 64
+
+
+def dt_for(ps, gamma=5.0 / 3.0):
+    import numpy as np
+    c = np.sqrt(gamma * (gamma - 1.0) * ps.u)
+    return 0.25 * float(np.min(ps.h / c))
+
+
+def run_gpu(ps, prec, steps, warmup, reps):
+    import torch
+    import paper_2007_03097_amd as sph
+    n = ps.n
+    ctx = sph.Context(n, adaptive_h=1, precision=prec)
+    pa = sph.ParticleArrays.from_numpy(ps)
+    dt = dt_for(ps)
+    sph.sph_step(ctx.h, pa, dt, max(warmup, 1), 0)       # load, prime, warm up, capture graphs
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    diag = sph.sph_step(ctx.h, pa, dt, steps, sph.SPH_STEP_RESUME)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    # pair counts of the final state (the tube evolves little over the timed steps)
+    sph.sph_build_tree(ctx.h, pa)
+    total = sph.sph_find_neighbors(ctx.h, None, None, 0)
+    pairs_dens, pairs_force = total, total - n
+    # per-kernel timing with events on the stream the kernels run on (torch's current stream)
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
+    sph.sph_compute_density(ctx.h, None, None, None, None)
+    torch.cuda.synchronize()
+    ev[0].record()
+    for _ in range(reps):
+        sph.sph_compute_density(ctx.h, None, None, None, None)
+    ev[1].record()
+    for _ in range(reps):
+        sph.sph_compute_forces(ctx.h, None, None, None, None)
+    ev[2].record()
+    torch.cuda.synchronize()
+    t_dens = ev[0].elapsed_time(ev[1]) / reps * 1e-3
+    t_force = ev[1].elapsed_time(ev[2]) / reps * 1e-3
+    leaf, group = sph.sph_get_tuning(ctx.h)
+    ctx.close()
+    return dict(ms_per_step=wall / steps * 1e3, wall=wall, pairs_dens=pairs_dens, pairs_force=pairs_force,
+                value=(pairs_dens + pairs_force) * steps / wall, steps_per_s=steps / wall,
+                t_dens=t_dens, t_force=t_force, pass_rate=(pairs_dens + pairs_force) / (t_dens + t_force),
+                diag=diag.tolist(), leaf=leaf, group=group, dt=dt)
+
+
+def cpu_baseline(ps, reps=3):
+    """The CPU FP64 reference on a bounded sample: the slab 0.47 < x < 0.53 of the same tube
+    (both lattices and the interface).  Brute-force neighbours are built once (reported,
+    not counted); density + force pair throughput is the baseline."""
+    import numpy as np
+    import oracle
+    sel = np.nonzero((ps.x > 0.47) & (ps.x < 0.53))[0]
+    sub = ps.subset(sel)
+    t0 = time.perf_counter()
+    csr = oracle.neighbors(sub.x, sub.y, sub.z, sub.h)
+    t_nbr = time.perf_counter() - t0
+    pairs = int(csr[0][-1]) + int(csr[0][-1] - sub.n)
+    best = math.inf
+    for _ in range(reps):
+        t0 = time.perf_counter()
+        rho, P, c, _ = oracle.density(sub.fields(), csr)
+        oracle.forces(sub.fields(), rho, P, c, csr)
+        best = min(best, time.perf_counter() - t0)
+    cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    return dict(value=pairs / best, unit="pair interactions/s", cores=cores, kind="oracle",
+                sample=f"slab 0.47<x<0.53 of the tube: {sub.n} particles, {pairs} density+force pairs; "
+                       f"best of {reps}: {best:.3f} s; brute-force neighbour search {t_nbr:.1f} s not counted")
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--ny", type=int, default=56, help="tube lattice resolution (56 -> 987,840 particles)")
+    ap.add_argument("--reps", type=int, default=20, help="repetitions of the per-kernel timing")
+    ap.add_argument("--no-cpu", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for {args.gpus}); the multi-GPU path is not built.",
+              file=sys.stderr)
+        sys.exit(2)
+    import torch
+    from workloads import sod_tube
+    assert torch.cuda.is_available(), "needs a GPU"
+    ps = sod_tube(args.ny)
+    r64 = run_gpu(ps, 0, args.steps, args.warmup, args.reps)
+    r32 = run_gpu(ps, 1, args.steps, args.warmup, args.reps)
+    n = ps.n
+    flops = r64["pairs_force"] * FLOP_FORCE_PAIR
+    achieved = flops / r64["t_force"] / 1e12
+    roof = {"bound": "alu", "kernel": "k_forces<fp64>", "achieved": achieved, "peak": FP64_PEAK_TFLOPS,
+            "unit": "TFLOP/s", "frac": achieved / FP64_PEAK_TFLOPS, "traffic": None,
+            "per_launch": {"pairs": r64["pairs_force"], "flop_per_pair": FLOP_FORCE_PAIR,
+                           "avg_ms": r64["t_force"] * 1e3}}
+    cpu = None if args.no_cpu else cpu_baseline(ps)
+    out = {
+        "metric": "pair interactions/sec (density+force) and steps/sec, FP64 vs FP32-comp, 1 GPU",
+        "value": r64["value"], "unit": "pair interactions/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": r64["ms_per_step"], "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": f"3D Sod-type tube, {n} particles, adaptive h, Monaghan AV, KDK leapfrog",
+                   "n_particles": n, "dt": r64["dt"], "leaf_size": r64["leaf"], "group_size": r64["group"]},
+        "steps_per_s": r64["steps_per_s"],
+        "pairs_per_step": r64["pairs_dens"] + r64["pairs_force"],
+        "pass_rate": r64["pass_rate"],
+        "kernel_ms": {"density": r64["t_dens"] * 1e3, "forces": r64["t_force"] * 1e3},
+        "fp32c": {"value": r32["value"], "ms_per_step": r32["ms_per_step"], "steps_per_s": r32["steps_per_s"],
+                  "pass_rate": r32["pass_rate"], "speedup_vs_fp64": r32["value"] / r64["value"],
+                  "pass_speedup_vs_fp64": r32["pass_rate"] / r64["pass_rate"],
+                  "kernel_ms": {"density": r32["t_dens"] * 1e3, "forces": r32["t_force"] * 1e3}},
+        "roofline": roof,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,744 @@
+// C ABI of the gfx950 SPH + octree library (declarations and contracts in include/sph.h).
+//
+// Host-side responsibilities: argument validation, carving the caller's workspace into the
+// device arrays, the host-built chunk and group tables, launch sequencing on the caller's
+// stream, capture of one leapfrog step per buffer parity into HIP graphs, the sticky device
+// error word, and the autotuner.  No device memory is allocated here.
+#include <algorithm>
+#include <cstdarg>
+#include <cmath>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <fstream>
+#include <sstream>
+#include <string>
+#include <vector>
+
+#include "common.h"
+#include "../../include/sph.h"
+
+namespace {
+
+constexpr int CHUNK = 4096;
+
+struct Tables {
+    int64_t n = -1;
+    int n_seg = 0;
+    int gsz = 0;
+    std::vector<int64_t> seg;  // offsets
+    int version = 0;           // bumped whenever the device tables change
+};
+
+}  // namespace
+
+struct sph_ctx {
+    sph_config cfg{};
+    int64_t n_cap = 0;
+    int seg_cap = 1;
+    int leaf_min = 16;        // smallest leaf size the workspace is sized for
+    int leaf_size = 16;
+    int group_size = 32;
+    int nbr_cap = 160;
+    char* ws = nullptr;
+    size_t ws_bytes = 0;
+    DevPtrs d[2]{};           // pointer sets: d[p] has the resident state in buffer set p
+    Dims dm{};
+    Tables tab;
+    hipStream_t stream = nullptr;
+    hipStream_t cap_stream = nullptr;
+    bool tree_ok = false, lists_ok = false, dens_ok = false, resident_ok = false;
+    int parity = 0;
+    // graphs
+    hipGraphExec_t gexec[2] = {nullptr, nullptr};
+    hipGraph_t graph[2] = {nullptr, nullptr};
+    double g_dt = 0.0;
+    int64_t g_n = -1;
+    int g_leaf = 0, g_gsz = 0, g_tabv = -1;
+    bool use_graph = true;
+    std::string err;
+};
+
+static const char* k_null_ctx_msg = "sph: NULL context";
+
+static sph_status fail(sph_ctx* c, sph_status st, const char* fmt, ...) {
+    if (c) {
+        char buf[512];
+        va_list ap;
+        va_start(ap, fmt);
+        vsnprintf(buf, sizeof buf, fmt, ap);
+        va_end(ap);
+        c->err = buf;
+    }
+    return st;
+}
+
+#define HIPCHK(ctx, call)                                                                            \
+    do {                                                                                             \
+        hipError_t e_ = (call);                                                                      \
+        if (e_ != hipSuccess) return fail((ctx), SPH_E_DEVICE, "%s: %s", #call, hipGetErrorString(e_)); \
+    } while (0)
+
+// ---------------------------------------------------------------------------------------
+// workspace layout
+
+static int64_t node_cap_for(int64_t n, int leaf) { return 2 * n + 21 * n / (leaf + 1) + 256; }
+
+struct Carver {
+    char* base;
+    size_t off = 0;
+    template <typename T>
+    T* take(size_t count) {
+        off = (off + 255) & ~(size_t)255;
+        T* p = base ? (T*)(base + off) : nullptr;
+        off += count * sizeof(T);
+        return p;
+    }
+};
+
+static size_t layout(const sph_ctx* c, char* base, DevPtrs* out) {
+    const size_t N = (size_t)std::max<int64_t>(c->n_cap, 1);
+    const size_t S = (size_t)c->seg_cap;
+    const size_t NC = (size_t)node_cap_for((int64_t)N, c->leaf_min);
+    const size_t GC = N / 8 + S + 1;                     // groups for the smallest group size
+    const size_t NBR = (N + (S + 1) * 64) * (size_t)c->nbr_cap;
+    const size_t CH = N / CHUNK + S + 1;
+    const size_t RSB = (N + 2047) / 2048;
+    const size_t SCB = (std::max(N + 1, 256 * RSB) + 2047) / 2048 + 16;
+    const size_t LST = (NC + 2047) / 2048 + 1;
+    Carver cv{base};
+    DevPtrs d{};
+    d.ctl = cv.take<DevCtl>(1);
+    d.key_a = cv.take<u64>(N);
+    d.key_b = cv.take<u64>(N);
+    d.val_a = cv.take<u32>(N);
+    d.val_b = cv.take<u32>(N);
+    d.rs_hist = cv.take<u32>(256 * RSB);
+    d.scan_tmp = cv.take<u64>(SCB);
+    double** f1[] = {&d.x, &d.y, &d.z, &d.vx, &d.vy, &d.vz, &d.m, &d.h, &d.u, &d.vpx, &d.vpy, &d.vpz, &d.up,
+                     &d.ax, &d.ay, &d.az, &d.du, &d.rho, &d.P, &d.cs, &d.hnext, &d.gx, &d.gy, &d.gz, &d.phi,
+                     &d.x2, &d.y2, &d.z2, &d.vx2, &d.vy2, &d.vz2, &d.m2, &d.h2, &d.u2, &d.vpx2, &d.vpy2, &d.vpz2,
+                     &d.up2};
+    for (double** p : f1) *p = cv.take<double>(N);
+    d.id = cv.take<u32>(N);
+    d.id2 = cv.take<u32>(N);
+    d.inv = cv.take<u32>(N);
+    d.pos4 = cv.take<double4>(N);
+    d.vel4 = cv.take<double4>(N);
+    d.thr4 = cv.take<double4>(N);
+    d.velf = cv.take<float4>(N);
+    d.thrf = cv.take<float4>(N);
+    d.lcp = cv.take<signed char>(N + 1);
+    d.lvl = cv.take<unsigned char>(N);
+    d.scan_in = cv.take<u64>(N + 1);
+    d.scan_out = cv.take<u64>(N + 1);
+    d.leaf_start = cv.take<int>(N + 1);
+    d.leaf_pre = cv.take<int>(N);
+    d.pre_level = cv.take<unsigned char>(NC);
+    d.pre_leaf = cv.take<unsigned char>(NC);
+    d.pre_start = cv.take<int>(NC);
+    d.pre_to_bfs = cv.take<int>(NC);
+    d.bfs_to_pre = cv.take<int>(NC);
+    d.lsort_hist = cv.take<int>(24 * LST);
+    d.topo = cv.take<int4>(NC);
+    d.parent = cv.take<int>(NC);
+    d.counter = cv.take<int>(NC);
+    d.range = cv.take<int2>(NC);
+    d.nbox_lo = cv.take<double4>(NC);
+    d.nbox_hi = cv.take<double4>(NC);
+    d.mom0 = cv.take<double4>(NC);
+    d.mom1 = cv.take<double4>(NC);
+    d.mom2 = cv.take<double4>(NC);
+    d.group = cv.take<int4>(GC);
+    d.nbr = cv.take<int>(NBR);
+    d.nbr_cnt = cv.take<int>(N);
+    d.nbr_base = cv.take<int>(N);
+    d.chunk = cv.take<int4>(CH);
+    d.seg_root_rank = cv.take<int>(S);
+    d.diag_part = cv.take<double>(16 * 256);
+    d.csr_tmp = cv.take<int64_t>(N + 1);
+    if (out) *out = d;
+    return cv.off + 256;
+}
+
+static DevPtrs swapped(const DevPtrs& a) {
+    DevPtrs b = a;
+    std::swap(b.x, b.x2); std::swap(b.y, b.y2); std::swap(b.z, b.z2);
+    std::swap(b.vx, b.vx2); std::swap(b.vy, b.vy2); std::swap(b.vz, b.vz2);
+    std::swap(b.m, b.m2); std::swap(b.h, b.h2); std::swap(b.u, b.u2);
+    std::swap(b.vpx, b.vpx2); std::swap(b.vpy, b.vpy2); std::swap(b.vpz, b.vpz2); std::swap(b.up, b.up2);
+    std::swap(b.id, b.id2);
+    return b;
+}
+
+// ---------------------------------------------------------------------------------------
+// validation helpers
+
+static sph_status check_config(sph_ctx* c, const sph_config* f) {
+    if (!f) return fail(c, SPH_E_ARG, "config is NULL");
+    if (f->precision != SPH_FP64 && f->precision != SPH_FP32C) return fail(c, SPH_E_ARG, "precision must be 0 or 1");
+    if (!(f->gamma > 1.0) || !std::isfinite(f->gamma)) return fail(c, SPH_E_ARG, "gamma must be > 1");
+    if (!(f->av_alpha >= 0.0) || !(f->av_beta >= 0.0) || !(f->av_eps >= 0.0))
+        return fail(c, SPH_E_ARG, "viscosity parameters must be >= 0");
+    if (!(f->h_coeff > 0.0)) return fail(c, SPH_E_ARG, "h_coeff must be > 0");
+    if (!(f->theta >= 0.0 && f->theta <= 1.0)) return fail(c, SPH_E_ARG, "theta must be in [0, 1]");
+    if (!(f->soft_eps >= 0.0) || !std::isfinite(f->soft_eps)) return fail(c, SPH_E_ARG, "soft_eps must be >= 0");
+    if (!std::isfinite(f->G)) return fail(c, SPH_E_ARG, "G must be finite");
+    const int L = f->leaf_size ? f->leaf_size : 16;
+    if (L < 1 || L > 64) return fail(c, SPH_E_ARG, "leaf_size must be in 1..64");
+    const int g = f->group_size ? f->group_size : 32;
+    if (g != 8 && g != 16 && g != 32 && g != 64) return fail(c, SPH_E_ARG, "group_size must be 8, 16, 32 or 64");
+    const int k = f->nbr_capacity ? f->nbr_capacity : 160;
+    if (k < 16 || k > 4096) return fail(c, SPH_E_ARG, "nbr_capacity must be in 16..4096");
+    return SPH_OK;
+}
+
+static sph_status check_particles(sph_ctx* c, const sph_particles* p) {
+    if (!p) return fail(c, SPH_E_ARG, "particles is NULL");
+    if (p->n < 0 || p->n > c->n_cap) return fail(c, SPH_E_ARG, "n = %lld outside 0..%lld", (long long)p->n, (long long)c->n_cap);
+    if (p->n_seg < 1 || p->n_seg > c->seg_cap) return fail(c, SPH_E_ARG, "n_seg = %d outside 1..%d", p->n_seg, c->seg_cap);
+    if (p->n_seg > 1 && !p->seg_offsets) return fail(c, SPH_E_ARG, "seg_offsets required when n_seg > 1");
+    if (p->seg_offsets) {
+        if (p->seg_offsets[0] != 0 || p->seg_offsets[p->n_seg] != p->n)
+            return fail(c, SPH_E_ARG, "seg_offsets must start at 0 and end at n");
+        for (int s = 0; s < p->n_seg; ++s)
+            if (p->seg_offsets[s + 1] < p->seg_offsets[s]) return fail(c, SPH_E_ARG, "seg_offsets not monotone");
+    }
+    if (p->n > 0 && (!p->x || !p->y || !p->z || !p->vx || !p->vy || !p->vz || !p->m || !p->h || !p->u))
+        return fail(c, SPH_E_ARG, "a particle array is NULL");
+    if (!c->ws) return fail(c, SPH_E_NOMEM, "no workspace set");
+    return SPH_OK;
+}
+
+// Host tables for the current set: chunks (bounding box / keys) and walk groups.
+static sph_status prepare(sph_ctx* c, const sph_particles* p) {
+    const int n_seg = p->n_seg;
+    std::vector<int64_t> seg(n_seg + 1);
+    if (p->seg_offsets) for (int s = 0; s <= n_seg; ++s) seg[s] = p->seg_offsets[s];
+    else { seg[0] = 0; seg[1] = p->n; }
+    Dims& dm = c->dm;
+    dm.n = (int)p->n;
+    dm.n_seg = n_seg;
+    dm.batched = n_seg > 1;
+    dm.leaf_size = c->leaf_size;
+    dm.group_size = c->group_size;
+    dm.nbr_cap = c->nbr_cap;
+    dm.node_cap = (int)node_cap_for(c->n_cap > 0 ? c->n_cap : 1, c->leaf_min);
+    dm.min_level = dm.batched ? 3 : 0;
+    const bool same = c->tab.n == p->n && c->tab.n_seg == n_seg && c->tab.gsz == c->group_size && c->tab.seg == seg;
+    std::vector<int4> chunks, groups;
+    std::vector<int> rank(n_seg, 0);
+    int r = 0;
+    for (int s = 0; s < n_seg; ++s) {
+        rank[s] = r;
+        if (seg[s + 1] > seg[s]) ++r;
+        for (int64_t b = seg[s]; b < seg[s + 1]; b += CHUNK)
+            chunks.push_back(make_int4((int)b, (int)std::min<int64_t>(seg[s + 1], b + CHUNK), s, 0));
+        for (int64_t b = seg[s]; b < seg[s + 1]; b += c->group_size)
+            groups.push_back(make_int4((int)b, (int)std::min<int64_t>(c->group_size, seg[s + 1] - b),
+                                       dm.batched ? rank[s] : -1, s));
+    }
+    dm.n_chunks = (int)chunks.size();
+    dm.n_groups = (int)groups.size();
+    if (!same) {
+        if (!chunks.empty())
+            HIPCHK(c, hipMemcpyAsync(c->d[0].chunk, chunks.data(), chunks.size() * sizeof(int4), hipMemcpyHostToDevice,
+                                     c->stream));
+        if (!groups.empty())
+            HIPCHK(c, hipMemcpyAsync(c->d[0].group, groups.data(), groups.size() * sizeof(int4), hipMemcpyHostToDevice,
+                                     c->stream));
+        HIPCHK(c, hipMemcpyAsync(c->d[0].seg_root_rank, rank.data(), rank.size() * sizeof(int), hipMemcpyHostToDevice,
+                                 c->stream));
+        HIPCHK(c, hipStreamSynchronize(c->stream));  // host vectors go out of scope
+        c->tab.n = p->n;
+        c->tab.n_seg = n_seg;
+        c->tab.gsz = c->group_size;
+        c->tab.seg = seg;
+        c->tab.version++;
+    }
+    return SPH_OK;
+}
+
+static sph_status read_err(sph_ctx* c) {
+    u32 e = 0;
+    HIPCHK(c, hipMemcpyAsync(&e, &c->d[0].ctl->err, sizeof e, hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    if (!e) return SPH_OK;
+    const u32 zero = 0;
+    HIPCHK(c, hipMemcpyAsync(&c->d[0].ctl->err, &zero, sizeof zero, hipMemcpyHostToDevice, c->stream));
+    int nmax = 0;
+    HIPCHK(c, hipMemcpyAsync(&nmax, &c->d[0].ctl->nbr_max, sizeof nmax, hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    if (e & (ERR_NONFINITE | ERR_NONPOSITIVE))
+        return fail(c, SPH_E_NONFINITE, "device: %s%s", (e & ERR_NONFINITE) ? "non-finite x/v/u " : "",
+                    (e & ERR_NONPOSITIVE) ? "h <= 0 or m <= 0" : "");
+    if (e & ERR_NBR_CAP) return fail(c, SPH_E_CAPACITY, "device: neighbour list overflow (%d > nbr_capacity %d)", nmax, c->nbr_cap);
+    if (e & ERR_WALK_STACK) return fail(c, SPH_E_CAPACITY, "device: tree-walk stack or candidate list overflow");
+    if (e & ERR_NODE_CAP) return fail(c, SPH_E_CAPACITY, "device: octree node capacity exceeded");
+    if (e & ERR_GRAV_LIST) return fail(c, SPH_E_CAPACITY, "device: gravity walk stack overflow");
+    return fail(c, SPH_E_DEVICE, "device error word 0x%x", e);
+}
+
+// keys (caller order) -> sort -> key-ordered snapshot in buffer set 0 -> octree
+static sph_status build_from_caller(sph_ctx* c, const sph_particles* p, const double* box_host, uint64_t* keys_out,
+                                    int64_t* order_out) {
+    sph_status st = prepare(c, p);
+    if (st != SPH_OK) return st;
+    c->parity = 0;
+    c->tree_ok = c->lists_ok = c->dens_ok = c->resident_ok = false;
+    const DevPtrs& d = c->d[0];
+    const Dims& dm = c->dm;
+    if (dm.n == 0) {
+        c->tree_ok = true;
+        return SPH_OK;
+    }
+    if (box_host) {
+        HIPCHK(c, hipMemcpyAsync(d.ctl->box, box_host, sizeof(double) * 6 * dm.n_seg, hipMemcpyHostToDevice, c->stream));
+        launch_set_box(c->stream, d, dm, 1);
+    } else {
+        launch_bbox(c->stream, d, dm, p->x, p->y, p->z, nullptr);
+        launch_set_box(c->stream, d, dm, 0);
+    }
+    launch_keys(c->stream, d, dm, p->x, p->y, p->z, p->vx, p->vy, p->vz, p->m, p->h, p->u, (u64*)keys_out, 1);
+    radix_sort(c->stream, d, dm.n);
+    launch_gather_input(c->stream, d, dm, p->x, p->y, p->z, p->vx, p->vy, p->vz, p->m, p->h, p->u, order_out);
+    build_octree(c->stream, d, dm);
+    HIPCHK(c, hipGetLastError());
+    c->tree_ok = true;
+    return SPH_OK;
+}
+
+static sph_status ensure_lists(sph_ctx* c) {
+    if (!c->tree_ok) return fail(c, SPH_E_STATE, "sph_build_tree has not been called");
+    if (!c->lists_ok) {
+        launch_nbr_lists(c->stream, c->d[c->parity], c->dm);
+        HIPCHK(c, hipGetLastError());
+        c->lists_ok = true;
+    }
+    return SPH_OK;
+}
+
+// ---------------------------------------------------------------------------------------
+extern "C" {
+
+void sph_config_default(sph_config* f) {
+    if (!f) return;
+    memset(f, 0, sizeof *f);
+    f->precision = SPH_FP64;
+    f->gamma = 5.0 / 3.0;
+    f->av_alpha = 1.0;
+    f->av_beta = 2.0;
+    f->av_eps = 0.01;
+    f->h_coeff = 1.2;
+    f->adaptive_h = 0;
+    f->G = 0.0;
+    f->soft_eps = 0.0;
+    f->theta = 0.5;
+    f->leaf_size = 16;
+    f->group_size = 32;
+    f->nbr_capacity = 160;
+    f->stream = nullptr;
+}
+
+sph_status sph_create(const sph_config* cfg, int64_t n_capacity, int32_t seg_capacity, sph_ctx** out) {
+    if (!out) return SPH_E_ARG;
+    *out = nullptr;
+    if (n_capacity < 0 || n_capacity > (1ll << 30)) return SPH_E_ARG;
+    if (seg_capacity < 1 || seg_capacity > 512) return SPH_E_ARG;
+    sph_ctx* c = new (std::nothrow) sph_ctx();
+    if (!c) return SPH_E_NOMEM;
+    sph_status st = check_config(c, cfg);
+    if (st != SPH_OK) {
+        delete c;
+        return st;
+    }
+    c->cfg = *cfg;
+    c->n_cap = n_capacity;
+    c->seg_cap = seg_capacity;
+    c->leaf_size = cfg->leaf_size ? cfg->leaf_size : 16;
+    c->leaf_min = std::min(c->leaf_size, 8);
+    c->group_size = cfg->group_size ? cfg->group_size : 32;
+    c->nbr_cap = cfg->nbr_capacity ? cfg->nbr_capacity : 160;
+    c->stream = (hipStream_t)cfg->stream;
+    const char* ng = getenv("SPH_NO_GRAPH");
+    c->use_graph = !(ng && ng[0] == '1');
+    *out = c;
+    return SPH_OK;
+}
+
+sph_status sph_destroy(sph_ctx* c) {
+    if (!c) return SPH_OK;
+    if (c->ws) (void)hipStreamSynchronize(c->stream);
+    for (int p = 0; p < 2; ++p) {
+        if (c->gexec[p]) (void)hipGraphExecDestroy(c->gexec[p]);
+        if (c->graph[p]) (void)hipGraphDestroy(c->graph[p]);
+    }
+    if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
+    delete c;
+    return SPH_OK;
+}
+
+sph_status sph_workspace_size(const sph_ctx* c, size_t* bytes) {
+    if (!c || !bytes) return SPH_E_ARG;
+    *bytes = layout(c, nullptr, nullptr);
+    return SPH_OK;
+}
+
+sph_status sph_set_workspace(sph_ctx* c, void* ptr, size_t bytes) {
+    if (!c) return SPH_E_ARG;
+    if (!ptr) return fail(c, SPH_E_ARG, "workspace pointer is NULL");
+    if (((uintptr_t)ptr) & 255) return fail(c, SPH_E_ARG, "workspace must be 256-byte aligned");
+    const size_t need = layout(c, nullptr, nullptr);
+    if (bytes < need) return fail(c, SPH_E_NOMEM, "workspace too small: %zu < %zu bytes", bytes, need);
+    c->ws = (char*)ptr;
+    c->ws_bytes = bytes;
+    layout(c, c->ws, &c->d[0]);
+    c->d[1] = swapped(c->d[0]);
+    DevCtl zero;
+    memset(&zero, 0, sizeof zero);
+    HIPCHK(c, hipMemcpyAsync(c->d[0].ctl, &zero, sizeof zero, hipMemcpyHostToDevice, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    c->tab = Tables();
+    c->tree_ok = c->lists_ok = c->dens_ok = c->resident_ok = false;
+    return SPH_OK;
+}
+
+sph_status sph_build_tree(sph_ctx* c, const sph_particles* p, const double* box_host, uint64_t* keys_out,
+                          int64_t* order_out) {
+    if (!c) return SPH_E_ARG;
+    sph_status st = check_particles(c, p);
+    if (st != SPH_OK) return st;
+    return build_from_caller(c, p, box_host, keys_out, order_out);
+}
+
+sph_status sph_tree_nodes(sph_ctx* c, int64_t capacity, uint64_t* key, int32_t* level, int32_t* leaf, int64_t* start,
+                          int64_t* count, int64_t* n_nodes_host) {
+    if (!c || !n_nodes_host) return SPH_E_ARG;
+    if (!c->tree_ok) return fail(c, SPH_E_STATE, "sph_build_tree has not been called");
+    int nn = 0;
+    if (c->dm.n > 0) {
+        HIPCHK(c, hipMemcpyAsync(&nn, &c->d[0].ctl->n_nodes, sizeof nn, hipMemcpyDeviceToHost, c->stream));
+        HIPCHK(c, hipStreamSynchronize(c->stream));
+    }
+    *n_nodes_host = nn;
+    if (nn > capacity) return fail(c, SPH_E_CAPACITY, "tree has %d nodes > capacity %lld", nn, (long long)capacity);
+    if (nn > 0) launch_tree_export(c->stream, c->d[c->parity], c->dm, (u64*)key, level, leaf, start, count);
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    return read_err(c);
+}
+
+sph_status sph_find_neighbors(sph_ctx* c, int64_t* offsets_out, int32_t* idx_out, int64_t capacity,
+                              int64_t* total_host) {
+    if (!c) return SPH_E_ARG;
+    sph_status st = ensure_lists(c);
+    if (st != SPH_OK) return st;
+    const DevPtrs& d = c->d[c->parity];
+    const int n = c->dm.n;
+    int64_t total = 0;
+    if (n > 0) {
+        launch_csr_count(c->stream, d, c->dm, d.csr_tmp);
+        scan_i64_inplace(c->stream, d.csr_tmp, n, d.scan_tmp);
+        HIPCHK(c, hipMemcpyAsync(&total, d.csr_tmp + n, sizeof total, hipMemcpyDeviceToHost, c->stream));
+        HIPCHK(c, hipStreamSynchronize(c->stream));
+    }
+    st = read_err(c);
+    if (st != SPH_OK) return st;
+    if (total_host) *total_host = total;
+    if (offsets_out) {
+        if (n > 0)
+            HIPCHK(c, hipMemcpyAsync(offsets_out, d.csr_tmp, sizeof(int64_t) * (n + 1), hipMemcpyDeviceToDevice, c->stream));
+        else {
+            const int64_t z = 0;
+            HIPCHK(c, hipMemcpyAsync(offsets_out, &z, sizeof z, hipMemcpyHostToDevice, c->stream));
+        }
+    }
+    if (idx_out) {
+        if (total > capacity) {
+            HIPCHK(c, hipStreamSynchronize(c->stream));
+            return fail(c, SPH_E_CAPACITY, "%lld neighbour entries > capacity %lld", (long long)total, (long long)capacity);
+        }
+        if (n > 0) launch_csr_fill(c->stream, d, c->dm, d.csr_tmp, idx_out);
+    }
+    HIPCHK(c, hipGetLastError());
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    return SPH_OK;
+}
+
+sph_status sph_compute_density(sph_ctx* c, double* rho, double* P, double* cs, double* h_next) {
+    if (!c) return SPH_E_ARG;
+    sph_status st = ensure_lists(c);
+    if (st != SPH_OK) return st;
+    const DevPtrs& d = c->d[c->parity];
+    const int n = c->dm.n;
+    launch_density(c->stream, d, c->dm, c->cfg.precision == SPH_FP32C, c->cfg.gamma, c->cfg.h_coeff, d.u);
+    launch_scatter_caller(c->stream, d, n, d.rho, rho);
+    launch_scatter_caller(c->stream, d, n, d.P, P);
+    launch_scatter_caller(c->stream, d, n, d.cs, cs);
+    launch_scatter_caller(c->stream, d, n, d.hnext, h_next);
+    HIPCHK(c, hipGetLastError());
+    c->dens_ok = true;
+    return SPH_OK;
+}
+
+sph_status sph_compute_forces(sph_ctx* c, const double* rho, const double* P, const double* cs, double* ax, double* ay,
+                              double* az, double* dudt) {
+    if (!c) return SPH_E_ARG;
+    const int n = c->dm.n;
+    const int given = (rho != nullptr) + (P != nullptr) + (cs != nullptr);
+    if (given != 0 && given != 3) return fail(c, SPH_E_ARG, "rho, P, cs must be all given or all NULL");
+    sph_status st = ensure_lists(c);
+    if (st != SPH_OK) return st;
+    const DevPtrs& d = c->d[c->parity];
+    if (given == 3) {
+        launch_thermo_from_caller(c->stream, d, c->dm, rho, P, cs);
+    } else if (!c->dens_ok) {
+        return fail(c, SPH_E_STATE, "sph_compute_density has not been called");
+    }
+    launch_forces(c->stream, d, c->dm, c->cfg.precision == SPH_FP32C, c->cfg.av_alpha, c->cfg.av_beta, c->cfg.av_eps,
+                  nullptr, nullptr, nullptr);
+    launch_scatter_caller(c->stream, d, n, d.ax, ax);
+    launch_scatter_caller(c->stream, d, n, d.ay, ay);
+    launch_scatter_caller(c->stream, d, n, d.az, az);
+    launch_scatter_caller(c->stream, d, n, d.du, dudt);
+    HIPCHK(c, hipGetLastError());
+    return SPH_OK;
+}
+
+sph_status sph_compute_gravity(sph_ctx* c, double* gx, double* gy, double* gz, double* phi) {
+    if (!c) return SPH_E_ARG;
+    const int n = c->dm.n;
+    if (!c->tree_ok) return fail(c, SPH_E_STATE, "sph_build_tree has not been called");
+    const DevPtrs& d = c->d[c->parity];
+    launch_gravity(c->stream, d, c->dm, c->cfg.precision == SPH_FP32C, c->cfg.G, c->cfg.soft_eps, c->cfg.theta, 0);
+    launch_scatter_caller(c->stream, d, n, d.gx, gx);
+    launch_scatter_caller(c->stream, d, n, d.gy, gy);
+    launch_scatter_caller(c->stream, d, n, d.gz, gz);
+    launch_scatter_caller(c->stream, d, n, d.phi, phi);
+    HIPCHK(c, hipGetLastError());
+    return SPH_OK;
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------------------
+// leapfrog driver
+
+// Accelerations of the resident state in buffer set p (tree already built).
+static void accel_pass(sph_ctx* c, hipStream_t s, const DevPtrs& d, const double* u_eos) {
+    const int fp32c = c->cfg.precision == SPH_FP32C;
+    launch_nbr_lists(s, d, c->dm);
+    launch_density(s, d, c->dm, fp32c, c->cfg.gamma, c->cfg.h_coeff, u_eos);
+    launch_forces(s, d, c->dm, fp32c, c->cfg.av_alpha, c->cfg.av_beta, c->cfg.av_eps, nullptr, nullptr, nullptr);
+    if (c->cfg.G != 0.0) launch_gravity(s, d, c->dm, fp32c, c->cfg.G, c->cfg.soft_eps, c->cfg.theta, 1);
+}
+
+// One KDK step from buffer set p into buffer set 1 - p.
+static void step_launches(sph_ctx* c, hipStream_t s, int p) {
+    const DevPtrs& a = c->d[p];
+    const DevPtrs& b = c->d[1 - p];
+    const int n = c->dm.n;
+    const double dt = c->g_dt;
+    launch_kick_drift(s, a, n, dt);
+    launch_bbox(s, a, c->dm, a.x, a.y, a.z, nullptr);
+    launch_set_box(s, a, c->dm, 0);
+    launch_step_keys(s, a, c->dm);
+    radix_sort(s, a, n);
+    launch_step_permute(s, a, n);
+    launch_pack_records(s, b, n);
+    build_octree(s, b, c->dm);
+    accel_pass(c, s, b, b.up);
+    launch_kick(s, b, n, dt, c->cfg.adaptive_h);
+}
+
+static sph_status run_steps(sph_ctx* c, double dt, int nsteps) {
+    if (nsteps <= 0 || c->dm.n == 0) return SPH_OK;
+    const bool regraph = c->g_dt != dt || c->g_n != c->dm.n || c->g_leaf != c->leaf_size ||
+                         c->g_gsz != c->group_size || c->g_tabv != c->tab.version;
+    c->g_dt = dt;
+    if (!c->use_graph) {
+        for (int k = 0; k < nsteps; ++k) {
+            step_launches(c, c->stream, c->parity);
+            c->parity ^= 1;
+        }
+        HIPCHK(c, hipGetLastError());
+        return SPH_OK;
+    }
+    if (regraph || !c->gexec[0] || !c->gexec[1]) {
+        if (!c->cap_stream) HIPCHK(c, hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking));
+        HIPCHK(c, hipStreamSynchronize(c->stream));
+        for (int p = 0; p < 2; ++p) {
+            if (c->gexec[p]) { (void)hipGraphExecDestroy(c->gexec[p]); c->gexec[p] = nullptr; }
+            if (c->graph[p]) { (void)hipGraphDestroy(c->graph[p]); c->graph[p] = nullptr; }
+            HIPCHK(c, hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeThreadLocal));
+            step_launches(c, c->cap_stream, p);
+            HIPCHK(c, hipStreamEndCapture(c->cap_stream, &c->graph[p]));
+            HIPCHK(c, hipGraphInstantiate(&c->gexec[p], c->graph[p], nullptr, nullptr, 0));
+        }
+        c->g_n = c->dm.n;
+        c->g_tabv = c->tab.version;
+        c->g_leaf = c->leaf_size;
+        c->g_gsz = c->group_size;
+    }
+    for (int k = 0; k < nsteps; ++k) {
+        HIPCHK(c, hipGraphLaunch(c->gexec[c->parity], c->stream));
+        c->parity ^= 1;
+    }
+    return SPH_OK;
+}
+
+static sph_status step_impl(sph_ctx* c, sph_particles* p, double dt, int32_t nsteps, uint32_t flags, double* diag,
+                            bool write_back) {
+    if (!(dt > 0.0) || !std::isfinite(dt)) return fail(c, SPH_E_ARG, "dt must be > 0");
+    if (nsteps < 0) return fail(c, SPH_E_ARG, "nsteps must be >= 0");
+    sph_status st;
+    if (flags & SPH_STEP_RESUME) {
+        if (!c->resident_ok) return fail(c, SPH_E_STATE, "SPH_STEP_RESUME without a previous sph_step");
+        if (!c->ws) return fail(c, SPH_E_NOMEM, "no workspace set");
+        if (p && p->n != c->dm.n) return fail(c, SPH_E_ARG, "SPH_STEP_RESUME with a different particle count");
+    } else {
+        st = check_particles(c, p);
+        if (st != SPH_OK) return st;
+        if ((flags & SPH_STEP_PRIMED) && p->n > 0 && (!p->ax || !p->ay || !p->az || !p->dudt))
+            return fail(c, SPH_E_ARG, "SPH_STEP_PRIMED needs ax, ay, az and dudt");
+        st = build_from_caller(c, p, nullptr, nullptr, nullptr);
+        if (st != SPH_OK) return st;
+        const DevPtrs& d = c->d[0];
+        const int n = c->dm.n;
+        if (n > 0) {
+            if (flags & SPH_STEP_PRIMED) {
+                launch_load_accel(c->stream, d, n, p->ax, p->ay, p->az, p->dudt);
+            } else {
+                accel_pass(c, c->stream, d, d.u);
+                if (c->cfg.adaptive_h) launch_set_hnext(c->stream, d, n);
+            }
+        }
+        HIPCHK(c, hipGetLastError());
+        c->resident_ok = true;
+    }
+    c->tree_ok = c->lists_ok = c->dens_ok = false;
+    st = run_steps(c, dt, nsteps);
+    if (st != SPH_OK) return st;
+    const DevPtrs& d = c->d[c->parity];
+    const int n = c->dm.n;
+    if (diag) {
+        launch_diag(c->stream, d, n, c->cfg.G != 0.0);
+        HIPCHK(c, hipMemcpyAsync(diag, d.ctl->diag, 9 * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+    }
+    if (write_back && p && p->x && n > 0)
+        launch_write_back(c->stream, d, n, p->x, p->y, p->z, p->vx, p->vy, p->vz, p->h, p->u, p->ax, p->ay, p->az,
+                          p->dudt);
+    HIPCHK(c, hipGetLastError());
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    return read_err(c);
+}
+
+extern "C" {
+
+sph_status sph_step(sph_ctx* c, sph_particles* p, double dt, int32_t nsteps, uint32_t flags, double* diag_host) {
+    if (!c) return SPH_E_ARG;
+    return step_impl(c, p, dt, nsteps, flags, diag_host, true);
+}
+
+sph_status sph_get_tuning(const sph_ctx* c, int32_t* leaf_size, int32_t* group_size) {
+    if (!c) return SPH_E_ARG;
+    if (leaf_size) *leaf_size = c->leaf_size;
+    if (group_size) *group_size = c->group_size;
+    return SPH_OK;
+}
+
+sph_status sph_autotune(sph_ctx* c, const sph_particles* p, double dt, const char* cache) {
+    if (!c) return SPH_E_ARG;
+    sph_status st = check_particles(c, p);
+    if (st != SPH_OK) return st;
+    char keybuf[160];
+    snprintf(keybuf, sizeof keybuf, "n%lld_s%d_p%d_g%d_a%d", (long long)p->n, p->n_seg, c->cfg.precision,
+             c->cfg.G != 0.0, c->cfg.adaptive_h);
+    const std::string key(keybuf);
+    if (cache) {  // tiny JSON reader: "key": [leaf, group]
+        std::ifstream f(cache);
+        if (f) {
+            std::stringstream ss;
+            ss << f.rdbuf();
+            const std::string s = ss.str();
+            const size_t at = s.find("\"" + key + "\"");
+            if (at != std::string::npos) {
+                int L = 0, G = 0;
+                if (sscanf(s.c_str() + s.find('[', at), "[%d, %d]", &L, &G) == 2 && L >= c->leaf_min && L <= 64 &&
+                    (G == 8 || G == 16 || G == 32 || G == 64)) {
+                    c->leaf_size = L;
+                    c->group_size = G;
+                    return SPH_OK;
+                }
+            }
+        }
+    }
+    const int leaves[] = {8, 12, 16, 24, 32};
+    const int groups[] = {16, 32, 64};
+    double best = 1e300;
+    int bL = c->leaf_size, bG = c->group_size;
+    sph_particles q = *p;
+    q.ax = q.ay = q.az = q.dudt = nullptr;
+    hipEvent_t e0, e1;
+    HIPCHK(c, hipEventCreate(&e0));
+    HIPCHK(c, hipEventCreate(&e1));
+    for (int L : leaves) {
+        if (L < c->leaf_min) continue;
+        for (int G : groups) {
+            c->leaf_size = L;
+            c->group_size = G;
+            st = step_impl(c, &q, dt, 1, 0, nullptr, false);  // load, prime, warm up, capture
+            if (st != SPH_OK) continue;
+            HIPCHK(c, hipEventRecord(e0, c->stream));
+            st = step_impl(c, &q, dt, 3, SPH_STEP_RESUME, nullptr, false);
+            HIPCHK(c, hipEventRecord(e1, c->stream));
+            HIPCHK(c, hipEventSynchronize(e1));
+            if (st != SPH_OK) continue;
+            float ms = 0.f;
+            HIPCHK(c, hipEventElapsedTime(&ms, e0, e1));
+            if (ms < best) {
+                best = ms;
+                bL = L;
+                bG = G;
+            }
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    c->leaf_size = bL;
+    c->group_size = bG;
+    c->resident_ok = false;
+    c->tab = Tables();
+    if (cache) {
+        std::string body;
+        {
+            std::ifstream f(cache);
+            if (f) {
+                std::stringstream ss;
+                ss << f.rdbuf();
+                body = ss.str();
+            }
+        }
+        const size_t close = body.rfind('}');
+        char entry[256];
+        snprintf(entry, sizeof entry, "\"%s\": [%d, %d]", key.c_str(), bL, bG);
+        if (close == std::string::npos || body.find('"') == std::string::npos) body = std::string("{\n  ") + entry + "\n}\n";
+        else body = body.substr(0, close) + ",\n  " + entry + "\n}\n";
+        std::ofstream o(cache);
+        o << body;
+    }
+    return best < 1e300 ? SPH_OK : fail(c, SPH_E_DEVICE, "autotune: no configuration ran");
+}
+
+sph_status sph_sync(sph_ctx* c) {
+    if (!c) return SPH_E_ARG;
+    if (!c->ws) return SPH_OK;
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    return read_err(c);
+}
+
+const char* sph_last_error(const sph_ctx* c) {
+    if (!c) return k_null_ctx_msg;
+    return c->err.c_str();
+}
+
+}  // extern "C"

@@ -1,0 +1,216 @@
+// Internal header of the gfx950 SPH + octree library: device helpers, the device-side
+// workspace layout and the kernel launchers shared between translation units.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+typedef unsigned long long u64;
+typedef unsigned int u32;
+
+// ---------------------------------------------------------------------------------------
+// Sticky device error bits (read back by sph_sync / synchronous calls).
+enum : u32 {
+    ERR_NONFINITE = 1u,      // non-finite position, velocity or energy
+    ERR_NONPOSITIVE = 2u,    // h <= 0 or m <= 0
+    ERR_NBR_CAP = 4u,        // a particle has more neighbours than nbr_capacity
+    ERR_WALK_STACK = 8u,     // tree-walk stack or candidate list overflow
+    ERR_NODE_CAP = 16u,      // octree node capacity exceeded
+    ERR_GRAV_LIST = 32u,     // gravity walk stack overflow
+};
+
+constexpr int MAX_LEVEL = 21;   // 21 three-bit digits below the sentinel bit 63
+constexpr double M_1_PI_D = 0.318309886183790671537767526745028724;
+
+// Small control block living in device memory.
+struct DevCtl {
+    u32 err;
+    int n_nodes;
+    int n_leaves;
+    int nbr_max;                  // largest neighbour count seen (for overflow reports)
+    int level_count[24];          // nodes per level
+    int level_off[24];            // exclusive prefix of level_count
+    u64 box_enc[512 * 6];         // per segment: ordered-integer min x,y,z then max x,y,z
+    double box[512 * 6];          // decoded per-segment box lo.xyz, hi.xyz
+    double scale[512];            // 2^B / L per segment (0 when L == 0)
+    double side[512];             // L (root cell side) per segment
+    double diag[16];              // step diagnostics
+};
+
+// Device pointers of one context.  All arrays are carved out of the caller's workspace.
+struct DevPtrs {
+    DevCtl* ctl;
+    // sort
+    u64 *key_a, *key_b;           // n_cap
+    u32 *val_a, *val_b;           // n_cap
+    u32* rs_hist;                 // 256 * rs_blocks_cap
+    void* scan_tmp;               // 8 * scan_blocks_cap (u64)
+    // Morton-ordered particle data (SoA FP64)
+    double *x, *y, *z, *vx, *vy, *vz, *m, *h, *u;
+    double *vpx, *vpy, *vpz, *up;  // predictors (step)
+    double *ax, *ay, *az, *du;
+    double *rho, *P, *cs, *hnext;
+    double *gx, *gy, *gz, *phi;
+    // second copies used while reordering between steps
+    double *x2, *y2, *z2, *vx2, *vy2, *vz2, *m2, *h2, *u2, *vpx2, *vpy2, *vpz2, *up2;
+    u32* id;                      // caller index of each Morton position
+    u32* id2;
+    u32* inv;                     // caller index -> Morton position of the previous order
+    double4* pos4;                // x, y, z, h (Morton order)
+    double4* vel4;                // vx(pred), vy, vz, m
+    double4* thr4;                // rho, P/rho^2, c, u
+    float4* velf;                 // FP32 copies for the compensated path: vx, vy, vz, m
+    float4* thrf;                 //   rho, P/rho^2, c, h
+    // tree
+    signed char* lcp;             // n_cap + 1: shared leading digits with the previous key
+    unsigned char* lvl;           // n_cap: leaf level of each sorted position
+    u64* scan_in;                 // n_cap + 1: (nodes at position << 32) | leaf start
+    u64* scan_out;                // n_cap + 1
+    int* leaf_start;              // n_cap + 1 (sorted position of each leaf, then n)
+    int* leaf_pre;                // n_cap: pre-order node of each leaf
+    unsigned char* pre_level;     // node_cap (pre-order)
+    unsigned char* pre_leaf;      // node_cap
+    int* pre_start;               // node_cap
+    int* pre_to_bfs;              // node_cap
+    int* bfs_to_pre;              // node_cap
+    int* lsort_hist;              // 24 * lsort_tiles_cap
+    int4* topo;                   // node_cap: {first, count, level, is_leaf}
+    int* parent;                  // node_cap
+    int* counter;                 // node_cap
+    int2* range;                  // node_cap: {start, count} in sorted order
+    double4* nbox_lo;             // node_cap: lo.xyz, hmax
+    double4* nbox_hi;             // node_cap: hi.xyz, cell side
+    double4* mom0;                // node_cap: M, com.xyz
+    double4* mom1;                // node_cap: Ixx, Iyy, Izz, tr I
+    double4* mom2;                // node_cap: Ixy, Ixz, Iyz, 0
+    // groups and neighbour lists
+    int4* group;                  // group_cap: {start, count, root node (-1 = 0), seg}
+    int* nbr;                     // group_cap * group_size * nbr_cap
+    int* nbr_cnt;                 // n_cap
+    int* nbr_base;                // n_cap: group whose lists hold the particle (-1 = none)
+    // seg / chunk tables
+    int4* chunk;                  // chunk_cap: {begin, end, seg, 0} in caller/Morton order
+    int* seg_root_rank;           // seg_cap: rank of the segment among non-empty segments
+    // diagnostics partials
+    double* diag_part;            // 16 * diag_blocks
+    // CSR export
+    int64_t* csr_tmp;             // n_cap + 1 (counts / offsets in caller order)
+};
+
+struct Dims {
+    int n;            // particles
+    int n_seg;        // 1 = one set
+    int batched;      // n_seg > 1
+    int leaf_size;
+    int group_size;
+    int nbr_cap;
+    int n_groups;
+    int n_chunks;
+    int node_cap;
+    int min_level;    // 3 when batched, else 0
+};
+
+// ---------------------------------------------------------------------------------------
+// Wave helpers (wave64 on gfx950)
+
+__device__ __forceinline__ int lane_id() { return __lane_id(); }
+
+__device__ __forceinline__ u64 lanemask_lt() { return (1ull << lane_id()) - 1ull; }
+
+__device__ __forceinline__ int wave_incl_scan(int v) {
+    const int lane = lane_id();
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+        int t = __shfl_up(v, d, 64);
+        if (lane >= d) v += t;
+    }
+    return v;
+}
+
+__device__ __forceinline__ double wave_min(double v) {
+#pragma unroll
+    for (int d = 32; d >= 1; d >>= 1) v = fmin(v, __shfl_xor(v, d, 64));
+    return v;
+}
+__device__ __forceinline__ double wave_max(double v) {
+#pragma unroll
+    for (int d = 32; d >= 1; d >>= 1) v = fmax(v, __shfl_xor(v, d, 64));
+    return v;
+}
+
+// Sum over the 64/gsz lanes that serve one target (lanes t, t+gsz, ...), fixed order.
+__device__ __forceinline__ double lanes_sum_d(double v, int gsz) {
+    for (int off = gsz; off < 64; off <<= 1) v += __shfl_xor(v, off, 64);
+    return v;
+}
+
+// Ordered-integer encoding of doubles for exact atomic min/max.
+__device__ __forceinline__ u64 enc_double(double d) {
+    u64 b = (u64)__double_as_longlong(d);
+    return (b >> 63) ? ~b : (b | 0x8000000000000000ull);
+}
+__device__ __forceinline__ double dec_double(u64 e) {
+    u64 b = (e >> 63) ? (e & 0x7fffffffffffffffull) : ~e;
+    return __longlong_as_double((long long)b);
+}
+
+__device__ __forceinline__ void set_err(DevCtl* ctl, u32 bits) { atomicOr(&ctl->err, bits); }
+
+// Leading equal 3-bit digits (0..21) of two keys below the sentinel.
+__device__ __forceinline__ int lcp_digits(u64 a, u64 b) {
+    u64 x = (a ^ b) & 0x7fffffffffffffffull;
+    if (x == 0) return MAX_LEVEL;
+    return (__clzll(x) - 1) / 3;
+}
+
+// ---------------------------------------------------------------------------------------
+// Launchers (defined in the .hip files)
+
+// k_build.hip
+void launch_fill_u32(hipStream_t s, u32* p, u32 v, int n);
+void launch_fill_i32(hipStream_t s, int* p, int v, int n);
+void launch_bbox(hipStream_t s, const DevPtrs& d, const Dims& dm, const double* x, const double* y,
+                 const double* z, const u32* perm_or_null);
+void launch_set_box(hipStream_t s, const DevPtrs& d, const Dims& dm, int from_host_box);
+void launch_keys(hipStream_t s, const DevPtrs& d, const Dims& dm, const double* x, const double* y,
+                 const double* z, const double* vx, const double* vy, const double* vz, const double* m,
+                 const double* h, const double* u, u64* keys_out_caller, int caller_order);
+void radix_sort(hipStream_t s, const DevPtrs& d, int n);
+void scan_u64(hipStream_t s, const u64* in, u64* out, int n, void* tmp);
+void launch_gather_input(hipStream_t s, const DevPtrs& d, const Dims& dm, const double* x, const double* y,
+                         const double* z, const double* vx, const double* vy, const double* vz, const double* m,
+                         const double* h, const double* u, int64_t* order_out);
+// k_tree.hip
+void build_octree(hipStream_t s, const DevPtrs& d, const Dims& dm);
+void launch_tree_export(hipStream_t s, const DevPtrs& d, const Dims& dm, u64* key, int32_t* level,
+                        int32_t* leaf, int64_t* start, int64_t* count);
+// k_walk.hip
+void launch_nbr_lists(hipStream_t s, const DevPtrs& d, const Dims& dm);
+void launch_csr_count(hipStream_t s, const DevPtrs& d, const Dims& dm, int64_t* counts_caller);
+void scan_i64_inplace(hipStream_t s, int64_t* a, int n, void* tmp);
+void launch_csr_fill(hipStream_t s, const DevPtrs& d, const Dims& dm, const int64_t* offsets, int32_t* idx);
+// k_sph.hip
+void launch_density(hipStream_t s, const DevPtrs& d, const Dims& dm, int fp32c, double gamma, double h_coeff,
+                    const double* u_eos);
+void launch_thermo_from_caller(hipStream_t s, const DevPtrs& d, const Dims& dm, const double* rho,
+                               const double* P, const double* cs);
+void launch_forces(hipStream_t s, const DevPtrs& d, const Dims& dm, int fp32c, double alpha, double beta,
+                   double eps_av, const double* vx, const double* vy, const double* vz);
+// k_grav.hip
+void launch_gravity(hipStream_t s, const DevPtrs& d, const Dims& dm, int fp32c, double G, double eps,
+                    double theta, int accumulate);
+// k_step.hip
+void launch_scatter_caller(hipStream_t s, const DevPtrs& d, int n, const double* src, double* dst);
+void launch_gather_caller(hipStream_t s, const DevPtrs& d, int n, const double* src_caller, double* dst);
+void launch_kick_drift(hipStream_t s, const DevPtrs& d, int n, double dt);
+void launch_step_keys(hipStream_t s, const DevPtrs& d, const Dims& dm);
+void launch_step_permute(hipStream_t s, const DevPtrs& d, int n);
+void launch_kick(hipStream_t s, const DevPtrs& d, int n, double dt, int adaptive_h);
+void launch_set_hnext(hipStream_t s, const DevPtrs& d, int n);
+void launch_diag(hipStream_t s, const DevPtrs& d, int n, int with_phi);
+void launch_write_back(hipStream_t s, const DevPtrs& d, int n, double* x, double* y, double* z, double* vx,
+                       double* vy, double* vz, double* h, double* u, double* ax, double* ay, double* az,
+                       double* du);
+void launch_load_accel(hipStream_t s, const DevPtrs& d, int n, const double* ax, const double* ay,
+                       const double* az, const double* du);
+void launch_pack_records(hipStream_t s, const DevPtrs& d, int n);

@@ -1,0 +1,183 @@
+// Leapfrog step support (kick-drift-kick with velocity and energy predictors), reordering
+// of the resident state between steps, diagnostics and caller-order copies.  All FP64.
+#include "common.h"
+
+static inline dim3 g256(int n) { return dim3((n + 255) / 256); }
+
+__global__ void k_scatter_caller(int n, const u32* __restrict__ id, const double* __restrict__ src, double* dst) {
+    const int q = blockIdx.x * blockDim.x + threadIdx.x;
+    if (q < n) dst[id[q]] = src[q];
+}
+void launch_scatter_caller(hipStream_t s, const DevPtrs& d, int n, const double* src, double* dst) {
+    if (n > 0 && dst) hipLaunchKernelGGL(k_scatter_caller, g256(n), dim3(256), 0, s, n, d.id, src, dst);
+}
+
+__global__ void k_gather_caller(int n, const u32* __restrict__ id, const double* __restrict__ src, double* dst) {
+    const int q = blockIdx.x * blockDim.x + threadIdx.x;
+    if (q < n) dst[q] = src[id[q]];
+}
+void launch_gather_caller(hipStream_t s, const DevPtrs& d, int n, const double* src_caller, double* dst) {
+    if (n > 0) hipLaunchKernelGGL(k_gather_caller, g256(n), dim3(256), 0, s, n, d.id, src_caller, dst);
+}
+
+// v' = v + dt/2 a; u' = u + dt/2 du; x += dt v'; predictors v^ = v' + dt/2 a, u^ = u' + dt/2 du.
+__global__ void k_kick_drift(int n, double dt, double* x, double* y, double* z, double* vx, double* vy, double* vz,
+                             double* u, const double* __restrict__ ax, const double* __restrict__ ay,
+                             const double* __restrict__ az, const double* __restrict__ du, double* vpx, double* vpy,
+                             double* vpz, double* up) {
+    const int q = blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= n) return;
+    const double half = 0.5 * dt;
+    const double a0 = ax[q], a1 = ay[q], a2 = az[q], d0 = du[q];
+    const double hx = vx[q] + half * a0, hy = vy[q] + half * a1, hz = vz[q] + half * a2;
+    const double uh = u[q] + half * d0;
+    x[q] = x[q] + dt * hx;
+    y[q] = y[q] + dt * hy;
+    z[q] = z[q] + dt * hz;
+    vx[q] = hx; vy[q] = hy; vz[q] = hz;
+    u[q] = uh;
+    vpx[q] = hx + half * a0;
+    vpy[q] = hy + half * a1;
+    vpz[q] = hz + half * a2;
+    up[q] = uh + half * d0;
+}
+void launch_kick_drift(hipStream_t s, const DevPtrs& d, int n, double dt) {
+    if (n > 0)
+        hipLaunchKernelGGL(k_kick_drift, g256(n), dim3(256), 0, s, n, dt, d.x, d.y, d.z, d.vx, d.vy, d.vz, d.u, d.ax,
+                           d.ay, d.az, d.du, d.vpx, d.vpy, d.vpz, d.up);
+}
+
+// New key order: q <- old position inv[val[q]]; the second buffer set receives the data.
+__global__ void k_step_permute(int n, const u32* __restrict__ val, const u32* __restrict__ inv, DevPtrs d) {
+    const int q = blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= n) return;
+    const u32 i = val[q];
+    const u32 p = inv[i];
+    d.id2[q] = i;
+    d.x2[q] = d.x[p]; d.y2[q] = d.y[p]; d.z2[q] = d.z[p];
+    d.vx2[q] = d.vx[p]; d.vy2[q] = d.vy[p]; d.vz2[q] = d.vz[p];
+    d.u2[q] = d.u[p]; d.m2[q] = d.m[p]; d.h2[q] = d.h[p];
+    d.vpx2[q] = d.vpx[p]; d.vpy2[q] = d.vpy[p]; d.vpz2[q] = d.vpz[p]; d.up2[q] = d.up[p];
+}
+void launch_step_permute(hipStream_t s, const DevPtrs& d, int n) {
+    if (n > 0) hipLaunchKernelGGL(k_step_permute, g256(n), dim3(256), 0, s, n, d.val_a, d.inv, d);
+}
+
+// Records read by the pair kernels: pos4 = (x, h), vel4 = (predicted v, m).
+__global__ void k_pack_records(int n, const double* __restrict__ x, const double* __restrict__ y,
+                               const double* __restrict__ z, const double* __restrict__ h,
+                               const double* __restrict__ vx, const double* __restrict__ vy,
+                               const double* __restrict__ vz, const double* __restrict__ m, double4* pos4,
+                               double4* vel4, float4* velf) {
+    const int q = blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= n) return;
+    const double mm = m[q], wx = vx[q], wy = vy[q], wz = vz[q];
+    pos4[q] = make_double4(x[q], y[q], z[q], h[q]);
+    vel4[q] = make_double4(wx, wy, wz, mm);
+    velf[q] = make_float4((float)wx, (float)wy, (float)wz, (float)mm);
+}
+void launch_pack_records(hipStream_t s, const DevPtrs& d, int n) {
+    if (n > 0)
+        hipLaunchKernelGGL(k_pack_records, g256(n), dim3(256), 0, s, n, d.x, d.y, d.z, d.h, d.vpx, d.vpy, d.vpz, d.m,
+                           d.pos4, d.vel4, d.velf);
+}
+
+// v = v' + dt/2 a_new;  u = u' + dt/2 du_new;  optional lagged h update.
+__global__ void k_kick(int n, double dt, double* vx, double* vy, double* vz, double* u, const double* __restrict__ ax,
+                       const double* __restrict__ ay, const double* __restrict__ az, const double* __restrict__ du,
+                       double* h, const double* __restrict__ hnext, int adaptive) {
+    const int q = blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= n) return;
+    const double half = 0.5 * dt;
+    vx[q] = vx[q] + half * ax[q];
+    vy[q] = vy[q] + half * ay[q];
+    vz[q] = vz[q] + half * az[q];
+    u[q] = u[q] + half * du[q];
+    if (adaptive) h[q] = hnext[q];
+}
+void launch_kick(hipStream_t s, const DevPtrs& d, int n, double dt, int adaptive_h) {
+    if (n > 0)
+        hipLaunchKernelGGL(k_kick, g256(n), dim3(256), 0, s, n, dt, d.vx, d.vy, d.vz, d.u, d.ax, d.ay, d.az, d.du, d.h,
+                           d.hnext, adaptive_h);
+}
+
+__global__ void k_set_hnext(int n, double* h, const double* __restrict__ hnext) {
+    const int q = blockIdx.x * blockDim.x + threadIdx.x;
+    if (q < n) h[q] = hnext[q];
+}
+void launch_set_hnext(hipStream_t s, const DevPtrs& d, int n) {
+    if (n > 0) hipLaunchKernelGGL(k_set_hnext, g256(n), dim3(256), 0, s, n, d.h, d.hnext);
+}
+
+// Diagnostics: Px, Py, Pz, Lx, Ly, Lz, Ekin, Eth, Egrav -- two fixed-order stages.
+constexpr int DIAG_BLOCKS = 256;
+__global__ void __launch_bounds__(256) k_diag1(int n, const double* __restrict__ x, const double* __restrict__ y,
+                                                const double* __restrict__ z, const double* __restrict__ vx,
+                                                const double* __restrict__ vy, const double* __restrict__ vz,
+                                                const double* __restrict__ m, const double* __restrict__ u,
+                                                const double* __restrict__ phi, double* part) {
+    double a[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
+    for (int q = blockIdx.x * blockDim.x + threadIdx.x; q < n; q += gridDim.x * blockDim.x) {
+        const double mm = m[q], px = x[q], py = y[q], pz = z[q], wx = vx[q], wy = vy[q], wz = vz[q];
+        a[0] += mm * wx; a[1] += mm * wy; a[2] += mm * wz;
+        a[3] += mm * (py * wz - pz * wy);
+        a[4] += mm * (pz * wx - px * wz);
+        a[5] += mm * (px * wy - py * wx);
+        a[6] += 0.5 * mm * (wx * wx + wy * wy + wz * wz);
+        a[7] += mm * u[q];
+        if (phi) a[8] += 0.5 * mm * phi[q];
+    }
+    __shared__ double red[4][9];
+    const int w = threadIdx.x >> 6;
+    for (int k = 0; k < 9; ++k) {
+        double v = a[k];
+        for (int d = 32; d >= 1; d >>= 1) v += __shfl_xor(v, d, 64);
+        if (lane_id() == 0) red[w][k] = v;
+    }
+    __syncthreads();
+    if (threadIdx.x < 9) part[blockIdx.x * 16 + threadIdx.x] = ((red[0][threadIdx.x] + red[1][threadIdx.x]) +
+                                                                red[2][threadIdx.x]) + red[3][threadIdx.x];
+}
+__global__ void k_diag2(const double* __restrict__ part, DevCtl* ctl) {
+    if (threadIdx.x < 9) {
+        double s = 0.0;
+        for (int b = 0; b < DIAG_BLOCKS; ++b) s += part[b * 16 + threadIdx.x];
+        ctl->diag[threadIdx.x] = s;
+    }
+}
+void launch_diag(hipStream_t s, const DevPtrs& d, int n, int with_phi) {
+    hipLaunchKernelGGL(k_diag1, dim3(DIAG_BLOCKS), dim3(256), 0, s, n, d.x, d.y, d.z, d.vx, d.vy, d.vz, d.m, d.u,
+                       with_phi ? d.phi : nullptr, d.diag_part);
+    hipLaunchKernelGGL(k_diag2, dim3(1), dim3(64), 0, s, d.diag_part, d.ctl);
+}
+
+// Resident key-ordered state -> caller order.
+__global__ void k_write_back(int n, DevPtrs d, double* x, double* y, double* z, double* vx, double* vy, double* vz,
+                             double* h, double* u, double* ax, double* ay, double* az, double* du) {
+    const int q = blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= n) return;
+    const u32 i = d.id[q];
+    x[i] = d.x[q]; y[i] = d.y[q]; z[i] = d.z[q];
+    vx[i] = d.vx[q]; vy[i] = d.vy[q]; vz[i] = d.vz[q];
+    h[i] = d.h[q]; u[i] = d.u[q];
+    if (ax) { ax[i] = d.ax[q]; ay[i] = d.ay[q]; az[i] = d.az[q]; du[i] = d.du[q]; }
+}
+void launch_write_back(hipStream_t s, const DevPtrs& d, int n, double* x, double* y, double* z, double* vx, double* vy,
+                       double* vz, double* h, double* u, double* ax, double* ay, double* az, double* du) {
+    if (n > 0)
+        hipLaunchKernelGGL(k_write_back, g256(n), dim3(256), 0, s, n, d, x, y, z, vx, vy, vz, h, u, ax, ay, az, du);
+}
+
+// Caller-supplied accelerations of the input state -> key order.
+__global__ void k_load_accel(int n, const u32* __restrict__ id, const double* __restrict__ ax,
+                             const double* __restrict__ ay, const double* __restrict__ az,
+                             const double* __restrict__ du, double* dax, double* day, double* daz, double* ddu) {
+    const int q = blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= n) return;
+    const u32 i = id[q];
+    dax[q] = ax[i]; day[q] = ay[i]; daz[q] = az[i]; ddu[q] = du[i];
+}
+void launch_load_accel(hipStream_t s, const DevPtrs& d, int n, const double* ax, const double* ay, const double* az,
+                       const double* du) {
+    if (n > 0) hipLaunchKernelGGL(k_load_accel, g256(n), dim3(256), 0, s, n, d.id, ax, ay, az, du, d.ax, d.ay, d.az, d.du);
+}

@@ -1,0 +1,382 @@
+// Octree over sorted keys (Sec. 2.1 "Tree topology" of arXiv:2007.03097, Fig. 1).
+//
+// A cell at level l is the run of sorted particles sharing the first l 3-bit digits of
+// their keys.  The root (level 0) is a node; a cell is a node when its parent cell is a
+// node holding more than leaf_size particles (and l <= 21); a node is a leaf when it holds
+// at most leaf_size particles, or at level 21.  This is the paper's refine-until-isolated
+// rule with "isolated" widened to leaf_size particles.
+//
+// Data-parallel construction, no recursion:
+//   lcp[i]   = leading equal digits of keys i-1 and i (-1 at i = 0 and i = n): cell
+//              boundaries at level l are the positions with lcp < l.
+//   lvl[i]   = level of the leaf holding i = 1 + min{v : the nearest boundaries with
+//              lcp <= v on both sides of i are at most leaf_size apart}, found by a binary
+//              search over v with windowed scans in LDS.
+//   position i starts the nodes of levels lcp[i]+1 .. lvl[i]; an exclusive scan of those
+//   counts numbers the nodes in pre-order.  A stable counting sort by level turns that
+//   into breadth-first order, where the children of a node are a contiguous run of the
+//   next level.  Moments are aggregated bottom-up by the last child to finish.
+#include "common.h"
+
+constexpr int TB = 256;          // positions per block in the leaf-level kernel
+constexpr int MAX_WIN = 256;     // largest supported leaf_size
+
+__global__ void __launch_bounds__(TB) k_leaf_levels(const u64* __restrict__ key, int n, int win, int min_level,
+                                                    signed char* lcp, unsigned char* lvl, u64* scan_in) {
+    __shared__ signed char c[TB + 2 * MAX_WIN + 2];
+    const int b0 = blockIdx.x * TB;
+    const int lo = b0 - win;                      // c[j] holds position lo + j
+    const int cnt = TB + 2 * win + 1;
+    for (int j = threadIdx.x; j < cnt; j += TB) {
+        const int p = lo + j;
+        int v = -1;
+        if (p > 0 && p < n) v = lcp_digits(key[p - 1], key[p]);
+        c[j] = (signed char)v;
+    }
+    __syncthreads();
+    const int i = b0 + threadIdx.x;
+    if (i >= n) return;
+    const int ci = i - lo;
+    // P(v): left boundary distance t (c(i-t) <= v, 0 <= t < win) plus right distance k
+    // (c(i+k) <= v, 1 <= k <= win) is at most win.
+    int vlo = -1, vhi = MAX_LEVEL;
+    while (vlo < vhi) {
+        const int v = (vlo + vhi) >> 1;
+        int t = 0;
+        while (t < win && c[ci - t] > v) ++t;
+        int k = 1;
+        while (k <= win && c[ci + k] > v) ++k;
+        if (t < win && k <= win && t + k <= win) vhi = v;
+        else vlo = v + 1;
+    }
+    int L = vlo + 1;
+    if (L > MAX_LEVEL) L = MAX_LEVEL;
+    if (L < min_level) L = min_level;
+    const int cc = c[ci];
+    const int nodes = L > cc ? L - cc : 0;
+    lcp[i] = (signed char)cc;
+    lvl[i] = (unsigned char)L;
+    scan_in[i] = ((u64)nodes << 32) | (u64)(nodes > 0 ? 1u : 0u);
+    if (i == n - 1) lcp[n] = -1;
+}
+
+// Pre-order node records, leaf table and per-level node counts.
+__global__ void __launch_bounds__(256) k_emit_nodes(int n, const signed char* __restrict__ lcp,
+                                                     const unsigned char* __restrict__ lvl,
+                                                     const u64* __restrict__ scan, unsigned char* pre_level,
+                                                     unsigned char* pre_leaf, int* pre_start, int* leaf_start,
+                                                     int* leaf_pre, DevCtl* ctl, int node_cap) {
+    __shared__ int hist[24];
+    if (threadIdx.x < 24) hist[threadIdx.x] = 0;
+    __syncthreads();
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    const u64 tot = scan[n];
+    const int n_nodes = (int)(tot >> 32), n_leaves = (int)(tot & 0xffffffffu);
+    if (i < n) {
+        const int c = lcp[i], L = lvl[i];
+        if (L > c) {
+            const u64 sv = scan[i];
+            const int base = (int)(sv >> 32), lf = (int)(sv & 0xffffffffu);
+            for (int l = c + 1; l <= L; ++l) {
+                const int idx = base + (l - c - 1);
+                if (idx < node_cap) {
+                    pre_level[idx] = (unsigned char)l;
+                    pre_leaf[idx] = (unsigned char)(l == L);
+                    pre_start[idx] = i;
+                }
+                atomicAdd(&hist[l], 1);
+            }
+            leaf_start[lf] = i;
+            leaf_pre[lf] = base + (L - c - 1);
+        }
+    }
+    if (i == 0) {
+        ctl->n_nodes = n_nodes < node_cap ? n_nodes : node_cap;
+        ctl->n_leaves = n_leaves;
+        leaf_start[n_leaves] = n;
+        if (n_nodes > node_cap) set_err(ctl, ERR_NODE_CAP);
+    }
+    __syncthreads();
+    if (threadIdx.x < 24 && hist[threadIdx.x]) atomicAdd(&ctl->level_count[threadIdx.x], hist[threadIdx.x]);
+}
+
+__global__ void k_tree_reset(DevCtl* ctl) {
+    if (threadIdx.x < 24) ctl->level_count[threadIdx.x] = 0;
+}
+
+__global__ void k_level_offsets(DevCtl* ctl) {
+    if (threadIdx.x == 0) {
+        int acc = 0;
+        for (int l = 0; l < 24; ++l) {
+            ctl->level_off[l] = acc;
+            acc += ctl->level_count[l];
+        }
+    }
+}
+
+// Stable counting sort of pre-order nodes by level (2048-node tiles, 5-bit digit).
+constexpr int LS_THREADS = 256, LS_ITEMS = 8, LS_TILE = LS_THREADS * LS_ITEMS, LS_WAVES = LS_THREADS / 64;
+
+__global__ void __launch_bounds__(LS_THREADS) k_lsort_hist(const DevCtl* __restrict__ ctl,
+                                                          const unsigned char* __restrict__ pre_level, int* hist) {
+    __shared__ int h[24];
+    const int nn = ctl->n_nodes;
+    const int ntiles = (nn + LS_TILE - 1) / LS_TILE;
+    for (int tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+        if (threadIdx.x < 24) h[threadIdx.x] = 0;
+        __syncthreads();
+        for (int r = 0; r < LS_ITEMS; ++r) {
+            const int i = tile * LS_TILE + r * LS_THREADS + threadIdx.x;
+            if (i < nn) atomicAdd(&h[pre_level[i]], 1);
+        }
+        __syncthreads();
+        if (threadIdx.x < 24) hist[tile * 24 + threadIdx.x] = h[threadIdx.x];
+        __syncthreads();
+    }
+}
+
+// One wave per level: exclusive scan of that level's tile counts, offset by level_off.
+__global__ void __launch_bounds__(64) k_lsort_scan(const DevCtl* __restrict__ ctl, int* hist) {
+    const int l = blockIdx.x;
+    const int nn = ctl->n_nodes;
+    const int ntiles = (nn + LS_TILE - 1) / LS_TILE;
+    int carry = ctl->level_off[l];
+    for (int t0 = 0; t0 < ntiles; t0 += 64) {
+        const int t = t0 + lane_id();
+        const int v = t < ntiles ? hist[t * 24 + l] : 0;
+        const int inc = wave_incl_scan(v);
+        if (t < ntiles) hist[t * 24 + l] = carry + inc - v;
+        carry += __shfl(inc, 63, 64);
+    }
+}
+
+__global__ void __launch_bounds__(LS_THREADS) k_lsort_scatter(const DevCtl* __restrict__ ctl,
+                                                             const unsigned char* __restrict__ pre_level,
+                                                             const int* __restrict__ hist, int* pre_to_bfs,
+                                                             int* bfs_to_pre) {
+    __shared__ int wcnt[LS_WAVES][24];
+    __shared__ int woff[LS_WAVES][24];
+    const int nn = ctl->n_nodes;
+    const int ntiles = (nn + LS_TILE - 1) / LS_TILE;
+    const int w = threadIdx.x >> 6, lane = lane_id();
+    const u64 lt = lanemask_lt();
+    for (int tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+        for (int j = threadIdx.x; j < LS_WAVES * 24; j += LS_THREADS) (&wcnt[0][0])[j] = 0;
+        __syncthreads();
+        const int base = tile * LS_TILE + w * (64 * LS_ITEMS) + lane;
+        int rank[LS_ITEMS], lev[LS_ITEMS];
+        for (int r = 0; r < LS_ITEMS; ++r) {
+            const int i = base + r * 64;
+            const bool ok = i < nn;
+            const int dg = ok ? pre_level[i] : 0;
+            lev[r] = dg;
+            u64 peers = __ballot(ok);
+#pragma unroll
+            for (int b = 0; b < 5; ++b) {
+                const bool bit = (dg >> b) & 1;
+                const u64 bb = __ballot(bit);
+                peers &= bit ? bb : ~bb;
+            }
+            const int before = ok ? wcnt[w][dg] : 0;
+            rank[r] = before + __popcll(peers & lt);
+            if (ok && (peers & lt) == 0ull) wcnt[w][dg] = before + __popcll(peers);
+        }
+        __syncthreads();
+        if (threadIdx.x < 24) {
+            int acc = hist[tile * 24 + threadIdx.x];
+            for (int q = 0; q < LS_WAVES; ++q) {
+                woff[q][threadIdx.x] = acc;
+                acc += wcnt[q][threadIdx.x];
+            }
+        }
+        __syncthreads();
+        for (int r = 0; r < LS_ITEMS; ++r) {
+            const int i = base + r * 64;
+            if (i < nn) {
+                const int bfs = woff[w][lev[r]] + rank[r];
+                pre_to_bfs[i] = bfs;
+                bfs_to_pre[bfs] = i;
+            }
+        }
+        __syncthreads();
+    }
+}
+
+// Topology in breadth-first order: leaf -> particle range; internal -> children range.
+__global__ void __launch_bounds__(256) k_finalize(DevCtl* ctl, const unsigned char* __restrict__ pre_level,
+                                                   const unsigned char* __restrict__ pre_leaf,
+                                                   const int* __restrict__ pre_start, const int* __restrict__ pre_to_bfs,
+                                                   const int* __restrict__ bfs_to_pre, const signed char* __restrict__ lcp,
+                                                   const u64* __restrict__ scan, const int* __restrict__ leaf_start,
+                                                   int4* topo, int* parent, int* counter, int2* range) {
+    const int nn = ctl->n_nodes;
+    for (int b = blockIdx.x * blockDim.x + threadIdx.x; b < nn; b += gridDim.x * blockDim.x) {
+        const int pre = bfs_to_pre[b];
+        const int l = pre_level[pre], s = pre_start[pre];
+        counter[b] = 0;
+        if (b == 0) parent[0] = -1;
+        if (pre_leaf[pre]) {
+            const int lf = (int)(scan[s] & 0xffffffffu);
+            const int cnt = leaf_start[lf + 1] - s;
+            topo[b] = make_int4(s, cnt, l, 1);
+            range[b] = make_int2(s, cnt);
+        } else if (pre + 1 >= nn) {  // only with a truncated (over-capacity) tree
+            topo[b] = make_int4(s, 0, l, 1);
+            range[b] = make_int2(s, 0);
+        } else {
+            const int fc = pre_to_bfs[pre + 1];
+            const int end = ctl->level_off[l + 1] + ctl->level_count[l + 1];
+            int nc = 1;
+            while (nc < 8 && fc + nc < end && lcp[pre_start[bfs_to_pre[fc + nc]]] >= l) ++nc;
+            topo[b] = make_int4(fc, nc, l, 0);
+            for (int k = 0; k < nc; ++k) parent[fc + k] = b;
+        }
+    }
+}
+
+// Leaf geometry and moments, then the last-arriving child aggregates its parent.
+__device__ void aggregate_node(int p, const int4 tp, double4* nbox_lo, double4* nbox_hi, double4* mom0,
+                               double4* mom1, double4* mom2, int2* range, double side) {
+    double lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
+    double hmax = 0.0, M = 0.0, sx = 0.0, sy = 0.0, sz = 0.0;
+    int cnt = 0;
+    for (int k = 0; k < tp.y; ++k) {
+        const int c = tp.x + k;
+        const double4 a = nbox_lo[c], b = nbox_hi[c], m0 = mom0[c];
+        lo[0] = fmin(lo[0], a.x); lo[1] = fmin(lo[1], a.y); lo[2] = fmin(lo[2], a.z);
+        hi[0] = fmax(hi[0], b.x); hi[1] = fmax(hi[1], b.y); hi[2] = fmax(hi[2], b.z);
+        hmax = fmax(hmax, a.w);
+        M += m0.x;
+        sx += m0.x * m0.y; sy += m0.x * m0.z; sz += m0.x * m0.w;
+        cnt += range[c].y;
+    }
+    const double cx = sx / M, cy = sy / M, cz = sz / M;
+    double I[6] = {0, 0, 0, 0, 0, 0};
+    for (int k = 0; k < tp.y; ++k) {
+        const int c = tp.x + k;
+        const double4 m0 = mom0[c], m1 = mom1[c], m2 = mom2[c];
+        const double dx = m0.y - cx, dy = m0.z - cy, dz = m0.w - cz;
+        I[0] += m1.x + m0.x * dx * dx; I[1] += m1.y + m0.x * dy * dy; I[2] += m1.z + m0.x * dz * dz;
+        I[3] += m2.x + m0.x * dx * dy; I[4] += m2.y + m0.x * dx * dz; I[5] += m2.z + m0.x * dy * dz;
+    }
+    nbox_lo[p] = make_double4(lo[0], lo[1], lo[2], hmax);
+    nbox_hi[p] = make_double4(hi[0], hi[1], hi[2], side);
+    mom0[p] = make_double4(M, cx, cy, cz);
+    mom1[p] = make_double4(I[0], I[1], I[2], I[0] + I[1] + I[2]);
+    mom2[p] = make_double4(I[3], I[4], I[5], 0.0);
+    range[p] = make_int2(range[tp.x].x, cnt);
+}
+
+__global__ void __launch_bounds__(256) k_moments(DevCtl* ctl, int batched, const u64* __restrict__ key,
+                                                  const int* __restrict__ leaf_start, const int* __restrict__ leaf_pre,
+                                                  const int* __restrict__ pre_to_bfs, const int4* __restrict__ topo,
+                                                  const int* __restrict__ parent, int* counter,
+                                                  const double4* __restrict__ pos4, const double* __restrict__ m,
+                                                  double4* nbox_lo, double4* nbox_hi, double4* mom0, double4* mom1,
+                                                  double4* mom2, int2* range) {
+    const int nl = ctl->n_leaves;
+    const int nn = ctl->n_nodes;
+    for (int lf = blockIdx.x * blockDim.x + threadIdx.x; lf < nl; lf += gridDim.x * blockDim.x) {
+        if (leaf_pre[lf] >= nn) continue;  // truncated tree (capacity error already flagged)
+        const int b = pre_to_bfs[leaf_pre[lf]];
+        const int s = leaf_start[lf], e = leaf_start[lf + 1];
+        const int seg = batched ? (int)((key[s] >> 54) & 511ull) : 0;
+        const double L = ctl->side[seg];
+        double lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
+        double hmax = 0.0, M = 0.0, sx = 0.0, sy = 0.0, sz = 0.0;
+        for (int j = s; j < e; ++j) {
+            const double4 p = pos4[j];
+            const double mj = m[j];
+            lo[0] = fmin(lo[0], p.x); lo[1] = fmin(lo[1], p.y); lo[2] = fmin(lo[2], p.z);
+            hi[0] = fmax(hi[0], p.x); hi[1] = fmax(hi[1], p.y); hi[2] = fmax(hi[2], p.z);
+            hmax = fmax(hmax, p.w);
+            M += mj; sx += mj * p.x; sy += mj * p.y; sz += mj * p.z;
+        }
+        const double cx = sx / M, cy = sy / M, cz = sz / M;
+        double I[6] = {0, 0, 0, 0, 0, 0};
+        for (int j = s; j < e; ++j) {
+            const double4 p = pos4[j];
+            const double mj = m[j];
+            const double dx = p.x - cx, dy = p.y - cy, dz = p.z - cz;
+            I[0] += mj * dx * dx; I[1] += mj * dy * dy; I[2] += mj * dz * dz;
+            I[3] += mj * dx * dy; I[4] += mj * dx * dz; I[5] += mj * dy * dz;
+        }
+        const int lev = topo[b].z;
+        nbox_lo[b] = make_double4(lo[0], lo[1], lo[2], hmax);
+        nbox_hi[b] = make_double4(hi[0], hi[1], hi[2], ldexp(L, -lev));
+        mom0[b] = make_double4(M, cx, cy, cz);
+        mom1[b] = make_double4(I[0], I[1], I[2], I[0] + I[1] + I[2]);
+        mom2[b] = make_double4(I[3], I[4], I[5], 0.0);
+        range[b] = make_int2(s, e - s);
+        // climb
+        int node = b;
+        __threadfence();
+        int p = parent[node];
+        for (int depth = 0; p >= 0 && depth < 2 * MAX_LEVEL + 2; ++depth) {
+            const int4 tp = topo[p];
+            const int old = __hip_atomic_fetch_add(&counter[p], 1, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+            if (old != tp.y - 1) break;
+            __threadfence();
+            aggregate_node(p, tp, nbox_lo, nbox_hi, mom0, mom1, mom2, range, ldexp(L, -tp.z));
+            __threadfence();
+            node = p;
+            p = parent[node];
+        }
+    }
+}
+
+static int grid_cap(int n, int bs, int cap) {
+    int g = (n + bs - 1) / bs;
+    return g < 1 ? 1 : (g > cap ? cap : g);
+}
+
+void build_octree(hipStream_t s, const DevPtrs& d, const Dims& dm) {
+    const int n = dm.n;
+    if (n <= 0) return;
+    hipLaunchKernelGGL(k_tree_reset, dim3(1), dim3(64), 0, s, d.ctl);
+    hipLaunchKernelGGL(k_leaf_levels, dim3((n + TB - 1) / TB), dim3(TB), 0, s, d.key_a, n, dm.leaf_size, dm.min_level,
+                       d.lcp, d.lvl, d.scan_in);
+    scan_u64(s, d.scan_in, d.scan_out, n, d.scan_tmp);
+    hipLaunchKernelGGL(k_emit_nodes, dim3((n + 255) / 256), dim3(256), 0, s, n, d.lcp, d.lvl, d.scan_out,
+                       d.pre_level, d.pre_leaf, d.pre_start, d.leaf_start, d.leaf_pre, d.ctl, dm.node_cap);
+    hipLaunchKernelGGL(k_level_offsets, dim3(1), dim3(64), 0, s, d.ctl);
+    const int tiles_cap = grid_cap(dm.node_cap, LS_TILE, 1024);
+    hipLaunchKernelGGL(k_lsort_hist, dim3(tiles_cap), dim3(LS_THREADS), 0, s, d.ctl, d.pre_level, d.lsort_hist);
+    hipLaunchKernelGGL(k_lsort_scan, dim3(22), dim3(64), 0, s, d.ctl, d.lsort_hist);
+    hipLaunchKernelGGL(k_lsort_scatter, dim3(tiles_cap), dim3(LS_THREADS), 0, s, d.ctl, d.pre_level, d.lsort_hist,
+                       d.pre_to_bfs, d.bfs_to_pre);
+    const int g = grid_cap(dm.node_cap, 256, 2048);
+    hipLaunchKernelGGL(k_finalize, dim3(g), dim3(256), 0, s, d.ctl, d.pre_level, d.pre_leaf, d.pre_start,
+                       d.pre_to_bfs, d.bfs_to_pre, d.lcp, d.scan_out, d.leaf_start, d.topo, d.parent, d.counter,
+                       d.range);
+    hipLaunchKernelGGL(k_moments, dim3(grid_cap(n, 256, 2048)), dim3(256), 0, s, d.ctl, dm.batched, d.key_a,
+                       d.leaf_start, d.leaf_pre, d.pre_to_bfs, d.topo, d.parent, d.counter, d.pos4, d.m, d.nbox_lo,
+                       d.nbox_hi, d.mom0, d.mom1, d.mom2, d.range);
+}
+
+// Export (test path): node keys etc. in breadth-first order.
+__global__ void k_tree_export(const DevCtl* __restrict__ ctl, int n, const u64* __restrict__ key,
+                              const int4* __restrict__ topo,
+                              const int2* __restrict__ range, u64* okey, int32_t* olevel, int32_t* oleaf,
+                              int64_t* ostart, int64_t* ocount) {
+    const int nn = ctl->n_nodes;
+    for (int b = blockIdx.x * blockDim.x + threadIdx.x; b < nn; b += gridDim.x * blockDim.x) {
+        const int4 t = topo[b];
+        int2 r = range[b];
+        if (r.x < 0 || r.x >= n) r.x = 0;
+        const int l = t.z;
+        const u64 body = key[r.x] & 0x7fffffffffffffffull;
+        const u64 digits = l == 0 ? 0ull : (body >> (3 * (MAX_LEVEL - l)));
+        if (okey) okey[b] = (1ull << (3 * l)) | digits;
+        if (olevel) olevel[b] = l;
+        if (oleaf) oleaf[b] = t.w;
+        if (ostart) ostart[b] = r.x;
+        if (ocount) ocount[b] = r.y;
+    }
+}
+
+void launch_tree_export(hipStream_t s, const DevPtrs& d, const Dims& dm, u64* key, int32_t* level, int32_t* leaf,
+                        int64_t* start, int64_t* count) {
+    hipLaunchKernelGGL(k_tree_export, dim3(grid_cap(dm.node_cap, 256, 2048)), dim3(256), 0, s, d.ctl, dm.n, d.key_a,
+                       d.topo, d.range, key, level, leaf, start, count);
+}

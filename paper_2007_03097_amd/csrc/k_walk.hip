@@ -1,0 +1,217 @@
+// Neighbour search (Sec. 2.1 of arXiv:2007.03097, last paragraph: the traversal runs for
+// a group of particles, prunes with the node bounds, and builds one neighbour list per
+// particle).
+//
+// One wavefront per target group (group_size consecutive particles in key order).
+//  1. Group box and largest h by wave reductions.
+//  2. Wide tree walk: up to 64 nodes are tested at once, one per lane, against the group
+//     box.  A node survives when the squared gap between the boxes, summed in the same
+//     operation order as the pair test, is below (hmax_group + hmax_node)^2; rounding is
+//     monotone in every operation, so no true neighbour pair is ever pruned.  Surviving
+//     leaves go to a candidate list, surviving internal nodes push their children.
+//  3. Candidate particles are staged 64 at a time in LDS; lane (t, phi) tests source
+//     phi of every group_size-wide step for target t with the exact predicate
+//     fl(fl(fl(dx dx) + fl(dy dy)) + fl(dz dz)) < fl(t t), and a ballot compacts the hits
+//     into target t's list in source order.
+// List layout: group g, target t, slot k at nbr[(g * nbr_cap + k) * group_size + t], so
+// consumers reading slot k of consecutive targets read consecutive words.
+#include "common.h"
+
+constexpr int WALK_STACK = 512;
+constexpr int WALK_CAND = 512;
+
+__device__ __forceinline__ u64 target_pattern(int gsz) {
+    return gsz == 64 ? 1ull : gsz == 32 ? 0x0000000100000001ull : gsz == 16 ? 0x0001000100010001ull
+                                                                            : 0x0101010101010101ull;
+}
+
+__global__ void __launch_bounds__(64) k_nbr_lists(DevCtl* ctl, const int4* __restrict__ group, int gsz, int cap,
+                                                  const int4* __restrict__ topo, const double4* __restrict__ nbox_lo,
+                                                  const double4* __restrict__ nbox_hi, const double4* __restrict__ pos4,
+                                                  int* __restrict__ nbr, int* __restrict__ nbr_cnt,
+                                                  int* __restrict__ list_base) {
+    __shared__ int stack[WALK_STACK];
+    __shared__ int cstart[WALK_CAND];
+    __shared__ int coff[WALK_CAND + 1];
+    __shared__ double4 tile[64];
+    __shared__ int sidx[64];
+
+    const int4 g = group[blockIdx.x];
+    const int lane = lane_id();
+    const int t = lane & (gsz - 1), phi = lane / gsz, P = 64 / gsz;
+    const bool tv = t < g.y;
+    const double4 me = tv ? pos4[g.x + t] : make_double4(0, 0, 0, 0);
+    double lo[3], hi[3];
+    lo[0] = wave_min(tv ? me.x : INFINITY); hi[0] = wave_max(tv ? me.x : -INFINITY);
+    lo[1] = wave_min(tv ? me.y : INFINITY); hi[1] = wave_max(tv ? me.y : -INFINITY);
+    lo[2] = wave_min(tv ? me.z : INFINITY); hi[2] = wave_max(tv ? me.z : -INFINITY);
+    const double hg = wave_max(tv ? me.w : 0.0);
+    const u64 lt = lanemask_lt();
+
+    // ---- walk
+    const int root = g.z < 0 ? 0 : ctl->level_off[3] + g.z;
+    if (lane == 0) stack[0] = root;
+    int sp = 1, nc = 0, iters = 0;
+    bool overflow = false;
+    __syncthreads();
+    while (sp > 0) {
+        if (++iters > (1 << 16)) {  // a tree walk never needs this many rounds
+            overflow = true;
+            break;
+        }
+        const int k = sp < 64 ? sp : 64;
+        const int node = lane < k ? stack[sp - k + lane] : -1;
+        __syncthreads();
+        sp -= k;
+        bool hit = false;
+        int4 tp = make_int4(0, 0, 0, 0);
+        if (node >= 0) {
+            tp = topo[node];
+            const double4 a = nbox_lo[node], b = nbox_hi[node];
+            const double gx = fmax(0.0, fmax(a.x - hi[0], lo[0] - b.x));
+            const double gy = fmax(0.0, fmax(a.y - hi[1], lo[1] - b.y));
+            const double gz = fmax(0.0, fmax(a.z - hi[2], lo[2] - b.z));
+            double r2 = gx * gx + gy * gy;
+            r2 = r2 + gz * gz;
+            const double tt = hg + a.w;
+            hit = r2 < tt * tt;
+        }
+        const bool isleaf = hit && tp.w;
+        const u64 bl = __ballot(isleaf);
+        if (isleaf) {
+            const int slot = nc + __popcll(bl & lt);
+            if (slot < WALK_CAND) cstart[slot] = node;
+        }
+        nc += __popcll(bl);
+        const int nch = (hit && !tp.w) ? tp.y : 0;
+        const int incl = wave_incl_scan(nch);
+        const int tot = __shfl(incl, 63, 64);
+        if (nc > WALK_CAND || sp + tot > WALK_STACK) {
+            overflow = true;
+            break;
+        }
+        for (int j = 0; j < nch; ++j) stack[sp + incl - nch + j] = tp.x + j;
+        sp += tot;
+        __syncthreads();
+    }
+    if (overflow) {
+        if (lane == 0) set_err(ctl, ERR_WALK_STACK);
+        if (tv && phi == 0) {
+            nbr_cnt[g.x + t] = 0;
+            list_base[g.x + t] = -1;
+        }
+        return;
+    }
+    __syncthreads();
+    // ---- candidate prefix: cstart[j] = first particle, coff = exclusive count prefix
+    int carry = 0;
+    for (int j0 = 0; j0 < nc; j0 += 64) {
+        const int j = j0 + lane;
+        int cnt = 0, st = 0;
+        if (j < nc) {
+            const int4 tp = topo[cstart[j]];
+            st = tp.x;
+            cnt = tp.y;
+        }
+        const int incl = wave_incl_scan(cnt);
+        __syncthreads();
+        if (j < nc) {
+            cstart[j] = st;
+            coff[j] = carry + incl - cnt;
+        }
+        carry += __shfl(incl, 63, 64);
+    }
+    if (lane == 0) coff[nc] = carry;
+    __syncthreads();
+    const int total = carry;
+
+    // ---- exact predicate over staged candidates
+    const u64 mask_t = target_pattern(gsz) << t;
+    int* mylist = nbr + (size_t)blockIdx.x * (size_t)gsz * (size_t)cap;
+    int cnt = 0;
+    for (int p0 = 0; p0 < total; p0 += 64) {
+        const int p = p0 + lane;
+        if (p < total) {
+            int a = 0, b = nc - 1;
+            while (a < b) {  // largest j with coff[j] <= p
+                const int mid = (a + b + 1) >> 1;
+                if (coff[mid] <= p) a = mid;
+                else b = mid - 1;
+            }
+            const int src = cstart[a] + (p - coff[a]);
+            tile[lane] = pos4[src];
+            sidx[lane] = src;
+        }
+        __syncthreads();
+        const int tn = total - p0 < 64 ? total - p0 : 64;
+        for (int s = 0; s < tn; s += P) {
+            const int j = s + phi;
+            bool pred = false;
+            if (tv && j < tn) {
+                const double4 b = tile[j];
+                const double dx = me.x - b.x, dy = me.y - b.y, dz = me.z - b.z;
+                double r2 = dx * dx + dy * dy;
+                r2 = r2 + dz * dz;
+                const double tt = me.w + b.w;
+                pred = r2 < tt * tt;
+            }
+            const u64 B = __ballot(pred);
+            if (pred) {
+                const int slot = cnt + __popcll(B & mask_t & lt);
+                if (slot < cap) mylist[slot * gsz + t] = sidx[j];
+            }
+            cnt += __popcll(B & mask_t);
+        }
+        __syncthreads();
+    }
+    if (tv && phi == 0) {
+        nbr_cnt[g.x + t] = cnt < cap ? cnt : cap;
+        list_base[g.x + t] = blockIdx.x;
+        if (cnt > cap) {
+            set_err(ctl, ERR_NBR_CAP);
+            atomicMax(&ctl->nbr_max, cnt);
+        }
+    }
+}
+
+void launch_nbr_lists(hipStream_t s, const DevPtrs& d, const Dims& dm) {
+    if (dm.n_groups <= 0) return;
+    hipLaunchKernelGGL(k_nbr_lists, dim3(dm.n_groups), dim3(64), 0, s, d.ctl, d.group, dm.group_size, dm.nbr_cap,
+                       d.topo, d.nbox_lo, d.nbox_hi, d.pos4, d.nbr, d.nbr_cnt, d.nbr_base);
+}
+
+// ---- CSR export in caller order (test and inspection path)
+__global__ void k_csr_count(int n, const u32* __restrict__ id, const int* __restrict__ cnt, int64_t* counts) {
+    const int q = blockIdx.x * blockDim.x + threadIdx.x;
+    if (q < n) counts[id[q]] = cnt[q];
+}
+
+void launch_csr_count(hipStream_t s, const DevPtrs& d, const Dims& dm, int64_t* counts_caller) {
+    if (dm.n > 0) hipLaunchKernelGGL(k_csr_count, dim3((dm.n + 255) / 256), dim3(256), 0, s, dm.n, d.id, d.nbr_cnt,
+                                     counts_caller);
+}
+
+__global__ void k_csr_fill(int n, int gsz, int cap, const int4* __restrict__ group, const u32* __restrict__ id,
+                           const int* __restrict__ cnt, const int* __restrict__ gidx, const int* __restrict__ nbr,
+                           const int64_t* __restrict__ off, int32_t* idx) {
+    const int q = blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= n) return;
+    const int c = cnt[q], g = gidx[q];
+    if (g < 0) return;
+    const int* lst = nbr + (size_t)g * gsz * cap + (q - group[g].x);
+    int32_t* out = idx + off[id[q]];
+    for (int k = 0; k < c; ++k) {   // insertion sort by caller index while copying
+        const int32_t v = (int32_t)id[lst[k * gsz]];
+        int j = k;
+        while (j > 0 && out[j - 1] > v) {
+            out[j] = out[j - 1];
+            --j;
+        }
+        out[j] = v;
+    }
+}
+
+void launch_csr_fill(hipStream_t s, const DevPtrs& d, const Dims& dm, const int64_t* offsets, int32_t* idx) {
+    if (dm.n > 0) hipLaunchKernelGGL(k_csr_fill, dim3((dm.n + 255) / 256), dim3(256), 0, s, dm.n, dm.group_size,
+                                     dm.nbr_cap, d.group, d.id, d.nbr_cnt, d.nbr_base, d.nbr, offsets, idx);
+}

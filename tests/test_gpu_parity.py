@@ -1,0 +1,357 @@
+"""GPU parity: the HIP path (through the C ABI) against the CPU FP64 oracle.
+
+Bars: keys, sorted order, octree and neighbour sets bit-exact; FP64 rho, P, c, h_next,
+accelerations and du/dt within 1e-12 of the oracle relative to the oracle's absolute-sum
+scale of each particle (|delta_a| <= 1e-12 S_a); gravity with theta = 0 equal to the direct
+sum within 1e-12, with theta = 0.5 within 1e-3 RMS relative of the direct sum.
+"""
+import math
+
+import numpy as np
+import pytest
+
+from workloads import ensemble, fig1_points, lattice_box, polytrope_n1, sod_tube, uniform_random
+from workloads.generators import ParticleSet
+
+from gpu_helpers import (gpu_density, gpu_forces, gpu_gravity, gpu_keys_order, gpu_neighbors, gpu_tree, make_ctx,
+                         parts, rel_err, vec_rel_err)
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-12
+
+
+def _dup_set():
+    """Duplicates, coincident points and a collinear line."""
+    ps = uniform_random(700, seed=77, h=(0.05, 0.1))
+    ps.x[100:140] = ps.x[100]; ps.y[100:140] = ps.y[100]; ps.z[100:140] = ps.z[100]
+    ps.x[200:260] = np.linspace(0.1, 0.9, 60); ps.y[200:260] = 0.5; ps.z[200:260] = 0.5
+    ps.x[300] = ps.x[301]; ps.y[300] = ps.y[301]; ps.z[300] = ps.z[301]
+    return ps
+
+
+def _clustered(n=3000, seed=12):
+    rng = np.random.default_rng(seed)
+    c = rng.uniform(0, 1, size=(6, 3))
+    k = rng.integers(0, 6, size=n)
+    p = c[k] + rng.normal(0, 0.02, size=(n, 3))
+    ps = uniform_random(n, seed=seed + 1, h=(0.005, 0.03))
+    ps.x, ps.y, ps.z = [np.ascontiguousarray(p[:, i]) for i in range(3)]
+    return ps
+
+
+CASES = {
+    "lattice4096": lambda: lattice_box(16),
+    "random_varh": lambda: uniform_random(3333, seed=4, h=(0.02, 0.08)),
+    "duplicates": _dup_set,
+    "clustered": _clustered,
+    "sod_small": lambda: sod_tube(8),
+    "polytrope": lambda: polytrope_n1(5000, seed=21),
+    "n1": lambda: uniform_random(1, seed=1),
+    "n2": lambda: uniform_random(2, seed=2, h=0.5),
+}
+
+
+# ---------------------------------------------------------------------------- keys, order, tree
+@pytest.mark.parametrize("case", list(CASES))
+def test_keys_and_order_bitexact(orc, case):
+    ps = CASES[case]()
+    ctx = make_ctx(ps.n)
+    k, o = gpu_keys_order(ctx, parts(ps))
+    assert np.array_equal(k, orc.keys(ps.x, ps.y, ps.z))
+    assert np.array_equal(o, orc.order(k))
+
+
+def test_fig1_tree_on_gpu(orc):
+    """The paper's Fig. 1 worked example through the GPU octree (leaf capacity 1)."""
+    x, y, z, box = fig1_points()
+    ps = uniform_random(10, seed=3)
+    ps.x, ps.y, ps.z = x, y, z
+    ctx = make_ctx(10, leaf_size=1)
+    k, o = gpu_keys_order(ctx, parts(ps), box=box)
+    assert np.array_equal(k, orc.keys(x, y, z, box=box))
+    t = gpu_tree(ctx)
+    ref = orc.octree(k[o], 1)
+    got = sorted(zip(t["key"].tolist(), t["level"].tolist(), t["leaf"].tolist(), t["start"].tolist(), t["count"].tolist()))
+    exp = sorted(zip(ref["key"].tolist(), ref["level"].tolist(), ref["leaf"].tolist(), ref["start"].tolist(),
+                     ref["count"].tolist()))
+    assert got == exp
+    assert sum(t["leaf"]) == 10 and len(t["leaf"]) == 16
+
+
+@pytest.mark.parametrize("case", ["random_varh", "duplicates", "clustered", "polytrope", "n1", "n2"])
+@pytest.mark.parametrize("leaf", [1, 5, 16, 64])
+def test_octree_matches_oracle(orc, case, leaf):
+    ps = CASES[case]()
+    ctx = make_ctx(ps.n, leaf_size=leaf)
+    k, o = gpu_keys_order(ctx, parts(ps))
+    t = gpu_tree(ctx)
+    ref = orc.octree(k[o], leaf)
+    got = sorted(zip(t["key"].tolist(), t["level"].tolist(), t["leaf"].tolist(), t["start"].tolist(), t["count"].tolist()))
+    exp = sorted(zip(ref["key"].tolist(), ref["level"].tolist(), ref["leaf"].tolist(), ref["start"].tolist(),
+                     ref["count"].tolist()))
+    assert got == exp
+
+
+# ---------------------------------------------------------------------------- neighbours
+@pytest.mark.parametrize("case", list(CASES))
+@pytest.mark.parametrize("group", [8, 32, 64])
+def test_neighbors_bitexact(orc, case, group):
+    ps = CASES[case]()
+    ctx = make_ctx(ps.n, group_size=group, leaf_size=12, nbr_capacity=512)
+    gpu_keys_order(ctx, parts(ps))
+    off, idx = gpu_neighbors(ctx, ps.n)
+    roff, ridx = orc.neighbors(ps.x, ps.y, ps.z, ps.h)
+    assert np.array_equal(off, roff)
+    assert np.array_equal(idx, ridx)
+
+
+# ---------------------------------------------------------------------------- density, forces
+def _oracle_sph(orc, ps):
+    csr = orc.neighbors(ps.x, ps.y, ps.z, ps.h)
+    rho, P, c, hn = orc.density(ps.fields(), csr)
+    ax, ay, az, du, Sa, Su = orc.forces(ps.fields(), rho, P, c, csr)
+    return rho, P, c, hn, ax, ay, az, du, Sa, Su
+
+
+@pytest.mark.parametrize("case", ["lattice4096", "random_varh", "sod_small", "polytrope", "duplicates", "n2"])
+@pytest.mark.parametrize("group", [16, 64])
+def test_density_forces_fp64(orc, case, group):
+    ps = CASES[case]()
+    ctx = make_ctx(ps.n, group_size=group, nbr_capacity=512)
+    gpu_keys_order(ctx, parts(ps))
+    rho, P, c, hn = gpu_density(ctx, ps.n)
+    ax, ay, az, du = gpu_forces(ctx, ps.n)
+    r_rho, r_P, r_c, r_hn, r_ax, r_ay, r_az, r_du, Sa, Su = _oracle_sph(orc, ps)
+    assert rel_err(rho, r_rho, r_rho) <= TOL
+    assert rel_err(P, r_P, np.abs(r_P)) <= TOL
+    assert rel_err(c, r_c, r_c) <= TOL
+    assert rel_err(hn, r_hn, r_hn) <= TOL
+    assert vec_rel_err((ax, ay, az), (r_ax, r_ay, r_az), Sa) <= TOL
+    assert rel_err(du, r_du, Su) <= TOL
+
+
+def test_forces_with_caller_thermo(orc):
+    """sph_compute_forces with rho, P, c passed in (the layered check used at full size)."""
+    ps = uniform_random(2000, seed=9, h=(0.05, 0.09), v_sigma=0.3)
+    ctx = make_ctx(ps.n)
+    gpu_keys_order(ctx, parts(ps))
+    r_rho, r_P, r_c, _, r_ax, r_ay, r_az, r_du, Sa, Su = _oracle_sph(orc, ps)
+    ax, ay, az, du = gpu_forces(ctx, ps.n, thermo=(r_rho, r_P, r_c))
+    assert vec_rel_err((ax, ay, az), (r_ax, r_ay, r_az), Sa) <= TOL
+    assert rel_err(du, r_du, Su) <= TOL
+
+
+def test_fp32c_error_budget(orc, capsys):
+    """FP32-compensated pair arithmetic: per-field error against the FP64 oracle, relative
+    to the absolute-sum scale; stated bound 2e-6 (max) and 2e-7 (median)."""
+    ps = lattice_box(16)
+    ctx = make_ctx(ps.n, precision=1)
+    gpu_keys_order(ctx, parts(ps))
+    rho, P, c, hn = gpu_density(ctx, ps.n)
+    ax, ay, az, du = gpu_forces(ctx, ps.n)
+    r_rho, r_P, r_c, r_hn, r_ax, r_ay, r_az, r_du, Sa, Su = _oracle_sph(orc, ps)
+    e_rho = np.abs(rho - r_rho) / r_rho
+    e_a = np.sqrt((ax - r_ax) ** 2 + (ay - r_ay) ** 2 + (az - r_az) ** 2) / Sa
+    e_u = np.abs(du - r_du) / Su
+    with capsys.disabled():
+        for name, e in (("rho", e_rho), ("a", e_a), ("du", e_u)):
+            print(f"\nFP32C {name}: median {np.median(e):.2e} p99 {np.quantile(e, 0.99):.2e} max {e.max():.2e}")
+    for e in (e_rho, e_a, e_u):
+        assert e.max() <= 2e-6 and np.median(e) <= 2e-7
+
+
+def test_lattice_pins_on_gpu():
+    """Perfect lattice: interior density is the closed lattice sum; du/dt = 0 everywhere."""
+    ps = lattice_box(16, jitter=0.0, v_sigma=0.0)
+    ctx = make_ctx(ps.n)
+    gpu_keys_order(ctx, parts(ps))
+    rho, P, c, hn = gpu_density(ctx, ps.n)
+    ax, ay, az, du = gpu_forces(ctx, ps.n)
+    dx = 1 / 16
+    inner = ((ps.x > 2.4 * dx) & (ps.x < 1 - 2.4 * dx) & (ps.y > 2.4 * dx) & (ps.y < 1 - 2.4 * dx)
+             & (ps.z > 2.4 * dx) & (ps.z < 1 - 2.4 * dx))
+    s = 0.0
+    for i in range(-3, 4):
+        for j in range(-3, 4):
+            for k in range(-3, 4):
+                q = math.sqrt(i * i + j * j + k * k) / 1.2
+                if q < 2:
+                    s += (1 - 1.5 * q * q + 0.75 * q ** 3 if q < 1 else 0.25 * (2 - q) ** 3) / (math.pi * 1.2 ** 3)
+    assert np.allclose(rho[inner], s, rtol=1e-13, atol=0)
+    assert np.all(du == 0)
+
+
+# ---------------------------------------------------------------------------- gravity
+def test_gravity_theta0_equals_direct(orc):
+    ps = polytrope_n1(4000, seed=5)
+    ctx = make_ctx(ps.n, theta=0.0, G=1.0, soft_eps=0.01)
+    gpu_keys_order(ctx, parts(ps))
+    gx, gy, gz, phi = gpu_gravity(ctx, ps.n)
+    dx, dy, dz, dp = orc.gravity_direct(ps.x, ps.y, ps.z, ps.m, 1.0, 0.01)
+    gm = np.sqrt(dx ** 2 + dy ** 2 + dz ** 2)
+    scale = np.abs(dp) / 1.0
+    assert vec_rel_err((gx, gy, gz), (dx, dy, dz), np.full_like(gm, gm.max())) <= TOL
+    assert rel_err(phi, dp, np.abs(dp)) <= TOL
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+def test_gravity_theta_half(orc, prec, capsys):
+    """theta = 0.5 quadrupole tree gravity: RMS relative error <= 1e-3 against the direct sum;
+    FP64 also agrees with the oracle's own tree walk (same tree, same groups) for 99% of
+    particles to 1e-9 (the rest differ only where a borderline opening decision flips)."""
+    ps = polytrope_n1(16384, seed=6)
+    ctx = make_ctx(ps.n, theta=0.5, G=1.0, soft_eps=0.01, precision=prec, leaf_size=16, group_size=32)
+    k, o = gpu_keys_order(ctx, parts(ps))
+    gx, gy, gz, phi = gpu_gravity(ctx, ps.n)
+    dx, dy, dz, dp = orc.gravity_direct(ps.x, ps.y, ps.z, ps.m, 1.0, 0.01)
+    gd = np.sqrt(dx ** 2 + dy ** 2 + dz ** 2)
+    e = np.sqrt((gx - dx) ** 2 + (gy - dy) ** 2 + (gz - dz) ** 2) / gd
+    rms = math.sqrt((e ** 2).mean())
+    with capsys.disabled():
+        print(f"\ngravity theta=0.5 prec={prec}: RMS {rms:.3e} median {np.median(e):.2e} p99 {np.quantile(e, .99):.2e}")
+    assert rms <= 1e-3
+    if prec == 0:
+        t = orc.octree(k[o], 16)
+        L = max(np.ptp(ps.x), np.ptp(ps.y), np.ptp(ps.z))
+        gs = np.arange(0, ps.n, 32)
+        tx, ty, tz, tp = orc.tree_gravity(ps.x[o], ps.y[o], ps.z[o], ps.m[o], t, L, 0.5, 1.0, 0.01, gs,
+                                          np.minimum(32, ps.n - gs))
+        ref = np.empty((ps.n, 3))
+        ref[o] = np.stack([tx, ty, tz], axis=1)
+        d = np.linalg.norm(np.stack([gx, gy, gz], axis=1) - ref, axis=1) / gd
+        assert np.quantile(d, 0.99) <= 1e-9 and d.max() <= 1e-3
+
+
+# ---------------------------------------------------------------------------- leapfrog
+def _state_from(ps, pa):
+    from gpu_helpers import to_np
+    st = {k: to_np(pa[k]).copy() for k in ("x", "y", "z", "vx", "vy", "vz", "m", "h", "u")}
+    for k in ("ax", "ay", "az", "dudt"):
+        if pa[k] is not None:
+            st[k] = to_np(pa[k]).copy()
+    return st
+
+
+@pytest.mark.parametrize("case,adaptive,dt", [("lattice4096", 0, 0.0178), ("sod_small", 1, 4.0e-4)])
+def test_step_lockstep(orc, case, adaptive, dt):
+    """KDK steps in lockstep: each GPU step starts from the GPU state, and the oracle takes
+    one step from that same state; fields agree to 1e-12 of their scale."""
+    import paper_2007_03097_amd as sph
+    ps = CASES[case]()
+    ctx = make_ctx(ps.n, adaptive_h=adaptive)
+    pa = parts(ps, with_accel=True)
+    prm = orc.Params(adaptive_h=bool(adaptive))
+    st = orc.prime(ps.fields(), prm)
+    flags = 0
+    for step in range(3):
+        start = st if step == 0 else _state_from(ps, pa)
+        if step > 0:
+            start = dict(start)
+        sph.sph_step(ctx.h, pa, dt, 1, flags)
+        got = _state_from(ps, pa)
+        ref = orc.kdk_step(start if step > 0 else st, dt, prm)
+        for k in ("x", "y", "z", "vx", "vy", "vz", "u", "h", "ax", "ay", "az", "dudt"):
+            scale = max(np.abs(ref[k]).max(), 1e-300)
+            assert np.abs(got[k] - ref[k]).max() <= 1e-11 * scale, (step, k)
+        flags = sph.SPH_STEP_PRIMED
+
+
+def test_graph_replay_matches_eager(monkeypatch):
+    """Steps replayed from the captured HIP graphs equal eager launches bit for bit."""
+    import paper_2007_03097_amd as sph
+    ps = sod_tube(8)
+    out = []
+    for no_graph in ("0", "1"):
+        monkeypatch.setenv("SPH_NO_GRAPH", no_graph)
+        ctx = make_ctx(ps.n, adaptive_h=1)
+        pa = parts(ps, with_accel=True)
+        sph.sph_step(ctx.h, pa, 4e-4, 2, 0)
+        sph.sph_step(ctx.h, pa, 4e-4, 3, sph.SPH_STEP_RESUME)
+        out.append(_state_from(ps, pa))
+    for k in out[0]:
+        assert np.array_equal(out[0][k], out[1][k]), k
+
+
+def test_step_conserves_momentum():
+    import paper_2007_03097_amd as sph
+    ps = lattice_box(16)
+    ctx = make_ctx(ps.n)
+    pa = parts(ps)
+    d0 = sph.sph_step(ctx.h, pa, 0.0178, 0, 0)
+    d1 = sph.sph_step(ctx.h, pa, 0.0178, 5, sph.SPH_STEP_RESUME)
+    assert np.abs(d1[:3] - d0[:3]).max() < 1e-14
+    assert abs((d1[6] + d1[7]) - (d0[6] + d0[7])) < 1e-4 * (d0[6] + d0[7])
+
+
+# ---------------------------------------------------------------------------- batched ensembles
+def test_batched_segments(orc):
+    """Independent sets in one launch: keys carry the set number; neighbours never cross sets;
+    density and forces per set equal the oracle's."""
+    ps = ensemble(n_boxes=7, seed=33, n_min=150, n_max=1500, side_lo=5, side_hi=11)
+    so = ps.seg_offsets
+    ctx = make_ctx(ps.n, seg_cap=8, group_size=32)
+    k, o = gpu_keys_order(ctx, parts(ps))
+    assert np.array_equal(k, orc.keys(ps.x, ps.y, ps.z, seg_offsets=so))
+    assert np.array_equal(o, orc.order(k))
+    t = gpu_tree(ctx)
+    ref = orc.octree(k[o], 16, min_level=3)
+    assert sorted(zip(t["key"].tolist(), t["leaf"].tolist())) == sorted(zip(ref["key"].tolist(), ref["leaf"].tolist()))
+    off, idx = gpu_neighbors(ctx, ps.n)
+    seg = orc.seg_ids(ps.n, so)
+    roff, ridx = orc.neighbors(ps.x, ps.y, ps.z, ps.h, seg=seg)
+    assert np.array_equal(off, roff) and np.array_equal(idx, ridx)
+    rho, P, c, hn = gpu_density(ctx, ps.n)
+    r = orc.density(ps.fields(), (roff, ridx))
+    assert rel_err(rho, r[0], r[0]) <= TOL
+
+
+# ---------------------------------------------------------------------------- determinism, errors
+def test_determinism():
+    ps = uniform_random(5000, seed=8, h=(0.03, 0.06))
+    res = []
+    for _ in range(2):
+        ctx = make_ctx(ps.n)
+        gpu_keys_order(ctx, parts(ps))
+        res.append(gpu_density(ctx, ps.n) + gpu_forces(ctx, ps.n))
+    for a, b in zip(*res):
+        assert np.array_equal(a, b)
+
+
+def test_error_paths():
+    import paper_2007_03097_amd as sph
+    ps = uniform_random(500, seed=3, h=0.1)
+    ctx = make_ctx(ps.n, nbr_capacity=16)
+    gpu_keys_order(ctx, parts(ps))
+    with pytest.raises(sph.SPHError) as e:
+        gpu_neighbors(ctx, ps.n)
+    assert e.value.status == -4
+    ctx2 = make_ctx(ps.n)
+    with pytest.raises(sph.SPHError) as e:
+        gpu_forces(ctx2, ps.n)
+    assert e.value.status == -2
+    bad = ps.copy()
+    bad.x[7] = np.nan
+    gpu_keys_order(ctx2, parts(bad))
+    with pytest.raises(sph.SPHError) as e:
+        sph.sph_sync(ctx2.h)
+    assert e.value.status == -6
+    bad = ps.copy()
+    bad.h[3] = 0.0
+    gpu_keys_order(ctx2, parts(bad))
+    with pytest.raises(sph.SPHError) as e:
+        sph.sph_sync(ctx2.h)
+    assert e.value.status == -6
+    big = uniform_random(600, seed=1)
+    with pytest.raises(sph.SPHError) as e:
+        gpu_keys_order(ctx2, parts(big))
+    assert e.value.status == -1
+
+
+def test_empty_set():
+    ps = uniform_random(0, seed=1)
+    ctx = make_ctx(1)
+    k, o = gpu_keys_order(ctx, parts(ps))
+    assert k.size == 0
+    off, idx = gpu_neighbors(ctx, 0)
+    assert off.tolist() == [0] and idx.size == 0
