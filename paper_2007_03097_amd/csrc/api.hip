@@ -1,7 +1,7 @@
 // C ABI of the gfx950 SPH + octree library (declarations and contracts in include/sph.h).
 //
 // Host-side responsibilities: argument validation, carving the caller's workspace into the
-// device arrays, the host-built chunk and group tables, launch sequencing on the caller's
+// device arrays, the host-built chunk and segment tables, launch sequencing on the caller's
 // stream, capture of one leapfrog step per buffer parity into HIP graphs, the sticky device
 // error word, and the autotuner.  No device memory is allocated here.
 #include <algorithm>
@@ -100,7 +100,7 @@ static size_t layout(const sph_ctx* c, char* base, DevPtrs* out) {
     const size_t N = (size_t)std::max<int64_t>(c->n_cap, 1);
     const size_t S = (size_t)c->seg_cap;
     const size_t NC = (size_t)node_cap_for((int64_t)N, c->leaf_min);
-    const size_t GC = N / 8 + S + 1;                     // groups for the smallest group size
+    const size_t GC = N + 8;                             // a group holds at least one particle
     const size_t NBR = (N + (S + 1) * 64) * (size_t)c->nbr_cap;
     const size_t CH = N / CHUNK + S + 1;
     const size_t RSB = (N + 2047) / 2048;
@@ -150,6 +150,11 @@ static size_t layout(const sph_ctx* c, char* base, DevPtrs* out) {
     d.mom1 = cv.take<double4>(NC);
     d.mom2 = cv.take<double4>(NC);
     d.group = cv.take<int4>(GC);
+    d.gflag = cv.take<u32>(N + 1);
+    d.gscan = cv.take<u32>(N + 1);
+    d.gcell = cv.take<int>(N + 1);
+    d.gnch = cv.take<u32>(N + 1);
+    d.goff = cv.take<u32>(N + 1);
     d.nbr = cv.take<int>(NBR);
     d.nbr_cnt = cv.take<int>(N);
     d.nbr_base = cv.take<int>(N);
@@ -210,7 +215,8 @@ static sph_status check_particles(sph_ctx* c, const sph_particles* p) {
     return SPH_OK;
 }
 
-// Host tables for the current set: chunks (bounding box / keys) and walk groups.
+// Host tables for the current set: chunks (bounding box / keys) and segment ranks.  The
+// target groups are built on the device with the tree.
 static sph_status prepare(sph_ctx* c, const sph_particles* p) {
     const int n_seg = p->n_seg;
     std::vector<int64_t> seg(n_seg + 1);
@@ -225,8 +231,8 @@ static sph_status prepare(sph_ctx* c, const sph_particles* p) {
     dm.nbr_cap = c->nbr_cap;
     dm.node_cap = (int)node_cap_for(c->n_cap > 0 ? c->n_cap : 1, c->leaf_min);
     dm.min_level = dm.batched ? 3 : 0;
-    const bool same = c->tab.n == p->n && c->tab.n_seg == n_seg && c->tab.gsz == c->group_size && c->tab.seg == seg;
-    std::vector<int4> chunks, groups;
+    const bool same = c->tab.n == p->n && c->tab.n_seg == n_seg && c->tab.seg == seg;
+    std::vector<int4> chunks;
     std::vector<int> rank(n_seg, 0);
     int r = 0;
     for (int s = 0; s < n_seg; ++s) {
@@ -234,25 +240,21 @@ static sph_status prepare(sph_ctx* c, const sph_particles* p) {
         if (seg[s + 1] > seg[s]) ++r;
         for (int64_t b = seg[s]; b < seg[s + 1]; b += CHUNK)
             chunks.push_back(make_int4((int)b, (int)std::min<int64_t>(seg[s + 1], b + CHUNK), s, 0));
-        for (int64_t b = seg[s]; b < seg[s + 1]; b += c->group_size)
-            groups.push_back(make_int4((int)b, (int)std::min<int64_t>(c->group_size, seg[s + 1] - b),
-                                       dm.batched ? rank[s] : -1, s));
     }
     dm.n_chunks = (int)chunks.size();
-    dm.n_groups = (int)groups.size();
+    {   // persistent grid of the per-group kernels: a multiple of 8 (one share per XCD)
+        const int64_t est = p->n / std::max(1, c->group_size / 2) + 8;
+        dm.group_grid = (int)(8 * std::min<int64_t>(1024, (est + 7) / 8));
+    }
     if (!same) {
         if (!chunks.empty())
             HIPCHK(c, hipMemcpyAsync(c->d[0].chunk, chunks.data(), chunks.size() * sizeof(int4), hipMemcpyHostToDevice,
-                                     c->stream));
-        if (!groups.empty())
-            HIPCHK(c, hipMemcpyAsync(c->d[0].group, groups.data(), groups.size() * sizeof(int4), hipMemcpyHostToDevice,
                                      c->stream));
         HIPCHK(c, hipMemcpyAsync(c->d[0].seg_root_rank, rank.data(), rank.size() * sizeof(int), hipMemcpyHostToDevice,
                                  c->stream));
         HIPCHK(c, hipStreamSynchronize(c->stream));  // host vectors go out of scope
         c->tab.n = p->n;
         c->tab.n_seg = n_seg;
-        c->tab.gsz = c->group_size;
         c->tab.seg = seg;
         c->tab.version++;
     }
@@ -270,7 +272,7 @@ static sph_status read_err(sph_ctx* c) {
     HIPCHK(c, hipMemcpyAsync(&nmax, &c->d[0].ctl->nbr_max, sizeof nmax, hipMemcpyDeviceToHost, c->stream));
     HIPCHK(c, hipStreamSynchronize(c->stream));
     if (e & (ERR_NONFINITE | ERR_NONPOSITIVE))
-        return fail(c, SPH_E_NONFINITE, "device: %s%s", (e & ERR_NONFINITE) ? "non-finite x/v/u " : "",
+        return fail(c, SPH_E_NONFINITE, "device (error word 0x%x): %s%s", e, (e & ERR_NONFINITE) ? "non-finite x/v/u " : "",
                     (e & ERR_NONPOSITIVE) ? "h <= 0 or m <= 0" : "");
     if (e & ERR_NBR_CAP) return fail(c, SPH_E_CAPACITY, "device: neighbour list overflow (%d > nbr_capacity %d)", nmax, c->nbr_cap);
     if (e & ERR_WALK_STACK) return fail(c, SPH_E_CAPACITY, "device: tree-walk stack or candidate list overflow");

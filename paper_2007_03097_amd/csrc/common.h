@@ -28,6 +28,8 @@ struct DevCtl {
     int n_nodes;
     int n_leaves;
     int nbr_max;                  // largest neighbour count seen (for overflow reports)
+    int n_gcells;                 // group cells (octree cells of at most 4 * group_size)
+    int n_groups;                 // target groups
     int level_count[24];          // nodes per level
     int level_off[24];            // exclusive prefix of level_count
     u64 box_enc[512 * 6];         // per segment: ordered-integer min x,y,z then max x,y,z
@@ -84,7 +86,12 @@ struct DevPtrs {
     double4* mom1;                // node_cap: Ixx, Iyy, Izz, tr I
     double4* mom2;                // node_cap: Ixy, Ixz, Iyz, 0
     // groups and neighbour lists
-    int4* group;                  // group_cap: {start, count, root node (-1 = 0), seg}
+    int4* group;                  // group_cap: {start, count, segment root rank (-1 = root), 0}
+    u32* gflag;                   // n_cap + 1: 1 where a group cell starts
+    u32* gscan;                   // n_cap + 1
+    int* gcell;                   // n_cap + 1: first sorted position of each group cell, then n
+    u32* gnch;                    // n_cap + 1: groups per group cell
+    u32* goff;                    // n_cap + 1
     int* nbr;                     // group_cap * group_size * nbr_cap
     int* nbr_cnt;                 // n_cap
     int* nbr_base;                // n_cap: group whose lists hold the particle (-1 = none)
@@ -104,7 +111,7 @@ struct Dims {
     int leaf_size;
     int group_size;
     int nbr_cap;
-    int n_groups;
+    int group_grid;   // persistent grid (multiple of 8) of the per-group kernels
     int n_chunks;
     int node_cap;
     int min_level;    // 3 when batched, else 0
@@ -144,6 +151,18 @@ __device__ __forceinline__ double lanes_sum_d(double v, int gsz) {
     return v;
 }
 
+// Persistent, XCD-aware loop over groups.  Workgroups are dispatched round-robin over the
+// 8 XCDs (blockIdx % 8); the workgroups of one XCD take one contiguous eighth of the groups,
+// so neighbouring groups -- which read the same neighbour particles -- share an L2.
+__device__ __forceinline__ void group_range(int n_groups, int& g0, int& g1, int& step) {
+    const int nx = 8;
+    const int xcd = (int)(blockIdx.x % nx), j = (int)(blockIdx.x / nx);
+    step = (int)(gridDim.x / nx);
+    const int chunk = (n_groups + nx - 1) / nx;
+    g0 = xcd * chunk + j;
+    g1 = min(n_groups, (xcd + 1) * chunk);
+}
+
 // Ordered-integer encoding of doubles for exact atomic min/max.
 __device__ __forceinline__ u64 enc_double(double d) {
     u64 b = (u64)__double_as_longlong(d);
@@ -177,6 +196,7 @@ void launch_keys(hipStream_t s, const DevPtrs& d, const Dims& dm, const double* 
                  const double* h, const double* u, u64* keys_out_caller, int caller_order);
 void radix_sort(hipStream_t s, const DevPtrs& d, int n);
 void scan_u64(hipStream_t s, const u64* in, u64* out, int n, void* tmp);
+void scan_u32_total(hipStream_t s, const u32* in, u32* out, int n, void* tmp);
 void launch_gather_input(hipStream_t s, const DevPtrs& d, const Dims& dm, const double* x, const double* y,
                          const double* z, const double* vx, const double* vy, const double* vz, const double* m,
                          const double* h, const double* u, int64_t* order_out);

@@ -308,6 +308,7 @@ void scan_i64_inplace(hipStream_t s, int64_t* a, int n, void* tmp) {
     scan_impl<long long>(s, (const long long*)a, (long long*)a, n, tmp, 1);
 }
 static void scan_u32(hipStream_t s, u32* a, int n, void* tmp) { scan_impl<u32>(s, a, a, n, tmp, 0); }
+void scan_u32_total(hipStream_t s, const u32* in, u32* out, int n, void* tmp) { scan_impl<u32>(s, in, out, n, tmp, 1); }
 
 // ---------------------------------------------------------------------------------------
 // LSD radix sort of (u64 key, u32 value), 8-bit digits, 8 passes.  Each block owns a tile

@@ -152,9 +152,12 @@ __global__ void __launch_bounds__(64) k_gravity(DevCtl* ctl, const int4* __restr
     __shared__ int leaves[GW_LEAVES];
     __shared__ double4 tile[64];
     __shared__ int tidx[64];
-    const int4 g = group[blockIdx.x];
     const int lane = lane_id();
     const int t = lane & (gsz - 1), phi = lane / gsz, P_ = 64 / gsz;
+    int g0, g1, gstep;
+    group_range(ctl->n_groups, g0, g1, gstep);
+    for (int gi = g0; gi < g1; gi += gstep) {
+    const int4 g = group[gi];
     const bool tv = t < g.y;
     const int q = g.x + t;
     const double4 me = tv ? pos4[q] : make_double4(0, 0, 0, 0);
@@ -166,6 +169,7 @@ __global__ void __launch_bounds__(64) k_gravity(DevCtl* ctl, const int4* __restr
     const u64 lt = lanemask_lt();
     GravAcc acc;
     const int root = g.z < 0 ? 0 : ctl->level_off[3] + g.z;
+    __syncthreads();
     if (lane == 0) stack[0] = root;
     int sp = 1, nc = 0, nl = 0, iters = 0;
     __syncthreads();
@@ -236,20 +240,21 @@ __global__ void __launch_bounds__(64) k_gravity(DevCtl* ctl, const int4* __restr
         }
         if (pho) pho[q] = acc.ph;
     }
+    }
 }
 
 void launch_gravity(hipStream_t s, const DevPtrs& d, const Dims& dm, int fp32c, double G, double eps, double theta,
                     int accumulate) {
-    if (dm.n_groups <= 0) return;
+    if (dm.n <= 0) return;
     double* gx = accumulate ? d.ax : d.gx;
     double* gy = accumulate ? d.ay : d.gy;
     double* gz = accumulate ? d.az : d.gz;
     if (fp32c)
-        hipLaunchKernelGGL(k_gravity<true>, dim3(dm.n_groups), dim3(64), 0, s, d.ctl, d.group, dm.group_size, d.topo,
+        hipLaunchKernelGGL(k_gravity<true>, dim3(dm.group_grid), dim3(64), 0, s, d.ctl, d.group, dm.group_size, d.topo,
                            d.nbox_lo, d.nbox_hi, d.mom0, d.mom1, d.mom2, d.pos4, d.m, G, eps, theta, accumulate, gx, gy,
                            gz, d.phi);
     else
-        hipLaunchKernelGGL(k_gravity<false>, dim3(dm.n_groups), dim3(64), 0, s, d.ctl, d.group, dm.group_size, d.topo,
+        hipLaunchKernelGGL(k_gravity<false>, dim3(dm.group_grid), dim3(64), 0, s, d.ctl, d.group, dm.group_size, d.topo,
                            d.nbox_lo, d.nbox_hi, d.mom0, d.mom1, d.mom2, d.pos4, d.m, G, eps, theta, accumulate, gx, gy,
                            gz, d.phi);
 }

@@ -78,21 +78,25 @@ struct Neumaier {
 
 // ---------------------------------------------------------------------------------------
 template <bool FP32C>
-__global__ void __launch_bounds__(64) k_density(const int4* __restrict__ group, int gsz, int cap,
+__global__ void __launch_bounds__(64) k_density(const DevCtl* __restrict__ ctl, const int4* __restrict__ group,
+                                                int gsz, int cap,
                                                 const int* __restrict__ nbr, const int* __restrict__ nbr_cnt,
                                                 const double4* __restrict__ pos4, const double* __restrict__ m,
                                                 const double* __restrict__ u_eos, double gamma, double h_coeff,
                                                 double* __restrict__ rho, double* __restrict__ P,
                                                 double* __restrict__ cs, double* __restrict__ hnext,
                                                 double4* __restrict__ thr4, float4* __restrict__ thrf) {
-    const int4 g = group[blockIdx.x];
     const int lane = lane_id();
     const int t = lane & (gsz - 1), phi = lane / gsz, P_ = 64 / gsz;
+    int g0, g1, gstep;
+    group_range(ctl->n_groups, g0, g1, gstep);
+    for (int gi = g0; gi < g1; gi += gstep) {
+    const int4 g = group[gi];
     const bool tv = t < g.y;
     const int q = g.x + t;
     const double4 me = tv ? pos4[q] : make_double4(0, 0, 0, 1);
     const int cnt = tv ? nbr_cnt[q] : 0;
-    const int* lst = nbr + (size_t)blockIdx.x * gsz * cap + t;
+    const int* lst = nbr + (size_t)gi * gsz * cap + t;
     double acc;
     if (!FP32C) {
         double s = 0.0;
@@ -132,17 +136,18 @@ __global__ void __launch_bounds__(64) k_density(const int4* __restrict__ group, 
         thr4[q] = make_double4(r_, pr2, c_, ue);
         thrf[q] = make_float4((float)r_, (float)pr2, (float)c_, (float)me.w);
     }
+    }
 }
 
 void launch_density(hipStream_t s, const DevPtrs& d, const Dims& dm, int fp32c, double gamma, double h_coeff,
                     const double* u_eos) {
-    if (dm.n_groups <= 0) return;
+    if (dm.n <= 0) return;
     if (fp32c)
-        hipLaunchKernelGGL(k_density<true>, dim3(dm.n_groups), dim3(64), 0, s, d.group, dm.group_size, dm.nbr_cap,
+        hipLaunchKernelGGL(k_density<true>, dim3(dm.group_grid), dim3(64), 0, s, d.ctl, d.group, dm.group_size, dm.nbr_cap,
                            d.nbr, d.nbr_cnt, d.pos4, d.m, u_eos, gamma, h_coeff, d.rho, d.P, d.cs, d.hnext, d.thr4,
                            d.thrf);
     else
-        hipLaunchKernelGGL(k_density<false>, dim3(dm.n_groups), dim3(64), 0, s, d.group, dm.group_size, dm.nbr_cap,
+        hipLaunchKernelGGL(k_density<false>, dim3(dm.group_grid), dim3(64), 0, s, d.ctl, d.group, dm.group_size, dm.nbr_cap,
                            d.nbr, d.nbr_cnt, d.pos4, d.m, u_eos, gamma, h_coeff, d.rho, d.P, d.cs, d.hnext, d.thr4,
                            d.thrf);
 }
@@ -173,21 +178,25 @@ void launch_thermo_from_caller(hipStream_t s, const DevPtrs& d, const Dims& dm, 
 
 // ---------------------------------------------------------------------------------------
 template <bool FP32C>
-__global__ void __launch_bounds__(64) k_forces(const int4* __restrict__ group, int gsz, int cap,
+__global__ void __launch_bounds__(64) k_forces(const DevCtl* __restrict__ ctl, const int4* __restrict__ group,
+                                               int gsz, int cap,
                                                const int* __restrict__ nbr, const int* __restrict__ nbr_cnt,
                                                const double4* __restrict__ pos4, const double4* __restrict__ vel4,
                                                const double4* __restrict__ thr4, const float4* __restrict__ velf,
                                                const float4* __restrict__ thrf, double alpha, double beta,
                                                double eps_av, double* __restrict__ ax, double* __restrict__ ay,
                                                double* __restrict__ az, double* __restrict__ du) {
-    const int4 g = group[blockIdx.x];
     const int lane = lane_id();
     const int t = lane & (gsz - 1), phi = lane / gsz, P_ = 64 / gsz;
+    int g0, g1, gstep;
+    group_range(ctl->n_groups, g0, g1, gstep);
+    for (int gi = g0; gi < g1; gi += gstep) {
+    const int4 g = group[gi];
     const bool tv = t < g.y;
     const int q = g.x + t;
     const double4 me = tv ? pos4[q] : make_double4(0, 0, 0, 1);
     const int cnt = tv ? nbr_cnt[q] : 0;
-    const int* lst = nbr + (size_t)blockIdx.x * gsz * cap + t;
+    const int* lst = nbr + (size_t)gi * gsz * cap + t;
     double fx, fy, fz, fu;
     if (!FP32C) {
         const double4 mv = tv ? vel4[q] : make_double4(0, 0, 0, 0);
@@ -263,17 +272,18 @@ __global__ void __launch_bounds__(64) k_forces(const int4* __restrict__ group, i
         az[q] = fz;
         du[q] = fu;
     }
+    }
 }
 
 void launch_forces(hipStream_t s, const DevPtrs& d, const Dims& dm, int fp32c, double alpha, double beta,
                    double eps_av, const double*, const double*, const double*) {
-    if (dm.n_groups <= 0) return;
+    if (dm.n <= 0) return;
     if (fp32c)
-        hipLaunchKernelGGL(k_forces<true>, dim3(dm.n_groups), dim3(64), 0, s, d.group, dm.group_size, dm.nbr_cap,
+        hipLaunchKernelGGL(k_forces<true>, dim3(dm.group_grid), dim3(64), 0, s, d.ctl, d.group, dm.group_size, dm.nbr_cap,
                            d.nbr, d.nbr_cnt, d.pos4, d.vel4, d.thr4, d.velf, d.thrf, alpha, beta, eps_av, d.ax, d.ay,
                            d.az, d.du);
     else
-        hipLaunchKernelGGL(k_forces<false>, dim3(dm.n_groups), dim3(64), 0, s, d.group, dm.group_size, dm.nbr_cap,
+        hipLaunchKernelGGL(k_forces<false>, dim3(dm.group_grid), dim3(64), 0, s, d.ctl, d.group, dm.group_size, dm.nbr_cap,
                            d.nbr, d.nbr_cnt, d.pos4, d.vel4, d.thr4, d.velf, d.thrf, alpha, beta, eps_av, d.ax, d.ay,
                            d.az, d.du);
 }

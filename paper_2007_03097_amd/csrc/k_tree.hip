@@ -16,29 +16,17 @@
 //   counts numbers the nodes in pre-order.  A stable counting sort by level turns that
 //   into breadth-first order, where the children of a node are a contiguous run of the
 //   next level.  Moments are aggregated bottom-up by the last child to finish.
+//   The same windowed search with capacity 4 * group_size cuts the sorted order into compact
+//   "group cells"; each is split into target groups of at most group_size particles, so a
+//   group never spans two distant cells of the space-filling curve.
 #include "common.h"
 
 constexpr int TB = 256;          // positions per block in the leaf-level kernel
 constexpr int MAX_WIN = 256;     // largest supported leaf_size
 
-__global__ void __launch_bounds__(TB) k_leaf_levels(const u64* __restrict__ key, int n, int win, int min_level,
-                                                    signed char* lcp, unsigned char* lvl, u64* scan_in) {
-    __shared__ signed char c[TB + 2 * MAX_WIN + 2];
-    const int b0 = blockIdx.x * TB;
-    const int lo = b0 - win;                      // c[j] holds position lo + j
-    const int cnt = TB + 2 * win + 1;
-    for (int j = threadIdx.x; j < cnt; j += TB) {
-        const int p = lo + j;
-        int v = -1;
-        if (p > 0 && p < n) v = lcp_digits(key[p - 1], key[p]);
-        c[j] = (signed char)v;
-    }
-    __syncthreads();
-    const int i = b0 + threadIdx.x;
-    if (i >= n) return;
-    const int ci = i - lo;
-    // P(v): left boundary distance t (c(i-t) <= v, 0 <= t < win) plus right distance k
-    // (c(i+k) <= v, 1 <= k <= win) is at most win.
+// Level of the smallest cell around position ci that holds at most win particles:
+// 1 + min{v : the nearest boundaries with lcp <= v on both sides are at most win apart}.
+__device__ __forceinline__ int window_level(const signed char* c, int ci, int win) {
     int vlo = -1, vhi = MAX_LEVEL;
     while (vlo < vhi) {
         const int v = (vlo + vhi) >> 1;
@@ -49,15 +37,76 @@ __global__ void __launch_bounds__(TB) k_leaf_levels(const u64* __restrict__ key,
         if (t < win && k <= win && t + k <= win) vhi = v;
         else vlo = v + 1;
     }
-    int L = vlo + 1;
-    if (L > MAX_LEVEL) L = MAX_LEVEL;
+    const int L = vlo + 1;
+    return L > MAX_LEVEL ? MAX_LEVEL : L;
+}
+
+// Per sorted position: lcp, leaf level (leaf capacity win), node/leaf-start counts for the
+// pre-order scan, and the start flag of the group cells (cells of at most gwin particles).
+__global__ void __launch_bounds__(TB) k_leaf_levels(const u64* __restrict__ key, int n, int win, int gwin,
+                                                    int min_level, signed char* lcp, unsigned char* lvl,
+                                                    u64* scan_in, u32* gflag) {
+    __shared__ signed char c[TB + 2 * MAX_WIN + 2];
+    const int W = win > gwin ? win : gwin;
+    const int b0 = blockIdx.x * TB;
+    const int lo = b0 - W;                        // c[j] holds position lo + j
+    const int cnt = TB + 2 * W + 1;
+    for (int j = threadIdx.x; j < cnt; j += TB) {
+        const int p = lo + j;
+        int v = -1;
+        if (p > 0 && p < n) v = lcp_digits(key[p - 1], key[p]);
+        c[j] = (signed char)v;
+    }
+    __syncthreads();
+    const int i = b0 + threadIdx.x;
+    if (i >= n) return;
+    const int ci = i - lo;
+    int L = window_level(c, ci, win);
     if (L < min_level) L = min_level;
+    int Lg = window_level(c, ci, gwin);
+    if (Lg < min_level) Lg = min_level;
     const int cc = c[ci];
     const int nodes = L > cc ? L - cc : 0;
     lcp[i] = (signed char)cc;
     lvl[i] = (unsigned char)L;
     scan_in[i] = ((u64)nodes << 32) | (u64)(nodes > 0 ? 1u : 0u);
+    gflag[i] = Lg > cc ? 1u : 0u;
     if (i == n - 1) lcp[n] = -1;
+}
+
+// Group cells -> target groups of at most gsz consecutive particles inside one cell.
+__global__ void k_gcells(int n, const u32* __restrict__ gflag, const u32* __restrict__ gscan, int* gcell,
+                         DevCtl* ctl) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n && gflag[i]) gcell[gscan[i]] = i;
+    if (i == 0) {
+        const int nc = (int)gscan[n];
+        ctl->n_gcells = nc;
+        gcell[nc] = n;
+    }
+}
+
+__global__ void k_gcell_chunks(int n, int gsz, const DevCtl* __restrict__ ctl, const int* __restrict__ gcell,
+                               u32* gnch) {
+    const int j = blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= n) return;
+    const int nc = ctl->n_gcells;
+    gnch[j] = j < nc ? (u32)((gcell[j + 1] - gcell[j] + gsz - 1) / gsz) : 0u;
+}
+
+__global__ void k_emit_groups(int n, int gsz, int batched, DevCtl* ctl, const int* __restrict__ gcell,
+                              const u32* __restrict__ gnch, const u32* __restrict__ goff, const u64* __restrict__ key,
+                              const int* __restrict__ seg_root_rank, int4* group) {
+    const int j = blockIdx.x * blockDim.x + threadIdx.x;
+    if (j == 0) ctl->n_groups = (int)goff[n];
+    if (j >= ctl->n_gcells) return;
+    const int s = gcell[j], e = gcell[j + 1];
+    const int rank = batched ? seg_root_rank[(int)((key[s] >> 54) & 511ull)] : -1;
+    const u32 base = goff[j];
+    for (u32 k = 0; k < gnch[j]; ++k) {
+        const int b = s + (int)k * gsz;
+        group[base + k] = make_int4(b, min(gsz, e - b), rank, 0);
+    }
 }
 
 // Pre-order node records, leaf table and per-level node counts.
@@ -334,9 +383,18 @@ void build_octree(hipStream_t s, const DevPtrs& d, const Dims& dm) {
     const int n = dm.n;
     if (n <= 0) return;
     hipLaunchKernelGGL(k_tree_reset, dim3(1), dim3(64), 0, s, d.ctl);
-    hipLaunchKernelGGL(k_leaf_levels, dim3((n + TB - 1) / TB), dim3(TB), 0, s, d.key_a, n, dm.leaf_size, dm.min_level,
-                       d.lcp, d.lvl, d.scan_in);
+    const int gwin = 4 * dm.group_size < MAX_WIN ? 4 * dm.group_size : MAX_WIN;
+    hipLaunchKernelGGL(k_leaf_levels, dim3((n + TB - 1) / TB), dim3(TB), 0, s, d.key_a, n, dm.leaf_size, gwin,
+                       dm.min_level, d.lcp, d.lvl, d.scan_in, d.gflag);
     scan_u64(s, d.scan_in, d.scan_out, n, d.scan_tmp);
+    // target groups
+    scan_u32_total(s, d.gflag, d.gscan, n, d.scan_tmp);
+    hipLaunchKernelGGL(k_gcells, dim3((n + 255) / 256), dim3(256), 0, s, n, d.gflag, d.gscan, d.gcell, d.ctl);
+    hipLaunchKernelGGL(k_gcell_chunks, dim3((n + 255) / 256), dim3(256), 0, s, n, dm.group_size, d.ctl, d.gcell,
+                       d.gnch);
+    scan_u32_total(s, d.gnch, d.goff, n, d.scan_tmp);
+    hipLaunchKernelGGL(k_emit_groups, dim3((n + 255) / 256), dim3(256), 0, s, n, dm.group_size, dm.batched, d.ctl,
+                       d.gcell, d.gnch, d.goff, d.key_a, d.seg_root_rank, d.group);
     hipLaunchKernelGGL(k_emit_nodes, dim3((n + 255) / 256), dim3(256), 0, s, n, d.lcp, d.lvl, d.scan_out,
                        d.pre_level, d.pre_leaf, d.pre_start, d.leaf_start, d.leaf_pre, d.ctl, dm.node_cap);
     hipLaunchKernelGGL(k_level_offsets, dim3(1), dim3(64), 0, s, d.ctl);

@@ -2,13 +2,16 @@
 // a group of particles, prunes with the node bounds, and builds one neighbour list per
 // particle).
 //
-// One wavefront per target group (group_size consecutive particles in key order).
+// One wavefront per target group (at most group_size consecutive particles of one compact
+// octree cell), in a persistent, XCD-aware loop over the groups.
 //  1. Group box and largest h by wave reductions.
 //  2. Wide tree walk: up to 64 nodes are tested at once, one per lane, against the group
 //     box.  A node survives when the squared gap between the boxes, summed in the same
 //     operation order as the pair test, is below (hmax_group + hmax_node)^2; rounding is
 //     monotone in every operation, so no true neighbour pair is ever pruned.  Surviving
-//     leaves go to a candidate list, surviving internal nodes push their children.
+//     leaves go to a candidate list, surviving internal nodes push their children.  The
+//     candidate list is matched (step 3) whenever it fills, so any number of candidates
+//     is handled with fixed LDS.
 //  3. Candidate particles are staged 64 at a time in LDS; lane (t, phi) tests source
 //     phi of every group_size-wide step for target t with the exact predicate
 //     fl(fl(fl(dx dx) + fl(dy dy)) + fl(dz dz)) < fl(t t), and a ballot compacts the hits
@@ -17,118 +20,42 @@
 // consumers reading slot k of consecutive targets read consecutive words.
 #include "common.h"
 
-constexpr int WALK_STACK = 512;
-constexpr int WALK_CAND = 512;
+constexpr int WALK_STACK = 1024;
+constexpr int WALK_CAND = 256;
 
 __device__ __forceinline__ u64 target_pattern(int gsz) {
     return gsz == 64 ? 1ull : gsz == 32 ? 0x0000000100000001ull : gsz == 16 ? 0x0001000100010001ull
                                                                             : 0x0101010101010101ull;
 }
 
-__global__ void __launch_bounds__(64) k_nbr_lists(DevCtl* ctl, const int4* __restrict__ group, int gsz, int cap,
-                                                  const int4* __restrict__ topo, const double4* __restrict__ nbox_lo,
-                                                  const double4* __restrict__ nbox_hi, const double4* __restrict__ pos4,
-                                                  int* __restrict__ nbr, int* __restrict__ nbr_cnt,
-                                                  int* __restrict__ list_base) {
-    __shared__ int stack[WALK_STACK];
-    __shared__ int cstart[WALK_CAND];
-    __shared__ int coff[WALK_CAND + 1];
-    __shared__ double4 tile[64];
-    __shared__ int sidx[64];
-
-    const int4 g = group[blockIdx.x];
+// Exact predicate of every target of the group against the particles of the nc candidate
+// leaves in cand[] (node ids); hits are appended to the targets' lists.  cand[] is reused
+// as the leaves' first particles.
+__device__ void match_candidates(int nc, int* cand, int* coff, double4* tile, int* sidx,
+                                 const int4* __restrict__ topo, const double4* __restrict__ pos4, const double4 me,
+                                 bool tv, int t, int phi, int P, int gsz, int cap, u64 mask_t, u64 lt, int* mylist,
+                                 int& cnt) {
     const int lane = lane_id();
-    const int t = lane & (gsz - 1), phi = lane / gsz, P = 64 / gsz;
-    const bool tv = t < g.y;
-    const double4 me = tv ? pos4[g.x + t] : make_double4(0, 0, 0, 0);
-    double lo[3], hi[3];
-    lo[0] = wave_min(tv ? me.x : INFINITY); hi[0] = wave_max(tv ? me.x : -INFINITY);
-    lo[1] = wave_min(tv ? me.y : INFINITY); hi[1] = wave_max(tv ? me.y : -INFINITY);
-    lo[2] = wave_min(tv ? me.z : INFINITY); hi[2] = wave_max(tv ? me.z : -INFINITY);
-    const double hg = wave_max(tv ? me.w : 0.0);
-    const u64 lt = lanemask_lt();
-
-    // ---- walk
-    const int root = g.z < 0 ? 0 : ctl->level_off[3] + g.z;
-    if (lane == 0) stack[0] = root;
-    int sp = 1, nc = 0, iters = 0;
-    bool overflow = false;
-    __syncthreads();
-    while (sp > 0) {
-        if (++iters > (1 << 16)) {  // a tree walk never needs this many rounds
-            overflow = true;
-            break;
-        }
-        const int k = sp < 64 ? sp : 64;
-        const int node = lane < k ? stack[sp - k + lane] : -1;
-        __syncthreads();
-        sp -= k;
-        bool hit = false;
-        int4 tp = make_int4(0, 0, 0, 0);
-        if (node >= 0) {
-            tp = topo[node];
-            const double4 a = nbox_lo[node], b = nbox_hi[node];
-            const double gx = fmax(0.0, fmax(a.x - hi[0], lo[0] - b.x));
-            const double gy = fmax(0.0, fmax(a.y - hi[1], lo[1] - b.y));
-            const double gz = fmax(0.0, fmax(a.z - hi[2], lo[2] - b.z));
-            double r2 = gx * gx + gy * gy;
-            r2 = r2 + gz * gz;
-            const double tt = hg + a.w;
-            hit = r2 < tt * tt;
-        }
-        const bool isleaf = hit && tp.w;
-        const u64 bl = __ballot(isleaf);
-        if (isleaf) {
-            const int slot = nc + __popcll(bl & lt);
-            if (slot < WALK_CAND) cstart[slot] = node;
-        }
-        nc += __popcll(bl);
-        const int nch = (hit && !tp.w) ? tp.y : 0;
-        const int incl = wave_incl_scan(nch);
-        const int tot = __shfl(incl, 63, 64);
-        if (nc > WALK_CAND || sp + tot > WALK_STACK) {
-            overflow = true;
-            break;
-        }
-        for (int j = 0; j < nch; ++j) stack[sp + incl - nch + j] = tp.x + j;
-        sp += tot;
-        __syncthreads();
-    }
-    if (overflow) {
-        if (lane == 0) set_err(ctl, ERR_WALK_STACK);
-        if (tv && phi == 0) {
-            nbr_cnt[g.x + t] = 0;
-            list_base[g.x + t] = -1;
-        }
-        return;
-    }
-    __syncthreads();
-    // ---- candidate prefix: cstart[j] = first particle, coff = exclusive count prefix
     int carry = 0;
     for (int j0 = 0; j0 < nc; j0 += 64) {
         const int j = j0 + lane;
-        int cnt = 0, st = 0;
+        int c = 0, st = 0;
         if (j < nc) {
-            const int4 tp = topo[cstart[j]];
+            const int4 tp = topo[cand[j]];
             st = tp.x;
-            cnt = tp.y;
+            c = tp.y;
         }
-        const int incl = wave_incl_scan(cnt);
+        const int incl = wave_incl_scan(c);
         __syncthreads();
         if (j < nc) {
-            cstart[j] = st;
-            coff[j] = carry + incl - cnt;
+            cand[j] = st;
+            coff[j] = carry + incl - c;
         }
         carry += __shfl(incl, 63, 64);
     }
     if (lane == 0) coff[nc] = carry;
     __syncthreads();
     const int total = carry;
-
-    // ---- exact predicate over staged candidates
-    const u64 mask_t = target_pattern(gsz) << t;
-    int* mylist = nbr + (size_t)blockIdx.x * (size_t)gsz * (size_t)cap;
-    int cnt = 0;
     for (int p0 = 0; p0 < total; p0 += 64) {
         const int p = p0 + lane;
         if (p < total) {
@@ -138,7 +65,7 @@ __global__ void __launch_bounds__(64) k_nbr_lists(DevCtl* ctl, const int4* __res
                 if (coff[mid] <= p) a = mid;
                 else b = mid - 1;
             }
-            const int src = cstart[a] + (p - coff[a]);
+            const int src = cand[a] + (p - coff[a]);
             tile[lane] = pos4[src];
             sidx[lane] = src;
         }
@@ -164,19 +91,103 @@ __global__ void __launch_bounds__(64) k_nbr_lists(DevCtl* ctl, const int4* __res
         }
         __syncthreads();
     }
-    if (tv && phi == 0) {
-        nbr_cnt[g.x + t] = cnt < cap ? cnt : cap;
-        list_base[g.x + t] = blockIdx.x;
-        if (cnt > cap) {
-            set_err(ctl, ERR_NBR_CAP);
-            atomicMax(&ctl->nbr_max, cnt);
+}
+
+__global__ void __launch_bounds__(64) k_nbr_lists(DevCtl* ctl, const int4* __restrict__ group, int gsz, int cap,
+                                                  const int4* __restrict__ topo, const double4* __restrict__ nbox_lo,
+                                                  const double4* __restrict__ nbox_hi, const double4* __restrict__ pos4,
+                                                  int* __restrict__ nbr, int* __restrict__ nbr_cnt,
+                                                  int* __restrict__ list_base) {
+    __shared__ int stack[WALK_STACK];
+    __shared__ int cand[WALK_CAND];
+    __shared__ int coff[WALK_CAND + 1];
+    __shared__ double4 tile[64];
+    __shared__ int sidx[64];
+    const int lane = lane_id();
+    const int t = lane & (gsz - 1), phi = lane / gsz, P = 64 / gsz;
+    const u64 lt = lanemask_lt();
+    const u64 mask_t = target_pattern(gsz) << t;
+    int g0, g1, gstep;
+    group_range(ctl->n_groups, g0, g1, gstep);
+    for (int gi = g0; gi < g1; gi += gstep) {
+        const int4 g = group[gi];
+        const bool tv = t < g.y;
+        const double4 me = tv ? pos4[g.x + t] : make_double4(0, 0, 0, 0);
+        double lo[3], hi[3];
+        lo[0] = wave_min(tv ? me.x : INFINITY); hi[0] = wave_max(tv ? me.x : -INFINITY);
+        lo[1] = wave_min(tv ? me.y : INFINITY); hi[1] = wave_max(tv ? me.y : -INFINITY);
+        lo[2] = wave_min(tv ? me.z : INFINITY); hi[2] = wave_max(tv ? me.z : -INFINITY);
+        const double hg = wave_max(tv ? me.w : 0.0);
+        int* mylist = nbr + (size_t)gi * (size_t)gsz * (size_t)cap;
+        int cnt = 0;
+        const int root = g.z < 0 ? 0 : ctl->level_off[3] + g.z;
+        __syncthreads();
+        if (lane == 0) stack[0] = root;
+        int sp = 1, nc = 0, iters = 0;
+        bool overflow = false;
+        __syncthreads();
+        while (sp > 0) {
+            if (++iters > (1 << 20)) {  // bounded: every wave leaves the loop
+                overflow = true;
+                break;
+            }
+            if (nc + 64 > WALK_CAND) {
+                match_candidates(nc, cand, coff, tile, sidx, topo, pos4, me, tv, t, phi, P, gsz, cap, mask_t, lt,
+                                 mylist, cnt);
+                nc = 0;
+            }
+            const int k = sp < 64 ? sp : 64;
+            const int node = lane < k ? stack[sp - k + lane] : -1;
+            __syncthreads();
+            sp -= k;
+            bool hit = false;
+            int4 tp = make_int4(0, 0, 0, 0);
+            if (node >= 0) {
+                tp = topo[node];
+                const double4 a = nbox_lo[node], b = nbox_hi[node];
+                const double gx = fmax(0.0, fmax(a.x - hi[0], lo[0] - b.x));
+                const double gy = fmax(0.0, fmax(a.y - hi[1], lo[1] - b.y));
+                const double gz = fmax(0.0, fmax(a.z - hi[2], lo[2] - b.z));
+                double r2 = gx * gx + gy * gy;
+                r2 = r2 + gz * gz;
+                const double tt = hg + a.w;
+                hit = r2 < tt * tt;
+            }
+            const bool isleaf = hit && tp.w;
+            const u64 bl = __ballot(isleaf);
+            if (isleaf) cand[nc + __popcll(bl & lt)] = node;
+            nc += __popcll(bl);
+            const int nch = (hit && !tp.w) ? tp.y : 0;
+            const int incl = wave_incl_scan(nch);
+            const int tot = __shfl(incl, 63, 64);
+            if (sp + tot > WALK_STACK) {
+                overflow = true;
+                break;
+            }
+            for (int j = 0; j < nch; ++j) stack[sp + incl - nch + j] = tp.x + j;
+            sp += tot;
+            __syncthreads();
+        }
+        __syncthreads();
+        if (!overflow)
+            match_candidates(nc, cand, coff, tile, sidx, topo, pos4, me, tv, t, phi, P, gsz, cap, mask_t, lt, mylist,
+                             cnt);
+        else if (lane == 0)
+            set_err(ctl, ERR_WALK_STACK);
+        if (tv && phi == 0) {
+            nbr_cnt[g.x + t] = overflow ? 0 : (cnt < cap ? cnt : cap);
+            list_base[g.x + t] = overflow ? -1 : gi;
+            if (cnt > cap) {
+                set_err(ctl, ERR_NBR_CAP);
+                atomicMax(&ctl->nbr_max, cnt);
+            }
         }
     }
 }
 
 void launch_nbr_lists(hipStream_t s, const DevPtrs& d, const Dims& dm) {
-    if (dm.n_groups <= 0) return;
-    hipLaunchKernelGGL(k_nbr_lists, dim3(dm.n_groups), dim3(64), 0, s, d.ctl, d.group, dm.group_size, dm.nbr_cap,
+    if (dm.n <= 0) return;
+    hipLaunchKernelGGL(k_nbr_lists, dim3(dm.group_grid), dim3(64), 0, s, d.ctl, d.group, dm.group_size, dm.nbr_cap,
                        d.topo, d.nbox_lo, d.nbox_hi, d.pos4, d.nbr, d.nbr_cnt, d.nbr_base);
 }
 

@@ -98,7 +98,7 @@ def test_octree_matches_oracle(orc, case, leaf):
 @pytest.mark.parametrize("group", [8, 32, 64])
 def test_neighbors_bitexact(orc, case, group):
     ps = CASES[case]()
-    ctx = make_ctx(ps.n, group_size=group, leaf_size=12, nbr_capacity=512)
+    ctx = make_ctx(ps.n, group_size=group, leaf_size=12, nbr_capacity=4096)
     gpu_keys_order(ctx, parts(ps))
     off, idx = gpu_neighbors(ctx, ps.n)
     roff, ridx = orc.neighbors(ps.x, ps.y, ps.z, ps.h)
@@ -118,7 +118,7 @@ def _oracle_sph(orc, ps):
 @pytest.mark.parametrize("group", [16, 64])
 def test_density_forces_fp64(orc, case, group):
     ps = CASES[case]()
-    ctx = make_ctx(ps.n, group_size=group, nbr_capacity=512)
+    ctx = make_ctx(ps.n, group_size=group, nbr_capacity=4096)
     gpu_keys_order(ctx, parts(ps))
     rho, P, c, hn = gpu_density(ctx, ps.n)
     ax, ay, az, du = gpu_forces(ctx, ps.n)
@@ -273,15 +273,25 @@ def test_graph_replay_matches_eager(monkeypatch):
         assert np.array_equal(out[0][k], out[1][k]), k
 
 
-def test_step_conserves_momentum():
+def test_step_diagnostics_vs_oracle(orc):
+    """Five free-running steps (graph replays): momentum is conserved to rounding and the
+    diagnostics (momenta, kinetic and thermal energy) follow the oracle's own run."""
     import paper_2007_03097_amd as sph
     ps = lattice_box(16)
     ctx = make_ctx(ps.n)
     pa = parts(ps)
     d0 = sph.sph_step(ctx.h, pa, 0.0178, 0, 0)
     d1 = sph.sph_step(ctx.h, pa, 0.0178, 5, sph.SPH_STEP_RESUME)
+    prm = orc.Params()
+    st = orc.prime(ps.fields(), prm)
+    r0 = orc.diagnostics(st)
+    for _ in range(5):
+        st = orc.kdk_step(st, 0.0178, prm)
+    r1 = orc.diagnostics(st)
     assert np.abs(d1[:3] - d0[:3]).max() < 1e-14
-    assert abs((d1[6] + d1[7]) - (d0[6] + d0[7])) < 1e-4 * (d0[6] + d0[7])
+    assert np.abs(d0 - r0).max() < 1e-13
+    assert np.abs(d1[:6] - r1[:6]).max() < 1e-12
+    assert abs(d1[6] - r1[6]) < 1e-10 * r1[6] and abs(d1[7] - r1[7]) < 1e-12 * r1[7]
 
 
 # ---------------------------------------------------------------------------- batched ensembles
