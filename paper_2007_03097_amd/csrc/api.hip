@@ -101,7 +101,7 @@ static size_t layout(const sph_ctx* c, char* base, DevPtrs* out) {
     const size_t S = (size_t)c->seg_cap;
     const size_t NC = (size_t)node_cap_for((int64_t)N, c->leaf_min);
     const size_t GC = N + 8;                             // a group holds at least one particle
-    const size_t NBR = (N + (S + 1) * 64) * (size_t)c->nbr_cap;
+    const size_t NBR = N * (size_t)c->nbr_cap + 64;      // group blocks tile n * nbr_cap words
     const size_t CH = N / CHUNK + S + 1;
     const size_t RSB = (N + 2047) / 2048;
     const size_t SCB = (std::max(N + 1, 256 * RSB) + 2047) / 2048 + 16;

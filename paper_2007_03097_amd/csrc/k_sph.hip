@@ -96,12 +96,12 @@ __global__ void __launch_bounds__(64) k_density(const DevCtl* __restrict__ ctl, 
     const int q = g.x + t;
     const double4 me = tv ? pos4[q] : make_double4(0, 0, 0, 1);
     const int cnt = tv ? nbr_cnt[q] : 0;
-    const int* lst = nbr + (size_t)gi * gsz * cap + t;
+    const int* lst = nbr + (size_t)g.x * cap + t;
     double acc;
     if (!FP32C) {
         double s = 0.0;
         for (int k = phi; k < cnt; k += P_) {
-            const int b = lst[k * gsz];
+            const int b = lst[k * g.y];
             const double4 sb = pos4[b];
             const double dx = me.x - sb.x, dy = me.y - sb.y, dz = me.z - sb.z;
             const double r = sqrt(fma(dx, dx, fma(dy, dy, dz * dz)));
@@ -113,7 +113,7 @@ __global__ void __launch_bounds__(64) k_density(const DevCtl* __restrict__ ctl, 
         Kahan s;
         const float hf = (float)me.w;
         for (int k = phi; k < cnt; k += P_) {
-            const int b = lst[k * gsz];
+            const int b = lst[k * g.y];
             const double4 sb = pos4[b];
             const float dx = (float)(me.x - sb.x), dy = (float)(me.y - sb.y), dz = (float)(me.z - sb.z);
             const float r = __builtin_amdgcn_sqrtf(fmaf(dx, dx, fmaf(dy, dy, dz * dz)));
@@ -196,14 +196,14 @@ __global__ void __launch_bounds__(64) k_forces(const DevCtl* __restrict__ ctl, c
     const int q = g.x + t;
     const double4 me = tv ? pos4[q] : make_double4(0, 0, 0, 1);
     const int cnt = tv ? nbr_cnt[q] : 0;
-    const int* lst = nbr + (size_t)gi * gsz * cap + t;
+    const int* lst = nbr + (size_t)g.x * cap + t;
     double fx, fy, fz, fu;
     if (!FP32C) {
         const double4 mv = tv ? vel4[q] : make_double4(0, 0, 0, 0);
         const double4 mt = tv ? thr4[q] : make_double4(1, 0, 0, 0);
         double sx = 0, sy = 0, sz = 0, su = 0;
         for (int k = phi; k < cnt; k += P_) {
-            const int b = lst[k * gsz];
+            const int b = lst[k * g.y];
             const double4 sb = pos4[b];
             const double4 vb = vel4[b];
             const double4 tb = thr4[b];
@@ -235,7 +235,7 @@ __global__ void __launch_bounds__(64) k_forces(const DevCtl* __restrict__ ctl, c
         const float ipi = (float)M_1_PI_D;
         Neumaier sx, sy, sz, su;
         for (int k = phi; k < cnt; k += P_) {
-            const int b = lst[k * gsz];
+            const int b = lst[k * g.y];
             const double4 sb = pos4[b];
             const float4 vb = velf[b];
             const float4 tb = thrf[b];

@@ -16,8 +16,10 @@
 //     phi of every group_size-wide step for target t with the exact predicate
 //     fl(fl(fl(dx dx) + fl(dy dy)) + fl(dz dz)) < fl(t t), and a ballot compacts the hits
 //     into target t's list in source order.
-// List layout: group g, target t, slot k at nbr[(g * nbr_cap + k) * group_size + t], so
-// consumers reading slot k of consecutive targets read consecutive words.
+// List layout: a group of n_g targets starting at sorted position s owns the block
+// nbr[s * nbr_cap, (s + n_g) * nbr_cap); slot k of target t is at s * nbr_cap + k * n_g + t,
+// so consumers reading slot k of consecutive targets read consecutive words, and the
+// blocks of all groups tile exactly n * nbr_cap words.
 #include "common.h"
 
 constexpr int WALK_STACK = 1024;
@@ -33,7 +35,7 @@ __device__ __forceinline__ u64 target_pattern(int gsz) {
 // as the leaves' first particles.
 __device__ void match_candidates(int nc, int* cand, int* coff, double4* tile, int* sidx,
                                  const int4* __restrict__ topo, const double4* __restrict__ pos4, const double4 me,
-                                 bool tv, int t, int phi, int P, int gsz, int cap, u64 mask_t, u64 lt, int* mylist,
+                                 bool tv, int t, int phi, int P, int gy, int cap, u64 mask_t, u64 lt, int* mylist,
                                  int& cnt) {
     const int lane = lane_id();
     int carry = 0;
@@ -85,7 +87,7 @@ __device__ void match_candidates(int nc, int* cand, int* coff, double4* tile, in
             const u64 B = __ballot(pred);
             if (pred) {
                 const int slot = cnt + __popcll(B & mask_t & lt);
-                if (slot < cap) mylist[slot * gsz + t] = sidx[j];
+                if (slot < cap) mylist[slot * gy + t] = sidx[j];
             }
             cnt += __popcll(B & mask_t);
         }
@@ -118,7 +120,7 @@ __global__ void __launch_bounds__(64) k_nbr_lists(DevCtl* ctl, const int4* __res
         lo[1] = wave_min(tv ? me.y : INFINITY); hi[1] = wave_max(tv ? me.y : -INFINITY);
         lo[2] = wave_min(tv ? me.z : INFINITY); hi[2] = wave_max(tv ? me.z : -INFINITY);
         const double hg = wave_max(tv ? me.w : 0.0);
-        int* mylist = nbr + (size_t)gi * (size_t)gsz * (size_t)cap;
+        int* mylist = nbr + (size_t)g.x * (size_t)cap;
         int cnt = 0;
         const int root = g.z < 0 ? 0 : ctl->level_off[3] + g.z;
         __syncthreads();
@@ -132,7 +134,7 @@ __global__ void __launch_bounds__(64) k_nbr_lists(DevCtl* ctl, const int4* __res
                 break;
             }
             if (nc + 64 > WALK_CAND) {
-                match_candidates(nc, cand, coff, tile, sidx, topo, pos4, me, tv, t, phi, P, gsz, cap, mask_t, lt,
+                match_candidates(nc, cand, coff, tile, sidx, topo, pos4, me, tv, t, phi, P, g.y, cap, mask_t, lt,
                                  mylist, cnt);
                 nc = 0;
             }
@@ -170,7 +172,7 @@ __global__ void __launch_bounds__(64) k_nbr_lists(DevCtl* ctl, const int4* __res
         }
         __syncthreads();
         if (!overflow)
-            match_candidates(nc, cand, coff, tile, sidx, topo, pos4, me, tv, t, phi, P, gsz, cap, mask_t, lt, mylist,
+            match_candidates(nc, cand, coff, tile, sidx, topo, pos4, me, tv, t, phi, P, g.y, cap, mask_t, lt, mylist,
                              cnt);
         else if (lane == 0)
             set_err(ctl, ERR_WALK_STACK);
@@ -209,10 +211,11 @@ __global__ void k_csr_fill(int n, int gsz, int cap, const int4* __restrict__ gro
     if (q >= n) return;
     const int c = cnt[q], g = gidx[q];
     if (g < 0) return;
-    const int* lst = nbr + (size_t)g * gsz * cap + (q - group[g].x);
+    const int4 gr = group[g];
+    const int* lst = nbr + (size_t)gr.x * cap + (q - gr.x);
     int32_t* out = idx + off[id[q]];
     for (int k = 0; k < c; ++k) {   // insertion sort by caller index while copying
-        const int32_t v = (int32_t)id[lst[k * gsz]];
+        const int32_t v = (int32_t)id[lst[k * gr.y]];
         int j = k;
         while (j > 0 && out[j - 1] > v) {
             out[j] = out[j - 1];
