@@ -214,9 +214,15 @@ def test_gravity_theta_half(orc, prec, capsys):
     if prec == 0:
         t = orc.octree(k[o], 16)
         L = max(np.ptp(ps.x), np.ptp(ps.y), np.ptp(ps.z))
-        gs = np.arange(0, ps.n, 32)
-        tx, ty, tz, tp = orc.tree_gravity(ps.x[o], ps.y[o], ps.z[o], ps.m[o], t, L, 0.5, 1.0, 0.01, gs,
-                                          np.minimum(32, ps.n - gs))
+        # target groups: cells of at most 4 * 32 particles, cut into runs of at most 32
+        cells = orc.octree(k[o], 128)
+        gs, gc = [], []
+        for s0, c0 in zip(cells["start"][cells["leaf"]], cells["count"][cells["leaf"]]):
+            for j in range(0, int(c0), 32):
+                gs.append(s0 + j)
+                gc.append(min(32, int(c0) - j))
+        tx, ty, tz, tp = orc.tree_gravity(ps.x[o], ps.y[o], ps.z[o], ps.m[o], t, L, 0.5, 1.0, 0.01, np.array(gs),
+                                          np.array(gc))
         ref = np.empty((ps.n, 3))
         ref[o] = np.stack([tx, ty, tz], axis=1)
         d = np.linalg.norm(np.stack([gx, gy, gz], axis=1) - ref, axis=1) / gd
