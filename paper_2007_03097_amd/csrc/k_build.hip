@@ -387,6 +387,33 @@ __global__ void __launch_bounds__(RS_THREADS) k_rs_scatter(const u64* __restrict
     }
 }
 
+// Digit offsets for one pass in a single launch: thread d scans digit d's per-block counts
+// (contiguous, digit-major), then the 256 digit totals are scanned in LDS and added.
+__global__ void __launch_bounds__(256) k_rs_offsets(u32* hist, int nb) {
+    __shared__ u32 tot[256];
+    const int d = threadIdx.x;
+    u32* h = hist + (size_t)d * nb;
+    u32 acc = 0;
+    for (int b = 0; b < nb; ++b) {
+        const u32 v = h[b];
+        h[b] = acc;
+        acc += v;
+    }
+    tot[d] = acc;
+    __syncthreads();
+    if (d == 0) {
+        u32 run = 0;
+        for (int k = 0; k < 256; ++k) {
+            const u32 v = tot[k];
+            tot[k] = run;
+            run += v;
+        }
+    }
+    __syncthreads();
+    const u32 base = tot[d];
+    for (int b = 0; b < nb; ++b) h[b] += base;
+}
+
 // Sorts (key_a, val_a) in place (ping-pong through key_b / val_b; 8 passes end in _a).
 void radix_sort(hipStream_t s, const DevPtrs& d, int n) {
     if (n <= 1) return;
@@ -396,7 +423,7 @@ void radix_sort(hipStream_t s, const DevPtrs& d, int n) {
     for (int pass = 0; pass < 8; ++pass) {
         const int shift = 8 * pass;
         hipLaunchKernelGGL(k_rs_hist, dim3(nb), dim3(RS_THREADS), 0, s, ki, n, shift, d.rs_hist, nb);
-        scan_u32(s, d.rs_hist, 256 * nb, d.scan_tmp);
+        hipLaunchKernelGGL(k_rs_offsets, dim3(1), dim3(256), 0, s, d.rs_hist, nb);
         hipLaunchKernelGGL(k_rs_scatter, dim3(nb), dim3(RS_THREADS), 0, s, ki, vi, ko, vo, n, shift, d.rs_hist, nb);
         u64* tk = ki; ki = ko; ko = tk;
         u32* tv = vi; vi = vo; vo = tv;

@@ -15,9 +15,9 @@
 //   position i starts the nodes of levels lcp[i]+1 .. lvl[i]; an exclusive scan of those
 //   counts numbers the nodes in pre-order.  A stable counting sort by level turns that
 //   into breadth-first order, where the children of a node are a contiguous run of the
-//   next level.  Moments are aggregated bottom-up by the last child to finish.
-//   The same windowed search with capacity 4 * group_size cuts the sorted order into compact
-//   "group cells"; each is split into target groups of at most group_size particles, so a
+//   next level.  Moments are aggregated bottom-up one level at a time.
+//   The largest nodes holding at most 4 * group_size particles form compact "group cells";
+//   each is split into target groups of at most group_size consecutive particles, so a
 //   group never spans two distant cells of the space-filling curve.
 #include "common.h"
 
@@ -41,16 +41,15 @@ __device__ __forceinline__ int window_level(const signed char* c, int ci, int wi
     return L > MAX_LEVEL ? MAX_LEVEL : L;
 }
 
-// Per sorted position: lcp, leaf level (leaf capacity win), node/leaf-start counts for the
-// pre-order scan, and the start flag of the group cells (cells of at most gwin particles).
-__global__ void __launch_bounds__(TB) k_leaf_levels(const u64* __restrict__ key, int n, int win, int gwin,
-                                                    int min_level, signed char* lcp, unsigned char* lvl,
-                                                    u64* scan_in, u32* gflag) {
+// Per sorted position: lcp, leaf level (leaf capacity win) and the node / leaf-start counts
+// for the pre-order scan.  The leaf level is at most max(lcp[i], lcp[i+1]) + 1 (the cell
+// holding i alone), which bounds the binary search.
+__global__ void __launch_bounds__(TB) k_leaf_levels(const u64* __restrict__ key, int n, int win, int min_level,
+                                                    signed char* lcp, unsigned char* lvl, u64* scan_in) {
     __shared__ signed char c[TB + 2 * MAX_WIN + 2];
-    const int W = win > gwin ? win : gwin;
     const int b0 = blockIdx.x * TB;
-    const int lo = b0 - W;                        // c[j] holds position lo + j
-    const int cnt = TB + 2 * W + 1;
+    const int lo = b0 - win;                      // c[j] holds position lo + j
+    const int cnt = TB + 2 * win + 1;
     for (int j = threadIdx.x; j < cnt; j += TB) {
         const int p = lo + j;
         int v = -1;
@@ -63,15 +62,29 @@ __global__ void __launch_bounds__(TB) k_leaf_levels(const u64* __restrict__ key,
     const int ci = i - lo;
     int L = window_level(c, ci, win);
     if (L < min_level) L = min_level;
-    int Lg = window_level(c, ci, gwin);
-    if (Lg < min_level) Lg = min_level;
     const int cc = c[ci];
     const int nodes = L > cc ? L - cc : 0;
     lcp[i] = (signed char)cc;
     lvl[i] = (unsigned char)L;
     scan_in[i] = ((u64)nodes << 32) | (u64)(nodes > 0 ? 1u : 0u);
-    gflag[i] = Lg > cc ? 1u : 0u;
     if (i == n - 1) lcp[n] = -1;
+}
+
+// Group cells: the largest nodes holding at most gcap particles (at or below min_level),
+// plus leaves that hold more (runs of equal keys).  They partition the sorted particles;
+// their first positions are flagged.
+__global__ void k_gcell_flags(const DevCtl* __restrict__ ctl, int gcap, int min_level, const int4* __restrict__ topo,
+                              const int* __restrict__ parent, const int2* __restrict__ range, u32* gflag) {
+    const int nn = ctl->n_nodes;
+    for (int b = blockIdx.x * blockDim.x + threadIdx.x; b < nn; b += gridDim.x * blockDim.x) {
+        const int4 tp = topo[b];
+        const bool fits = range[b].y <= gcap && tp.z >= min_level;
+        if (!(fits || tp.w)) continue;
+        const int p = parent[b];
+        bool pfits = false;
+        if (p >= 0) pfits = range[p].y <= gcap && topo[p].z >= min_level;
+        if (!pfits) gflag[range[b].x] = 1u;
+    }
 }
 
 // Group cells -> target groups of at most gsz consecutive particles inside one cell.
@@ -316,13 +329,13 @@ __device__ void aggregate_node(int p, const int4 tp, double4* nbox_lo, double4* 
     range[p] = make_int2(range[tp.x].x, cnt);
 }
 
-__global__ void __launch_bounds__(256) k_moments(DevCtl* ctl, int batched, const u64* __restrict__ key,
-                                                  const int* __restrict__ leaf_start, const int* __restrict__ leaf_pre,
-                                                  const int* __restrict__ pre_to_bfs, const int4* __restrict__ topo,
-                                                  const int* __restrict__ parent, int* counter,
-                                                  const double4* __restrict__ pos4, const double* __restrict__ m,
-                                                  double4* nbox_lo, double4* nbox_hi, double4* mom0, double4* mom1,
-                                                  double4* mom2, int2* range) {
+__global__ void __launch_bounds__(256) k_leaf_moments(const DevCtl* __restrict__ ctl, int batched,
+                                                       const u64* __restrict__ key, const int* __restrict__ leaf_start,
+                                                       const int* __restrict__ leaf_pre,
+                                                       const int* __restrict__ pre_to_bfs, const int4* __restrict__ topo,
+                                                       const double4* __restrict__ pos4, const double* __restrict__ m,
+                                                       double4* nbox_lo, double4* nbox_hi, double4* mom0,
+                                                       double4* mom1, double4* mom2, int2* range) {
     const int nl = ctl->n_leaves;
     const int nn = ctl->n_nodes;
     for (int lf = blockIdx.x * blockDim.x + threadIdx.x; lf < nl; lf += gridDim.x * blockDim.x) {
@@ -357,20 +370,23 @@ __global__ void __launch_bounds__(256) k_moments(DevCtl* ctl, int batched, const
         mom1[b] = make_double4(I[0], I[1], I[2], I[0] + I[1] + I[2]);
         mom2[b] = make_double4(I[3], I[4], I[5], 0.0);
         range[b] = make_int2(s, e - s);
-        // climb
-        int node = b;
-        __threadfence();
-        int p = parent[node];
-        for (int depth = 0; p >= 0 && depth < 2 * MAX_LEVEL + 2; ++depth) {
-            const int4 tp = topo[p];
-            const int old = __hip_atomic_fetch_add(&counter[p], 1, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
-            if (old != tp.y - 1) break;
-            __threadfence();
-            aggregate_node(p, tp, nbox_lo, nbox_hi, mom0, mom1, mom2, range, ldexp(L, -tp.z));
-            __threadfence();
-            node = p;
-            p = parent[node];
-        }
+    }
+}
+
+// Internal nodes of one level from their children (one launch per level, deepest first:
+// children are complete when their parents are read, with no cross-workgroup waiting).
+__global__ void __launch_bounds__(256) k_level_moments(const DevCtl* __restrict__ ctl, int level, int batched,
+                                                        const u64* __restrict__ key, const int4* __restrict__ topo,
+                                                        double4* nbox_lo, double4* nbox_hi, double4* mom0,
+                                                        double4* mom1, double4* mom2, int2* range) {
+    const int b0 = ctl->level_off[level], nb = ctl->level_count[level];
+    for (int k = blockIdx.x * blockDim.x + threadIdx.x; k < nb; k += gridDim.x * blockDim.x) {
+        const int b = b0 + k;
+        const int4 tp = topo[b];
+        if (tp.w) continue;
+        const int s = range[tp.x].x;
+        const int seg = batched ? (int)((key[s] >> 54) & 511ull) : 0;
+        aggregate_node(b, tp, nbox_lo, nbox_hi, mom0, mom1, mom2, range, ldexp(ctl->side[seg], -level));
     }
 }
 
@@ -383,18 +399,9 @@ void build_octree(hipStream_t s, const DevPtrs& d, const Dims& dm) {
     const int n = dm.n;
     if (n <= 0) return;
     hipLaunchKernelGGL(k_tree_reset, dim3(1), dim3(64), 0, s, d.ctl);
-    const int gwin = 4 * dm.group_size < MAX_WIN ? 4 * dm.group_size : MAX_WIN;
-    hipLaunchKernelGGL(k_leaf_levels, dim3((n + TB - 1) / TB), dim3(TB), 0, s, d.key_a, n, dm.leaf_size, gwin,
-                       dm.min_level, d.lcp, d.lvl, d.scan_in, d.gflag);
+    hipLaunchKernelGGL(k_leaf_levels, dim3((n + TB - 1) / TB), dim3(TB), 0, s, d.key_a, n, dm.leaf_size, dm.min_level,
+                       d.lcp, d.lvl, d.scan_in);
     scan_u64(s, d.scan_in, d.scan_out, n, d.scan_tmp);
-    // target groups
-    scan_u32_total(s, d.gflag, d.gscan, n, d.scan_tmp);
-    hipLaunchKernelGGL(k_gcells, dim3((n + 255) / 256), dim3(256), 0, s, n, d.gflag, d.gscan, d.gcell, d.ctl);
-    hipLaunchKernelGGL(k_gcell_chunks, dim3((n + 255) / 256), dim3(256), 0, s, n, dm.group_size, d.ctl, d.gcell,
-                       d.gnch);
-    scan_u32_total(s, d.gnch, d.goff, n, d.scan_tmp);
-    hipLaunchKernelGGL(k_emit_groups, dim3((n + 255) / 256), dim3(256), 0, s, n, dm.group_size, dm.batched, d.ctl,
-                       d.gcell, d.gnch, d.goff, d.key_a, d.seg_root_rank, d.group);
     hipLaunchKernelGGL(k_emit_nodes, dim3((n + 255) / 256), dim3(256), 0, s, n, d.lcp, d.lvl, d.scan_out,
                        d.pre_level, d.pre_leaf, d.pre_start, d.leaf_start, d.leaf_pre, d.ctl, dm.node_cap);
     hipLaunchKernelGGL(k_level_offsets, dim3(1), dim3(64), 0, s, d.ctl);
@@ -407,9 +414,24 @@ void build_octree(hipStream_t s, const DevPtrs& d, const Dims& dm) {
     hipLaunchKernelGGL(k_finalize, dim3(g), dim3(256), 0, s, d.ctl, d.pre_level, d.pre_leaf, d.pre_start,
                        d.pre_to_bfs, d.bfs_to_pre, d.lcp, d.scan_out, d.leaf_start, d.topo, d.parent, d.counter,
                        d.range);
-    hipLaunchKernelGGL(k_moments, dim3(grid_cap(n, 256, 2048)), dim3(256), 0, s, d.ctl, dm.batched, d.key_a,
-                       d.leaf_start, d.leaf_pre, d.pre_to_bfs, d.topo, d.parent, d.counter, d.pos4, d.m, d.nbox_lo,
-                       d.nbox_hi, d.mom0, d.mom1, d.mom2, d.range);
+    hipLaunchKernelGGL(k_leaf_moments, dim3(grid_cap(n, 256, 2048)), dim3(256), 0, s, d.ctl, dm.batched, d.key_a,
+                       d.leaf_start, d.leaf_pre, d.pre_to_bfs, d.topo, d.pos4, d.m, d.nbox_lo, d.nbox_hi, d.mom0,
+                       d.mom1, d.mom2, d.range);
+    for (int lev = MAX_LEVEL - 1; lev >= 0; --lev)
+        hipLaunchKernelGGL(k_level_moments, dim3(lev < 4 ? 1 : 64), dim3(256), 0, s, d.ctl, lev, dm.batched, d.key_a,
+                           d.topo, d.nbox_lo, d.nbox_hi, d.mom0, d.mom1, d.mom2, d.range);
+    // target groups: cells of at most 4 * group_size particles, cut into runs of group_size
+    const int gcap = 4 * dm.group_size;
+    launch_fill_u32(s, d.gflag, 0u, n + 1);
+    hipLaunchKernelGGL(k_gcell_flags, dim3(g), dim3(256), 0, s, d.ctl, gcap, dm.min_level, d.topo, d.parent, d.range,
+                       d.gflag);
+    scan_u32_total(s, d.gflag, d.gscan, n, d.scan_tmp);
+    hipLaunchKernelGGL(k_gcells, dim3((n + 255) / 256), dim3(256), 0, s, n, d.gflag, d.gscan, d.gcell, d.ctl);
+    hipLaunchKernelGGL(k_gcell_chunks, dim3((n + 255) / 256), dim3(256), 0, s, n, dm.group_size, d.ctl, d.gcell,
+                       d.gnch);
+    scan_u32_total(s, d.gnch, d.goff, n, d.scan_tmp);
+    hipLaunchKernelGGL(k_emit_groups, dim3((n + 255) / 256), dim3(256), 0, s, n, dm.group_size, dm.batched, d.ctl,
+                       d.gcell, d.gnch, d.goff, d.key_a, d.seg_root_rank, d.group);
 }
 
 // Export (test path): node keys etc. in breadth-first order.
