@@ -79,6 +79,88 @@ def run_gpu(ps, prec, steps, warmup, reps):
                 diag=diag.tolist(), leaf=leaf, group=group, dt=dt)
 
 
+def _pairs(ctx, pa, n):
+    import paper_2007_03097_amd as sph
+    sph.sph_build_tree(ctx.h, pa)
+    total = sph.sph_find_neighbors(ctx.h, None, None, 0)
+    return total + (total - n)
+
+
+def run_polytrope(ps, steps, prec):
+    """n = 1 polytrope with self-gravity (theta = 0.5 quadrupole, eps = 0.01, G = 1), adaptive h."""
+    import numpy as np
+    import torch
+    import paper_2007_03097_amd as sph
+    n = ps.n
+    ctx = sph.Context(n, adaptive_h=1, precision=prec, G=1.0, soft_eps=0.01, theta=0.5, nbr_capacity=512)
+    pa = sph.ParticleArrays.from_numpy(ps, with_accel=True)
+    sph.sph_step(ctx.h, pa, 1e-9, 0, 0)                  # prime: accelerations of the initial state
+    a = np.sqrt(sum(pa[k].cpu().numpy() ** 2 for k in ("ax", "ay", "az")))
+    c = np.sqrt((5.0 / 3.0) * (2.0 / 3.0) * ps.u)
+    dt = 0.25 * min(float(np.min(pa["h"].cpu().numpy() / c)), float(np.sqrt(0.01 / a.max())))
+    sph.sph_step(ctx.h, pa, dt, 1, sph.SPH_STEP_PRIMED)  # warm up, capture graphs
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    sph.sph_step(ctx.h, pa, dt, steps, sph.SPH_STEP_RESUME)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    pairs = _pairs(ctx, pa, n)
+    ctx.close()
+    torch.cuda.empty_cache()
+    return dict(ms_per_step=wall / steps * 1e3, steps_per_s=steps / wall, value=pairs * steps / wall, dt=dt)
+
+
+def run_ensemble(steps):
+    """256 independent boxes: one batched context (all boxes in one graph-captured step,
+    FP32C) against a loop of per-box FP64 contexts."""
+    import torch
+    import paper_2007_03097_amd as sph
+    from workloads import ensemble
+    ps = ensemble(256, seed=1004)
+    so = ps.seg_offsets
+    n = ps.n
+    dt = dt_for(ps)
+    out = {"n_particles": n, "n_boxes": 256, "dt": dt}
+    # batched, FP32C and FP64
+    for prec, key in ((1, "batched_fp32c"), (0, "batched_fp64")):
+        ctx = sph.Context(n, seg_capacity=256, precision=prec)
+        pa = sph.ParticleArrays.from_numpy(ps)
+        sph.sph_step(ctx.h, pa, dt, 1, 0)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        sph.sph_step(ctx.h, pa, dt, steps, sph.SPH_STEP_RESUME)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        pairs = _pairs(ctx, pa, n)
+        out[key] = {"ms_per_step": wall / steps * 1e3, "value": pairs * steps / wall}
+        ctx.close()
+        del pa
+        torch.cuda.empty_cache()
+    # per-box FP64 loop
+    ctxs, pas = [], []
+    for b in range(256):
+        sub = ps.subset(slice(int(so[b]), int(so[b + 1])))
+        ctx = sph.Context(sub.n, precision=0)
+        pa = sph.ParticleArrays.from_numpy(sub)
+        sph.sph_step(ctx.h, pa, dt, 1, 0)
+        ctxs.append(ctx)
+        pas.append(pa)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        for ctx in ctxs:
+            sph.sph_step(ctx.h, None, dt, 1, sph.SPH_STEP_RESUME)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    pairs = sum(_pairs(c, p, p.n) for c, p in zip(ctxs, pas))
+    out["per_box_fp64_loop"] = {"ms_per_step": wall / steps * 1e3, "value": pairs * steps / wall}
+    out["batched_fp32c_speedup_vs_loop"] = out["batched_fp32c"]["value"] / out["per_box_fp64_loop"]["value"]
+    for c in ctxs:
+        c.close()
+    torch.cuda.empty_cache()
+    return out
+
+
 def cpu_baseline(ps, reps=10):
     """The CPU FP64 reference on a bounded sample: the slab 0.42 < x < 0.58 of the same tube
     (both lattices and the interface).  Brute-force neighbours are built once (reported,
@@ -111,6 +193,7 @@ def main():
     ap.add_argument("--ny", type=int, default=56, help="tube lattice resolution (56 -> 987,840 particles)")
     ap.add_argument("--reps", type=int, default=20, help="repetitions of the per-kernel timing")
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-extra", action="store_true", help="skip the polytrope and ensemble workloads")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); the multi-GPU path is not built.",
@@ -129,6 +212,14 @@ def main():
             "unit": "TFLOP/s", "frac": achieved / FP64_PEAK_TFLOPS, "traffic": None,
             "per_launch": {"pairs": r64["pairs_force"], "flop_per_pair": FLOP_FORCE_PAIR,
                            "avg_ms": r64["t_force"] * 1e3}}
+    extra = {}
+    if not args.no_extra:
+        from workloads import polytrope_n1
+        pp = polytrope_n1(4194304, seed=1003)
+        extra["polytrope_4m_gravity"] = {"n_particles": pp.n, "fp64": run_polytrope(pp, 5, 0),
+                                         "fp32c": run_polytrope(pp, 5, 1)}
+        del pp
+        extra["ensemble_256"] = run_ensemble(5)
     cpu = None if args.no_cpu else cpu_baseline(ps)
     out = {
         "metric": "pair interactions/sec (density+force) and steps/sec, FP64 vs FP32-comp, 1 GPU",
@@ -147,6 +238,7 @@ def main():
                   "kernel_ms": {"density": r32["t_dens"] * 1e3, "forces": r32["t_force"] * 1e3}},
         "roofline": roof,
         "cpu_baseline": cpu,
+        **extra,
     }
     print(json.dumps(out), flush=True)
 

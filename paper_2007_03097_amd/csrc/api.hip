@@ -114,6 +114,7 @@ static size_t layout(const sph_ctx* c, char* base, DevPtrs* out) {
     d.val_a = cv.take<u32>(N);
     d.val_b = cv.take<u32>(N);
     d.rs_hist = cv.take<u32>(256 * RSB);
+    d.rs_dtot = cv.take<u32>(256);
     d.scan_tmp = cv.take<u64>(SCB);
     double** f1[] = {&d.x, &d.y, &d.z, &d.vx, &d.vy, &d.vz, &d.m, &d.h, &d.u, &d.vpx, &d.vpy, &d.vpz, &d.up,
                      &d.ax, &d.ay, &d.az, &d.du, &d.rho, &d.P, &d.cs, &d.hnext, &d.gx, &d.gy, &d.gz, &d.phi,

@@ -46,6 +46,7 @@ struct DevPtrs {
     u64 *key_a, *key_b;           // n_cap
     u32 *val_a, *val_b;           // n_cap
     u32* rs_hist;                 // 256 * rs_blocks_cap
+    u32* rs_dtot;                 // 256 digit totals of the current pass
     void* scan_tmp;               // 8 * scan_blocks_cap (u64)
     // Morton-ordered particle data (SoA FP64)
     double *x, *y, *z, *vx, *vy, *vz, *m, *h, *u;

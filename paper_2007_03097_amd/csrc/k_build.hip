@@ -336,11 +336,18 @@ __global__ void __launch_bounds__(RS_THREADS) k_rs_hist(const u64* __restrict__ 
 
 __global__ void __launch_bounds__(RS_THREADS) k_rs_scatter(const u64* __restrict__ kin, const u32* __restrict__ vin,
                                                            u64* __restrict__ kout, u32* __restrict__ vout, int n,
-                                                           int shift, const u32* __restrict__ offs, int nb) {
+                                                           int shift, const u32* __restrict__ offs, int nb,
+                                                           const u32* __restrict__ digit_tot) {
     __shared__ u32 wcnt[RS_WAVES][256];
     __shared__ u32 woff[RS_WAVES][256];
+    __shared__ u32 dbase[256];
     const int w = threadIdx.x >> 6, lane = lane_id();
     for (int i = threadIdx.x; i < RS_WAVES * 256; i += RS_THREADS) (&wcnt[0][0])[i] = 0;
+    {   // exclusive scan of the digit totals
+        u32 tot;
+        const u32 e = block_excl_scan<u32>(digit_tot[threadIdx.x], &tot);
+        dbase[threadIdx.x] = e;
+    }
     __syncthreads();
     const int base = blockIdx.x * RS_TILE + w * (64 * RS_ITEMS) + lane;
     u64 k[RS_ITEMS];
@@ -369,8 +376,9 @@ __global__ void __launch_bounds__(RS_THREADS) k_rs_scatter(const u64* __restrict
     {
         const int dg = threadIdx.x;
         u32 acc = 0;
+        const u32 base = dbase[dg] + offs[dg * nb + blockIdx.x];
         for (int q = 0; q < RS_WAVES; ++q) {
-            woff[q][dg] = acc + offs[dg * nb + blockIdx.x];
+            woff[q][dg] = acc + base;
             acc += wcnt[q][dg];
         }
     }
@@ -387,31 +395,32 @@ __global__ void __launch_bounds__(RS_THREADS) k_rs_scatter(const u64* __restrict
     }
 }
 
-// Digit offsets for one pass in a single launch: thread d scans digit d's per-block counts
-// (contiguous, digit-major), then the 256 digit totals are scanned in LDS and added.
-__global__ void __launch_bounds__(256) k_rs_offsets(u32* hist, int nb) {
-    __shared__ u32 tot[256];
-    const int d = threadIdx.x;
-    u32* h = hist + (size_t)d * nb;
-    u32 acc = 0;
-    for (int b = 0; b < nb; ++b) {
-        const u32 v = h[b];
-        h[b] = acc;
-        acc += v;
-    }
-    tot[d] = acc;
-    __syncthreads();
-    if (d == 0) {
-        u32 run = 0;
-        for (int k = 0; k < 256; ++k) {
-            const u32 v = tot[k];
-            tot[k] = run;
-            run += v;
+// Per-digit exclusive scan of the per-block counts: one workgroup per digit scans that
+// digit's contiguous row (digit-major table) and records the digit total.
+__global__ void __launch_bounds__(SC_THREADS) k_rs_digit_scan(u32* hist, int nb, u32* digit_tot) {
+    u32* h = hist + (size_t)blockIdx.x * nb;
+    u32 carry = 0;
+    for (int b0 = 0; b0 < nb; b0 += SC_TILE) {
+        u32 v[SC_ITEMS];
+        u32 s = 0;
+#pragma unroll
+        for (int k = 0; k < SC_ITEMS; ++k) {
+            const int i = b0 + threadIdx.x * SC_ITEMS + k;
+            v[k] = i < nb ? h[i] : 0u;
+            s += v[k];
         }
+        u32 tot;
+        u32 e = block_excl_scan<u32>(s, &tot) + carry;
+#pragma unroll
+        for (int k = 0; k < SC_ITEMS; ++k) {
+            const int i = b0 + threadIdx.x * SC_ITEMS + k;
+            if (i < nb) h[i] = e;
+            e += v[k];
+        }
+        carry += tot;
+        __syncthreads();
     }
-    __syncthreads();
-    const u32 base = tot[d];
-    for (int b = 0; b < nb; ++b) h[b] += base;
+    if (threadIdx.x == 0) digit_tot[blockIdx.x] = carry;
 }
 
 // Sorts (key_a, val_a) in place (ping-pong through key_b / val_b; 8 passes end in _a).
@@ -423,8 +432,9 @@ void radix_sort(hipStream_t s, const DevPtrs& d, int n) {
     for (int pass = 0; pass < 8; ++pass) {
         const int shift = 8 * pass;
         hipLaunchKernelGGL(k_rs_hist, dim3(nb), dim3(RS_THREADS), 0, s, ki, n, shift, d.rs_hist, nb);
-        hipLaunchKernelGGL(k_rs_offsets, dim3(1), dim3(256), 0, s, d.rs_hist, nb);
-        hipLaunchKernelGGL(k_rs_scatter, dim3(nb), dim3(RS_THREADS), 0, s, ki, vi, ko, vo, n, shift, d.rs_hist, nb);
+        hipLaunchKernelGGL(k_rs_digit_scan, dim3(256), dim3(SC_THREADS), 0, s, d.rs_hist, nb, d.rs_dtot);
+        hipLaunchKernelGGL(k_rs_scatter, dim3(nb), dim3(RS_THREADS), 0, s, ki, vi, ko, vo, n, shift, d.rs_hist, nb,
+                           d.rs_dtot);
         u64* tk = ki; ki = ko; ko = tk;
         u32* tv = vi; vi = vo; vo = tv;
     }

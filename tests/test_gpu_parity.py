@@ -371,3 +371,29 @@ def test_empty_set():
     assert k.size == 0
     off, idx = gpu_neighbors(ctx, 0)
     assert off.tolist() == [0] and idx.size == 0
+
+
+def test_autotune_keeps_results_and_caches(tmp_path):
+    """The autotuner leaves the particle set unchanged, picks a valid setting, writes the
+    cache and reuses it; integer outputs do not depend on the tuning."""
+    import paper_2007_03097_amd as sph
+    ps = sod_tube(8)
+    ctx = make_ctx(ps.n, adaptive_h=1)
+    pa = parts(ps)
+    before = {k: pa[k].cpu().numpy().copy() for k in ("x", "vx", "u", "h")}
+    cache = str(tmp_path / "tune.json")
+    sph.sph_autotune(ctx.h, pa, 4e-4, cache)
+    leaf, group = sph.sph_get_tuning(ctx.h)
+    assert leaf in (8, 12, 16, 24, 32) and group in (16, 32, 64)
+    for k, v in before.items():
+        assert np.array_equal(pa[k].cpu().numpy(), v)
+    assert f"[{leaf}, {group}]" in open(cache).read()
+    ctx2 = make_ctx(ps.n, adaptive_h=1)
+    sph.sph_autotune(ctx2.h, pa, 4e-4, cache)
+    assert sph.sph_get_tuning(ctx2.h) == (leaf, group)
+    k1, o1 = gpu_keys_order(ctx2, pa)
+    off1, idx1 = gpu_neighbors(ctx2, ps.n)
+    ctx3 = make_ctx(ps.n, leaf_size=8, group_size=64)
+    k3, o3 = gpu_keys_order(ctx3, pa)
+    off3, idx3 = gpu_neighbors(ctx3, ps.n)
+    assert np.array_equal(o1, o3) and np.array_equal(off1, off3) and np.array_equal(idx1, idx3)
