@@ -92,7 +92,7 @@ def run_polytrope(ps, steps, prec):
     import torch
     import paper_2007_03097_amd as sph
     n = ps.n
-    ctx = sph.Context(n, adaptive_h=1, precision=prec, G=1.0, soft_eps=0.01, theta=0.5, nbr_capacity=512)
+    ctx = sph.Context(n, adaptive_h=1, precision=prec, G=1.0, soft_eps=0.01, theta=0.5, nbr_capacity=2048)
     pa = sph.ParticleArrays.from_numpy(ps, with_accel=True)
     sph.sph_step(ctx.h, pa, 1e-9, 0, 0)                  # prime: accelerations of the initial state
     a = np.sqrt(sum(pa[k].cpu().numpy() ** 2 for k in ("ax", "ay", "az")))
