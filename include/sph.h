@@ -137,7 +137,9 @@ sph_status sph_tree_nodes(sph_ctx* ctx, int64_t capacity, uint64_t* key, int32_t
  * sorted by ascending caller index.  Synchronous.
  *   offsets_out device int64[n + 1];  idx_out device int32[capacity].
  *   *total_host receives the number of entries; SPH_E_CAPACITY (nothing written to
- *   idx_out) if it exceeds capacity.  Either output may be NULL to only count. */
+ *   idx_out) if it exceeds capacity.  Either output may be NULL to only count.  With all
+ *   three of offsets_out, idx_out and total_host NULL the call only (re)builds the device
+ *   lists, asynchronously (used to time the list kernel). */
 sph_status sph_find_neighbors(sph_ctx* ctx, int64_t* offsets_out, int32_t* idx_out, int64_t capacity,
                               int64_t* total_host);
 

@@ -131,12 +131,13 @@ def sph_tree_nodes(ctx, capacity: int, key=None, level=None, leaf=None, start=No
     return int(n.value)
 
 
-def sph_find_neighbors(ctx, offsets_out=None, idx_out=None, capacity: int = 0) -> int:
+def sph_find_neighbors(ctx, offsets_out=None, idx_out=None, capacity: int = 0, count: bool = True) -> int:
+    """count=False with no outputs only (re)builds the device lists (asynchronous)."""
     import torch
     tot = ctypes.c_int64()
     _check(ctx, _lib().sph_find_neighbors(ctx, _ptr(offsets_out, torch.int64), _ptr(idx_out, torch.int32),
-                                          int(capacity), ctypes.byref(tot)))
-    return int(tot.value)
+                                          int(capacity), ctypes.byref(tot) if count else None))
+    return int(tot.value) if count else -1
 
 
 def sph_compute_density(ctx, rho, P, cs, h_next=None):

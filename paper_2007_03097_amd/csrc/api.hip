@@ -433,6 +433,11 @@ sph_status sph_tree_nodes(sph_ctx* c, int64_t capacity, uint64_t* key, int32_t* 
 sph_status sph_find_neighbors(sph_ctx* c, int64_t* offsets_out, int32_t* idx_out, int64_t capacity,
                               int64_t* total_host) {
     if (!c) return SPH_E_ARG;
+    if (!offsets_out && !idx_out && !total_host) {  // rebuild the lists only (asynchronous)
+        if (!c->tree_ok) return fail(c, SPH_E_STATE, "sph_build_tree has not been called");
+        c->lists_ok = false;
+        return ensure_lists(c);
+    }
     sph_status st = ensure_lists(c);
     if (st != SPH_OK) return st;
     const DevPtrs& d = c->d[c->parity];

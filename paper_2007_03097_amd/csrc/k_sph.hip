@@ -9,9 +9,10 @@
 //                       mu = h_ab v_ab . r_ab / (r^2 + eps h_ab^2)
 // with the M4 cubic spline W = w(q)/(pi h^3), grad_a W_ab = r_ab g(q)/(pi h^5), g = w'(q)/q.
 //
-// One wavefront per group of group_size targets; target t is served by 64/group_size
-// lanes that take every (64/group_size)-th entry of its neighbour list, then combine in a
-// fixed butterfly order, so results are bitwise reproducible.  The pair sums are not a
+// One wavefront per group of group_size targets (four consecutive groups per workgroup, so
+// their neighbour gathers share one L1); target t is served by 64/group_size lanes that take
+// every (64/group_size)-th entry of its neighbour list, then combine in a fixed butterfly
+// order, so results are bitwise reproducible.  The pair sums are not a
 // dense contraction (each target has its own irregular list), so they run on the vector
 // ALUs, not on the matrix cores.
 //
@@ -78,7 +79,7 @@ struct Neumaier {
 
 // ---------------------------------------------------------------------------------------
 template <bool FP32C>
-__global__ void __launch_bounds__(64) k_density(const DevCtl* __restrict__ ctl, const int4* __restrict__ group,
+__global__ void __launch_bounds__(256) k_density(const DevCtl* __restrict__ ctl, const int4* __restrict__ group,
                                                 int gsz, int cap,
                                                 const int* __restrict__ nbr, const int* __restrict__ nbr_cnt,
                                                 const double4* __restrict__ pos4, const double* __restrict__ m,
@@ -88,9 +89,12 @@ __global__ void __launch_bounds__(64) k_density(const DevCtl* __restrict__ ctl, 
                                                 double4* __restrict__ thr4, float4* __restrict__ thrf) {
     const int lane = lane_id();
     const int t = lane & (gsz - 1), phi = lane / gsz, P_ = 64 / gsz;
+    const int ng = ctl->n_groups;
     int g0, g1, gstep;
-    group_range(ctl->n_groups, g0, g1, gstep);
-    for (int gi = g0; gi < g1; gi += gstep) {
+    group_range((ng + 3) >> 2, g0, g1, gstep);   // four consecutive groups per workgroup share L1
+    for (int gq = g0; gq < g1; gq += gstep) {
+    const int gi = 4 * gq + (int)(threadIdx.x >> 6);
+    if (gi >= ng) continue;
     const int4 g = group[gi];
     const bool tv = t < g.y;
     const int q = g.x + t;
@@ -143,11 +147,11 @@ void launch_density(hipStream_t s, const DevPtrs& d, const Dims& dm, int fp32c, 
                     const double* u_eos) {
     if (dm.n <= 0) return;
     if (fp32c)
-        hipLaunchKernelGGL(k_density<true>, dim3(dm.group_grid), dim3(64), 0, s, d.ctl, d.group, dm.group_size, dm.nbr_cap,
+        hipLaunchKernelGGL(k_density<true>, dim3(dm.group_grid / 4 > 8 ? (dm.group_grid / 4) & ~7 : 8), dim3(256), 0, s, d.ctl, d.group, dm.group_size, dm.nbr_cap,
                            d.nbr, d.nbr_cnt, d.pos4, d.m, u_eos, gamma, h_coeff, d.rho, d.P, d.cs, d.hnext, d.thr4,
                            d.thrf);
     else
-        hipLaunchKernelGGL(k_density<false>, dim3(dm.group_grid), dim3(64), 0, s, d.ctl, d.group, dm.group_size, dm.nbr_cap,
+        hipLaunchKernelGGL(k_density<false>, dim3(dm.group_grid / 4 > 8 ? (dm.group_grid / 4) & ~7 : 8), dim3(256), 0, s, d.ctl, d.group, dm.group_size, dm.nbr_cap,
                            d.nbr, d.nbr_cnt, d.pos4, d.m, u_eos, gamma, h_coeff, d.rho, d.P, d.cs, d.hnext, d.thr4,
                            d.thrf);
 }
@@ -178,7 +182,7 @@ void launch_thermo_from_caller(hipStream_t s, const DevPtrs& d, const Dims& dm, 
 
 // ---------------------------------------------------------------------------------------
 template <bool FP32C>
-__global__ void __launch_bounds__(64) k_forces(const DevCtl* __restrict__ ctl, const int4* __restrict__ group,
+__global__ void __launch_bounds__(256) k_forces(const DevCtl* __restrict__ ctl, const int4* __restrict__ group,
                                                int gsz, int cap,
                                                const int* __restrict__ nbr, const int* __restrict__ nbr_cnt,
                                                const double4* __restrict__ pos4, const double4* __restrict__ vel4,
@@ -188,9 +192,12 @@ __global__ void __launch_bounds__(64) k_forces(const DevCtl* __restrict__ ctl, c
                                                double* __restrict__ az, double* __restrict__ du) {
     const int lane = lane_id();
     const int t = lane & (gsz - 1), phi = lane / gsz, P_ = 64 / gsz;
+    const int ng = ctl->n_groups;
     int g0, g1, gstep;
-    group_range(ctl->n_groups, g0, g1, gstep);
-    for (int gi = g0; gi < g1; gi += gstep) {
+    group_range((ng + 3) >> 2, g0, g1, gstep);   // four consecutive groups per workgroup share L1
+    for (int gq = g0; gq < g1; gq += gstep) {
+    const int gi = 4 * gq + (int)(threadIdx.x >> 6);
+    if (gi >= ng) continue;
     const int4 g = group[gi];
     const bool tv = t < g.y;
     const int q = g.x + t;
@@ -279,11 +286,11 @@ void launch_forces(hipStream_t s, const DevPtrs& d, const Dims& dm, int fp32c, d
                    double eps_av, const double*, const double*, const double*) {
     if (dm.n <= 0) return;
     if (fp32c)
-        hipLaunchKernelGGL(k_forces<true>, dim3(dm.group_grid), dim3(64), 0, s, d.ctl, d.group, dm.group_size, dm.nbr_cap,
+        hipLaunchKernelGGL(k_forces<true>, dim3(dm.group_grid / 4 > 8 ? (dm.group_grid / 4) & ~7 : 8), dim3(256), 0, s, d.ctl, d.group, dm.group_size, dm.nbr_cap,
                            d.nbr, d.nbr_cnt, d.pos4, d.vel4, d.thr4, d.velf, d.thrf, alpha, beta, eps_av, d.ax, d.ay,
                            d.az, d.du);
     else
-        hipLaunchKernelGGL(k_forces<false>, dim3(dm.group_grid), dim3(64), 0, s, d.ctl, d.group, dm.group_size, dm.nbr_cap,
+        hipLaunchKernelGGL(k_forces<false>, dim3(dm.group_grid / 4 > 8 ? (dm.group_grid / 4) & ~7 : 8), dim3(256), 0, s, d.ctl, d.group, dm.group_size, dm.nbr_cap,
                            d.nbr, d.nbr_cnt, d.pos4, d.vel4, d.thr4, d.velf, d.thrf, alpha, beta, eps_av, d.ax, d.ay,
                            d.az, d.du);
 }

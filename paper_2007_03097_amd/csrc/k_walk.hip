@@ -12,10 +12,10 @@
 //     leaves go to a candidate list, surviving internal nodes push their children.  The
 //     candidate list is matched (step 3) whenever it fills, so any number of candidates
 //     is handled with fixed LDS.
-//  3. Candidate particles are staged 64 at a time in LDS; lane (t, phi) tests source
-//     phi of every group_size-wide step for target t with the exact predicate
-//     fl(fl(fl(dx dx) + fl(dy dy)) + fl(dz dz)) < fl(t t), and a ballot compacts the hits
-//     into target t's list in source order.
+//  3. Candidate particles are staged 64 at a time in LDS; lane (t, phi) tests sources
+//     phi, phi + P, ... (P = 64 / group_size) for target t with the exact predicate
+//     fl(fl(fl(dx dx) + fl(dy dy)) + fl(dz dz)) < fl(t t), recording hits as bits; the
+//     P lanes of a target then take consecutive slot ranges and write their hits.
 // List layout: a group of n_g targets starting at sorted position s owns the block
 // nbr[s * nbr_cap, (s + n_g) * nbr_cap); slot k of target t is at s * nbr_cap + k * n_g + t,
 // so consumers reading slot k of consecutive targets read consecutive words, and the
@@ -25,18 +25,15 @@
 constexpr int WALK_STACK = 1024;
 constexpr int WALK_CAND = 256;
 
-__device__ __forceinline__ u64 target_pattern(int gsz) {
-    return gsz == 64 ? 1ull : gsz == 32 ? 0x0000000100000001ull : gsz == 16 ? 0x0001000100010001ull
-                                                                            : 0x0101010101010101ull;
-}
 
 // Exact predicate of every target of the group against the particles of the nc candidate
 // leaves in cand[] (node ids); hits are appended to the targets' lists.  cand[] is reused
-// as the leaves' first particles.
+// as the leaves' first particles.  Per 64-source tile, lane (t, phi) tests sources
+// phi, phi + P, ... and records hits as bits; afterwards the P lanes of a target take
+// consecutive slot ranges (phi order) and write their hits in source order.
 __device__ void match_candidates(int nc, int* cand, int* coff, double4* tile, int* sidx,
                                  const int4* __restrict__ topo, const double4* __restrict__ pos4, const double4 me,
-                                 bool tv, int t, int phi, int P, int gy, int cap, u64 mask_t, u64 lt, int* mylist,
-                                 int& cnt) {
+                                 bool tv, int t, int phi, int P, int gsz, int gy, int cap, int* mylist, int& cnt) {
     const int lane = lane_id();
     int carry = 0;
     for (int j0 = 0; j0 < nc; j0 += 64) {
@@ -73,24 +70,34 @@ __device__ void match_candidates(int nc, int* cand, int* coff, double4* tile, in
         }
         __syncthreads();
         const int tn = total - p0 < 64 ? total - p0 : 64;
-        for (int s = 0; s < tn; s += P) {
-            const int j = s + phi;
-            bool pred = false;
-            if (tv && j < tn) {
+        u64 bits = 0;
+        if (tv) {
+            int it = 0;
+            for (int j = phi; j < tn; j += P, ++it) {
                 const double4 b = tile[j];
                 const double dx = me.x - b.x, dy = me.y - b.y, dz = me.z - b.z;
                 double r2 = dx * dx + dy * dy;
                 r2 = r2 + dz * dz;
                 const double tt = me.w + b.w;
-                pred = r2 < tt * tt;
+                if (r2 < tt * tt) bits |= 1ull << it;
             }
-            const u64 B = __ballot(pred);
-            if (pred) {
-                const int slot = cnt + __popcll(B & mask_t & lt);
-                if (slot < cap) mylist[slot * gy + t] = sidx[j];
-            }
-            cnt += __popcll(B & mask_t);
         }
+        // slot ranges of the P lanes of each target (lanes t, t + gsz, ...), in phi order
+        const int mine = __popcll(bits);
+        int incl = mine;
+        for (int d = gsz; d < 64; d <<= 1) {
+            const int v = __shfl_up(incl, d, 64);
+            if (lane >= d) incl += v;
+        }
+        const int tot = __shfl(incl, t + gsz * (P - 1), 64);
+        int slot = cnt + incl - mine;
+        while (bits) {
+            const int it = __ffsll((long long)bits) - 1;
+            bits &= bits - 1;
+            if (slot < cap) mylist[slot * gy + t] = sidx[it * P + phi];
+            ++slot;
+        }
+        cnt += tot;
         __syncthreads();
     }
 }
@@ -108,7 +115,6 @@ __global__ void __launch_bounds__(64) k_nbr_lists(DevCtl* ctl, const int4* __res
     const int lane = lane_id();
     const int t = lane & (gsz - 1), phi = lane / gsz, P = 64 / gsz;
     const u64 lt = lanemask_lt();
-    const u64 mask_t = target_pattern(gsz) << t;
     int g0, g1, gstep;
     group_range(ctl->n_groups, g0, g1, gstep);
     for (int gi = g0; gi < g1; gi += gstep) {
@@ -134,8 +140,8 @@ __global__ void __launch_bounds__(64) k_nbr_lists(DevCtl* ctl, const int4* __res
                 break;
             }
             if (nc + 64 > WALK_CAND) {
-                match_candidates(nc, cand, coff, tile, sidx, topo, pos4, me, tv, t, phi, P, g.y, cap, mask_t, lt,
-                                 mylist, cnt);
+                match_candidates(nc, cand, coff, tile, sidx, topo, pos4, me, tv, t, phi, P, gsz, g.y, cap, mylist,
+                                 cnt);
                 nc = 0;
             }
             const int k = sp < 64 ? sp : 64;
@@ -172,8 +178,7 @@ __global__ void __launch_bounds__(64) k_nbr_lists(DevCtl* ctl, const int4* __res
         }
         __syncthreads();
         if (!overflow)
-            match_candidates(nc, cand, coff, tile, sidx, topo, pos4, me, tv, t, phi, P, g.y, cap, mask_t, lt, mylist,
-                             cnt);
+            match_candidates(nc, cand, coff, tile, sidx, topo, pos4, me, tv, t, phi, P, gsz, g.y, cap, mylist, cnt);
         else if (lane == 0)
             set_err(ctl, ERR_WALK_STACK);
         if (tv && phi == 0) {
