@@ -22,7 +22,7 @@
 // blocks of all groups tile exactly n * nbr_cap words.
 #include "common.h"
 
-constexpr int WALK_STACK = 1024;
+constexpr int WALK_STACK = 256;
 constexpr int WALK_CAND = 256;
 
 
