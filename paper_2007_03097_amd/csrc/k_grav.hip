@@ -184,7 +184,9 @@ __global__ void __launch_bounds__(64) k_gravity(DevCtl* ctl, const int4* __restr
             nc = nl = 0;
             __syncthreads();
         }
-        const int k = sp < 64 ? sp : 64;
+        int k = sp < 64 ? sp : 64;
+        const int room = (GW_STACK - sp) / 8;
+        if (k > room) k = room > 1 ? room : 1;
         const int node = lane < k ? stack[sp - k + lane] : -1;
         __syncthreads();
         sp -= k;

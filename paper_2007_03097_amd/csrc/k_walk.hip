@@ -22,7 +22,7 @@
 // blocks of all groups tile exactly n * nbr_cap words.
 #include "common.h"
 
-constexpr int WALK_STACK = 256;
+constexpr int WALK_STACK = 512;
 constexpr int WALK_CAND = 256;
 
 
@@ -144,7 +144,10 @@ __global__ void __launch_bounds__(64) k_nbr_lists(DevCtl* ctl, const int4* __res
                                  cnt);
                 nc = 0;
             }
-            const int k = sp < 64 ? sp : 64;
+            // pop at most as many nodes as the free stack can take the children of (8 each)
+            int k = sp < 64 ? sp : 64;
+            const int room = (WALK_STACK - sp) / 8;
+            if (k > room) k = room > 1 ? room : 1;
             const int node = lane < k ? stack[sp - k + lane] : -1;
             __syncthreads();
             sp -= k;
