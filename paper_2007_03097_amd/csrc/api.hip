@@ -125,8 +125,10 @@ static size_t layout(const sph_ctx* c, char* base, DevPtrs* out) {
     d.id2 = cv.take<u32>(N);
     d.inv = cv.take<u32>(N);
     d.pos4 = cv.take<double4>(N);
-    d.rec = cv.take<double4>(4 * N);
-    d.recf = cv.take<RecF>(N);
+    d.vel4 = cv.take<double4>(N);
+    d.thr4 = cv.take<double4>(N);
+    d.velf = cv.take<float4>(N);
+    d.thrf = cv.take<float4>(N);
     d.lcp = cv.take<signed char>(N + 1);
     d.lvl = cv.take<unsigned char>(N);
     d.scan_in = cv.take<u64>(N + 1);

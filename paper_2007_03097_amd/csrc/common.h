@@ -39,16 +39,6 @@ struct DevCtl {
     double diag[16];              // step diagnostics
 };
 
-// Records read by the neighbour-pair kernels, one per key-ordered particle, so that a
-// neighbour costs one cache line.  FP64 (PairRec layout in rec[4q .. 4q+3]):
-//   rec[4q]   = (x, y, z, h)      rec[4q+1] = (m, rho, P/rho^2, c)
-//   rec[4q+2] = (vx, vy, vz, u)   rec[4q+3] unused; v is the velocity the forces use.
-// FP32C: FP64 position (differences are formed in FP64) and FP32 everything else.
-struct RecF {
-    double x, y, z;
-    float h, m, rho, pr2, c, vx, vy, vz, u, pad;
-};
-
 // Device pointers of one context.  All arrays are carved out of the caller's workspace.
 struct DevPtrs {
     DevCtl* ctl;
@@ -70,8 +60,10 @@ struct DevPtrs {
     u32* id2;
     u32* inv;                     // caller index -> Morton position of the previous order
     double4* pos4;                // x, y, z, h (Morton order)
-    double4* rec;                 // 4 per particle (one 128-byte line): see PairRec
-    struct RecF* recf;            // one 64-byte FP32C record per particle
+    double4* vel4;                // vx(pred), vy, vz, m
+    double4* thr4;                // rho, P/rho^2, c, u
+    float4* velf;                 // FP32 copies for the compensated path: vx, vy, vz, m
+    float4* thrf;                 //   rho, P/rho^2, c, h
     // tree
     signed char* lcp;             // n_cap + 1: shared leading digits with the previous key
     unsigned char* lvl;           // n_cap: leaf level of each sorted position

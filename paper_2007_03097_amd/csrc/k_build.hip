@@ -458,14 +458,8 @@ __global__ void __launch_bounds__(256) k_gather_input(int n, const u32* __restri
     d.vx[q] = wx; d.vy[q] = wy; d.vz[q] = wz;
     d.m[q] = pm; d.h[q] = ph; d.u[q] = pu;
     d.pos4[q] = make_double4(px, py, pz, ph);
-    d.rec[4 * (size_t)q] = make_double4(px, py, pz, ph);
-    d.rec[4 * (size_t)q + 1] = make_double4(pm, 0.0, 0.0, 0.0);
-    d.rec[4 * (size_t)q + 2] = make_double4(wx, wy, wz, pu);
-    RecF f;
-    f.x = px; f.y = py; f.z = pz;
-    f.h = (float)ph; f.m = (float)pm; f.rho = 0.f; f.pr2 = 0.f; f.c = 0.f;
-    f.vx = (float)wx; f.vy = (float)wy; f.vz = (float)wz; f.u = (float)pu; f.pad = 0.f;
-    d.recf[q] = f;
+    d.vel4[q] = make_double4(wx, wy, wz, pm);
+    d.velf[q] = make_float4((float)wx, (float)wy, (float)wz, (float)pm);
     if (order_out) order_out[q] = (int64_t)i;
 }
 

@@ -63,29 +63,23 @@ void launch_step_permute(hipStream_t s, const DevPtrs& d, int n) {
     if (n > 0) hipLaunchKernelGGL(k_step_permute, g256(n), dim3(256), 0, s, n, d.val_a, d.inv, d);
 }
 
-// Records read by the tree, the walks and the pair kernels (predicted velocity and energy).
+// Records read by the pair kernels: pos4 = (x, h), vel4 = (predicted v, m).
 __global__ void k_pack_records(int n, const double* __restrict__ x, const double* __restrict__ y,
                                const double* __restrict__ z, const double* __restrict__ h,
                                const double* __restrict__ vx, const double* __restrict__ vy,
-                               const double* __restrict__ vz, const double* __restrict__ m,
-                               const double* __restrict__ u, double4* pos4, double4* rec, RecF* recf) {
+                               const double* __restrict__ vz, const double* __restrict__ m, double4* pos4,
+                               double4* vel4, float4* velf) {
     const int q = blockIdx.x * blockDim.x + threadIdx.x;
     if (q >= n) return;
-    const double mm = m[q], wx = vx[q], wy = vy[q], wz = vz[q], px = x[q], py = y[q], pz = z[q], ph = h[q], pu = u[q];
-    pos4[q] = make_double4(px, py, pz, ph);
-    rec[4 * (size_t)q] = make_double4(px, py, pz, ph);
-    rec[4 * (size_t)q + 1] = make_double4(mm, 0.0, 0.0, 0.0);
-    rec[4 * (size_t)q + 2] = make_double4(wx, wy, wz, pu);
-    RecF f;
-    f.x = px; f.y = py; f.z = pz;
-    f.h = (float)ph; f.m = (float)mm; f.rho = 0.f; f.pr2 = 0.f; f.c = 0.f;
-    f.vx = (float)wx; f.vy = (float)wy; f.vz = (float)wz; f.u = (float)pu; f.pad = 0.f;
-    recf[q] = f;
+    const double mm = m[q], wx = vx[q], wy = vy[q], wz = vz[q];
+    pos4[q] = make_double4(x[q], y[q], z[q], h[q]);
+    vel4[q] = make_double4(wx, wy, wz, mm);
+    velf[q] = make_float4((float)wx, (float)wy, (float)wz, (float)mm);
 }
 void launch_pack_records(hipStream_t s, const DevPtrs& d, int n) {
     if (n > 0)
         hipLaunchKernelGGL(k_pack_records, g256(n), dim3(256), 0, s, n, d.x, d.y, d.z, d.h, d.vpx, d.vpy, d.vpz, d.m,
-                           d.up, d.pos4, d.rec, d.recf);
+                           d.pos4, d.vel4, d.velf);
 }
 
 // v = v' + dt/2 a_new;  u = u' + dt/2 du_new;  optional lagged h update.
