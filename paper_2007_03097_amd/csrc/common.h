@@ -184,6 +184,67 @@ __device__ __forceinline__ int lcp_digits(u64 a, u64 b) {
 }
 
 // ---------------------------------------------------------------------------------------
+// M4 cubic spline (support 2h): W = w(q) / (pi h^3), grad_a W_ab = r_ab g(q) / (pi h^5),
+// g = w'(q) / q; and compensated FP32 accumulators.
+
+__device__ __forceinline__ double m4_w(double q) {
+    if (q < 1.0) return fma(q * q, fma(0.75, q, -1.5), 1.0);
+    if (q < 2.0) {
+        const double t = 2.0 - q;
+        return 0.25 * t * t * t;
+    }
+    return 0.0;
+}
+__device__ __forceinline__ double m4_g(double q) {
+    if (q < 1.0) return fma(2.25, q, -3.0);
+    if (q < 2.0) {
+        const double t = 2.0 - q;
+        return -0.75 * t * t / q;
+    }
+    return 0.0;
+}
+__device__ __forceinline__ float m4_wf(float q) {
+    if (q < 1.0f) return fmaf(q * q, fmaf(0.75f, q, -1.5f), 1.0f);
+    if (q < 2.0f) {
+        const float t = 2.0f - q;
+        return 0.25f * t * t * t;
+    }
+    return 0.0f;
+}
+__device__ __forceinline__ float m4_gf(float q, float inv_q) {
+    if (q < 1.0f) return fmaf(2.25f, q, -3.0f);
+    if (q < 2.0f) {
+        const float t = 2.0f - q;
+        return -0.75f * t * t * inv_q;
+    }
+    return 0.0f;
+}
+
+
+// Kahan / Neumaier accumulators (explicit operation order; the library is built without
+// floating-point contraction, so these are not fused).
+struct Kahan {
+    float s = 0.0f, c = 0.0f;
+    __device__ __forceinline__ void add(float x) {
+        const float y = x - c;
+        const float t = s + y;
+        c = (t - s) - y;
+        s = t;
+    }
+    __device__ __forceinline__ double value() const { return (double)s - (double)c; }
+};
+struct Neumaier {
+    float s = 0.0f, c = 0.0f;
+    __device__ __forceinline__ void add(float x) {
+        const float t = s + x;
+        c += (fabsf(s) >= fabsf(x)) ? ((s - t) + x) : ((x - t) + s);
+        s = t;
+    }
+    __device__ __forceinline__ double value() const { return (double)s + (double)c; }
+};
+
+
+// ---------------------------------------------------------------------------------------
 // Launchers (defined in the .hip files)
 
 // k_build.hip
@@ -206,13 +267,13 @@ void build_octree(hipStream_t s, const DevPtrs& d, const Dims& dm);
 void launch_tree_export(hipStream_t s, const DevPtrs& d, const Dims& dm, u64* key, int32_t* level,
                         int32_t* leaf, int64_t* start, int64_t* count);
 // k_walk.hip
-void launch_nbr_lists(hipStream_t s, const DevPtrs& d, const Dims& dm);
+// neighbour lists + density, EOS and h_next (u_eos: the energy the EOS uses)
+void launch_nbr_lists(hipStream_t s, const DevPtrs& d, const Dims& dm, int fp32c, double gamma, double h_coeff,
+                      const double* u_eos);
 void launch_csr_count(hipStream_t s, const DevPtrs& d, const Dims& dm, int64_t* counts_caller);
 void scan_i64_inplace(hipStream_t s, int64_t* a, int n, void* tmp);
 void launch_csr_fill(hipStream_t s, const DevPtrs& d, const Dims& dm, const int64_t* offsets, int32_t* idx);
 // k_sph.hip
-void launch_density(hipStream_t s, const DevPtrs& d, const Dims& dm, int fp32c, double gamma, double h_coeff,
-                    const double* u_eos);
 void launch_thermo_from_caller(hipStream_t s, const DevPtrs& d, const Dims& dm, const double* rho,
                                const double* P, const double* cs);
 void launch_forces(hipStream_t s, const DevPtrs& d, const Dims& dm, int fp32c, double alpha, double beta,

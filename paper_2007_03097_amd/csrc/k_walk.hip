@@ -1,6 +1,7 @@
 // Neighbour search (Sec. 2.1 of arXiv:2007.03097, last paragraph: the traversal runs for
-// a group of particles, prunes with the node bounds, and builds one neighbour list per
-// particle).
+// a group of particles, prunes with the node bounds, builds one neighbour list per particle
+// and calls the physics during the traversal) fused with the density sum, EOS and
+// adaptive smoothing length (Sec. 2.2.1, eqs. (7), (9)).
 //
 // One wavefront per target group (at most group_size consecutive particles of one compact
 // octree cell), in a persistent, XCD-aware loop over the groups.
@@ -15,7 +16,10 @@
 //  3. Candidate particles are staged 64 at a time in LDS; lane (t, phi) tests sources
 //     phi, phi + P, ... (P = 64 / group_size) for target t with the exact predicate
 //     fl(fl(fl(dx dx) + fl(dy dy)) + fl(dz dz)) < fl(t t), recording hits as bits; the
-//     P lanes of a target then take consecutive slot ranges and write their hits.
+//     P lanes of a target then take consecutive slot ranges and write their hits, adding
+//     each hit's density term m_b W(r_ab, h_ab) from the staged tile (self included).
+//  4. The P partial densities of a target are combined in a fixed butterfly order and the
+//     EOS, P/rho^2, c and h_next are written.
 // List layout: a group of n_g targets starting at sorted position s owns the block
 // nbr[s * nbr_cap, (s + n_g) * nbr_cap); slot k of target t is at s * nbr_cap + k * n_g + t,
 // so consumers reading slot k of consecutive targets read consecutive words, and the
@@ -26,14 +30,44 @@ constexpr int WALK_STACK = 512;
 constexpr int WALK_CAND = 256;
 
 
+// Density accumulator of one lane: FP64, or FP32 on FP64 position differences with Kahan
+// compensation.  One term is m_b w(r/h_ab) / h_ab^3 (the 1/pi is applied at the end).
+template <bool FP32C>
+struct DensAcc;
+template <>
+struct DensAcc<false> {
+    double s = 0.0;
+    __device__ __forceinline__ void add(const double4 me, const double4 b, double mb) {
+        const double dx = me.x - b.x, dy = me.y - b.y, dz = me.z - b.z;
+        const double r = sqrt(fma(dx, dx, fma(dy, dy, dz * dz)));
+        const double ih = 1.0 / (0.5 * (me.w + b.w));
+        s = fma(mb * m4_w(r * ih), ih * ih * ih, s);
+    }
+    __device__ __forceinline__ double value() const { return s; }
+};
+template <>
+struct DensAcc<true> {
+    Kahan k;
+    __device__ __forceinline__ void add(const double4 me, const double4 b, double mb) {
+        const float dx = (float)(me.x - b.x), dy = (float)(me.y - b.y), dz = (float)(me.z - b.z);
+        const float r = __builtin_amdgcn_sqrtf(fmaf(dx, dx, fmaf(dy, dy, dz * dz)));
+        const float ih = __builtin_amdgcn_rcpf(0.5f * ((float)me.w + (float)b.w));
+        k.add((float)mb * m4_wf(r * ih) * (ih * ih * ih));
+    }
+    __device__ __forceinline__ double value() const { return k.value(); }
+};
+
 // Exact predicate of every target of the group against the particles of the nc candidate
-// leaves in cand[] (node ids); hits are appended to the targets' lists.  cand[] is reused
-// as the leaves' first particles.  Per 64-source tile, lane (t, phi) tests sources
-// phi, phi + P, ... and records hits as bits; afterwards the P lanes of a target take
-// consecutive slot ranges (phi order) and write their hits in source order.
-__device__ void match_candidates(int nc, int* cand, int* coff, double4* tile, int* sidx,
-                                 const int4* __restrict__ topo, const double4* __restrict__ pos4, const double4 me,
-                                 bool tv, int t, int phi, int P, int gsz, int gy, int cap, int* mylist, int& cnt) {
+// leaves in cand[] (node ids); hits are appended to the targets' lists and summed into
+// their densities.  cand[] is reused as the leaves' first particles.  Per 64-source tile,
+// lane (t, phi) tests sources phi, phi + P, ... and records hits as bits; afterwards the P
+// lanes of a target take consecutive slot ranges (phi order) and, for each hit in source
+// order, write the list entry and add the density term from the staged tile.
+template <bool FP32C>
+__device__ void match_candidates(int nc, int* cand, int* coff, double4* tile, double* tmass, int* sidx,
+                                 const int4* __restrict__ topo, const double4* __restrict__ pos4,
+                                 const double* __restrict__ m, const double4 me, bool tv, int t, int phi, int P,
+                                 int gsz, int gy, int cap, int* mylist, int& cnt, DensAcc<FP32C>& dens) {
     const int lane = lane_id();
     int carry = 0;
     for (int j0 = 0; j0 < nc; j0 += 64) {
@@ -66,6 +100,7 @@ __device__ void match_candidates(int nc, int* cand, int* coff, double4* tile, in
             }
             const int src = cand[a] + (p - coff[a]);
             tile[lane] = pos4[src];
+            tmass[lane] = m[src];
             sidx[lane] = src;
         }
         __syncthreads();
@@ -94,26 +129,34 @@ __device__ void match_candidates(int nc, int* cand, int* coff, double4* tile, in
         while (bits) {
             const int it = __ffsll((long long)bits) - 1;
             bits &= bits - 1;
-            if (slot < cap) mylist[slot * gy + t] = sidx[it * P + phi];
+            const int j = it * P + phi;
+            if (slot < cap) mylist[slot * gy + t] = sidx[j];
             ++slot;
+            dens.add(me, tile[j], tmass[j]);
         }
         cnt += tot;
         __syncthreads();
     }
 }
 
+template <bool FP32C>
 __global__ void __launch_bounds__(64) k_nbr_lists(DevCtl* ctl, const int4* __restrict__ group, int gsz, int cap,
                                                   const int4* __restrict__ topo, const double4* __restrict__ nbox_lo,
                                                   const double4* __restrict__ nbox_hi, const double4* __restrict__ pos4,
-                                                  int* __restrict__ nbr, int* __restrict__ nbr_cnt,
-                                                  int* __restrict__ list_base) {
+                                                  const double* __restrict__ m, const double* __restrict__ u_eos,
+                                                  double gamma, double h_coeff, int* __restrict__ nbr,
+                                                  int* __restrict__ nbr_cnt, int* __restrict__ list_base,
+                                                  double* __restrict__ rho, double* __restrict__ P,
+                                                  double* __restrict__ cs, double* __restrict__ hnext,
+                                                  double4* __restrict__ thr4, float4* __restrict__ thrf) {
     __shared__ int stack[WALK_STACK];
     __shared__ int cand[WALK_CAND];
     __shared__ int coff[WALK_CAND + 1];
     __shared__ double4 tile[64];
+    __shared__ double tmass[64];
     __shared__ int sidx[64];
     const int lane = lane_id();
-    const int t = lane & (gsz - 1), phi = lane / gsz, P = 64 / gsz;
+    const int t = lane & (gsz - 1), phi = lane / gsz, PL = 64 / gsz;
     const u64 lt = lanemask_lt();
     int g0, g1, gstep;
     group_range(ctl->n_groups, g0, g1, gstep);
@@ -128,6 +171,7 @@ __global__ void __launch_bounds__(64) k_nbr_lists(DevCtl* ctl, const int4* __res
         const double hg = wave_max(tv ? me.w : 0.0);
         int* mylist = nbr + (size_t)g.x * (size_t)cap;
         int cnt = 0;
+        DensAcc<FP32C> dens;
         const int root = g.z < 0 ? 0 : ctl->level_off[3] + g.z;
         __syncthreads();
         if (lane == 0) stack[0] = root;
@@ -140,8 +184,8 @@ __global__ void __launch_bounds__(64) k_nbr_lists(DevCtl* ctl, const int4* __res
                 break;
             }
             if (nc + 64 > WALK_CAND) {
-                match_candidates(nc, cand, coff, tile, sidx, topo, pos4, me, tv, t, phi, P, gsz, g.y, cap, mylist,
-                                 cnt);
+                match_candidates<FP32C>(nc, cand, coff, tile, tmass, sidx, topo, pos4, m, me, tv, t, phi, PL, gsz,
+                                        g.y, cap, mylist, cnt, dens);
                 nc = 0;
             }
             // pop at most as many nodes as the free stack can take the children of (8 each)
@@ -181,24 +225,46 @@ __global__ void __launch_bounds__(64) k_nbr_lists(DevCtl* ctl, const int4* __res
         }
         __syncthreads();
         if (!overflow)
-            match_candidates(nc, cand, coff, tile, sidx, topo, pos4, me, tv, t, phi, P, gsz, g.y, cap, mylist, cnt);
+            match_candidates<FP32C>(nc, cand, coff, tile, tmass, sidx, topo, pos4, m, me, tv, t, phi, PL, gsz, g.y,
+                                    cap, mylist, cnt, dens);
         else if (lane == 0)
             set_err(ctl, ERR_WALK_STACK);
+        // density, EOS, next smoothing length (eqs. (7), (9))
+        const double acc = lanes_sum_d(dens.value(), gsz);
         if (tv && phi == 0) {
-            nbr_cnt[g.x + t] = overflow ? 0 : (cnt < cap ? cnt : cap);
-            list_base[g.x + t] = overflow ? -1 : gi;
+            const int q = g.x + t;
+            nbr_cnt[q] = overflow ? 0 : (cnt < cap ? cnt : cap);
+            list_base[q] = overflow ? -1 : gi;
             if (cnt > cap) {
                 set_err(ctl, ERR_NBR_CAP);
                 atomicMax(&ctl->nbr_max, cnt);
             }
+            const double r_ = acc * M_1_PI_D;
+            const double ue = u_eos[q];
+            const double p_ = (gamma - 1.0) * r_ * ue;
+            const double c_ = sqrt(gamma * p_ / r_);
+            const double pr2 = p_ / (r_ * r_);
+            rho[q] = r_;
+            P[q] = p_;
+            cs[q] = c_;
+            hnext[q] = h_coeff * cbrt(m[q] / r_);
+            thr4[q] = make_double4(r_, pr2, c_, ue);
+            thrf[q] = make_float4((float)r_, (float)pr2, (float)c_, (float)me.w);
         }
     }
 }
 
-void launch_nbr_lists(hipStream_t s, const DevPtrs& d, const Dims& dm) {
+void launch_nbr_lists(hipStream_t s, const DevPtrs& d, const Dims& dm, int fp32c, double gamma, double h_coeff,
+                      const double* u_eos) {
     if (dm.n <= 0) return;
-    hipLaunchKernelGGL(k_nbr_lists, dim3(dm.group_grid), dim3(64), 0, s, d.ctl, d.group, dm.group_size, dm.nbr_cap,
-                       d.topo, d.nbox_lo, d.nbox_hi, d.pos4, d.nbr, d.nbr_cnt, d.nbr_base);
+    if (fp32c)
+        hipLaunchKernelGGL(k_nbr_lists<true>, dim3(dm.group_grid), dim3(64), 0, s, d.ctl, d.group, dm.group_size,
+                           dm.nbr_cap, d.topo, d.nbox_lo, d.nbox_hi, d.pos4, d.m, u_eos, gamma, h_coeff, d.nbr,
+                           d.nbr_cnt, d.nbr_base, d.rho, d.P, d.cs, d.hnext, d.thr4, d.thrf);
+    else
+        hipLaunchKernelGGL(k_nbr_lists<false>, dim3(dm.group_grid), dim3(64), 0, s, d.ctl, d.group, dm.group_size,
+                           dm.nbr_cap, d.topo, d.nbox_lo, d.nbox_hi, d.pos4, d.m, u_eos, gamma, h_coeff, d.nbr,
+                           d.nbr_cnt, d.nbr_base, d.rho, d.P, d.cs, d.hnext, d.thr4, d.thrf);
 }
 
 // ---- CSR export in caller order (test and inspection path)
