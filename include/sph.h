@@ -139,17 +139,13 @@ sph_status sph_tree_nodes(sph_ctx* ctx, int64_t capacity, uint64_t* key, int32_t
  *   *total_host receives the number of entries; SPH_E_CAPACITY (nothing written to
  *   idx_out) if it exceeds capacity.  Either output may be NULL to only count.  With all
  *   three of offsets_out, idx_out and total_host NULL the call only (re)builds the device
- *   lists, asynchronously (used to time the list kernel).
- * The kernel that builds the lists also sums each particle's density, EOS and h_next over
- * the neighbours it finds (the values sph_compute_density returns). */
+ *   lists, asynchronously (used to time the list kernel). */
 sph_status sph_find_neighbors(sph_ctx* ctx, int64_t* offsets_out, int32_t* idx_out, int64_t capacity,
                               int64_t* total_host);
 
 /* Eq. (7) density with W_ab = W(r_ab, h_ab), h_ab = (h_a + h_b)/2, M4 cubic spline of
  * support 2h, self term included; ideal-gas EOS P = (gamma-1) rho u, c = sqrt(gamma P/rho);
- * eq. (9) h_next = h_coeff (m/rho)^(1/3).  The sums are taken by the neighbour-list kernel;
- * this call runs it if the lists of the last tree have not been built, or if the last
- * sph_compute_forces replaced the thermodynamic state with caller values.
+ * eq. (9) h_next = h_coeff (m/rho)^(1/3).  Builds neighbour lists if needed.
  * Outputs: device double[n] in caller order; any may be NULL (the values stay in the
  * workspace for sph_compute_forces either way). */
 sph_status sph_compute_density(sph_ctx* ctx, double* rho, double* P, double* cs, double* h_next);
@@ -158,9 +154,8 @@ sph_status sph_compute_density(sph_ctx* ctx, double* rho, double* P, double* cs,
  * grad_a W_ab and du_a/dt = sum_b m_b (P_a/rho_a^2 + Pi_ab/2) v_ab . grad_a W_ab, with the
  * Monaghan viscosity Pi_ab = (-alpha cbar mu + beta mu^2)/rhobar for v_ab . r_ab < 0,
  * mu = h_ab v_ab . r_ab / (r^2 + eps h_ab^2).  rho, P, cs: device double[n] in caller order,
- * or all NULL to use the density computed with the neighbour lists of the last tree
- * (SPH_E_STATE if the last call replaced it with caller values and no sph_compute_density
- * has run since).
+ * or all NULL to use the values of the last sph_compute_density (SPH_E_STATE if none
+ * since the last sph_build_tree, or if the last sph_compute_forces was given values).
  * Outputs: device double[n] in caller order; any may be NULL (not copied out). */
 sph_status sph_compute_forces(sph_ctx* ctx, const double* rho, const double* P, const double* cs,
                               double* ax, double* ay, double* az, double* dudt);

@@ -159,6 +159,8 @@ static size_t layout(const sph_ctx* c, char* base, DevPtrs* out) {
     d.nbr = cv.take<int>(NBR);
     d.nbr_cnt = cv.take<int>(N);
     d.nbr_base = cv.take<int>(N);
+    d.uni = cv.take<int>(NBR);
+    d.ucnt = cv.take<int>(GC);
     d.chunk = cv.take<int4>(CH);
     d.seg_root_rank = cv.take<int>(S);
     d.diag_part = cv.take<double>(16 * 256);
@@ -313,11 +315,10 @@ static sph_status build_from_caller(sph_ctx* c, const sph_particles* p, const do
 
 static sph_status ensure_lists(sph_ctx* c) {
     if (!c->tree_ok) return fail(c, SPH_E_STATE, "sph_build_tree has not been called");
-    if (!c->lists_ok) {  // the list kernel also sums density, EOS and h_next
-        const DevPtrs& d = c->d[c->parity];
-        launch_nbr_lists(c->stream, d, c->dm, c->cfg.precision == SPH_FP32C, c->cfg.gamma, c->cfg.h_coeff, d.u);
+    if (!c->lists_ok) {
+        launch_nbr_lists(c->stream, c->d[c->parity], c->dm);
         HIPCHK(c, hipGetLastError());
-        c->lists_ok = c->dens_ok = true;
+        c->lists_ok = true;
     }
     return SPH_OK;
 }
@@ -475,16 +476,17 @@ sph_status sph_find_neighbors(sph_ctx* c, int64_t* offsets_out, int32_t* idx_out
 
 sph_status sph_compute_density(sph_ctx* c, double* rho, double* P, double* cs, double* h_next) {
     if (!c) return SPH_E_ARG;
-    if (!c->dens_ok) c->lists_ok = false;  // caller thermo replaced the computed one
     sph_status st = ensure_lists(c);
     if (st != SPH_OK) return st;
     const DevPtrs& d = c->d[c->parity];
     const int n = c->dm.n;
+    launch_density(c->stream, d, c->dm, c->cfg.precision == SPH_FP32C, c->cfg.gamma, c->cfg.h_coeff, d.u);
     launch_scatter_caller(c->stream, d, n, d.rho, rho);
     launch_scatter_caller(c->stream, d, n, d.P, P);
     launch_scatter_caller(c->stream, d, n, d.cs, cs);
     launch_scatter_caller(c->stream, d, n, d.hnext, h_next);
     HIPCHK(c, hipGetLastError());
+    c->dens_ok = true;
     return SPH_OK;
 }
 
@@ -535,7 +537,8 @@ sph_status sph_compute_gravity(sph_ctx* c, double* gx, double* gy, double* gz, d
 // Accelerations of the resident state in buffer set p (tree already built).
 static void accel_pass(sph_ctx* c, hipStream_t s, const DevPtrs& d, const double* u_eos) {
     const int fp32c = c->cfg.precision == SPH_FP32C;
-    launch_nbr_lists(s, d, c->dm, fp32c, c->cfg.gamma, c->cfg.h_coeff, u_eos);
+    launch_nbr_lists(s, d, c->dm);
+    launch_density(s, d, c->dm, fp32c, c->cfg.gamma, c->cfg.h_coeff, u_eos);
     launch_forces(s, d, c->dm, fp32c, c->cfg.av_alpha, c->cfg.av_beta, c->cfg.av_eps, nullptr, nullptr, nullptr);
     if (c->cfg.G != 0.0) launch_gravity(s, d, c->dm, fp32c, c->cfg.G, c->cfg.soft_eps, c->cfg.theta, 1);
 }

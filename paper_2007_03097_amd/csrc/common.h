@@ -93,9 +93,11 @@ struct DevPtrs {
     int* gcell;                   // n_cap + 1: first sorted position of each group cell, then n
     u32* gnch;                    // n_cap + 1: groups per group cell
     u32* goff;                    // n_cap + 1
-    int* nbr;                     // group_cap * group_size * nbr_cap
+    int* nbr;                     // n_cap * nbr_cap: list slots, indices into the group's union
     int* nbr_cnt;                 // n_cap
     int* nbr_base;                // n_cap: group whose lists hold the particle (-1 = none)
+    int* uni;                     // n_cap * nbr_cap: per group, particles of its source union
+    int* ucnt;                    // group_cap: size of each group's union
     // seg / chunk tables
     int4* chunk;                  // chunk_cap: {begin, end, seg, 0} in caller/Morton order
     int* seg_root_rank;           // seg_cap: rank of the segment among non-empty segments
@@ -268,8 +270,9 @@ void launch_tree_export(hipStream_t s, const DevPtrs& d, const Dims& dm, u64* ke
                         int32_t* leaf, int64_t* start, int64_t* count);
 // k_walk.hip
 // neighbour lists + density, EOS and h_next (u_eos: the energy the EOS uses)
-void launch_nbr_lists(hipStream_t s, const DevPtrs& d, const Dims& dm, int fp32c, double gamma, double h_coeff,
-                      const double* u_eos);
+void launch_nbr_lists(hipStream_t s, const DevPtrs& d, const Dims& dm);
+void launch_density(hipStream_t s, const DevPtrs& d, const Dims& dm, int fp32c, double gamma, double h_coeff,
+                    const double* u_eos);
 void launch_csr_count(hipStream_t s, const DevPtrs& d, const Dims& dm, int64_t* counts_caller);
 void scan_i64_inplace(hipStream_t s, int64_t* a, int n, void* tmp);
 void launch_csr_fill(hipStream_t s, const DevPtrs& d, const Dims& dm, const int64_t* offsets, int32_t* idx);

@@ -1,21 +1,24 @@
-// SPH momentum and energy pair sums (Sec. 2.2.1 of arXiv:2007.03097).  The density, EOS and
-// h_next (eqs. (7), (9)) are summed inside the neighbour-list kernel (k_walk.hip).
-//
+// SPH pair sums (Sec. 2.2.1 of arXiv:2007.03097):
+//   density (eq. (7)):  rho_a = sum_b m_b W(r_ab, h_ab), self included; ideal-gas EOS
+//                       P = (gamma - 1) rho u, c = sqrt(gamma P / rho); h_next (eq. (9))
 //   momentum (eq. (6)): dv_a/dt = -sum_b m_b ((P_a/rho_a^2 + P_b/rho_b^2) + Pi_ab) grad_a W_ab
 //   energy (eq. (5)):   du_a/dt =  sum_b m_b (P_a/rho_a^2 + Pi_ab/2) v_ab . grad_a W_ab
 //   viscosity:          Pi_ab = (-alpha cbar mu + beta mu^2)/rhobar if v_ab . r_ab < 0,
 //                       mu = h_ab v_ab . r_ab / (r^2 + eps h_ab^2)
-// with the M4 cubic spline, grad_a W_ab = r_ab g(q)/(pi h^5), g = w'(q)/q.
+// with the M4 cubic spline, W = w(q)/(pi h^3), grad_a W_ab = r_ab g(q)/(pi h^5), g = w'(q)/q.
 //
-// One wavefront per group of group_size targets; target t is served by 64/group_size
-// lanes that take every (64/group_size)-th entry of its neighbour list, then combine in a
-// fixed butterfly order, so results are bitwise reproducible.  The pair sums are not a
-// dense contraction (each target has its own irregular list), so they run on the vector
-// ALUs, not on the matrix cores.
+// One 256-thread workgroup per target group, in a persistent, XCD-aware loop.  The group's
+// source union (built with the lists) is staged in LDS in chunks; target t is served by
+// 256/group_size threads that take every (256/group_size)-th entry of its list -- entries
+// are ascending union indices, so each thread walks its entries once across the chunks --
+// and read the source records from LDS.  The partial sums of a target are added in a
+// fixed order, so results are bitwise reproducible.  The pair sums are not a dense
+// contraction (each target has its own irregular list), so they run on the vector ALUs,
+// not on the matrix cores.
 //
 // FP32C: the position difference is formed in FP64 and rounded to FP32; everything else
-// of the pair term is FP32, summed per lane with Neumaier compensation; lanes combine in
-// FP64 and results are stored in FP64.
+// of the pair term is FP32, summed per thread with Kahan (density) or Neumaier (forces)
+// compensation; the partial sums combine in FP64 and results are stored in FP64.
 #include "common.h"
 
 // rho, P, c given by the caller (caller order) -> key-ordered thermo records
@@ -42,17 +45,49 @@ void launch_thermo_from_caller(hipStream_t s, const DevPtrs& d, const Dims& dm, 
                            cs, d.rho, d.P, d.cs, d.thr4, d.thrf);
 }
 
+constexpr int PAIR_THREADS = 256;
+constexpr int DENS_CHUNK = 512;
+constexpr int FORCE_CHUNK = 256;
+
+// Density term of one pair: FP64, or FP32 on the FP64 position difference with Kahan
+// compensation.  One term is m_b w(r/h_ab) / h_ab^3 (1/pi applied at the end).
 template <bool FP32C>
-__global__ void __launch_bounds__(64) k_forces(const DevCtl* __restrict__ ctl, const int4* __restrict__ group,
-                                               int gsz, int cap, const int* __restrict__ nbr,
-                                               const int* __restrict__ nbr_cnt, const double4* __restrict__ pos4,
-                                               const double4* __restrict__ vel4, const double4* __restrict__ thr4,
-                                               const float4* __restrict__ velf, const float4* __restrict__ thrf,
-                                               double alpha, double beta, double eps_av, double* __restrict__ ax,
-                                               double* __restrict__ ay, double* __restrict__ az,
-                                               double* __restrict__ du) {
-    const int lane = lane_id();
-    const int t = lane & (gsz - 1), phi = lane / gsz, P_ = 64 / gsz;
+struct DensAcc;
+template <>
+struct DensAcc<false> {
+    double s = 0.0;
+    __device__ __forceinline__ void add(const double4 me, const double4 b, double mb) {
+        const double dx = me.x - b.x, dy = me.y - b.y, dz = me.z - b.z;
+        const double r = sqrt(fma(dx, dx, fma(dy, dy, dz * dz)));
+        const double ih = 1.0 / (0.5 * (me.w + b.w));
+        s = fma(mb * m4_w(r * ih), ih * ih * ih, s);
+    }
+    __device__ __forceinline__ double value() const { return s; }
+};
+template <>
+struct DensAcc<true> {
+    Kahan k;
+    __device__ __forceinline__ void add(const double4 me, const double4 b, double mb) {
+        const float dx = (float)(me.x - b.x), dy = (float)(me.y - b.y), dz = (float)(me.z - b.z);
+        const float r = __builtin_amdgcn_sqrtf(fmaf(dx, dx, fmaf(dy, dy, dz * dz)));
+        const float ih = __builtin_amdgcn_rcpf(0.5f * ((float)me.w + (float)b.w));
+        k.add((float)mb * m4_wf(r * ih) * (ih * ih * ih));
+    }
+    __device__ __forceinline__ double value() const { return k.value(); }
+};
+
+template <bool FP32C>
+__global__ void __launch_bounds__(PAIR_THREADS) k_density(
+    const DevCtl* __restrict__ ctl, const int4* __restrict__ group, int gsz, int cap, const int* __restrict__ nbr,
+    const int* __restrict__ nbr_cnt, const int* __restrict__ uni, const int* __restrict__ ucnt,
+    const double4* __restrict__ pos4, const double4* __restrict__ vel4, const double* __restrict__ m,
+    const double* __restrict__ u_eos, double gamma, double h_coeff, double* __restrict__ rho,
+    double* __restrict__ P, double* __restrict__ cs, double* __restrict__ hnext, double4* __restrict__ thr4,
+    float4* __restrict__ thrf) {
+    __shared__ double4 spos[DENS_CHUNK];
+    __shared__ double smass[DENS_CHUNK];
+    const int tid = threadIdx.x;
+    const int t = tid & (gsz - 1), phi = tid / gsz, PL = PAIR_THREADS / gsz;
     int g0, g1, gstep;
     group_range(ctl->n_groups, g0, g1, gstep);
     for (int gi = g0; gi < g1; gi += gstep) {
@@ -62,35 +97,149 @@ __global__ void __launch_bounds__(64) k_forces(const DevCtl* __restrict__ ctl, c
         const double4 me = tv ? pos4[q] : make_double4(0, 0, 0, 1);
         const int cnt = tv ? nbr_cnt[q] : 0;
         const int* lst = nbr + (size_t)g.x * cap + t;
+        const int* un = uni + (size_t)g.x * cap;
+        const int nu = ucnt[gi];
+        DensAcc<FP32C> acc;
+        int k = phi;
+        int e = k < cnt ? lst[k * g.y] : INT_MAX;
+        for (int c0 = 0; c0 < nu; c0 += DENS_CHUNK) {
+            const int cn = nu - c0 < DENS_CHUNK ? nu - c0 : DENS_CHUNK;
+            __syncthreads();
+            for (int i = tid; i < cn; i += PAIR_THREADS) {
+                const int b = un[c0 + i];
+                spos[i] = pos4[b];
+                smass[i] = m[b];
+            }
+            __syncthreads();
+            const int ce = c0 + cn;
+            while (e < ce) {
+                const int kn = k + PL;
+                const int en = kn < cnt ? lst[kn * g.y] : INT_MAX;
+                acc.add(me, spos[e - c0], smass[e - c0]);
+                k = kn;
+                e = en;
+            }
+        }
+        __syncthreads();
+        double* red = reinterpret_cast<double*>(spos);
+        red[tid] = acc.value();
+        __syncthreads();
+        if (tv && phi == 0) {
+            double sum = red[t];
+            for (int f = 1; f < PL; ++f) sum += red[t + gsz * f];
+            const double r_ = sum * M_1_PI_D;
+            const double ue = u_eos[q];
+            const double p_ = (gamma - 1.0) * r_ * ue;
+            const double c_ = sqrt(gamma * p_ / r_);
+            const double pr2 = p_ / (r_ * r_);
+            rho[q] = r_;
+            P[q] = p_;
+            cs[q] = c_;
+            hnext[q] = h_coeff * cbrt(m[q] / r_);
+            thr4[q] = make_double4(r_, pr2, c_, ue);
+            thrf[q] = make_float4((float)r_, (float)pr2, (float)c_, (float)me.w);
+        }
+    }
+}
+
+void launch_density(hipStream_t s, const DevPtrs& d, const Dims& dm, int fp32c, double gamma, double h_coeff,
+                    const double* u_eos) {
+    if (dm.n <= 0) return;
+    if (fp32c)
+        hipLaunchKernelGGL(k_density<true>, dim3(dm.group_grid), dim3(PAIR_THREADS), 0, s, d.ctl, d.group,
+                           dm.group_size, dm.nbr_cap, d.nbr, d.nbr_cnt, d.uni, d.ucnt, d.pos4, d.vel4, d.m, u_eos,
+                           gamma, h_coeff, d.rho, d.P, d.cs, d.hnext, d.thr4, d.thrf);
+    else
+        hipLaunchKernelGGL(k_density<false>, dim3(dm.group_grid), dim3(PAIR_THREADS), 0, s, d.ctl, d.group,
+                           dm.group_size, dm.nbr_cap, d.nbr, d.nbr_cnt, d.uni, d.ucnt, d.pos4, d.vel4, d.m, u_eos,
+                           gamma, h_coeff, d.rho, d.P, d.cs, d.hnext, d.thr4, d.thrf);
+}
+
+// Source records in LDS for the force sums: FP64 (x, h), (v, m), (rho, P/rho^2, c), or
+// FP32C (x, h) in FP64 and (v, m), (rho, P/rho^2, c, h) in FP32.
+template <bool FP32C>
+struct ForceSrc;
+template <>
+struct ForceSrc<false> {
+    double4 pos[FORCE_CHUNK];
+    double4 vel[FORCE_CHUNK];
+    double4 thr[FORCE_CHUNK];
+};
+template <>
+struct ForceSrc<true> {
+    double4 pos[FORCE_CHUNK];
+    float4 vel[FORCE_CHUNK];
+    float4 thr[FORCE_CHUNK];
+};
+
+template <bool FP32C>
+__global__ void __launch_bounds__(PAIR_THREADS) k_forces(
+    const DevCtl* __restrict__ ctl, const int4* __restrict__ group, int gsz, int cap, const int* __restrict__ nbr,
+    const int* __restrict__ nbr_cnt, const int* __restrict__ uni, const int* __restrict__ ucnt,
+    const double4* __restrict__ pos4, const double4* __restrict__ vel4, const double4* __restrict__ thr4,
+    const float4* __restrict__ velf, const float4* __restrict__ thrf, double alpha, double beta, double eps_av,
+    double* __restrict__ ax, double* __restrict__ ay, double* __restrict__ az, double* __restrict__ du) {
+    __shared__ ForceSrc<FP32C> S;
+    const int tid = threadIdx.x;
+    const int t = tid & (gsz - 1), phi = tid / gsz, PL = PAIR_THREADS / gsz;
+    int g0, g1, gstep;
+    group_range(ctl->n_groups, g0, g1, gstep);
+    for (int gi = g0; gi < g1; gi += gstep) {
+        const int4 g = group[gi];
+        const bool tv = t < g.y;
+        const int q = g.x + t;
+        const double4 me = tv ? pos4[q] : make_double4(0, 0, 0, 1);
+        const int cnt = tv ? nbr_cnt[q] : 0;
+        const int* lst = nbr + (size_t)g.x * cap + t;
+        const int* un = uni + (size_t)g.x * cap;
+        const int nu = ucnt[gi];
+        int k = phi;
+        int e = k < cnt ? lst[k * g.y] : INT_MAX;
         double fx, fy, fz, fu;
         if (!FP32C) {
             const double4 mv = tv ? vel4[q] : make_double4(0, 0, 0, 0);
             const double4 mt = tv ? thr4[q] : make_double4(1, 0, 0, 0);
             double sx = 0, sy = 0, sz = 0, su = 0;
-            for (int k = phi; k < cnt; k += P_) {
-                const int b = lst[k * g.y];
-                const double4 sb = pos4[b];
-                const double4 vb = vel4[b];
-                const double4 tb = thr4[b];
-                const double dx = me.x - sb.x, dy = me.y - sb.y, dz = me.z - sb.z;
-                const double r2 = fma(dx, dx, fma(dy, dy, dz * dz));
-                const double r = sqrt(r2);
-                const double hab = 0.5 * (me.w + sb.w);
-                const double ih = 1.0 / hab;
-                const double ih2 = ih * ih;
-                const double gw = m4_g(r * ih) * (ih2 * ih2 * ih) * M_1_PI_D;
-                const double wx = mv.x - vb.x, wy = mv.y - vb.y, wz = mv.z - vb.z;
-                const double vr = fma(wx, dx, fma(wy, dy, wz * dz));
-                double Pi = 0.0;
-                if (vr < 0.0) {
-                    const double mu = hab * vr / fma(eps_av * hab, hab, r2);
-                    Pi = fma(-alpha * 0.5 * (mt.z + tb.z), mu, beta * mu * mu) / (0.5 * (mt.x + tb.x));
+            for (int c0 = 0; c0 < nu; c0 += FORCE_CHUNK) {
+                const int cn = nu - c0 < FORCE_CHUNK ? nu - c0 : FORCE_CHUNK;
+                __syncthreads();
+                for (int i = tid; i < cn; i += PAIR_THREADS) {
+                    const int b = un[c0 + i];
+                    S.pos[i] = pos4[b];
+                    reinterpret_cast<double4*>(S.vel)[i] = vel4[b];
+                    reinterpret_cast<double4*>(S.thr)[i] = thr4[b];
                 }
-                const double term = vb.w * ((mt.y + tb.y) + Pi) * gw;
-                sx = fma(-term, dx, sx);
-                sy = fma(-term, dy, sy);
-                sz = fma(-term, dz, sz);
-                su = fma(vb.w * fma(0.5, Pi, mt.y) * gw, vr, su);
+                __syncthreads();
+                const int ce = c0 + cn;
+                while (e < ce) {
+                    const int kn = k + PL;
+                    const int en = kn < cnt ? lst[kn * g.y] : INT_MAX;
+                    const int j = e - c0;
+                    const double4 sb = S.pos[j];
+                    const double4 vb = reinterpret_cast<const double4*>(S.vel)[j];
+                    const double4 tb = reinterpret_cast<const double4*>(S.thr)[j];
+                    const double dx = me.x - sb.x, dy = me.y - sb.y, dz = me.z - sb.z;
+                    const double r2 = fma(dx, dx, fma(dy, dy, dz * dz));
+                    const double r = sqrt(r2);
+                    const double hab = 0.5 * (me.w + sb.w);
+                    const double ih = 1.0 / hab;
+                    const double ih2 = ih * ih;
+                    const double gw = m4_g(r * ih) * (ih2 * ih2 * ih) * M_1_PI_D;
+                    const double wx = mv.x - vb.x, wy = mv.y - vb.y, wz = mv.z - vb.z;
+                    const double vr = fma(wx, dx, fma(wy, dy, wz * dz));
+                    double Pi = 0.0;
+                    if (vr < 0.0) {
+                        const double mu = hab * vr / fma(eps_av * hab, hab, r2);
+                        Pi = fma(-alpha * 0.5 * (mt.z + tb.z), mu, beta * mu * mu) / (0.5 * (mt.x + tb.x));
+                    }
+                    const double term = vb.w * ((mt.y + tb.y) + Pi) * gw;
+                    sx = fma(-term, dx, sx);
+                    sy = fma(-term, dy, sy);
+                    sz = fma(-term, dz, sz);
+                    su = fma(vb.w * fma(0.5, Pi, mt.y) * gw, vr, su);
+                    k = kn;
+                    e = en;
+                }
             }
             fx = sx; fy = sy; fz = sz; fu = su;
         } else {
@@ -99,43 +248,71 @@ __global__ void __launch_bounds__(64) k_forces(const DevCtl* __restrict__ ctl, c
             const float alf = (float)alpha, bef = (float)beta, epf = (float)eps_av;
             const float ipi = (float)M_1_PI_D;
             Neumaier sx, sy, sz, su;
-            for (int k = phi; k < cnt; k += P_) {
-                const int b = lst[k * g.y];
-                const double4 sb = pos4[b];
-                const float4 vb = velf[b];
-                const float4 tb = thrf[b];
-                const float dx = (float)(me.x - sb.x), dy = (float)(me.y - sb.y), dz = (float)(me.z - sb.z);
-                const float r2 = fmaf(dx, dx, fmaf(dy, dy, dz * dz));
-                const float r = __builtin_amdgcn_sqrtf(r2);
-                const float hab = 0.5f * (mt.w + tb.w);
-                const float ih = __builtin_amdgcn_rcpf(hab);
-                const float ih2 = ih * ih;
-                const float qq = r * ih;
-                const float gw = m4_gf(qq, __builtin_amdgcn_rcpf(qq)) * (ih2 * ih2 * ih) * ipi;
-                const float wx = mv.x - vb.x, wy = mv.y - vb.y, wz = mv.z - vb.z;
-                const float vr = fmaf(wx, dx, fmaf(wy, dy, wz * dz));
-                float Pi = 0.0f;
-                if (vr < 0.0f) {
-                    const float mu = hab * vr * __builtin_amdgcn_rcpf(fmaf(epf * hab, hab, r2));
-                    Pi = fmaf(-alf * 0.5f * (mt.z + tb.z), mu, bef * mu * mu) * __builtin_amdgcn_rcpf(0.5f * (mt.x + tb.x));
+            for (int c0 = 0; c0 < nu; c0 += FORCE_CHUNK) {
+                const int cn = nu - c0 < FORCE_CHUNK ? nu - c0 : FORCE_CHUNK;
+                __syncthreads();
+                for (int i = tid; i < cn; i += PAIR_THREADS) {
+                    const int b = un[c0 + i];
+                    S.pos[i] = pos4[b];
+                    reinterpret_cast<float4*>(S.vel)[i] = velf[b];
+                    reinterpret_cast<float4*>(S.thr)[i] = thrf[b];
                 }
-                const float term = vb.w * ((mt.y + tb.y) + Pi) * gw;
-                sx.add(-term * dx);
-                sy.add(-term * dy);
-                sz.add(-term * dz);
-                su.add(vb.w * fmaf(0.5f, Pi, mt.y) * gw * vr);
+                __syncthreads();
+                const int ce = c0 + cn;
+                while (e < ce) {
+                    const int kn = k + PL;
+                    const int en = kn < cnt ? lst[kn * g.y] : INT_MAX;
+                    const int j = e - c0;
+                    const double4 sb = S.pos[j];
+                    const float4 vb = reinterpret_cast<const float4*>(S.vel)[j];
+                    const float4 tb = reinterpret_cast<const float4*>(S.thr)[j];
+                    const float dx = (float)(me.x - sb.x), dy = (float)(me.y - sb.y), dz = (float)(me.z - sb.z);
+                    const float r2 = fmaf(dx, dx, fmaf(dy, dy, dz * dz));
+                    const float r = __builtin_amdgcn_sqrtf(r2);
+                    const float hab = 0.5f * (mt.w + tb.w);
+                    const float ih = __builtin_amdgcn_rcpf(hab);
+                    const float ih2 = ih * ih;
+                    const float qq = r * ih;
+                    const float gw = m4_gf(qq, __builtin_amdgcn_rcpf(qq)) * (ih2 * ih2 * ih) * ipi;
+                    const float wx = mv.x - vb.x, wy = mv.y - vb.y, wz = mv.z - vb.z;
+                    const float vr = fmaf(wx, dx, fmaf(wy, dy, wz * dz));
+                    float Pi = 0.0f;
+                    if (vr < 0.0f) {
+                        const float mu = hab * vr * __builtin_amdgcn_rcpf(fmaf(epf * hab, hab, r2));
+                        Pi = fmaf(-alf * 0.5f * (mt.z + tb.z), mu, bef * mu * mu) *
+                             __builtin_amdgcn_rcpf(0.5f * (mt.x + tb.x));
+                    }
+                    const float term = vb.w * ((mt.y + tb.y) + Pi) * gw;
+                    sx.add(-term * dx);
+                    sy.add(-term * dy);
+                    sz.add(-term * dz);
+                    su.add(vb.w * fmaf(0.5f, Pi, mt.y) * gw * vr);
+                    k = kn;
+                    e = en;
+                }
             }
             fx = sx.value(); fy = sy.value(); fz = sz.value(); fu = su.value();
         }
-        fx = lanes_sum_d(fx, gsz);
-        fy = lanes_sum_d(fy, gsz);
-        fz = lanes_sum_d(fz, gsz);
-        fu = lanes_sum_d(fu, gsz);
+        __syncthreads();
+        double* red = reinterpret_cast<double*>(S.pos);  // 4 x 256 doubles
+        red[tid] = fx;
+        red[PAIR_THREADS + tid] = fy;
+        red[2 * PAIR_THREADS + tid] = fz;
+        red[3 * PAIR_THREADS + tid] = fu;
+        __syncthreads();
         if (tv && phi == 0) {
-            ax[q] = fx;
-            ay[q] = fy;
-            az[q] = fz;
-            du[q] = fu;
+            double s0 = red[t], s1 = red[PAIR_THREADS + t], s2 = red[2 * PAIR_THREADS + t], s3 = red[3 * PAIR_THREADS + t];
+            for (int f = 1; f < PL; ++f) {
+                const int i = t + gsz * f;
+                s0 += red[i];
+                s1 += red[PAIR_THREADS + i];
+                s2 += red[2 * PAIR_THREADS + i];
+                s3 += red[3 * PAIR_THREADS + i];
+            }
+            ax[q] = s0;
+            ay[q] = s1;
+            az[q] = s2;
+            du[q] = s3;
         }
     }
 }
@@ -144,11 +321,11 @@ void launch_forces(hipStream_t s, const DevPtrs& d, const Dims& dm, int fp32c, d
                    double eps_av, const double*, const double*, const double*) {
     if (dm.n <= 0) return;
     if (fp32c)
-        hipLaunchKernelGGL(k_forces<true>, dim3(dm.group_grid), dim3(64), 0, s, d.ctl, d.group, dm.group_size,
-                           dm.nbr_cap, d.nbr, d.nbr_cnt, d.pos4, d.vel4, d.thr4, d.velf, d.thrf, alpha, beta, eps_av,
-                           d.ax, d.ay, d.az, d.du);
+        hipLaunchKernelGGL(k_forces<true>, dim3(dm.group_grid), dim3(PAIR_THREADS), 0, s, d.ctl, d.group,
+                           dm.group_size, dm.nbr_cap, d.nbr, d.nbr_cnt, d.uni, d.ucnt, d.pos4, d.vel4, d.thr4,
+                           d.velf, d.thrf, alpha, beta, eps_av, d.ax, d.ay, d.az, d.du);
     else
-        hipLaunchKernelGGL(k_forces<false>, dim3(dm.group_grid), dim3(64), 0, s, d.ctl, d.group, dm.group_size,
-                           dm.nbr_cap, d.nbr, d.nbr_cnt, d.pos4, d.vel4, d.thr4, d.velf, d.thrf, alpha, beta, eps_av,
-                           d.ax, d.ay, d.az, d.du);
+        hipLaunchKernelGGL(k_forces<false>, dim3(dm.group_grid), dim3(PAIR_THREADS), 0, s, d.ctl, d.group,
+                           dm.group_size, dm.nbr_cap, d.nbr, d.nbr_cnt, d.uni, d.ucnt, d.pos4, d.vel4, d.thr4,
+                           d.velf, d.thrf, alpha, beta, eps_av, d.ax, d.ay, d.az, d.du);
 }

@@ -1,7 +1,6 @@
 // Neighbour search (Sec. 2.1 of arXiv:2007.03097, last paragraph: the traversal runs for
-// a group of particles, prunes with the node bounds, builds one neighbour list per particle
-// and calls the physics during the traversal) fused with the density sum, EOS and
-// adaptive smoothing length (Sec. 2.2.1, eqs. (7), (9)).
+// a group of particles, prunes with the node bounds and builds one neighbour list per
+// particle).
 //
 // One wavefront per target group (at most group_size consecutive particles of one compact
 // octree cell), in a persistent, XCD-aware loop over the groups.
@@ -13,62 +12,32 @@
 //     leaves go to a candidate list, surviving internal nodes push their children.  The
 //     candidate list is matched (step 3) whenever it fills, so any number of candidates
 //     is handled with fixed LDS.
-//  3. Candidate particles are staged 64 at a time in LDS; lane (t, phi) tests sources
-//     phi, phi + P, ... (P = 64 / group_size) for target t with the exact predicate
-//     fl(fl(fl(dx dx) + fl(dy dy)) + fl(dz dz)) < fl(t t), recording hits as bits; the
-//     P lanes of a target then take consecutive slot ranges and write their hits, adding
-//     each hit's density term m_b W(r_ab, h_ab) from the staged tile (self included).
-//  4. The P partial densities of a target are combined in a fixed butterfly order and the
-//     EOS, P/rho^2, c and h_next are written.
-// List layout: a group of n_g targets starting at sorted position s owns the block
-// nbr[s * nbr_cap, (s + n_g) * nbr_cap); slot k of target t is at s * nbr_cap + k * n_g + t,
-// so consumers reading slot k of consecutive targets read consecutive words, and the
-// blocks of all groups tile exactly n * nbr_cap words.
+//  3. Candidate particles are staged 64 at a time in LDS; lane (t, phi) tests the block of
+//     sources phi*G .. phi*G + G - 1 (G = group_size, P = 64/G lanes per target) for
+//     target t with the exact predicate fl(fl(fl(dx dx) + fl(dy dy)) + fl(dz dz)) < fl(t t),
+//     recording hits as bits.  The OR of all lanes' bits is the tile's part of the group's
+//     source union U (sources that are a neighbour of at least one target), appended to
+//     U in staging order.  The P lanes of a target then take consecutive slot ranges and
+//     write, for each hit, the source's index in U.
+// Outputs per group (n_g targets starting at sorted position s):
+//   uni[s*cap + i], i < ucnt[group]: particle index of the i-th member of U;
+//   nbr[s*cap + k*n_g + t]: slot k of target t, an index into U, ascending in k; the blocks
+//   of all groups tile exactly n * cap words, and consumers reading slot k of consecutive
+//   targets read consecutive words.
+// The pair kernels stage U in LDS and read their sources there.
 #include "common.h"
 
 constexpr int WALK_STACK = 512;
 constexpr int WALK_CAND = 256;
 
-
-// Density accumulator of one lane: FP64, or FP32 on FP64 position differences with Kahan
-// compensation.  One term is m_b w(r/h_ab) / h_ab^3 (the 1/pi is applied at the end).
-template <bool FP32C>
-struct DensAcc;
-template <>
-struct DensAcc<false> {
-    double s = 0.0;
-    __device__ __forceinline__ void add(const double4 me, const double4 b, double mb) {
-        const double dx = me.x - b.x, dy = me.y - b.y, dz = me.z - b.z;
-        const double r = sqrt(fma(dx, dx, fma(dy, dy, dz * dz)));
-        const double ih = 1.0 / (0.5 * (me.w + b.w));
-        s = fma(mb * m4_w(r * ih), ih * ih * ih, s);
-    }
-    __device__ __forceinline__ double value() const { return s; }
-};
-template <>
-struct DensAcc<true> {
-    Kahan k;
-    __device__ __forceinline__ void add(const double4 me, const double4 b, double mb) {
-        const float dx = (float)(me.x - b.x), dy = (float)(me.y - b.y), dz = (float)(me.z - b.z);
-        const float r = __builtin_amdgcn_sqrtf(fmaf(dx, dx, fmaf(dy, dy, dz * dz)));
-        const float ih = __builtin_amdgcn_rcpf(0.5f * ((float)me.w + (float)b.w));
-        k.add((float)mb * m4_wf(r * ih) * (ih * ih * ih));
-    }
-    __device__ __forceinline__ double value() const { return k.value(); }
-};
-
 // Exact predicate of every target of the group against the particles of the nc candidate
-// leaves in cand[] (node ids); hits are appended to the targets' lists and summed into
-// their densities.  cand[] is reused as the leaves' first particles.  Per 64-source tile,
-// lane (t, phi) tests sources phi, phi + P, ... and records hits as bits; afterwards the P
-// lanes of a target take consecutive slot ranges (phi order) and, for each hit in source
-// order, write the list entry and add the density term from the staged tile.
-template <bool FP32C>
-__device__ void match_candidates(int nc, int* cand, int* coff, double4* tile, double* tmass, int* sidx,
-                                 const int4* __restrict__ topo, const double4* __restrict__ pos4,
-                                 const double* __restrict__ m, const double4 me, bool tv, int t, int phi, int P,
-                                 int gsz, int gy, int cap, int* mylist, int& cnt, DensAcc<FP32C>& dens) {
+// leaves in cand[] (node ids); hits are appended to the union and to the targets' lists.
+// cand[] is reused as the leaves' first particles.
+__device__ void match_candidates(int nc, int* cand, int* coff, double4* tile, const int4* __restrict__ topo,
+                                 const double4* __restrict__ pos4, const double4 me, bool tv, int t, int phi,
+                                 int gsz, int gy, int cap, int* mylist, int* myuni, int ulim, int& cnt, int& ucnt) {
     const int lane = lane_id();
+    const u64 lt = lanemask_lt();
     int carry = 0;
     for (int j0 = 0; j0 < nc; j0 += 64) {
         const int j = j0 + lane;
@@ -91,6 +60,7 @@ __device__ void match_candidates(int nc, int* cand, int* coff, double4* tile, do
     const int total = carry;
     for (int p0 = 0; p0 < total; p0 += 64) {
         const int p = p0 + lane;
+        int src = -1;
         if (p < total) {
             int a = 0, b = nc - 1;
             while (a < b) {  // largest j with coff[j] <= p
@@ -98,24 +68,30 @@ __device__ void match_candidates(int nc, int* cand, int* coff, double4* tile, do
                 if (coff[mid] <= p) a = mid;
                 else b = mid - 1;
             }
-            const int src = cand[a] + (p - coff[a]);
+            src = cand[a] + (p - coff[a]);
             tile[lane] = pos4[src];
-            tmass[lane] = m[src];
-            sidx[lane] = src;
         }
         __syncthreads();
         const int tn = total - p0 < 64 ? total - p0 : 64;
         u64 bits = 0;
         if (tv) {
-            int it = 0;
-            for (int j = phi; j < tn; j += P, ++it) {
-                const double4 b = tile[j];
+            const int j0 = phi * gsz;
+            const int je = tn - j0 < gsz ? tn - j0 : gsz;
+            for (int it = 0; it < je; ++it) {
+                const double4 b = tile[j0 + it];
                 const double dx = me.x - b.x, dy = me.y - b.y, dz = me.z - b.z;
                 double r2 = dx * dx + dy * dy;
                 r2 = r2 + dz * dz;
                 const double tt = me.w + b.w;
                 if (r2 < tt * tt) bits |= 1ull << it;
             }
+        }
+        // union of the tile, bit j = staged source j
+        u64 ub = bits << (phi * gsz);
+        for (int d = 1; d < 64; d <<= 1) ub |= __shfl_xor(ub, d, 64);
+        if ((ub >> lane) & 1ull) {
+            const int r = ucnt + __popcll(ub & lt);
+            if (r < ulim) myuni[r] = src;
         }
         // slot ranges of the P lanes of each target (lanes t, t + gsz, ...), in phi order
         const int mine = __popcll(bits);
@@ -124,39 +100,33 @@ __device__ void match_candidates(int nc, int* cand, int* coff, double4* tile, do
             const int v = __shfl_up(incl, d, 64);
             if (lane >= d) incl += v;
         }
-        const int tot = __shfl(incl, t + gsz * (P - 1), 64);
+        const int tot = __shfl(incl, t + gsz * (64 / gsz - 1), 64);
         int slot = cnt + incl - mine;
         while (bits) {
             const int it = __ffsll((long long)bits) - 1;
             bits &= bits - 1;
-            const int j = it * P + phi;
-            if (slot < cap) mylist[slot * gy + t] = sidx[j];
+            const int j = phi * gsz + it;
+            if (slot < cap) mylist[slot * gy + t] = ucnt + __popcll(ub & ((1ull << j) - 1ull));
             ++slot;
-            dens.add(me, tile[j], tmass[j]);
         }
         cnt += tot;
+        ucnt += __popcll(ub);
         __syncthreads();
     }
 }
 
-template <bool FP32C>
 __global__ void __launch_bounds__(64) k_nbr_lists(DevCtl* ctl, const int4* __restrict__ group, int gsz, int cap,
                                                   const int4* __restrict__ topo, const double4* __restrict__ nbox_lo,
                                                   const double4* __restrict__ nbox_hi, const double4* __restrict__ pos4,
-                                                  const double* __restrict__ m, const double* __restrict__ u_eos,
-                                                  double gamma, double h_coeff, int* __restrict__ nbr,
-                                                  int* __restrict__ nbr_cnt, int* __restrict__ list_base,
-                                                  double* __restrict__ rho, double* __restrict__ P,
-                                                  double* __restrict__ cs, double* __restrict__ hnext,
-                                                  double4* __restrict__ thr4, float4* __restrict__ thrf) {
+                                                  int* __restrict__ nbr, int* __restrict__ nbr_cnt,
+                                                  int* __restrict__ list_base, int* __restrict__ uni,
+                                                  int* __restrict__ ucnt_out) {
     __shared__ int stack[WALK_STACK];
     __shared__ int cand[WALK_CAND];
     __shared__ int coff[WALK_CAND + 1];
     __shared__ double4 tile[64];
-    __shared__ double tmass[64];
-    __shared__ int sidx[64];
     const int lane = lane_id();
-    const int t = lane & (gsz - 1), phi = lane / gsz, PL = 64 / gsz;
+    const int t = lane & (gsz - 1), phi = lane / gsz;
     const u64 lt = lanemask_lt();
     int g0, g1, gstep;
     group_range(ctl->n_groups, g0, g1, gstep);
@@ -170,8 +140,9 @@ __global__ void __launch_bounds__(64) k_nbr_lists(DevCtl* ctl, const int4* __res
         lo[2] = wave_min(tv ? me.z : INFINITY); hi[2] = wave_max(tv ? me.z : -INFINITY);
         const double hg = wave_max(tv ? me.w : 0.0);
         int* mylist = nbr + (size_t)g.x * (size_t)cap;
-        int cnt = 0;
-        DensAcc<FP32C> dens;
+        int* myuni = uni + (size_t)g.x * (size_t)cap;
+        const int ulim = g.y * cap;
+        int cnt = 0, ucnt = 0;
         const int root = g.z < 0 ? 0 : ctl->level_off[3] + g.z;
         __syncthreads();
         if (lane == 0) stack[0] = root;
@@ -184,8 +155,8 @@ __global__ void __launch_bounds__(64) k_nbr_lists(DevCtl* ctl, const int4* __res
                 break;
             }
             if (nc + 64 > WALK_CAND) {
-                match_candidates<FP32C>(nc, cand, coff, tile, tmass, sidx, topo, pos4, m, me, tv, t, phi, PL, gsz,
-                                        g.y, cap, mylist, cnt, dens);
+                match_candidates(nc, cand, coff, tile, topo, pos4, me, tv, t, phi, gsz, g.y, cap, mylist, myuni,
+                                 ulim, cnt, ucnt);
                 nc = 0;
             }
             // pop at most as many nodes as the free stack can take the children of (8 each)
@@ -225,12 +196,11 @@ __global__ void __launch_bounds__(64) k_nbr_lists(DevCtl* ctl, const int4* __res
         }
         __syncthreads();
         if (!overflow)
-            match_candidates<FP32C>(nc, cand, coff, tile, tmass, sidx, topo, pos4, m, me, tv, t, phi, PL, gsz, g.y,
-                                    cap, mylist, cnt, dens);
+            match_candidates(nc, cand, coff, tile, topo, pos4, me, tv, t, phi, gsz, g.y, cap, mylist, myuni, ulim,
+                             cnt, ucnt);
         else if (lane == 0)
             set_err(ctl, ERR_WALK_STACK);
-        // density, EOS, next smoothing length (eqs. (7), (9))
-        const double acc = lanes_sum_d(dens.value(), gsz);
+        if (lane == 0) ucnt_out[gi] = overflow ? 0 : (ucnt < ulim ? ucnt : ulim);
         if (tv && phi == 0) {
             const int q = g.x + t;
             nbr_cnt[q] = overflow ? 0 : (cnt < cap ? cnt : cap);
@@ -239,32 +209,14 @@ __global__ void __launch_bounds__(64) k_nbr_lists(DevCtl* ctl, const int4* __res
                 set_err(ctl, ERR_NBR_CAP);
                 atomicMax(&ctl->nbr_max, cnt);
             }
-            const double r_ = acc * M_1_PI_D;
-            const double ue = u_eos[q];
-            const double p_ = (gamma - 1.0) * r_ * ue;
-            const double c_ = sqrt(gamma * p_ / r_);
-            const double pr2 = p_ / (r_ * r_);
-            rho[q] = r_;
-            P[q] = p_;
-            cs[q] = c_;
-            hnext[q] = h_coeff * cbrt(m[q] / r_);
-            thr4[q] = make_double4(r_, pr2, c_, ue);
-            thrf[q] = make_float4((float)r_, (float)pr2, (float)c_, (float)me.w);
         }
     }
 }
 
-void launch_nbr_lists(hipStream_t s, const DevPtrs& d, const Dims& dm, int fp32c, double gamma, double h_coeff,
-                      const double* u_eos) {
+void launch_nbr_lists(hipStream_t s, const DevPtrs& d, const Dims& dm) {
     if (dm.n <= 0) return;
-    if (fp32c)
-        hipLaunchKernelGGL(k_nbr_lists<true>, dim3(dm.group_grid), dim3(64), 0, s, d.ctl, d.group, dm.group_size,
-                           dm.nbr_cap, d.topo, d.nbox_lo, d.nbox_hi, d.pos4, d.m, u_eos, gamma, h_coeff, d.nbr,
-                           d.nbr_cnt, d.nbr_base, d.rho, d.P, d.cs, d.hnext, d.thr4, d.thrf);
-    else
-        hipLaunchKernelGGL(k_nbr_lists<false>, dim3(dm.group_grid), dim3(64), 0, s, d.ctl, d.group, dm.group_size,
-                           dm.nbr_cap, d.topo, d.nbox_lo, d.nbox_hi, d.pos4, d.m, u_eos, gamma, h_coeff, d.nbr,
-                           d.nbr_cnt, d.nbr_base, d.rho, d.P, d.cs, d.hnext, d.thr4, d.thrf);
+    hipLaunchKernelGGL(k_nbr_lists, dim3(dm.group_grid), dim3(64), 0, s, d.ctl, d.group, dm.group_size, dm.nbr_cap,
+                       d.topo, d.nbox_lo, d.nbox_hi, d.pos4, d.nbr, d.nbr_cnt, d.nbr_base, d.uni, d.ucnt);
 }
 
 // ---- CSR export in caller order (test and inspection path)
@@ -280,16 +232,17 @@ void launch_csr_count(hipStream_t s, const DevPtrs& d, const Dims& dm, int64_t* 
 
 __global__ void k_csr_fill(int n, int gsz, int cap, const int4* __restrict__ group, const u32* __restrict__ id,
                            const int* __restrict__ cnt, const int* __restrict__ gidx, const int* __restrict__ nbr,
-                           const int64_t* __restrict__ off, int32_t* idx) {
+                           const int* __restrict__ uni, const int64_t* __restrict__ off, int32_t* idx) {
     const int q = blockIdx.x * blockDim.x + threadIdx.x;
     if (q >= n) return;
     const int c = cnt[q], g = gidx[q];
     if (g < 0) return;
     const int4 gr = group[g];
     const int* lst = nbr + (size_t)gr.x * cap + (q - gr.x);
+    const int* un = uni + (size_t)gr.x * cap;
     int32_t* out = idx + off[id[q]];
     for (int k = 0; k < c; ++k) {   // insertion sort by caller index while copying
-        const int32_t v = (int32_t)id[lst[k * gr.y]];
+        const int32_t v = (int32_t)id[un[lst[k * gr.y]]];
         int j = k;
         while (j > 0 && out[j - 1] > v) {
             out[j] = out[j - 1];
@@ -301,5 +254,5 @@ __global__ void k_csr_fill(int n, int gsz, int cap, const int4* __restrict__ gro
 
 void launch_csr_fill(hipStream_t s, const DevPtrs& d, const Dims& dm, const int64_t* offsets, int32_t* idx) {
     if (dm.n > 0) hipLaunchKernelGGL(k_csr_fill, dim3((dm.n + 255) / 256), dim3(256), 0, s, dm.n, dm.group_size,
-                                     dm.nbr_cap, d.group, d.id, d.nbr_cnt, d.nbr_base, d.nbr, offsets, idx);
+                                     dm.nbr_cap, d.group, d.id, d.nbr_cnt, d.nbr_base, d.nbr, d.uni, offsets, idx);
 }
