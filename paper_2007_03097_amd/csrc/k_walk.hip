@@ -12,10 +12,11 @@
 //     leaves go to a candidate list, surviving internal nodes push their children.  The
 //     candidate list is matched (step 3) whenever it fills, so any number of candidates
 //     is handled with fixed LDS.
-//  3. Candidate particles are staged 64 at a time in LDS; lane (t, phi) tests the block of
-//     sources phi*G .. phi*G + G - 1 (G = group_size, P = 64/G lanes per target) for
-//     target t with the exact predicate fl(fl(fl(dx dx) + fl(dy dy)) + fl(dz dz)) < fl(t t),
-//     recording hits as bits.  The OR of all lanes' bits is the tile's part of the group's
+//  3. Each candidate particle is tested against the group box (conservatively, as the
+//     nodes are); survivors are staged in an LDS ring and matched 64 at a time: lane
+//     (t, phi) tests the block of sources phi*G .. phi*G + G - 1 (G = group_size, P = 64/G
+//     lanes per target) for target t with the exact predicate
+//     fl(fl(fl(dx dx) + fl(dy dy)) + fl(dz dz)) < fl(t t), recording hits as bits.  The OR of all lanes' bits is the tile's part of the group's
 //     source union U (sources that are a neighbour of at least one target), appended to
 //     U in staging order.  The P lanes of a target then take consecutive slot ranges and
 //     write, for each hit, the source's index in U.
@@ -30,12 +31,71 @@
 constexpr int WALK_STACK = 512;
 constexpr int WALK_CAND = 256;
 
-// Exact predicate of every target of the group against the particles of the nc candidate
-// leaves in cand[] (node ids); hits are appended to the union and to the targets' lists.
-// cand[] is reused as the leaves' first particles.
-__device__ void match_candidates(int nc, int* cand, int* coff, double4* tile, const int4* __restrict__ topo,
+constexpr int TILE_RING = 128;
+
+// Group-level state of the matching step.
+struct GroupBox {
+    double lo[3], hi[3], hg;
+};
+
+// Exact predicate for the 64 (or, at the end, fewer) filtered sources at ring positions
+// head .. head + tn - 1: lane (t, phi) tests ring entries head + phi*G + it, it < G, for
+// target t; hits go to the union and to the target's list.
+__device__ __forceinline__ void test_tile(int head, int tn, const double4* tile, const int* tsrc, const double4 me,
+                                          bool tv, int t, int phi, int gsz, int gy, int cap, int* mylist,
+                                          int* myuni, int ulim, int& cnt, int& ucnt) {
+    const int lane = lane_id();
+    u64 bits = 0;
+    if (tv) {
+        const int j0 = phi * gsz;
+        const int je = tn - j0 < gsz ? tn - j0 : gsz;
+        for (int it = 0; it < je; ++it) {
+            const double4 b = tile[(head + j0 + it) & (TILE_RING - 1)];
+            const double dx = me.x - b.x, dy = me.y - b.y, dz = me.z - b.z;
+            double r2 = dx * dx + dy * dy;
+            r2 = r2 + dz * dz;
+            const double tt = me.w + b.w;
+            if (r2 < tt * tt) bits |= 1ull << it;
+        }
+    }
+    // union of the tile, bit j = ring entry head + j
+    u64 ub = bits << (phi * gsz);
+    for (int d = 1; d < 64; d <<= 1) ub |= __shfl_xor(ub, d, 64);
+    if ((ub >> lane) & 1ull) {
+        const int r = ucnt + __popcll(ub & lanemask_lt());
+        if (r < ulim) myuni[r] = tsrc[(head + lane) & (TILE_RING - 1)];
+    }
+    // slot ranges of the P lanes of each target (lanes t, t + gsz, ...), in phi order
+    const int mine = __popcll(bits);
+    int incl = mine;
+    for (int d = gsz; d < 64; d <<= 1) {
+        const int v = __shfl_up(incl, d, 64);
+        if (lane >= d) incl += v;
+    }
+    const int tot = __shfl(incl, t + gsz * (64 / gsz - 1), 64);
+    int slot = cnt + incl - mine;
+    while (bits) {
+        const int it = __ffsll((long long)bits) - 1;
+        bits &= bits - 1;
+        const int j = phi * gsz + it;
+        if (slot < cap) mylist[slot * gy + t] = ucnt + __popcll(ub & ((1ull << j) - 1ull));
+        ++slot;
+    }
+    cnt += tot;
+    ucnt += __popcll(ub);
+}
+
+// Matching of the group's targets against the particles of the nc candidate leaves in
+// cand[] (node ids; reused for the leaves' first particles).  Each candidate particle is
+// first tested against the group box, in the same monotone operation order as the node
+// test (gap^2 < (hmax_group + h_b)^2), so no true neighbour is dropped; survivors enter an
+// LDS ring and are matched 64 at a time.  Sources left in the ring (< 64) are matched by
+// the caller's final flush.
+__device__ void match_candidates(int nc, int* cand, int* coff, double4* tile, int* tsrc, int& head, int& tail,
+                                 const GroupBox& gb, const int4* __restrict__ topo,
                                  const double4* __restrict__ pos4, const double4 me, bool tv, int t, int phi,
-                                 int gsz, int gy, int cap, int* mylist, int* myuni, int ulim, int& cnt, int& ucnt) {
+                                 int gsz, int gy, int cap, int* mylist, int* myuni, int ulim, int& cnt,
+                                 int& ucnt) {
     const int lane = lane_id();
     const u64 lt = lanemask_lt();
     int carry = 0;
@@ -60,57 +120,38 @@ __device__ void match_candidates(int nc, int* cand, int* coff, double4* tile, co
     const int total = carry;
     for (int p0 = 0; p0 < total; p0 += 64) {
         const int p = p0 + lane;
-        int src = -1;
+        bool pass = false;
+        int src = 0;
+        double4 b = make_double4(0, 0, 0, 0);
         if (p < total) {
-            int a = 0, b = nc - 1;
-            while (a < b) {  // largest j with coff[j] <= p
-                const int mid = (a + b + 1) >> 1;
+            int a = 0, bb = nc - 1;
+            while (a < bb) {  // largest j with coff[j] <= p
+                const int mid = (a + bb + 1) >> 1;
                 if (coff[mid] <= p) a = mid;
-                else b = mid - 1;
+                else bb = mid - 1;
             }
             src = cand[a] + (p - coff[a]);
-            tile[lane] = pos4[src];
+            b = pos4[src];
+            const double gx = fmax(0.0, fmax(b.x - gb.hi[0], gb.lo[0] - b.x));
+            const double gy2 = fmax(0.0, fmax(b.y - gb.hi[1], gb.lo[1] - b.y));
+            const double gz = fmax(0.0, fmax(b.z - gb.hi[2], gb.lo[2] - b.z));
+            double r2 = gx * gx + gy2 * gy2;
+            r2 = r2 + gz * gz;
+            const double tt = gb.hg + b.w;
+            pass = r2 < tt * tt;
         }
+        const u64 bal = __ballot(pass);
+        if (pass) {
+            const int r = (tail + __popcll(bal & lt)) & (TILE_RING - 1);
+            tile[r] = b;
+            tsrc[r] = src;
+        }
+        tail += __popcll(bal);
         __syncthreads();
-        const int tn = total - p0 < 64 ? total - p0 : 64;
-        u64 bits = 0;
-        if (tv) {
-            const int j0 = phi * gsz;
-            const int je = tn - j0 < gsz ? tn - j0 : gsz;
-            for (int it = 0; it < je; ++it) {
-                const double4 b = tile[j0 + it];
-                const double dx = me.x - b.x, dy = me.y - b.y, dz = me.z - b.z;
-                double r2 = dx * dx + dy * dy;
-                r2 = r2 + dz * dz;
-                const double tt = me.w + b.w;
-                if (r2 < tt * tt) bits |= 1ull << it;
-            }
+        if (tail - head >= 64) {
+            test_tile(head, 64, tile, tsrc, me, tv, t, phi, gsz, gy, cap, mylist, myuni, ulim, cnt, ucnt);
+            head += 64;
         }
-        // union of the tile, bit j = staged source j
-        u64 ub = bits << (phi * gsz);
-        for (int d = 1; d < 64; d <<= 1) ub |= __shfl_xor(ub, d, 64);
-        if ((ub >> lane) & 1ull) {
-            const int r = ucnt + __popcll(ub & lt);
-            if (r < ulim) myuni[r] = src;
-        }
-        // slot ranges of the P lanes of each target (lanes t, t + gsz, ...), in phi order
-        const int mine = __popcll(bits);
-        int incl = mine;
-        for (int d = gsz; d < 64; d <<= 1) {
-            const int v = __shfl_up(incl, d, 64);
-            if (lane >= d) incl += v;
-        }
-        const int tot = __shfl(incl, t + gsz * (64 / gsz - 1), 64);
-        int slot = cnt + incl - mine;
-        while (bits) {
-            const int it = __ffsll((long long)bits) - 1;
-            bits &= bits - 1;
-            const int j = phi * gsz + it;
-            if (slot < cap) mylist[slot * gy + t] = ucnt + __popcll(ub & ((1ull << j) - 1ull));
-            ++slot;
-        }
-        cnt += tot;
-        ucnt += __popcll(ub);
         __syncthreads();
     }
 }
@@ -124,7 +165,8 @@ __global__ void __launch_bounds__(64) k_nbr_lists(DevCtl* ctl, const int4* __res
     __shared__ int stack[WALK_STACK];
     __shared__ int cand[WALK_CAND];
     __shared__ int coff[WALK_CAND + 1];
-    __shared__ double4 tile[64];
+    __shared__ double4 tile[TILE_RING];
+    __shared__ int tsrc[TILE_RING];
     const int lane = lane_id();
     const int t = lane & (gsz - 1), phi = lane / gsz;
     const u64 lt = lanemask_lt();
@@ -134,15 +176,18 @@ __global__ void __launch_bounds__(64) k_nbr_lists(DevCtl* ctl, const int4* __res
         const int4 g = group[gi];
         const bool tv = t < g.y;
         const double4 me = tv ? pos4[g.x + t] : make_double4(0, 0, 0, 0);
-        double lo[3], hi[3];
-        lo[0] = wave_min(tv ? me.x : INFINITY); hi[0] = wave_max(tv ? me.x : -INFINITY);
-        lo[1] = wave_min(tv ? me.y : INFINITY); hi[1] = wave_max(tv ? me.y : -INFINITY);
-        lo[2] = wave_min(tv ? me.z : INFINITY); hi[2] = wave_max(tv ? me.z : -INFINITY);
-        const double hg = wave_max(tv ? me.w : 0.0);
+        GroupBox gb;
+        gb.lo[0] = wave_min(tv ? me.x : INFINITY); gb.hi[0] = wave_max(tv ? me.x : -INFINITY);
+        gb.lo[1] = wave_min(tv ? me.y : INFINITY); gb.hi[1] = wave_max(tv ? me.y : -INFINITY);
+        gb.lo[2] = wave_min(tv ? me.z : INFINITY); gb.hi[2] = wave_max(tv ? me.z : -INFINITY);
+        gb.hg = wave_max(tv ? me.w : 0.0);
+        const double* lo = gb.lo;
+        const double* hi = gb.hi;
+        const double hg = gb.hg;
         int* mylist = nbr + (size_t)g.x * (size_t)cap;
         int* myuni = uni + (size_t)g.x * (size_t)cap;
         const int ulim = g.y * cap;
-        int cnt = 0, ucnt = 0;
+        int cnt = 0, ucnt = 0, head = 0, tail = 0;
         const int root = g.z < 0 ? 0 : ctl->level_off[3] + g.z;
         __syncthreads();
         if (lane == 0) stack[0] = root;
@@ -155,8 +200,8 @@ __global__ void __launch_bounds__(64) k_nbr_lists(DevCtl* ctl, const int4* __res
                 break;
             }
             if (nc + 64 > WALK_CAND) {
-                match_candidates(nc, cand, coff, tile, topo, pos4, me, tv, t, phi, gsz, g.y, cap, mylist, myuni,
-                                 ulim, cnt, ucnt);
+                match_candidates(nc, cand, coff, tile, tsrc, head, tail, gb, topo, pos4, me, tv, t, phi, gsz, g.y,
+                                 cap, mylist, myuni, ulim, cnt, ucnt);
                 nc = 0;
             }
             // pop at most as many nodes as the free stack can take the children of (8 each)
@@ -195,10 +240,14 @@ __global__ void __launch_bounds__(64) k_nbr_lists(DevCtl* ctl, const int4* __res
             __syncthreads();
         }
         __syncthreads();
-        if (!overflow)
-            match_candidates(nc, cand, coff, tile, topo, pos4, me, tv, t, phi, gsz, g.y, cap, mylist, myuni, ulim,
-                             cnt, ucnt);
-        else if (lane == 0)
+        if (!overflow) {
+            match_candidates(nc, cand, coff, tile, tsrc, head, tail, gb, topo, pos4, me, tv, t, phi, gsz, g.y, cap,
+                             mylist, myuni, ulim, cnt, ucnt);
+            if (tail > head)
+                test_tile(head, tail - head, tile, tsrc, me, tv, t, phi, gsz, g.y, cap, mylist, myuni, ulim, cnt,
+                          ucnt);
+            __syncthreads();
+        } else if (lane == 0)
             set_err(ctl, ERR_WALK_STACK);
         if (lane == 0) ucnt_out[gi] = overflow ? 0 : (ucnt < ulim ? ucnt : ulim);
         if (tv && phi == 0) {
