@@ -187,41 +187,56 @@ __device__ __forceinline__ int lcp_digits(u64 a, u64 b) {
 
 // ---------------------------------------------------------------------------------------
 // M4 cubic spline (support 2h): W = w(q) / (pi h^3), grad_a W_ab = r_ab g(q) / (pi h^5),
-// g = w'(q) / q; and compensated FP32 accumulators.
+// g = w'(q) / q; and compensated FP32 accumulators.  Both pieces are evaluated and one is
+// selected, so a wavefront never splits on q.
 
 __device__ __forceinline__ double m4_w(double q) {
-    if (q < 1.0) return fma(q * q, fma(0.75, q, -1.5), 1.0);
-    if (q < 2.0) {
-        const double t = 2.0 - q;
-        return 0.25 * t * t * t;
-    }
-    return 0.0;
+    const double t = fmax(2.0 - q, 0.0);
+    const double wo = 0.25 * (t * t * t);
+    const double wi = fma(q * q, fma(0.75, q, -1.5), 1.0);
+    return q < 1.0 ? wi : wo;
 }
-__device__ __forceinline__ double m4_g(double q) {
-    if (q < 1.0) return fma(2.25, q, -3.0);
-    if (q < 2.0) {
-        const double t = 2.0 - q;
-        return -0.75 * t * t / q;
-    }
-    return 0.0;
+// g(q) given 1/q (unused, and may be inf or NaN, for q < 1)
+__device__ __forceinline__ double m4_g(double q, double inv_q) {
+    const double t = fmax(2.0 - q, 0.0);
+    const double go = -0.75 * (t * t) * inv_q;
+    const double gi = fma(2.25, q, -3.0);
+    return q < 1.0 ? gi : go;
 }
 __device__ __forceinline__ float m4_wf(float q) {
-    if (q < 1.0f) return fmaf(q * q, fmaf(0.75f, q, -1.5f), 1.0f);
-    if (q < 2.0f) {
-        const float t = 2.0f - q;
-        return 0.25f * t * t * t;
-    }
-    return 0.0f;
+    const float t = fmaxf(2.0f - q, 0.0f);
+    const float wo = 0.25f * (t * t * t);
+    const float wi = fmaf(q * q, fmaf(0.75f, q, -1.5f), 1.0f);
+    return q < 1.0f ? wi : wo;
 }
 __device__ __forceinline__ float m4_gf(float q, float inv_q) {
-    if (q < 1.0f) return fmaf(2.25f, q, -3.0f);
-    if (q < 2.0f) {
-        const float t = 2.0f - q;
-        return -0.75f * t * t * inv_q;
-    }
-    return 0.0f;
+    const float t = fmaxf(2.0f - q, 0.0f);
+    const float go = -0.75f * (t * t) * inv_q;
+    const float gi = fmaf(2.25f, q, -3.0f);
+    return q < 1.0f ? gi : go;
 }
 
+// FP64 reciprocal and square root for the pair sums, from the hardware estimates refined
+// by Newton-Raphson steps (reciprocal: r <- r + r (1 - x r), twice) and by one Goldschmidt
+// step plus one Newton correction (square root); a few ulp, not correctly rounded.
+// rcp_nr: x positive and normal.  sqrt_nr: a >= 0 (0 gives 0).
+__device__ __forceinline__ double rcp_nr(double x) {
+    double r = __builtin_amdgcn_rcp(x);
+    double e = fma(-x, r, 1.0);
+    r = fma(r, e, r);
+    e = fma(-x, r, 1.0);
+    return fma(r, e, r);
+}
+__device__ __forceinline__ double sqrt_nr(double a) {
+    const double y = __builtin_amdgcn_rsq(a);
+    double r = a * y, h = 0.5 * y;
+    const double e = fma(-r, h, 0.5);
+    r = fma(r, e, r);
+    h = fma(h, e, h);
+    const double d = fma(-r, r, a);
+    r = fma(d, h, r);
+    return a > 0.0 ? r : 0.0;
+}
 
 // Kahan / Neumaier accumulators (explicit operation order; the library is built without
 // floating-point contraction, so these are not fused).

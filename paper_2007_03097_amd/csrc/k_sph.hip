@@ -58,8 +58,8 @@ struct DensAcc<false> {
     double s = 0.0;
     __device__ __forceinline__ void add(const double4 me, const double4 b, double mb) {
         const double dx = me.x - b.x, dy = me.y - b.y, dz = me.z - b.z;
-        const double r = sqrt(fma(dx, dx, fma(dy, dy, dz * dz)));
-        const double ih = 1.0 / (0.5 * (me.w + b.w));
+        const double r = sqrt_nr(fma(dx, dx, fma(dy, dy, dz * dz)));
+        const double ih = rcp_nr(0.5 * (me.w + b.w));
         s = fma(mb * m4_w(r * ih), ih * ih * ih, s);
     }
     __device__ __forceinline__ double value() const { return s; }
@@ -220,17 +220,18 @@ __global__ void __launch_bounds__(PAIR_THREADS) k_forces(
                     const double4 tb = reinterpret_cast<const double4*>(S.thr)[j];
                     const double dx = me.x - sb.x, dy = me.y - sb.y, dz = me.z - sb.z;
                     const double r2 = fma(dx, dx, fma(dy, dy, dz * dz));
-                    const double r = sqrt(r2);
+                    const double r = sqrt_nr(r2);
                     const double hab = 0.5 * (me.w + sb.w);
-                    const double ih = 1.0 / hab;
+                    const double ih = rcp_nr(hab);
                     const double ih2 = ih * ih;
-                    const double gw = m4_g(r * ih) * (ih2 * ih2 * ih) * M_1_PI_D;
+                    const double qq = r * ih;
+                    const double gw = m4_g(qq, hab * rcp_nr(r)) * (ih2 * ih2 * ih) * M_1_PI_D;
                     const double wx = mv.x - vb.x, wy = mv.y - vb.y, wz = mv.z - vb.z;
                     const double vr = fma(wx, dx, fma(wy, dy, wz * dz));
                     double Pi = 0.0;
                     if (vr < 0.0) {
-                        const double mu = hab * vr / fma(eps_av * hab, hab, r2);
-                        Pi = fma(-alpha * 0.5 * (mt.z + tb.z), mu, beta * mu * mu) / (0.5 * (mt.x + tb.x));
+                        const double mu = hab * vr * rcp_nr(fma(eps_av * hab, hab, r2));
+                        Pi = fma(-alpha * 0.5 * (mt.z + tb.z), mu, beta * mu * mu) * rcp_nr(0.5 * (mt.x + tb.x));
                     }
                     const double term = vb.w * ((mt.y + tb.y) + Pi) * gw;
                     sx = fma(-term, dx, sx);
