@@ -390,6 +390,26 @@ __global__ void __launch_bounds__(256) k_level_moments(const DevCtl* __restrict_
     }
 }
 
+// Levels top .. 0 in one workgroup, a barrier between levels (their nodes are few).
+constexpr int TOP_LEVELS = 5;
+__global__ void __launch_bounds__(1024) k_top_moments(const DevCtl* __restrict__ ctl, int batched,
+                                                       const u64* __restrict__ key, const int4* __restrict__ topo,
+                                                       double4* nbox_lo, double4* nbox_hi, double4* mom0,
+                                                       double4* mom1, double4* mom2, int2* range) {
+    for (int level = TOP_LEVELS - 1; level >= 0; --level) {
+        const int b0 = ctl->level_off[level], nb = ctl->level_count[level];
+        for (int k = threadIdx.x; k < nb; k += blockDim.x) {
+            const int b = b0 + k;
+            const int4 tp = topo[b];
+            if (tp.w) continue;
+            const int s = range[tp.x].x;
+            const int seg = batched ? (int)((key[s] >> 54) & 511ull) : 0;
+            aggregate_node(b, tp, nbox_lo, nbox_hi, mom0, mom1, mom2, range, ldexp(ctl->side[seg], -level));
+        }
+        __syncthreads();
+    }
+}
+
 static int grid_cap(int n, int bs, int cap) {
     int g = (n + bs - 1) / bs;
     return g < 1 ? 1 : (g > cap ? cap : g);
@@ -417,9 +437,13 @@ void build_octree(hipStream_t s, const DevPtrs& d, const Dims& dm) {
     hipLaunchKernelGGL(k_leaf_moments, dim3(grid_cap(n, 256, 2048)), dim3(256), 0, s, d.ctl, dm.batched, d.key_a,
                        d.leaf_start, d.leaf_pre, d.pre_to_bfs, d.topo, d.pos4, d.m, d.nbox_lo, d.nbox_hi, d.mom0,
                        d.mom1, d.mom2, d.range);
-    for (int lev = MAX_LEVEL - 1; lev >= 0; --lev)
-        hipLaunchKernelGGL(k_level_moments, dim3(lev < 4 ? 1 : 64), dim3(256), 0, s, d.ctl, lev, dm.batched, d.key_a,
-                           d.topo, d.nbox_lo, d.nbox_hi, d.mom0, d.mom1, d.mom2, d.range);
+    // one node per thread on the wide levels (a level holds fewer than n / 2 internal nodes)
+    const int gl = grid_cap(n / 2 + 1, 256, 4096);
+    for (int lev = MAX_LEVEL - 1; lev >= TOP_LEVELS; --lev)
+        hipLaunchKernelGGL(k_level_moments, dim3(gl), dim3(256), 0, s, d.ctl, lev, dm.batched, d.key_a, d.topo,
+                           d.nbox_lo, d.nbox_hi, d.mom0, d.mom1, d.mom2, d.range);
+    hipLaunchKernelGGL(k_top_moments, dim3(1), dim3(1024), 0, s, d.ctl, dm.batched, d.key_a, d.topo, d.nbox_lo,
+                       d.nbox_hi, d.mom0, d.mom1, d.mom2, d.range);
     // target groups: cells of at most 4 * group_size particles, cut into runs of group_size
     const int gcap = 4 * dm.group_size;
     launch_fill_u32(s, d.gflag, 0u, n + 1);
