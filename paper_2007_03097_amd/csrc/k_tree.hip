@@ -296,7 +296,8 @@ __global__ void __launch_bounds__(256) k_finalize(DevCtl* ctl, const unsigned ch
     }
 }
 
-// Leaf geometry and moments, then the last-arriving child aggregates its parent.
+// Internal node from its children: box, largest h, mass, centre of mass, and second
+// moments about the centre of mass (parallel-axis shifts of the children's).
 __device__ void aggregate_node(int p, const int4 tp, double4* nbox_lo, double4* nbox_hi, double4* mom0,
                                double4* mom1, double4* mom2, int2* range, double side) {
     double lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
@@ -329,83 +330,122 @@ __device__ void aggregate_node(int p, const int4 tp, double4* nbox_lo, double4* 
     range[p] = make_int2(range[tp.x].x, cnt);
 }
 
-__global__ void __launch_bounds__(256) k_leaf_moments(const DevCtl* __restrict__ ctl, int batched,
-                                                       const u64* __restrict__ key, const int* __restrict__ leaf_start,
-                                                       const int* __restrict__ leaf_pre,
-                                                       const int* __restrict__ pre_to_bfs, const int4* __restrict__ topo,
-                                                       const double4* __restrict__ pos4, const double* __restrict__ m,
-                                                       double4* nbox_lo, double4* nbox_hi, double4* mom0,
-                                                       double4* mom1, double4* mom2, int2* range) {
-    const int nl = ctl->n_leaves;
-    const int nn = ctl->n_nodes;
-    for (int lf = blockIdx.x * blockDim.x + threadIdx.x; lf < nl; lf += gridDim.x * blockDim.x) {
-        if (leaf_pre[lf] >= nn) continue;  // truncated tree (capacity error already flagged)
-        const int b = pre_to_bfs[leaf_pre[lf]];
-        const int s = leaf_start[lf], e = leaf_start[lf + 1];
-        const int seg = batched ? (int)((key[s] >> 54) & 511ull) : 0;
-        const double L = ctl->side[seg];
-        double lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
-        double hmax = 0.0, M = 0.0, sx = 0.0, sy = 0.0, sz = 0.0;
-        for (int j = s; j < e; ++j) {
-            const double4 p = pos4[j];
-            const double mj = m[j];
-            lo[0] = fmin(lo[0], p.x); lo[1] = fmin(lo[1], p.y); lo[2] = fmin(lo[2], p.z);
-            hi[0] = fmax(hi[0], p.x); hi[1] = fmax(hi[1], p.y); hi[2] = fmax(hi[2], p.z);
-            hmax = fmax(hmax, p.w);
-            M += mj; sx += mj * p.x; sy += mj * p.y; sz += mj * p.z;
+// Leaf geometry and moments from its particles [s, s + c).
+__device__ void leaf_node(int b, int s, int c, const double4* __restrict__ pos4, const double* __restrict__ m,
+                          double4* nbox_lo, double4* nbox_hi, double4* mom0, double4* mom1, double4* mom2,
+                          int2* range, double side) {
+    double lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
+    double hmax = 0.0, M = 0.0, sx = 0.0, sy = 0.0, sz = 0.0;
+    const int e = s + c;
+#pragma unroll 4
+    for (int j = s; j < e; ++j) {
+        const double4 p = pos4[j];
+        const double mj = m[j];
+        lo[0] = fmin(lo[0], p.x); lo[1] = fmin(lo[1], p.y); lo[2] = fmin(lo[2], p.z);
+        hi[0] = fmax(hi[0], p.x); hi[1] = fmax(hi[1], p.y); hi[2] = fmax(hi[2], p.z);
+        hmax = fmax(hmax, p.w);
+        M += mj; sx += mj * p.x; sy += mj * p.y; sz += mj * p.z;
+    }
+    const double cx = sx / M, cy = sy / M, cz = sz / M;
+    double I[6] = {0, 0, 0, 0, 0, 0};
+#pragma unroll 4
+    for (int j = s; j < e; ++j) {
+        const double4 p = pos4[j];
+        const double mj = m[j];
+        const double dx = p.x - cx, dy = p.y - cy, dz = p.z - cz;
+        I[0] += mj * dx * dx; I[1] += mj * dy * dy; I[2] += mj * dz * dz;
+        I[3] += mj * dx * dy; I[4] += mj * dx * dz; I[5] += mj * dy * dz;
+    }
+    nbox_lo[b] = make_double4(lo[0], lo[1], lo[2], hmax);
+    nbox_hi[b] = make_double4(hi[0], hi[1], hi[2], side);
+    mom0[b] = make_double4(M, cx, cy, cz);
+    mom1[b] = make_double4(I[0], I[1], I[2], I[0] + I[1] + I[2]);
+    mom2[b] = make_double4(I[3], I[4], I[5], 0.0);
+    range[b] = make_int2(s, c);
+}
+
+struct MomArgs {
+    const DevCtl* ctl;
+    int batched;
+    const u64* key;
+    const int4* topo;
+    const double4* pos4;
+    const double* m;
+    double4 *nbox_lo, *nbox_hi, *mom0, *mom1, *mom2;
+    int2* range;
+};
+
+// Node b: a leaf from its particles, an internal node from its (finished) children.
+__device__ __forceinline__ void node_moments(const MomArgs& A, int b) {
+    const int4 tp = A.topo[b];
+    const int s = tp.w ? tp.x : A.range[tp.x].x;
+    const int seg = A.batched ? (int)((A.key[s] >> 54) & 511ull) : 0;
+    const double side = ldexp(A.ctl->side[seg], -tp.z);
+    if (tp.w)
+        leaf_node(b, tp.x, tp.y, A.pos4, A.m, A.nbox_lo, A.nbox_hi, A.mom0, A.mom1, A.mom2, A.range, side);
+    else
+        aggregate_node(b, tp, A.nbox_lo, A.nbox_hi, A.mom0, A.mom1, A.mom2, A.range, side);
+}
+
+// Every node at level >= CUT_LEVEL: one wavefront per level-CUT_LEVEL cell finishes its
+// whole subtree bottom-up.  A subtree's nodes at each level are one contiguous run in
+// breadth-first order (from the first child of its first internal node to the last child
+// of its last internal node), so the runs are found top-down, then the levels are done
+// deepest first with the wavefront's own results as inputs.
+constexpr int CUT_LEVEL = 6;
+__global__ void __launch_bounds__(64) k_subtree_moments(MomArgs A) {
+    __shared__ int run_lo[MAX_LEVEL + 1], run_hi[MAX_LEVEL + 1];
+    const int lane = lane_id();
+    const int nroot = A.ctl->level_count[CUT_LEVEL], r0 = A.ctl->level_off[CUT_LEVEL];
+    for (int ri = blockIdx.x; ri < nroot; ri += gridDim.x) {
+        int lo = r0 + ri, hi = lo, deep = CUT_LEVEL;
+        if (lane == 0) {
+            run_lo[CUT_LEVEL] = lo;
+            run_hi[CUT_LEVEL] = hi;
         }
-        const double cx = sx / M, cy = sy / M, cz = sz / M;
-        double I[6] = {0, 0, 0, 0, 0, 0};
-        for (int j = s; j < e; ++j) {
-            const double4 p = pos4[j];
-            const double mj = m[j];
-            const double dx = p.x - cx, dy = p.y - cy, dz = p.z - cz;
-            I[0] += mj * dx * dx; I[1] += mj * dy * dy; I[2] += mj * dz * dz;
-            I[3] += mj * dx * dy; I[4] += mj * dx * dz; I[5] += mj * dy * dz;
+        for (int l = CUT_LEVEL; l < MAX_LEVEL; ++l) {
+            int first = -1, last = -1;
+            for (int k0 = lo; k0 <= hi && first < 0; k0 += 64) {  // first internal node
+                const int k = k0 + lane;
+                const u64 bl = __ballot(k <= hi && !A.topo[k].w);
+                if (bl) first = k0 + __ffsll((long long)bl) - 1;
+            }
+            if (first < 0) break;
+            for (int k1 = hi; k1 >= lo && last < 0; k1 -= 64) {  // last internal node
+                const int k = k1 - lane;
+                const u64 bl = __ballot(k >= lo && !A.topo[k].w);
+                if (bl) last = k1 - (__ffsll((long long)bl) - 1);
+            }
+            const int4 tf = A.topo[first], tl = A.topo[last];
+            lo = tf.x;
+            hi = tl.x + tl.y - 1;
+            deep = l + 1;
+            if (lane == 0) {
+                run_lo[deep] = lo;
+                run_hi[deep] = hi;
+            }
         }
-        const int lev = topo[b].z;
-        nbox_lo[b] = make_double4(lo[0], lo[1], lo[2], hmax);
-        nbox_hi[b] = make_double4(hi[0], hi[1], hi[2], ldexp(L, -lev));
-        mom0[b] = make_double4(M, cx, cy, cz);
-        mom1[b] = make_double4(I[0], I[1], I[2], I[0] + I[1] + I[2]);
-        mom2[b] = make_double4(I[3], I[4], I[5], 0.0);
-        range[b] = make_int2(s, e - s);
+        __syncthreads();
+        for (int l = deep; l >= CUT_LEVEL; --l) {
+            const int a = run_lo[l], e = run_hi[l];
+            for (int k = a + lane; k <= e; k += 64) node_moments(A, k);
+            __syncthreads();
+        }
     }
 }
 
-// Internal nodes of one level from their children (one launch per level, deepest first:
-// children are complete when their parents are read, with no cross-workgroup waiting).
-__global__ void __launch_bounds__(256) k_level_moments(const DevCtl* __restrict__ ctl, int level, int batched,
-                                                        const u64* __restrict__ key, const int4* __restrict__ topo,
-                                                        double4* nbox_lo, double4* nbox_hi, double4* mom0,
-                                                        double4* mom1, double4* mom2, int2* range) {
-    const int b0 = ctl->level_off[level], nb = ctl->level_count[level];
-    for (int k = blockIdx.x * blockDim.x + threadIdx.x; k < nb; k += gridDim.x * blockDim.x) {
-        const int b = b0 + k;
-        const int4 tp = topo[b];
-        if (tp.w) continue;
-        const int s = range[tp.x].x;
-        const int seg = batched ? (int)((key[s] >> 54) & 511ull) : 0;
-        aggregate_node(b, tp, nbox_lo, nbox_hi, mom0, mom1, mom2, range, ldexp(ctl->side[seg], -level));
-    }
+// Nodes of one level (the level below it complete), one node per thread.
+__global__ void __launch_bounds__(256) k_level_moments(MomArgs A, int level) {
+    const int b0 = A.ctl->level_off[level], nb = A.ctl->level_count[level];
+    for (int k = blockIdx.x * blockDim.x + threadIdx.x; k < nb; k += gridDim.x * blockDim.x) node_moments(A, b0 + k);
 }
 
-// Levels top .. 0 in one workgroup, a barrier between levels (their nodes are few).
+// Levels TOP_LEVELS - 1 .. 0 in one workgroup, a barrier between levels (their nodes are few).
 constexpr int TOP_LEVELS = 5;
-__global__ void __launch_bounds__(1024) k_top_moments(const DevCtl* __restrict__ ctl, int batched,
-                                                       const u64* __restrict__ key, const int4* __restrict__ topo,
-                                                       double4* nbox_lo, double4* nbox_hi, double4* mom0,
-                                                       double4* mom1, double4* mom2, int2* range) {
+__global__ void __launch_bounds__(1024) k_top_moments(MomArgs A) {
     for (int level = TOP_LEVELS - 1; level >= 0; --level) {
-        const int b0 = ctl->level_off[level], nb = ctl->level_count[level];
-        for (int k = threadIdx.x; k < nb; k += blockDim.x) {
-            const int b = b0 + k;
-            const int4 tp = topo[b];
-            if (tp.w) continue;
-            const int s = range[tp.x].x;
-            const int seg = batched ? (int)((key[s] >> 54) & 511ull) : 0;
-            aggregate_node(b, tp, nbox_lo, nbox_hi, mom0, mom1, mom2, range, ldexp(ctl->side[seg], -level));
-        }
+        const int b0 = A.ctl->level_off[level], nb = A.ctl->level_count[level];
+        for (int k = threadIdx.x; k < nb; k += blockDim.x) node_moments(A, b0 + k);
         __syncthreads();
     }
 }
@@ -434,16 +474,13 @@ void build_octree(hipStream_t s, const DevPtrs& d, const Dims& dm) {
     hipLaunchKernelGGL(k_finalize, dim3(g), dim3(256), 0, s, d.ctl, d.pre_level, d.pre_leaf, d.pre_start,
                        d.pre_to_bfs, d.bfs_to_pre, d.lcp, d.scan_out, d.leaf_start, d.topo, d.parent, d.counter,
                        d.range);
-    hipLaunchKernelGGL(k_leaf_moments, dim3(grid_cap(n, 256, 2048)), dim3(256), 0, s, d.ctl, dm.batched, d.key_a,
-                       d.leaf_start, d.leaf_pre, d.pre_to_bfs, d.topo, d.pos4, d.m, d.nbox_lo, d.nbox_hi, d.mom0,
-                       d.mom1, d.mom2, d.range);
-    // one node per thread on the wide levels (a level holds fewer than n / 2 internal nodes)
-    const int gl = grid_cap(n / 2 + 1, 256, 4096);
-    for (int lev = MAX_LEVEL - 1; lev >= TOP_LEVELS; --lev)
-        hipLaunchKernelGGL(k_level_moments, dim3(gl), dim3(256), 0, s, d.ctl, lev, dm.batched, d.key_a, d.topo,
-                           d.nbox_lo, d.nbox_hi, d.mom0, d.mom1, d.mom2, d.range);
-    hipLaunchKernelGGL(k_top_moments, dim3(1), dim3(1024), 0, s, d.ctl, dm.batched, d.key_a, d.topo, d.nbox_lo,
-                       d.nbox_hi, d.mom0, d.mom1, d.mom2, d.range);
+    // moments: subtrees below CUT_LEVEL, then the levels between, then the top levels
+    static_assert(CUT_LEVEL == TOP_LEVELS + 1, "one wide level between the top block and the subtrees");
+    const MomArgs A{d.ctl, dm.batched, d.key_a, d.topo, d.pos4, d.m, d.nbox_lo, d.nbox_hi, d.mom0, d.mom1, d.mom2,
+                    d.range};
+    hipLaunchKernelGGL(k_subtree_moments, dim3(grid_cap(n, 64, 8192)), dim3(64), 0, s, A);
+    hipLaunchKernelGGL(k_level_moments, dim3(grid_cap(n / 2 + 1, 256, 256)), dim3(256), 0, s, A, TOP_LEVELS);
+    hipLaunchKernelGGL(k_top_moments, dim3(1), dim3(1024), 0, s, A);
     // target groups: cells of at most 4 * group_size particles, cut into runs of group_size
     const int gcap = 4 * dm.group_size;
     launch_fill_u32(s, d.gflag, 0u, n + 1);
