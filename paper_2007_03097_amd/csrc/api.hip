@@ -20,7 +20,7 @@
 
 namespace {
 
-constexpr int CHUNK = 4096;
+constexpr int CHUNK = 1024;
 
 struct Tables {
     int64_t n = -1;
@@ -242,7 +242,7 @@ static sph_status prepare(sph_ctx* c, const sph_particles* p) {
         rank[s] = r;
         if (seg[s + 1] > seg[s]) ++r;
         for (int64_t b = seg[s]; b < seg[s + 1]; b += CHUNK)
-            chunks.push_back(make_int4((int)b, (int)std::min<int64_t>(seg[s + 1], b + CHUNK), s, 0));
+            chunks.push_back(make_int4((int)b, (int)std::min<int64_t>(seg[s + 1], b + CHUNK), s, b == seg[s]));
     }
     dm.n_chunks = (int)chunks.size();
     {   // persistent grid of the per-group kernels: a multiple of 8 (one share per XCD)
@@ -549,13 +549,11 @@ static void step_launches(sph_ctx* c, hipStream_t s, int p) {
     const DevPtrs& b = c->d[1 - p];
     const int n = c->dm.n;
     const double dt = c->g_dt;
-    launch_kick_drift(s, a, n, dt);
-    launch_bbox(s, a, c->dm, a.x, a.y, a.z, nullptr);
-    launch_set_box(s, a, c->dm, 0);
-    launch_step_keys(s, a, c->dm);
+    launch_box_init(s, a, c->dm);
+    launch_kick_drift(s, a, c->dm, dt);   // also merges the new box
+    launch_step_keys(s, a, c->dm);        // also derives L and S
     radix_sort(s, a, n);
-    launch_step_permute(s, a, n);
-    launch_pack_records(s, b, n);
+    launch_step_permute(s, a, n);         // also writes the pair records
     build_octree(s, b, c->dm);
     accel_pass(c, s, b, b.up);
     launch_kick(s, b, n, dt, c->cfg.adaptive_h);

@@ -178,6 +178,33 @@ __device__ __forceinline__ double dec_double(u64 e) {
 
 __device__ __forceinline__ void set_err(DevCtl* ctl, u32 bits) { atomicOr(&ctl->err, bits); }
 
+// Block-wide min/max of a chunk's positions (blockDim.x a multiple of 64, at most 1024),
+// merged into the segment's box with order-independent atomics on the encoded values.
+__device__ __forceinline__ void box_block_merge(DevCtl* ctl, int seg, double lo[3], double hi[3], bool any) {
+    __shared__ double red[16][6];
+    const int w = threadIdx.x >> 6;
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        lo[c] = wave_min(lo[c]);
+        hi[c] = wave_max(hi[c]);
+    }
+    if (lane_id() == 0) {
+        for (int c = 0; c < 3; ++c) {
+            red[w][c] = lo[c];
+            red[w][3 + c] = hi[c];
+        }
+    }
+    __syncthreads();
+    if (threadIdx.x < 6 && any) {
+        const int c = threadIdx.x;
+        double v = red[0][c];
+        for (int k = 1; k < (int)(blockDim.x >> 6); ++k) v = (c < 3) ? fmin(v, red[k][c]) : fmax(v, red[k][c]);
+        u64* slot = &ctl->box_enc[6 * seg + c];
+        if (c < 3) atomicMin(slot, enc_double(v));
+        else atomicMax(slot, enc_double(v));
+    }
+}
+
 // Leading equal 3-bit digits (0..21) of two keys below the sentinel.
 __device__ __forceinline__ int lcp_digits(u64 a, u64 b) {
     u64 x = (a ^ b) & 0x7fffffffffffffffull;
@@ -302,7 +329,8 @@ void launch_gravity(hipStream_t s, const DevPtrs& d, const Dims& dm, int fp32c, 
 // k_step.hip
 void launch_scatter_caller(hipStream_t s, const DevPtrs& d, int n, const double* src, double* dst);
 void launch_gather_caller(hipStream_t s, const DevPtrs& d, int n, const double* src_caller, double* dst);
-void launch_kick_drift(hipStream_t s, const DevPtrs& d, int n, double dt);
+void launch_box_init(hipStream_t s, const DevPtrs& d, const Dims& dm);
+void launch_kick_drift(hipStream_t s, const DevPtrs& d, const Dims& dm, double dt);
 void launch_step_keys(hipStream_t s, const DevPtrs& d, const Dims& dm);
 void launch_step_permute(hipStream_t s, const DevPtrs& d, int n);
 void launch_kick(hipStream_t s, const DevPtrs& d, int n, double dt, int adaptive_h);
@@ -313,4 +341,3 @@ void launch_write_back(hipStream_t s, const DevPtrs& d, int n, double* x, double
                        double* du);
 void launch_load_accel(hipStream_t s, const DevPtrs& d, int n, const double* ax, const double* ay,
                        const double* az, const double* du);
-void launch_pack_records(hipStream_t s, const DevPtrs& d, int n);

@@ -53,28 +53,11 @@ __global__ void __launch_bounds__(256) k_bbox(DevCtl* ctl, const int4* chunk, co
             hi[c] = fmax(hi[c], v[c]);
         }
     }
-    __shared__ double red[4][6];
-    const int w = threadIdx.x >> 6;
-#pragma unroll
-    for (int c = 0; c < 3; ++c) {
-        lo[c] = wave_min(lo[c]);
-        hi[c] = wave_max(hi[c]);
-    }
-    if (lane_id() == 0) {
-        for (int c = 0; c < 3; ++c) {
-            red[w][c] = lo[c];
-            red[w][3 + c] = hi[c];
-        }
-    }
-    __syncthreads();
-    if (threadIdx.x < 6 && ch.y > ch.x) {
-        const int c = threadIdx.x;
-        double v = red[0][c];
-        for (int k = 1; k < (int)(blockDim.x >> 6); ++k) v = (c < 3) ? fmin(v, red[k][c]) : fmax(v, red[k][c]);
-        u64* slot = &ctl->box_enc[6 * ch.z + c];
-        if (c < 3) atomicMin(slot, enc_double(v));
-        else atomicMax(slot, enc_double(v));
-    }
+    box_block_merge(ctl, ch.z, lo, hi, ch.y > ch.x);
+}
+
+void launch_box_init(hipStream_t s, const DevPtrs& d, const Dims& dm) {
+    hipLaunchKernelGGL(k_box_init, dim3((dm.n_seg + 255) / 256), dim3(256), 0, s, d.ctl, dm.n_seg);
 }
 
 void launch_bbox(hipStream_t s, const DevPtrs& d, const Dims& dm, const double* x, const double* y,
@@ -127,13 +110,12 @@ __device__ __forceinline__ u32 quantise(double x, double lo, double S, u32 top) 
     return (u32)t;
 }
 
-__device__ __forceinline__ u64 make_key(double x, double y, double z, const DevCtl* ctl, int seg, int batched) {
+__device__ __forceinline__ u64 make_key(double x, double y, double z, const double* lo, double S, int seg,
+                                        int batched) {
     const int bits = batched ? 18 : 21;
     const u32 top = (1u << bits) - 1u;
-    const double S = ctl->scale[seg];
-    const double* b = ctl->box + 6 * seg;
-    u64 m = spread3(quantise(x, b[0], S, top)) | (spread3(quantise(y, b[1], S, top)) << 1) |
-            (spread3(quantise(z, b[2], S, top)) << 2);
+    u64 m = spread3(quantise(x, lo[0], S, top)) | (spread3(quantise(y, lo[1], S, top)) << 1) |
+            (spread3(quantise(z, lo[2], S, top)) << 2);
     u64 k = (1ull << 63) | m;
     if (batched) k |= (u64)seg << 54;
     return k;
@@ -154,7 +136,7 @@ __global__ void __launch_bounds__(256) k_keys(DevCtl* ctl, const int4* chunk, in
             !isfinite(vz[i]) || !isfinite(u[i]))
             bad |= ERR_NONFINITE;
         if (!(h[i] > 0.0) || !(m[i] > 0.0) || !isfinite(h[i]) || !isfinite(m[i])) bad |= ERR_NONPOSITIVE;
-        u64 k = make_key(px, py, pz, ctl, ch.z, batched);
+        u64 k = make_key(px, py, pz, ctl->box + 6 * ch.z, ctl->scale[ch.z], ch.z, batched);
         key[i] = k;
         val[i] = (u32)i;
         if (key_out) key_out[i] = k;
@@ -180,6 +162,24 @@ __global__ void __launch_bounds__(256) k_step_keys(DevCtl* ctl, const int4* chun
                                                     const double* __restrict__ u, const u32* __restrict__ id,
                                                     u64* key, u32* val, u32* inv) {
     const int4 ch = chunk[blockIdx.x];
+    // the segment's box from the merged encodings, L and S = 2^B / L (one IEEE division);
+    // the segment's first chunk publishes them for the tree build
+    double box[6];
+    for (int c = 0; c < 6; ++c) box[c] = dec_double(ctl->box_enc[6 * ch.z + c]);
+    double L = 0.0;
+    for (int c = 0; c < 3; ++c) L = fmax(L, box[3 + c] - box[c]);
+    double S = 0.0;
+    if (L > 0.0) {
+        S = (double)(1u << (batched ? 18 : 21)) / L;
+        if (!isfinite(S)) S = 0.0;
+    }
+    if (ch.w && threadIdx.x < 6) {
+        ctl->box[6 * ch.z + threadIdx.x] = box[threadIdx.x];
+        if (threadIdx.x == 0) {
+            ctl->scale[ch.z] = S;
+            ctl->side[ch.z] = L;
+        }
+    }
     u32 bad = 0;
     for (int p = ch.x + threadIdx.x; p < ch.y; p += blockDim.x) {
         double px = x[p], py = y[p], pz = z[p];
@@ -187,7 +187,7 @@ __global__ void __launch_bounds__(256) k_step_keys(DevCtl* ctl, const int4* chun
             !isfinite(vz[p]) || !isfinite(u[p]))
             bad |= ERR_NONFINITE;
         const u32 i = id[p];
-        key[i] = make_key(px, py, pz, ctl, ch.z, batched);
+        key[i] = make_key(px, py, pz, box, S, ch.z, batched);
         val[i] = i;
         inv[i] = (u32)p;
     }

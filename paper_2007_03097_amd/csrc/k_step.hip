@@ -21,65 +21,61 @@ void launch_gather_caller(hipStream_t s, const DevPtrs& d, int n, const double* 
 }
 
 // v' = v + dt/2 a; u' = u + dt/2 du; x += dt v'; predictors v^ = v' + dt/2 a, u^ = u' + dt/2 du.
-__global__ void k_kick_drift(int n, double dt, double* x, double* y, double* z, double* vx, double* vy, double* vz,
-                             double* u, const double* __restrict__ ax, const double* __restrict__ ay,
-                             const double* __restrict__ az, const double* __restrict__ du, double* vpx, double* vpy,
-                             double* vpz, double* up) {
-    const int q = blockIdx.x * blockDim.x + threadIdx.x;
-    if (q >= n) return;
+// One block per chunk (chunks never cross a segment); the new positions' box is merged
+// into the segment's box on the way.
+__global__ void __launch_bounds__(256) k_kick_drift(DevCtl* ctl, const int4* __restrict__ chunk, double dt, double* x,
+                                                    double* y, double* z, double* vx, double* vy, double* vz, double* u,
+                                                    const double* __restrict__ ax, const double* __restrict__ ay,
+                                                    const double* __restrict__ az, const double* __restrict__ du,
+                                                    double* vpx, double* vpy, double* vpz, double* up) {
+    const int4 ch = chunk[blockIdx.x];
     const double half = 0.5 * dt;
-    const double a0 = ax[q], a1 = ay[q], a2 = az[q], d0 = du[q];
-    const double hx = vx[q] + half * a0, hy = vy[q] + half * a1, hz = vz[q] + half * a2;
-    const double uh = u[q] + half * d0;
-    x[q] = x[q] + dt * hx;
-    y[q] = y[q] + dt * hy;
-    z[q] = z[q] + dt * hz;
-    vx[q] = hx; vy[q] = hy; vz[q] = hz;
-    u[q] = uh;
-    vpx[q] = hx + half * a0;
-    vpy[q] = hy + half * a1;
-    vpz[q] = hz + half * a2;
-    up[q] = uh + half * d0;
+    double lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
+    for (int q = ch.x + threadIdx.x; q < ch.y; q += blockDim.x) {
+        const double a0 = ax[q], a1 = ay[q], a2 = az[q], d0 = du[q];
+        const double hx = vx[q] + half * a0, hy = vy[q] + half * a1, hz = vz[q] + half * a2;
+        const double uh = u[q] + half * d0;
+        const double nx = x[q] + dt * hx, ny = y[q] + dt * hy, nz = z[q] + dt * hz;
+        x[q] = nx;
+        y[q] = ny;
+        z[q] = nz;
+        vx[q] = hx; vy[q] = hy; vz[q] = hz;
+        u[q] = uh;
+        vpx[q] = hx + half * a0;
+        vpy[q] = hy + half * a1;
+        vpz[q] = hz + half * a2;
+        up[q] = uh + half * d0;
+        lo[0] = fmin(lo[0], nx); lo[1] = fmin(lo[1], ny); lo[2] = fmin(lo[2], nz);
+        hi[0] = fmax(hi[0], nx); hi[1] = fmax(hi[1], ny); hi[2] = fmax(hi[2], nz);
+    }
+    box_block_merge(ctl, ch.z, lo, hi, ch.y > ch.x);
 }
-void launch_kick_drift(hipStream_t s, const DevPtrs& d, int n, double dt) {
-    if (n > 0)
-        hipLaunchKernelGGL(k_kick_drift, g256(n), dim3(256), 0, s, n, dt, d.x, d.y, d.z, d.vx, d.vy, d.vz, d.u, d.ax,
-                           d.ay, d.az, d.du, d.vpx, d.vpy, d.vpz, d.up);
+void launch_kick_drift(hipStream_t s, const DevPtrs& d, const Dims& dm, double dt) {
+    if (dm.n_chunks > 0)
+        hipLaunchKernelGGL(k_kick_drift, dim3(dm.n_chunks), dim3(256), 0, s, d.ctl, d.chunk, dt, d.x, d.y, d.z, d.vx,
+                           d.vy, d.vz, d.u, d.ax, d.ay, d.az, d.du, d.vpx, d.vpy, d.vpz, d.up);
 }
 
-// New key order: q <- old position inv[val[q]]; the second buffer set receives the data.
+// New key order: q <- old position inv[val[q]]; the second buffer set receives the data,
+// and the pair kernels' records pos4 = (x, h), vel4 = (predicted v, m) are written too.
 __global__ void k_step_permute(int n, const u32* __restrict__ val, const u32* __restrict__ inv, DevPtrs d) {
     const int q = blockIdx.x * blockDim.x + threadIdx.x;
     if (q >= n) return;
     const u32 i = val[q];
     const u32 p = inv[i];
     d.id2[q] = i;
-    d.x2[q] = d.x[p]; d.y2[q] = d.y[p]; d.z2[q] = d.z[p];
+    const double px = d.x[p], py = d.y[p], pz = d.z[p], hh = d.h[p], mm = d.m[p];
+    const double wx = d.vpx[p], wy = d.vpy[p], wz = d.vpz[p];
+    d.x2[q] = px; d.y2[q] = py; d.z2[q] = pz;
     d.vx2[q] = d.vx[p]; d.vy2[q] = d.vy[p]; d.vz2[q] = d.vz[p];
-    d.u2[q] = d.u[p]; d.m2[q] = d.m[p]; d.h2[q] = d.h[p];
-    d.vpx2[q] = d.vpx[p]; d.vpy2[q] = d.vpy[p]; d.vpz2[q] = d.vpz[p]; d.up2[q] = d.up[p];
+    d.u2[q] = d.u[p]; d.m2[q] = mm; d.h2[q] = hh;
+    d.vpx2[q] = wx; d.vpy2[q] = wy; d.vpz2[q] = wz; d.up2[q] = d.up[p];
+    d.pos4[q] = make_double4(px, py, pz, hh);
+    d.vel4[q] = make_double4(wx, wy, wz, mm);
+    d.velf[q] = make_float4((float)wx, (float)wy, (float)wz, (float)mm);
 }
 void launch_step_permute(hipStream_t s, const DevPtrs& d, int n) {
     if (n > 0) hipLaunchKernelGGL(k_step_permute, g256(n), dim3(256), 0, s, n, d.val_a, d.inv, d);
-}
-
-// Records read by the pair kernels: pos4 = (x, h), vel4 = (predicted v, m).
-__global__ void k_pack_records(int n, const double* __restrict__ x, const double* __restrict__ y,
-                               const double* __restrict__ z, const double* __restrict__ h,
-                               const double* __restrict__ vx, const double* __restrict__ vy,
-                               const double* __restrict__ vz, const double* __restrict__ m, double4* pos4,
-                               double4* vel4, float4* velf) {
-    const int q = blockIdx.x * blockDim.x + threadIdx.x;
-    if (q >= n) return;
-    const double mm = m[q], wx = vx[q], wy = vy[q], wz = vz[q];
-    pos4[q] = make_double4(x[q], y[q], z[q], h[q]);
-    vel4[q] = make_double4(wx, wy, wz, mm);
-    velf[q] = make_float4((float)wx, (float)wy, (float)wz, (float)mm);
-}
-void launch_pack_records(hipStream_t s, const DevPtrs& d, int n) {
-    if (n > 0)
-        hipLaunchKernelGGL(k_pack_records, g256(n), dim3(256), 0, s, n, d.x, d.y, d.z, d.h, d.vpx, d.vpy, d.vpz, d.m,
-                           d.pos4, d.vel4, d.velf);
 }
 
 // v = v' + dt/2 a_new;  u = u' + dt/2 du_new;  optional lagged h update.
