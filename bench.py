@@ -38,7 +38,8 @@ FLOP_FORCE_PAIR = 54     # momentum + energy without the viscosity branch (69 wi
 def measured_traffic(kernel):
     """HBM bytes per launch of `kernel` from the committed hardware-counter summary, or None
     when there is none or the kernel's source has changed since the counters were taken.
-    Summary lines read: 'traffic: <kernel> <source file> <sha256 of it> <bytes per launch>'."""
+    Summary lines read: 'traffic: <kernel> <source files, comma-separated> <sha256 of their
+    concatenated contents> <bytes per launch>'."""
     import hashlib
     prof = os.path.join(ROOT, "profiles")
     if not os.path.isdir(prof):
@@ -49,9 +50,11 @@ def measured_traffic(kernel):
         for line in open(os.path.join(prof, fn)):
             f = line.split()
             if len(f) == 5 and f[0] == "traffic:" and f[1] == kernel:
-                src = os.path.join(ROOT, f[2])
-                if os.path.isfile(src) and hashlib.sha256(open(src, "rb").read()).hexdigest() == f[3]:
-                    return float(f[4])
+                srcs = [os.path.join(ROOT, s) for s in f[2].split(",")]
+                if all(os.path.isfile(s) for s in srcs):
+                    h = hashlib.sha256(b"".join(open(s, "rb").read() for s in srcs)).hexdigest()
+                    if h == f[3]:
+                        return float(f[4])
     return None
 
 
