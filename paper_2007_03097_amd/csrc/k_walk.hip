@@ -14,12 +14,13 @@
 //     is handled with fixed LDS.
 //  3. Each candidate particle is tested against the group box (conservatively, as the
 //     nodes are); survivors are staged in an LDS ring and matched 64 at a time: lane
-//     (t, phi) tests the block of sources phi*G .. phi*G + G - 1 (G = group_size, P = 64/G
-//     lanes per target) for target t with the exact predicate
-//     fl(fl(fl(dx dx) + fl(dy dy)) + fl(dz dz)) < fl(t t), recording hits as bits.  The OR of all lanes' bits is the tile's part of the group's
+//     (tp, phi) tests the block of sources phi*T .. phi*T + T - 1 (T = group_size/2) against
+//     its two targets tp and tp + T with the exact predicate
+//     fl(fl(fl(dx dx) + fl(dy dy)) + fl(dz dz)) < fl(t t), recording hits as bits (two
+//     targets per lane halve the LDS reads per pair test).  The OR of all lanes' bits is the tile's part of the group's
 //     source union U (sources that are a neighbour of at least one target), appended to
-//     U in staging order.  The P lanes of a target then take consecutive slot ranges and
-//     write, for each hit, the source's index in U.
+//     U in staging order.  The 64/T lanes of a target then take consecutive slot ranges
+//     and write, for each hit, the source's index in U.
 // Outputs per group (n_g targets starting at sorted position s):
 //   uni[s*cap + i], i < ucnt[group]: particle index of the i-th member of U;
 //   nbr[s*cap + k*n_g + t]: slot k of target t, an index into U, ascending in k; the blocks
@@ -38,50 +39,77 @@ struct GroupBox {
     double lo[3], hi[3], hg;
 };
 
-// Exact predicate for the 64 (or, at the end, fewer) filtered sources at ring positions
-// head .. head + tn - 1: lane (t, phi) tests ring entries head + phi*G + it, it < G, for
-// target t; hits go to the union and to the target's list.
-__device__ __forceinline__ void test_tile(int head, int tn, const double4* tile, const int* tsrc, const double4 me,
-                                          bool tv, int t, int phi, int gsz, int gy, int cap, int* mylist,
-                                          int* myuni, int ulim, int& cnt, int& ucnt) {
+// Each lane serves two targets of the group, tp and tp + TP (TP = group_size / 2), and a
+// block of B = TP staged sources; the P = 64 / TP lanes with the same tp cover the tile.
+// One LDS read of a source feeds two pair tests.
+struct LaneTargets {
+    double4 a, b;   // targets tp and tp + TP
+    bool va, vb;    // they exist
+    int tp, phi, TP, P;
+    int cnt_a, cnt_b;
+};
+
+// Slots for one target's hits: the P lanes of the target take consecutive slot ranges in
+// phi order, each in ascending source order; the entry is the source's index in the union.
+__device__ __forceinline__ void append_hits(u32 bits, int t, int& cnt, const LaneTargets& L, u64 ub, int ucnt,
+                                            int gy, int cap, int* mylist) {
     const int lane = lane_id();
-    u64 bits = 0;
-    if (tv) {
-        const int j0 = phi * gsz;
-        const int je = tn - j0 < gsz ? tn - j0 : gsz;
-        for (int it = 0; it < je; ++it) {
-            const double4 b = tile[(head + j0 + it) & (TILE_RING - 1)];
-            const double dx = me.x - b.x, dy = me.y - b.y, dz = me.z - b.z;
+    const int mine = __popc(bits);
+    int incl = mine;
+    for (int d = L.TP; d < 64; d <<= 1) {
+        const int v = __shfl_up(incl, d, 64);
+        if (lane >= d) incl += v;
+    }
+    const int tot = __shfl(incl, L.tp + L.TP * (L.P - 1), 64);
+    int slot = cnt + incl - mine;
+    const int j0 = L.phi * L.TP;
+    while (bits) {
+        const int it = __ffs(bits) - 1;
+        bits &= bits - 1;
+        const int j = j0 + it;
+        if (slot < cap) mylist[slot * gy + t] = ucnt + __popcll(ub & ((1ull << j) - 1ull));
+        ++slot;
+    }
+    cnt += tot;
+}
+
+// Exact predicate fl(fl(fl(dx dx) + fl(dy dy)) + fl(dz dz)) < fl(t t), t = fl(h_a + h_b),
+// for the 64 (or, at the end, fewer) filtered sources at ring positions head .. head+tn-1;
+// hits go to the group's union and to the targets' lists.
+__device__ __forceinline__ void test_tile(int head, int tn, const double4* tile, const int* tsrc, LaneTargets& L,
+                                          int gy, int cap, int* mylist, int* myuni, int ulim, int& ucnt) {
+    const int lane = lane_id();
+    const int j0 = L.phi * L.TP;
+    const int je = tn - j0 < L.TP ? tn - j0 : L.TP;
+    u32 ba = 0, bb = 0;
+    for (int it = 0; it < je; ++it) {
+        const double4 s = tile[(head + j0 + it) & (TILE_RING - 1)];
+        {
+            const double dx = L.a.x - s.x, dy = L.a.y - s.y, dz = L.a.z - s.z;
             double r2 = dx * dx + dy * dy;
             r2 = r2 + dz * dz;
-            const double tt = me.w + b.w;
-            if (r2 < tt * tt) bits |= 1ull << it;
+            const double tt = L.a.w + s.w;
+            if (r2 < tt * tt) ba |= 1u << it;
+        }
+        {
+            const double dx = L.b.x - s.x, dy = L.b.y - s.y, dz = L.b.z - s.z;
+            double r2 = dx * dx + dy * dy;
+            r2 = r2 + dz * dz;
+            const double tt = L.b.w + s.w;
+            if (r2 < tt * tt) bb |= 1u << it;
         }
     }
+    if (!L.va) ba = 0u;
+    if (!L.vb) bb = 0u;
     // union of the tile, bit j = ring entry head + j
-    u64 ub = bits << (phi * gsz);
+    u64 ub = (u64)(ba | bb) << j0;
     for (int d = 1; d < 64; d <<= 1) ub |= __shfl_xor(ub, d, 64);
     if ((ub >> lane) & 1ull) {
         const int r = ucnt + __popcll(ub & lanemask_lt());
         if (r < ulim) myuni[r] = tsrc[(head + lane) & (TILE_RING - 1)];
     }
-    // slot ranges of the P lanes of each target (lanes t, t + gsz, ...), in phi order
-    const int mine = __popcll(bits);
-    int incl = mine;
-    for (int d = gsz; d < 64; d <<= 1) {
-        const int v = __shfl_up(incl, d, 64);
-        if (lane >= d) incl += v;
-    }
-    const int tot = __shfl(incl, t + gsz * (64 / gsz - 1), 64);
-    int slot = cnt + incl - mine;
-    while (bits) {
-        const int it = __ffsll((long long)bits) - 1;
-        bits &= bits - 1;
-        const int j = phi * gsz + it;
-        if (slot < cap) mylist[slot * gy + t] = ucnt + __popcll(ub & ((1ull << j) - 1ull));
-        ++slot;
-    }
-    cnt += tot;
+    append_hits(ba, L.tp, L.cnt_a, L, ub, ucnt, gy, cap, mylist);
+    append_hits(bb, L.tp + L.TP, L.cnt_b, L, ub, ucnt, gy, cap, mylist);
     ucnt += __popcll(ub);
 }
 
@@ -93,9 +121,8 @@ __device__ __forceinline__ void test_tile(int head, int tn, const double4* tile,
 // the caller's final flush.
 __device__ void match_candidates(int nc, int* cand, int* coff, double4* tile, int* tsrc, int& head, int& tail,
                                  const GroupBox& gb, const int4* __restrict__ topo,
-                                 const double4* __restrict__ pos4, const double4 me, bool tv, int t, int phi,
-                                 int gsz, int gy, int cap, int* mylist, int* myuni, int ulim, int& cnt,
-                                 int& ucnt) {
+                                 const double4* __restrict__ pos4, LaneTargets& L, int gy, int cap, int* mylist,
+                                 int* myuni, int ulim, int& ucnt) {
     const int lane = lane_id();
     const u64 lt = lanemask_lt();
     int carry = 0;
@@ -149,7 +176,7 @@ __device__ void match_candidates(int nc, int* cand, int* coff, double4* tile, in
         tail += __popcll(bal);
         __syncthreads();
         if (tail - head >= 64) {
-            test_tile(head, 64, tile, tsrc, me, tv, t, phi, gsz, gy, cap, mylist, myuni, ulim, cnt, ucnt);
+            test_tile(head, 64, tile, tsrc, L, gy, cap, mylist, myuni, ulim, ucnt);
             head += 64;
         }
         __syncthreads();
@@ -168,26 +195,36 @@ __global__ void __launch_bounds__(64) k_nbr_lists(DevCtl* ctl, const int4* __res
     __shared__ double4 tile[TILE_RING];
     __shared__ int tsrc[TILE_RING];
     const int lane = lane_id();
-    const int t = lane & (gsz - 1), phi = lane / gsz;
     const u64 lt = lanemask_lt();
+    LaneTargets L;
+    L.TP = gsz >> 1;
+    L.P = 64 / L.TP;
+    L.tp = lane & (L.TP - 1);
+    L.phi = lane / L.TP;
     int g0, g1, gstep;
     group_range(ctl->n_groups, g0, g1, gstep);
     for (int gi = g0; gi < g1; gi += gstep) {
         const int4 g = group[gi];
-        const bool tv = t < g.y;
-        const double4 me = tv ? pos4[g.x + t] : make_double4(0, 0, 0, 0);
+        L.va = L.tp < g.y;
+        L.vb = L.tp + L.TP < g.y;
+        L.a = L.va ? pos4[g.x + L.tp] : make_double4(0, 0, 0, 0);
+        L.b = L.vb ? pos4[g.x + L.tp + L.TP] : make_double4(0, 0, 0, 0);
+        L.cnt_a = L.cnt_b = 0;
         GroupBox gb;
-        gb.lo[0] = wave_min(tv ? me.x : INFINITY); gb.hi[0] = wave_max(tv ? me.x : -INFINITY);
-        gb.lo[1] = wave_min(tv ? me.y : INFINITY); gb.hi[1] = wave_max(tv ? me.y : -INFINITY);
-        gb.lo[2] = wave_min(tv ? me.z : INFINITY); gb.hi[2] = wave_max(tv ? me.z : -INFINITY);
-        gb.hg = wave_max(tv ? me.w : 0.0);
+        gb.lo[0] = wave_min(fmin(L.va ? L.a.x : INFINITY, L.vb ? L.b.x : INFINITY));
+        gb.lo[1] = wave_min(fmin(L.va ? L.a.y : INFINITY, L.vb ? L.b.y : INFINITY));
+        gb.lo[2] = wave_min(fmin(L.va ? L.a.z : INFINITY, L.vb ? L.b.z : INFINITY));
+        gb.hi[0] = wave_max(fmax(L.va ? L.a.x : -INFINITY, L.vb ? L.b.x : -INFINITY));
+        gb.hi[1] = wave_max(fmax(L.va ? L.a.y : -INFINITY, L.vb ? L.b.y : -INFINITY));
+        gb.hi[2] = wave_max(fmax(L.va ? L.a.z : -INFINITY, L.vb ? L.b.z : -INFINITY));
+        gb.hg = wave_max(fmax(L.va ? L.a.w : 0.0, L.vb ? L.b.w : 0.0));
         const double* lo = gb.lo;
         const double* hi = gb.hi;
         const double hg = gb.hg;
         int* mylist = nbr + (size_t)g.x * (size_t)cap;
         int* myuni = uni + (size_t)g.x * (size_t)cap;
         const int ulim = g.y * cap;
-        int cnt = 0, ucnt = 0, head = 0, tail = 0;
+        int ucnt = 0, head = 0, tail = 0;
         const int root = g.z < 0 ? 0 : ctl->level_off[3] + g.z;
         __syncthreads();
         if (lane == 0) stack[0] = root;
@@ -200,8 +237,8 @@ __global__ void __launch_bounds__(64) k_nbr_lists(DevCtl* ctl, const int4* __res
                 break;
             }
             if (nc + 64 > WALK_CAND) {
-                match_candidates(nc, cand, coff, tile, tsrc, head, tail, gb, topo, pos4, me, tv, t, phi, gsz, g.y,
-                                 cap, mylist, myuni, ulim, cnt, ucnt);
+                match_candidates(nc, cand, coff, tile, tsrc, head, tail, gb, topo, pos4, L, g.y, cap, mylist, myuni,
+                                 ulim, ucnt);
                 nc = 0;
             }
             // pop at most as many nodes as the free stack can take the children of (8 each)
@@ -241,22 +278,24 @@ __global__ void __launch_bounds__(64) k_nbr_lists(DevCtl* ctl, const int4* __res
         }
         __syncthreads();
         if (!overflow) {
-            match_candidates(nc, cand, coff, tile, tsrc, head, tail, gb, topo, pos4, me, tv, t, phi, gsz, g.y, cap,
-                             mylist, myuni, ulim, cnt, ucnt);
-            if (tail > head)
-                test_tile(head, tail - head, tile, tsrc, me, tv, t, phi, gsz, g.y, cap, mylist, myuni, ulim, cnt,
-                          ucnt);
+            match_candidates(nc, cand, coff, tile, tsrc, head, tail, gb, topo, pos4, L, g.y, cap, mylist, myuni, ulim,
+                             ucnt);
+            if (tail > head) test_tile(head, tail - head, tile, tsrc, L, g.y, cap, mylist, myuni, ulim, ucnt);
             __syncthreads();
         } else if (lane == 0)
             set_err(ctl, ERR_WALK_STACK);
         if (lane == 0) ucnt_out[gi] = overflow ? 0 : (ucnt < ulim ? ucnt : ulim);
-        if (tv && phi == 0) {
-            const int q = g.x + t;
-            nbr_cnt[q] = overflow ? 0 : (cnt < cap ? cnt : cap);
-            list_base[q] = overflow ? -1 : gi;
-            if (cnt > cap) {
-                set_err(ctl, ERR_NBR_CAP);
-                atomicMax(&ctl->nbr_max, cnt);
+        if (L.phi == 0) {
+            for (int s = 0; s < 2; ++s) {
+                if (!(s ? L.vb : L.va)) continue;
+                const int q = g.x + L.tp + s * L.TP;
+                const int cnt = s ? L.cnt_b : L.cnt_a;
+                nbr_cnt[q] = overflow ? 0 : (cnt < cap ? cnt : cap);
+                list_base[q] = overflow ? -1 : gi;
+                if (cnt > cap) {
+                    set_err(ctl, ERR_NBR_CAP);
+                    atomicMax(&ctl->nbr_max, cnt);
+                }
             }
         }
     }
