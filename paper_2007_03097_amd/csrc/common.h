@@ -254,6 +254,13 @@ __device__ __forceinline__ double rcp_nr(double x) {
     e = fma(-x, r, 1.0);
     return fma(r, e, r);
 }
+// 1/sqrt(a) for a positive and normal: two Newton steps y <- y (3/2 - a y^2 / 2).
+__device__ __forceinline__ double rsq_nr(double a) {
+    double y = __builtin_amdgcn_rsq(a);
+    const double h = 0.5 * a;
+    y = y * fma(-h * y, y, 1.5);
+    return y * fma(-h * y, y, 1.5);
+}
 __device__ __forceinline__ double sqrt_nr(double a) {
     const double y = __builtin_amdgcn_rsq(a);
     double r = a * y, h = 0.5 * y;

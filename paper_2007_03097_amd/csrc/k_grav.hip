@@ -11,7 +11,8 @@
 //   g   +=  G [-M R/s^3 + 3 I.R/s^5 - (15/2) (R.I.R) R/s^7 + (3/2) tr(I) R/s^5]
 // with R = r_a - R_B, s^2 = |R|^2 + eps^2, I = sum m y y^T about R_B.  Unaccepted leaves
 // contribute softened particle sums with the target itself skipped.  Cell and leaf lists
-// live in LDS and are evaluated whenever they fill, so the walk needs no global scratch.
+// live in LDS and are evaluated whenever they fill, so the walk needs no global scratch;
+// the evaluation stages cell moments and leaf particles through LDS 64 at a time.
 #include "common.h"
 
 constexpr int GW_STACK = 1024;
@@ -22,48 +23,61 @@ struct GravAcc {
     double gx = 0, gy = 0, gz = 0, ph = 0;
 };
 
+// LDS staging shared by the cell and particle phases of one evaluation.
+struct GravStage {
+    double4 c0[64], c1[64], c2[64];  // cell moments (M, com), (Ixx, Iyy, Izz, tr I), (Ixy, Ixz, Iyz, -)
+    int loff[GW_LEAVES + 1];         // particle offsets of the staged leaves
+    int src[64];                     // particle index of each staged source (self test)
+};
+
+// Accepted cells (monopole + quadrupole) and unaccepted leaves (softened particle sums,
+// self skipped) for target `me` (index q).  Cells are staged 64 at a time (one lane loads
+// one cell); the leaves' particles are concatenated and staged 64 at a time, so every
+// staging round is one load per lane.  Lane (t, phi) takes every P_-th staged item.
 template <bool FP32C>
-__device__ void eval_lists(int ncell, int nleaf, const int* cells, const int* leaves, double4* tile, int* tidx,
+__device__ void eval_lists(int ncell, int nleaf, const int* cells, int* leaves, GravStage& S, double4* tile,
                            const int4* __restrict__ topo, const double4* __restrict__ mom0,
                            const double4* __restrict__ mom1, const double4* __restrict__ mom2,
                            const double4* __restrict__ pos4, const double* __restrict__ m, const double4 me, int q,
                            bool tv, int phi, int P_, double G, double eps, GravAcc& acc) {
+    const int lane = lane_id();
     const double e2 = eps * eps;
-    // cells
-    if (!FP32C) {
-        double gx = 0, gy = 0, gz = 0, ph = 0;
-        if (tv) {
-            for (int k = phi; k < ncell; k += P_) {
-                const int c = cells[k];
-                const double4 a = mom0[c], b = mom1[c], d = mom2[c];
+    // ---- cells
+    double cgx = 0, cgy = 0, cgz = 0, cph = 0;
+    float fgx = 0, fgy = 0, fgz = 0, fph = 0, kgx = 0, kgy = 0, kgz = 0, kph = 0;
+    auto nadd = [](float& s, float& c, float x) {
+        const float t = s + x;
+        c += (fabsf(s) >= fabsf(x)) ? ((s - t) + x) : ((x - t) + s);
+        s = t;
+    };
+    for (int k0 = 0; k0 < ncell; k0 += 64) {
+        __syncthreads();
+        if (k0 + lane < ncell) {
+            const int c = cells[k0 + lane];
+            S.c0[lane] = mom0[c];
+            S.c1[lane] = mom1[c];
+            S.c2[lane] = mom2[c];
+        }
+        __syncthreads();
+        const int cn = ncell - k0 < 64 ? ncell - k0 : 64;
+        if (!tv) continue;
+        for (int k = phi; k < cn; k += P_) {
+            const double4 a = S.c0[k], b = S.c1[k], d = S.c2[k];
+            if (!FP32C) {
                 const double Rx = me.x - a.y, Ry = me.y - a.z, Rz = me.z - a.w;
                 const double IRx = fma(b.x, Rx, fma(d.x, Ry, d.y * Rz));
                 const double IRy = fma(d.x, Rx, fma(b.y, Ry, d.z * Rz));
                 const double IRz = fma(d.y, Rx, fma(d.z, Ry, b.z * Rz));
                 const double RIR = fma(Rx, IRx, fma(Ry, IRy, Rz * IRz));
                 const double s2 = fma(Rx, Rx, fma(Ry, Ry, fma(Rz, Rz, e2)));
-                const double i1 = 1.0 / sqrt(s2);
+                const double i1 = rsq_nr(s2);
                 const double i2 = i1 * i1, i3 = i1 * i2, i5 = i3 * i2, i7 = i5 * i2;
                 const double cR = -a.x * i3 + 1.5 * b.w * i5 - 7.5 * RIR * i7;
-                gx = fma(cR, Rx, fma(3.0 * i5, IRx, gx));
-                gy = fma(cR, Ry, fma(3.0 * i5, IRy, gy));
-                gz = fma(cR, Rz, fma(3.0 * i5, IRz, gz));
-                ph -= a.x * i1 + 1.5 * RIR * i5 - 0.5 * b.w * i3;
-            }
-        }
-        acc.gx += G * gx; acc.gy += G * gy; acc.gz += G * gz; acc.ph += G * ph;
-    } else {
-        float gx = 0, gy = 0, gz = 0, ph = 0, cgx = 0, cgy = 0, cgz = 0, cph = 0;
-        const float e2f = (float)e2;
-        auto nadd = [](float& s, float& c, float x) {
-            const float t = s + x;
-            c += (fabsf(s) >= fabsf(x)) ? ((s - t) + x) : ((x - t) + s);
-            s = t;
-        };
-        if (tv) {
-            for (int k = phi; k < ncell; k += P_) {
-                const int c = cells[k];
-                const double4 a = mom0[c], b = mom1[c], d = mom2[c];
+                cgx = fma(cR, Rx, fma(3.0 * i5, IRx, cgx));
+                cgy = fma(cR, Ry, fma(3.0 * i5, IRy, cgy));
+                cgz = fma(cR, Rz, fma(3.0 * i5, IRz, cgz));
+                cph -= a.x * i1 + 1.5 * RIR * i5 - 0.5 * b.w * i3;
+            } else {
                 const float Rx = (float)(me.x - a.y), Ry = (float)(me.y - a.z), Rz = (float)(me.z - a.w);
                 const float bx = (float)b.x, by = (float)b.y, bz = (float)b.z, tr = (float)b.w;
                 const float dxy = (float)d.x, dxz = (float)d.y, dyz = (float)d.z, M = (float)a.x;
@@ -71,71 +85,90 @@ __device__ void eval_lists(int ncell, int nleaf, const int* cells, const int* le
                 const float IRy = fmaf(dxy, Rx, fmaf(by, Ry, dyz * Rz));
                 const float IRz = fmaf(dxz, Rx, fmaf(dyz, Ry, bz * Rz));
                 const float RIR = fmaf(Rx, IRx, fmaf(Ry, IRy, Rz * IRz));
-                const float s2 = fmaf(Rx, Rx, fmaf(Ry, Ry, fmaf(Rz, Rz, e2f)));
+                const float s2 = fmaf(Rx, Rx, fmaf(Ry, Ry, fmaf(Rz, Rz, (float)e2)));
                 const float i1 = __builtin_amdgcn_rsqf(s2);
                 const float i2 = i1 * i1, i3 = i1 * i2, i5 = i3 * i2, i7 = i5 * i2;
                 const float cR = -M * i3 + 1.5f * tr * i5 - 7.5f * RIR * i7;
-                nadd(gx, cgx, fmaf(cR, Rx, 3.0f * i5 * IRx));
-                nadd(gy, cgy, fmaf(cR, Ry, 3.0f * i5 * IRy));
-                nadd(gz, cgz, fmaf(cR, Rz, 3.0f * i5 * IRz));
-                nadd(ph, cph, -(M * i1 + 1.5f * RIR * i5 - 0.5f * tr * i3));
+                nadd(fgx, kgx, fmaf(cR, Rx, 3.0f * i5 * IRx));
+                nadd(fgy, kgy, fmaf(cR, Ry, 3.0f * i5 * IRy));
+                nadd(fgz, kgz, fmaf(cR, Rz, 3.0f * i5 * IRz));
+                nadd(fph, kph, -(M * i1 + 1.5f * RIR * i5 - 0.5f * tr * i3));
             }
         }
-        acc.gx += G * ((double)gx + (double)cgx);
-        acc.gy += G * ((double)gy + (double)cgy);
-        acc.gz += G * ((double)gz + (double)cgz);
-        acc.ph += G * ((double)ph + (double)cph);
     }
-    // leaves: stage particles 64 at a time
-    const int lane = lane_id();
-    for (int l0 = 0; l0 < nleaf; ++l0) {
-        const int4 tp = topo[leaves[l0]];
-        for (int p0 = 0; p0 < tp.y; p0 += 64) {
-            const int src = tp.x + p0 + lane;
-            __syncthreads();
-            if (p0 + lane < tp.y) {
-                const double4 p = pos4[src];
-                tile[lane] = make_double4(p.x, p.y, p.z, m[src]);
-                tidx[lane] = src;
+    // ---- leaves: offsets of their particles, then the particles 64 at a time
+    int carry = 0;
+    for (int j0 = 0; j0 < nleaf; j0 += 64) {
+        const int j = j0 + lane;
+        int c = 0, st = 0;
+        if (j < nleaf) {
+            const int4 tp = topo[leaves[j]];
+            st = tp.x;
+            c = tp.y;
+        }
+        const int incl = wave_incl_scan(c);
+        __syncthreads();
+        if (j < nleaf) {
+            leaves[j] = st;
+            S.loff[j] = carry + incl - c;
+        }
+        carry += __shfl(incl, 63, 64);
+    }
+    __syncthreads();
+    const int total = carry;
+    for (int p0 = 0; p0 < total; p0 += 64) {
+        const int p = p0 + lane;
+        __syncthreads();
+        if (p < total) {
+            int a = 0, b = nleaf - 1;
+            while (a < b) {  // largest j with loff[j] <= p
+                const int mid = (a + b + 1) >> 1;
+                if (S.loff[mid] <= p) a = mid;
+                else b = mid - 1;
             }
-            __syncthreads();
-            const int tn = tp.y - p0 < 64 ? tp.y - p0 : 64;
-            if (!tv) continue;
+            const int src = leaves[a] + (p - S.loff[a]);
+            const double4 ps = pos4[src];
+            tile[lane] = make_double4(ps.x, ps.y, ps.z, m[src]);
+            S.src[lane] = src;
+        }
+        __syncthreads();
+        const int tn = total - p0 < 64 ? total - p0 : 64;
+        if (!tv) continue;
+        for (int j = phi; j < tn; j += P_) {
+            const double4 sb = tile[j];
+            if (S.src[j] == q) continue;
             if (!FP32C) {
-                double gx = 0, gy = 0, gz = 0, ph = 0;
-                for (int j = phi; j < tn; j += P_) {
-                    const double4 sb = tile[j];
-                    if (tidx[j] == q) continue;
-                    const double dx = me.x - sb.x, dy = me.y - sb.y, dz = me.z - sb.z;
-                    const double s2 = fma(dx, dx, fma(dy, dy, fma(dz, dz, e2)));
-                    const double i1 = 1.0 / sqrt(s2);
-                    const double mi3 = sb.w * i1 * i1 * i1;
-                    gx = fma(-mi3, dx, gx);
-                    gy = fma(-mi3, dy, gy);
-                    gz = fma(-mi3, dz, gz);
-                    ph = fma(-sb.w, i1, ph);
-                }
-                acc.gx += G * gx; acc.gy += G * gy; acc.gz += G * gz; acc.ph += G * ph;
+                const double dx = me.x - sb.x, dy = me.y - sb.y, dz = me.z - sb.z;
+                const double s2 = fma(dx, dx, fma(dy, dy, fma(dz, dz, e2)));
+                const double i1 = rsq_nr(s2);
+                const double mi3 = sb.w * i1 * i1 * i1;
+                cgx = fma(-mi3, dx, cgx);
+                cgy = fma(-mi3, dy, cgy);
+                cgz = fma(-mi3, dz, cgz);
+                cph = fma(-sb.w, i1, cph);
             } else {
-                float gx = 0, gy = 0, gz = 0, ph = 0;
-                const float e2f = (float)e2;
-                for (int j = phi; j < tn; j += P_) {
-                    const double4 sb = tile[j];
-                    if (tidx[j] == q) continue;
-                    const float dx = (float)(me.x - sb.x), dy = (float)(me.y - sb.y), dz = (float)(me.z - sb.z);
-                    const float s2 = fmaf(dx, dx, fmaf(dy, dy, fmaf(dz, dz, e2f)));
-                    const float i1 = __builtin_amdgcn_rsqf(s2);
-                    const float mb = (float)sb.w;
-                    const float mi3 = mb * i1 * i1 * i1;
-                    gx = fmaf(-mi3, dx, gx);
-                    gy = fmaf(-mi3, dy, gy);
-                    gz = fmaf(-mi3, dz, gz);
-                    ph = fmaf(-mb, i1, ph);
-                }
-                acc.gx += G * (double)gx; acc.gy += G * (double)gy; acc.gz += G * (double)gz; acc.ph += G * (double)ph;
+                const float dx = (float)(me.x - sb.x), dy = (float)(me.y - sb.y), dz = (float)(me.z - sb.z);
+                const float s2 = fmaf(dx, dx, fmaf(dy, dy, fmaf(dz, dz, (float)e2)));
+                const float i1 = __builtin_amdgcn_rsqf(s2);
+                const float mb = (float)sb.w;
+                const float mi3 = mb * i1 * i1 * i1;
+                nadd(fgx, kgx, -mi3 * dx);
+                nadd(fgy, kgy, -mi3 * dy);
+                nadd(fgz, kgz, -mi3 * dz);
+                nadd(fph, kph, -mb * i1);
             }
         }
     }
+    if (FP32C) {
+        cgx = (double)fgx + (double)kgx;
+        cgy = (double)fgy + (double)kgy;
+        cgz = (double)fgz + (double)kgz;
+        cph = (double)fph + (double)kph;
+    }
+    acc.gx += G * cgx;
+    acc.gy += G * cgy;
+    acc.gz += G * cgz;
+    acc.ph += G * cph;
 }
 
 template <bool FP32C>
@@ -151,7 +184,7 @@ __global__ void __launch_bounds__(64) k_gravity(DevCtl* ctl, const int4* __restr
     __shared__ int cells[GW_CELLS];
     __shared__ int leaves[GW_LEAVES];
     __shared__ double4 tile[64];
-    __shared__ int tidx[64];
+    __shared__ GravStage S;
     const int lane = lane_id();
     const int t = lane & (gsz - 1), phi = lane / gsz, P_ = 64 / gsz;
     int g0, g1, gstep;
@@ -179,7 +212,7 @@ __global__ void __launch_bounds__(64) k_gravity(DevCtl* ctl, const int4* __restr
             break;
         }
         if (nc + 64 > GW_CELLS || nl + 64 > GW_LEAVES) {
-            eval_lists<FP32C>(nc, nl, cells, leaves, tile, tidx, topo, mom0, mom1, mom2, pos4, m, me, q, tv, phi, P_,
+            eval_lists<FP32C>(nc, nl, cells, leaves, S, tile, topo, mom0, mom1, mom2, pos4, m, me, q, tv, phi, P_,
                               G, eps, acc);
             nc = nl = 0;
             __syncthreads();
@@ -224,7 +257,7 @@ __global__ void __launch_bounds__(64) k_gravity(DevCtl* ctl, const int4* __restr
         __syncthreads();
     }
     __syncthreads();
-    eval_lists<FP32C>(nc, nl, cells, leaves, tile, tidx, topo, mom0, mom1, mom2, pos4, m, me, q, tv, phi, P_, G, eps,
+    eval_lists<FP32C>(nc, nl, cells, leaves, S, tile, topo, mom0, mom1, mom2, pos4, m, me, q, tv, phi, P_, G, eps,
                       acc);
     acc.gx = lanes_sum_d(acc.gx, gsz);
     acc.gy = lanes_sum_d(acc.gy, gsz);
