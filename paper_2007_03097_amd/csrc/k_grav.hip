@@ -15,7 +15,7 @@
 // the evaluation stages cell moments and leaf particles through LDS 64 at a time.
 #include "common.h"
 
-constexpr int GW_STACK = 1024;
+constexpr int GW_STACK = 512;
 constexpr int GW_CELLS = 512;
 constexpr int GW_LEAVES = 256;
 
@@ -23,46 +23,68 @@ struct GravAcc {
     double gx = 0, gy = 0, gz = 0, ph = 0;
 };
 
-// LDS staging shared by the cell and particle phases of one evaluation.
+// LDS staging of one evaluation: cell moments in the cell phase, particles in the leaf phase.
 struct GravStage {
-    double4 c0[64], c1[64], c2[64];  // cell moments (M, com), (Ixx, Iyy, Izz, tr I), (Ixy, Ixz, Iyz, -)
-    int loff[GW_LEAVES + 1];         // particle offsets of the staged leaves
-    int src[64];                     // particle index of each staged source (self test)
+    union {
+        struct {
+            double4 c0[64], c1[64], c2[64];  // (M, com), (Ixx, Iyy, Izz, tr I), (Ixy, Ixz, Iyz, -)
+        } cell;
+        struct {
+            double4 pm[64];  // (x, y, z, m)
+            int src[64];     // particle index (self test without softening)
+        } part;
+    };
+    int loff[GW_LEAVES + 1];  // particle offsets of the staged leaves
+};
+
+// Kahan-compensated FP32 sum of FP32 partial sums (one add per staged tile).
+struct KahanF {
+    float s = 0.0f, c = 0.0f;
+    __device__ __forceinline__ void add(float x) {
+        const float y = x - c;
+        const float t = s + y;
+        c = (t - s) - y;
+        s = t;
+    }
+    __device__ __forceinline__ double value() const { return (double)s - (double)c; }
 };
 
 // Accepted cells (monopole + quadrupole) and unaccepted leaves (softened particle sums,
 // self skipped) for target `me` (index q).  Cells are staged 64 at a time (one lane loads
 // one cell); the leaves' particles are concatenated and staged 64 at a time, so every
 // staging round is one load per lane.  Lane (t, phi) takes every P_-th staged item.
+// Accepted cells (monopole + quadrupole) and unaccepted leaves (softened particle sums,
+// self excluded) for target `me` (index q).  Cells are staged 64 at a time (one lane loads
+// one cell); the leaves' particles are concatenated and staged 64 at a time, so every
+// staging round is one load per lane.  Lane (t, phi) takes every P_-th staged item.
+// FP32C: the terms of one staged tile are summed in FP32, and the tile sums enter Kahan-
+// compensated FP32 accumulators.  With softening the self pair is evaluated like any
+// other (it adds no force) and its potential term -m_q/eps is taken out at the end.
 template <bool FP32C>
-__device__ void eval_lists(int ncell, int nleaf, const int* cells, int* leaves, GravStage& S, double4* tile,
+__device__ void eval_lists(int ncell, int nleaf, const int* cells, int* leaves, GravStage& S,
                            const int4* __restrict__ topo, const double4* __restrict__ mom0,
                            const double4* __restrict__ mom1, const double4* __restrict__ mom2,
                            const double4* __restrict__ pos4, const double* __restrict__ m, const double4 me, int q,
                            bool tv, int phi, int P_, double G, double eps, GravAcc& acc) {
     const int lane = lane_id();
     const double e2 = eps * eps;
-    // ---- cells
     double cgx = 0, cgy = 0, cgz = 0, cph = 0;
-    float fgx = 0, fgy = 0, fgz = 0, fph = 0, kgx = 0, kgy = 0, kgz = 0, kph = 0;
-    auto nadd = [](float& s, float& c, float x) {
-        const float t = s + x;
-        c += (fabsf(s) >= fabsf(x)) ? ((s - t) + x) : ((x - t) + s);
-        s = t;
-    };
+    KahanF kx, ky, kz, kp;
+    // ---- cells
     for (int k0 = 0; k0 < ncell; k0 += 64) {
         __syncthreads();
         if (k0 + lane < ncell) {
             const int c = cells[k0 + lane];
-            S.c0[lane] = mom0[c];
-            S.c1[lane] = mom1[c];
-            S.c2[lane] = mom2[c];
+            S.cell.c0[lane] = mom0[c];
+            S.cell.c1[lane] = mom1[c];
+            S.cell.c2[lane] = mom2[c];
         }
         __syncthreads();
         const int cn = ncell - k0 < 64 ? ncell - k0 : 64;
         if (!tv) continue;
+        float tx = 0.0f, ty = 0.0f, tz = 0.0f, tph = 0.0f;
         for (int k = phi; k < cn; k += P_) {
-            const double4 a = S.c0[k], b = S.c1[k], d = S.c2[k];
+            const double4 a = S.cell.c0[k], b = S.cell.c1[k], d = S.cell.c2[k];
             if (!FP32C) {
                 const double Rx = me.x - a.y, Ry = me.y - a.z, Rz = me.z - a.w;
                 const double IRx = fma(b.x, Rx, fma(d.x, Ry, d.y * Rz));
@@ -89,11 +111,14 @@ __device__ void eval_lists(int ncell, int nleaf, const int* cells, int* leaves, 
                 const float i1 = __builtin_amdgcn_rsqf(s2);
                 const float i2 = i1 * i1, i3 = i1 * i2, i5 = i3 * i2, i7 = i5 * i2;
                 const float cR = -M * i3 + 1.5f * tr * i5 - 7.5f * RIR * i7;
-                nadd(fgx, kgx, fmaf(cR, Rx, 3.0f * i5 * IRx));
-                nadd(fgy, kgy, fmaf(cR, Ry, 3.0f * i5 * IRy));
-                nadd(fgz, kgz, fmaf(cR, Rz, 3.0f * i5 * IRz));
-                nadd(fph, kph, -(M * i1 + 1.5f * RIR * i5 - 0.5f * tr * i3));
+                tx = fmaf(cR, Rx, fmaf(3.0f * i5, IRx, tx));
+                ty = fmaf(cR, Ry, fmaf(3.0f * i5, IRy, ty));
+                tz = fmaf(cR, Rz, fmaf(3.0f * i5, IRz, tz));
+                tph -= M * i1 + 1.5f * RIR * i5 - 0.5f * tr * i3;
             }
+        }
+        if (FP32C) {
+            kx.add(tx); ky.add(ty); kz.add(tz); kp.add(tph);
         }
     }
     // ---- leaves: offsets of their particles, then the particles 64 at a time
@@ -116,6 +141,7 @@ __device__ void eval_lists(int ncell, int nleaf, const int* cells, int* leaves, 
     }
     __syncthreads();
     const int total = carry;
+    const bool soft = e2 > 0.0;
     for (int p0 = 0; p0 < total; p0 += 64) {
         const int p = p0 + lane;
         __syncthreads();
@@ -128,15 +154,16 @@ __device__ void eval_lists(int ncell, int nleaf, const int* cells, int* leaves, 
             }
             const int src = leaves[a] + (p - S.loff[a]);
             const double4 ps = pos4[src];
-            tile[lane] = make_double4(ps.x, ps.y, ps.z, m[src]);
-            S.src[lane] = src;
+            S.part.pm[lane] = make_double4(ps.x, ps.y, ps.z, m[src]);
+            S.part.src[lane] = src;
         }
         __syncthreads();
         const int tn = total - p0 < 64 ? total - p0 : 64;
         if (!tv) continue;
+        float tx = 0.0f, ty = 0.0f, tz = 0.0f, tph = 0.0f;
         for (int j = phi; j < tn; j += P_) {
-            const double4 sb = tile[j];
-            if (S.src[j] == q) continue;
+            const double4 sb = S.part.pm[j];
+            if (!soft && S.part.src[j] == q) continue;
             if (!FP32C) {
                 const double dx = me.x - sb.x, dy = me.y - sb.y, dz = me.z - sb.z;
                 const double s2 = fma(dx, dx, fma(dy, dy, fma(dz, dz, e2)));
@@ -152,18 +179,21 @@ __device__ void eval_lists(int ncell, int nleaf, const int* cells, int* leaves, 
                 const float i1 = __builtin_amdgcn_rsqf(s2);
                 const float mb = (float)sb.w;
                 const float mi3 = mb * i1 * i1 * i1;
-                nadd(fgx, kgx, -mi3 * dx);
-                nadd(fgy, kgy, -mi3 * dy);
-                nadd(fgz, kgz, -mi3 * dz);
-                nadd(fph, kph, -mb * i1);
+                tx = fmaf(-mi3, dx, tx);
+                ty = fmaf(-mi3, dy, ty);
+                tz = fmaf(-mi3, dz, tz);
+                tph = fmaf(-mb, i1, tph);
             }
+        }
+        if (FP32C) {
+            kx.add(tx); ky.add(ty); kz.add(tz); kp.add(tph);
         }
     }
     if (FP32C) {
-        cgx = (double)fgx + (double)kgx;
-        cgy = (double)fgy + (double)kgy;
-        cgz = (double)fgz + (double)kgz;
-        cph = (double)fph + (double)kph;
+        cgx = kx.value();
+        cgy = ky.value();
+        cgz = kz.value();
+        cph = kp.value();
     }
     acc.gx += G * cgx;
     acc.gy += G * cgy;
@@ -183,7 +213,6 @@ __global__ void __launch_bounds__(64) k_gravity(DevCtl* ctl, const int4* __restr
     __shared__ int stack[GW_STACK];
     __shared__ int cells[GW_CELLS];
     __shared__ int leaves[GW_LEAVES];
-    __shared__ double4 tile[64];
     __shared__ GravStage S;
     const int lane = lane_id();
     const int t = lane & (gsz - 1), phi = lane / gsz, P_ = 64 / gsz;
@@ -212,7 +241,7 @@ __global__ void __launch_bounds__(64) k_gravity(DevCtl* ctl, const int4* __restr
             break;
         }
         if (nc + 64 > GW_CELLS || nl + 64 > GW_LEAVES) {
-            eval_lists<FP32C>(nc, nl, cells, leaves, S, tile, topo, mom0, mom1, mom2, pos4, m, me, q, tv, phi, P_,
+            eval_lists<FP32C>(nc, nl, cells, leaves, S, topo, mom0, mom1, mom2, pos4, m, me, q, tv, phi, P_,
                               G, eps, acc);
             nc = nl = 0;
             __syncthreads();
@@ -257,13 +286,18 @@ __global__ void __launch_bounds__(64) k_gravity(DevCtl* ctl, const int4* __restr
         __syncthreads();
     }
     __syncthreads();
-    eval_lists<FP32C>(nc, nl, cells, leaves, S, tile, topo, mom0, mom1, mom2, pos4, m, me, q, tv, phi, P_, G, eps,
+    eval_lists<FP32C>(nc, nl, cells, leaves, S, topo, mom0, mom1, mom2, pos4, m, me, q, tv, phi, P_, G, eps,
                       acc);
     acc.gx = lanes_sum_d(acc.gx, gsz);
     acc.gy = lanes_sum_d(acc.gy, gsz);
     acc.gz = lanes_sum_d(acc.gz, gsz);
     acc.ph = lanes_sum_d(acc.ph, gsz);
     if (tv && phi == 0) {
+        if (eps > 0.0) {  // take out the self pair's potential term (see eval_lists)
+            const double e2 = eps * eps;
+            const double is = FP32C ? (double)__builtin_amdgcn_rsqf((float)e2) : rsq_nr(e2);
+            acc.ph += G * (m[q] * is);
+        }
         if (accumulate) {
             gxo[q] += acc.gx;
             gyo[q] += acc.gy;
