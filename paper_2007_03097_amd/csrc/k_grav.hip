@@ -1,7 +1,7 @@
 // Octree self-gravity (Sec. 2.2.2 of arXiv:2007.03097, eq. (10), with Plummer softening
 // and quadrupole moments).
 //
-// One wavefront per target group.  The wide walk tests up to 64 nodes at once against the
+// One wavefront per target group, two targets per lane.  The wide walk tests up to 64 nodes at once against the
 // group's box: a cell B of side s_B is accepted for the whole group when its particle box
 // does not touch the group box and s_B < theta d, d being the distance from B's centre of
 // mass to the group box (theta = 0 opens everything: the exact direct sum).  Accepted
@@ -18,10 +18,6 @@
 constexpr int GW_STACK = 512;
 constexpr int GW_CELLS = 512;
 constexpr int GW_LEAVES = 256;
-
-struct GravAcc {
-    double gx = 0, gy = 0, gz = 0, ph = 0;
-};
 
 // LDS staging of one evaluation: cell moments in the cell phase, particles in the leaf phase.
 struct GravStage {
@@ -49,76 +45,124 @@ struct KahanF {
     __device__ __forceinline__ double value() const { return (double)s - (double)c; }
 };
 
+// Per-target accumulators: FP64 sums, or FP32 sums of one staged tile (t*) that enter
+// Kahan-compensated FP32 accumulators (k*) once per tile.
+struct TargetSums {
+    double gx = 0, gy = 0, gz = 0, ph = 0;
+    float tx = 0, ty = 0, tz = 0, tph = 0;
+    KahanF kx, ky, kz, kp;
+    __device__ __forceinline__ void flush_tile() {
+        kx.add(tx); ky.add(ty); kz.add(tz); kp.add(tph);
+        tx = ty = tz = tph = 0.0f;
+    }
+};
+
+// Monopole + quadrupole of cell (a = (M, com), b = (Ixx, Iyy, Izz, tr I), d = (Ixy, Ixz, Iyz)).
+template <bool FP32C>
+__device__ __forceinline__ void cell_term(const double4 me, const double4 a, const double4 b, const double4 d,
+                                          double e2, TargetSums& S) {
+    if (!FP32C) {
+        const double Rx = me.x - a.y, Ry = me.y - a.z, Rz = me.z - a.w;
+        const double IRx = fma(b.x, Rx, fma(d.x, Ry, d.y * Rz));
+        const double IRy = fma(d.x, Rx, fma(b.y, Ry, d.z * Rz));
+        const double IRz = fma(d.y, Rx, fma(d.z, Ry, b.z * Rz));
+        const double RIR = fma(Rx, IRx, fma(Ry, IRy, Rz * IRz));
+        const double s2 = fma(Rx, Rx, fma(Ry, Ry, fma(Rz, Rz, e2)));
+        const double i1 = rsq_nr(s2);
+        const double i2 = i1 * i1, i3 = i1 * i2, i5 = i3 * i2, i7 = i5 * i2;
+        const double cR = -a.x * i3 + 1.5 * b.w * i5 - 7.5 * RIR * i7;
+        S.gx = fma(cR, Rx, fma(3.0 * i5, IRx, S.gx));
+        S.gy = fma(cR, Ry, fma(3.0 * i5, IRy, S.gy));
+        S.gz = fma(cR, Rz, fma(3.0 * i5, IRz, S.gz));
+        S.ph -= a.x * i1 + 1.5 * RIR * i5 - 0.5 * b.w * i3;
+    } else {
+        const float Rx = (float)(me.x - a.y), Ry = (float)(me.y - a.z), Rz = (float)(me.z - a.w);
+        const float bx = (float)b.x, by = (float)b.y, bz = (float)b.z, tr = (float)b.w;
+        const float dxy = (float)d.x, dxz = (float)d.y, dyz = (float)d.z, M = (float)a.x;
+        const float IRx = fmaf(bx, Rx, fmaf(dxy, Ry, dxz * Rz));
+        const float IRy = fmaf(dxy, Rx, fmaf(by, Ry, dyz * Rz));
+        const float IRz = fmaf(dxz, Rx, fmaf(dyz, Ry, bz * Rz));
+        const float RIR = fmaf(Rx, IRx, fmaf(Ry, IRy, Rz * IRz));
+        const float s2 = fmaf(Rx, Rx, fmaf(Ry, Ry, fmaf(Rz, Rz, (float)e2)));
+        const float i1 = __builtin_amdgcn_rsqf(s2);
+        const float i2 = i1 * i1, i3 = i1 * i2, i5 = i3 * i2, i7 = i5 * i2;
+        const float cR = -M * i3 + 1.5f * tr * i5 - 7.5f * RIR * i7;
+        S.tx = fmaf(cR, Rx, fmaf(3.0f * i5, IRx, S.tx));
+        S.ty = fmaf(cR, Ry, fmaf(3.0f * i5, IRy, S.ty));
+        S.tz = fmaf(cR, Rz, fmaf(3.0f * i5, IRz, S.tz));
+        S.tph -= M * i1 + 1.5f * RIR * i5 - 0.5f * tr * i3;
+    }
+}
+
+// Softened particle term of source sb = (x, y, z, m).
+template <bool FP32C>
+__device__ __forceinline__ void part_term(const double4 me, const double4 sb, double e2, TargetSums& S) {
+    if (!FP32C) {
+        const double dx = me.x - sb.x, dy = me.y - sb.y, dz = me.z - sb.z;
+        const double s2 = fma(dx, dx, fma(dy, dy, fma(dz, dz, e2)));
+        const double i1 = rsq_nr(s2);
+        const double mi3 = sb.w * i1 * i1 * i1;
+        S.gx = fma(-mi3, dx, S.gx);
+        S.gy = fma(-mi3, dy, S.gy);
+        S.gz = fma(-mi3, dz, S.gz);
+        S.ph = fma(-sb.w, i1, S.ph);
+    } else {
+        const float dx = (float)(me.x - sb.x), dy = (float)(me.y - sb.y), dz = (float)(me.z - sb.z);
+        const float s2 = fmaf(dx, dx, fmaf(dy, dy, fmaf(dz, dz, (float)e2)));
+        const float i1 = __builtin_amdgcn_rsqf(s2);
+        const float mb = (float)sb.w;
+        const float mi3 = mb * i1 * i1 * i1;
+        S.tx = fmaf(-mi3, dx, S.tx);
+        S.ty = fmaf(-mi3, dy, S.ty);
+        S.tz = fmaf(-mi3, dz, S.tz);
+        S.tph = fmaf(-mb, i1, S.tph);
+    }
+}
+
+// Two targets per lane: tp and tp + TP (TP = group_size / 2); the P = 64 / TP lanes with
+// the same tp split every staged tile, so each LDS read of a cell or particle feeds two
+// evaluations.
+struct GravTargets {
+    double4 a, b;
+    int qa, qb;
+    bool va, vb;
+    int tp, phi, TP, P;
+};
+
 // Accepted cells (monopole + quadrupole) and unaccepted leaves (softened particle sums,
-// self skipped) for target `me` (index q).  Cells are staged 64 at a time (one lane loads
+// self excluded) for the lane's targets.  Cells are staged 64 at a time (one lane loads
 // one cell); the leaves' particles are concatenated and staged 64 at a time, so every
-// staging round is one load per lane.  Lane (t, phi) takes every P_-th staged item.
-// Accepted cells (monopole + quadrupole) and unaccepted leaves (softened particle sums,
-// self excluded) for target `me` (index q).  Cells are staged 64 at a time (one lane loads
-// one cell); the leaves' particles are concatenated and staged 64 at a time, so every
-// staging round is one load per lane.  Lane (t, phi) takes every P_-th staged item.
-// FP32C: the terms of one staged tile are summed in FP32, and the tile sums enter Kahan-
-// compensated FP32 accumulators.  With softening the self pair is evaluated like any
+// staging round is one load per lane.  With softening the self pair is evaluated like any
 // other (it adds no force) and its potential term -m_q/eps is taken out at the end.
 template <bool FP32C>
-__device__ void eval_lists(int ncell, int nleaf, const int* cells, int* leaves, GravStage& S,
+__device__ void eval_lists(int ncell, int nleaf, const int* cells, int* leaves, GravStage& St,
                            const int4* __restrict__ topo, const double4* __restrict__ mom0,
                            const double4* __restrict__ mom1, const double4* __restrict__ mom2,
-                           const double4* __restrict__ pos4, const double* __restrict__ m, const double4 me, int q,
-                           bool tv, int phi, int P_, double G, double eps, GravAcc& acc) {
+                           const double4* __restrict__ pos4, const double* __restrict__ m, const GravTargets& T,
+                           double eps, TargetSums& A, TargetSums& B) {
     const int lane = lane_id();
     const double e2 = eps * eps;
-    double cgx = 0, cgy = 0, cgz = 0, cph = 0;
-    KahanF kx, ky, kz, kp;
+    const bool any = T.va || T.vb;
     // ---- cells
     for (int k0 = 0; k0 < ncell; k0 += 64) {
         __syncthreads();
         if (k0 + lane < ncell) {
             const int c = cells[k0 + lane];
-            S.cell.c0[lane] = mom0[c];
-            S.cell.c1[lane] = mom1[c];
-            S.cell.c2[lane] = mom2[c];
+            St.cell.c0[lane] = mom0[c];
+            St.cell.c1[lane] = mom1[c];
+            St.cell.c2[lane] = mom2[c];
         }
         __syncthreads();
         const int cn = ncell - k0 < 64 ? ncell - k0 : 64;
-        if (!tv) continue;
-        float tx = 0.0f, ty = 0.0f, tz = 0.0f, tph = 0.0f;
-        for (int k = phi; k < cn; k += P_) {
-            const double4 a = S.cell.c0[k], b = S.cell.c1[k], d = S.cell.c2[k];
-            if (!FP32C) {
-                const double Rx = me.x - a.y, Ry = me.y - a.z, Rz = me.z - a.w;
-                const double IRx = fma(b.x, Rx, fma(d.x, Ry, d.y * Rz));
-                const double IRy = fma(d.x, Rx, fma(b.y, Ry, d.z * Rz));
-                const double IRz = fma(d.y, Rx, fma(d.z, Ry, b.z * Rz));
-                const double RIR = fma(Rx, IRx, fma(Ry, IRy, Rz * IRz));
-                const double s2 = fma(Rx, Rx, fma(Ry, Ry, fma(Rz, Rz, e2)));
-                const double i1 = rsq_nr(s2);
-                const double i2 = i1 * i1, i3 = i1 * i2, i5 = i3 * i2, i7 = i5 * i2;
-                const double cR = -a.x * i3 + 1.5 * b.w * i5 - 7.5 * RIR * i7;
-                cgx = fma(cR, Rx, fma(3.0 * i5, IRx, cgx));
-                cgy = fma(cR, Ry, fma(3.0 * i5, IRy, cgy));
-                cgz = fma(cR, Rz, fma(3.0 * i5, IRz, cgz));
-                cph -= a.x * i1 + 1.5 * RIR * i5 - 0.5 * b.w * i3;
-            } else {
-                const float Rx = (float)(me.x - a.y), Ry = (float)(me.y - a.z), Rz = (float)(me.z - a.w);
-                const float bx = (float)b.x, by = (float)b.y, bz = (float)b.z, tr = (float)b.w;
-                const float dxy = (float)d.x, dxz = (float)d.y, dyz = (float)d.z, M = (float)a.x;
-                const float IRx = fmaf(bx, Rx, fmaf(dxy, Ry, dxz * Rz));
-                const float IRy = fmaf(dxy, Rx, fmaf(by, Ry, dyz * Rz));
-                const float IRz = fmaf(dxz, Rx, fmaf(dyz, Ry, bz * Rz));
-                const float RIR = fmaf(Rx, IRx, fmaf(Ry, IRy, Rz * IRz));
-                const float s2 = fmaf(Rx, Rx, fmaf(Ry, Ry, fmaf(Rz, Rz, (float)e2)));
-                const float i1 = __builtin_amdgcn_rsqf(s2);
-                const float i2 = i1 * i1, i3 = i1 * i2, i5 = i3 * i2, i7 = i5 * i2;
-                const float cR = -M * i3 + 1.5f * tr * i5 - 7.5f * RIR * i7;
-                tx = fmaf(cR, Rx, fmaf(3.0f * i5, IRx, tx));
-                ty = fmaf(cR, Ry, fmaf(3.0f * i5, IRy, ty));
-                tz = fmaf(cR, Rz, fmaf(3.0f * i5, IRz, tz));
-                tph -= M * i1 + 1.5f * RIR * i5 - 0.5f * tr * i3;
-            }
+        if (!any) continue;
+        for (int k = T.phi; k < cn; k += T.P) {
+            const double4 a = St.cell.c0[k], b = St.cell.c1[k], d = St.cell.c2[k];
+            cell_term<FP32C>(T.a, a, b, d, e2, A);
+            cell_term<FP32C>(T.b, a, b, d, e2, B);
         }
         if (FP32C) {
-            kx.add(tx); ky.add(ty); kz.add(tz); kp.add(tph);
+            A.flush_tile();
+            B.flush_tile();
         }
     }
     // ---- leaves: offsets of their particles, then the particles 64 at a time
@@ -135,7 +179,7 @@ __device__ void eval_lists(int ncell, int nleaf, const int* cells, int* leaves, 
         __syncthreads();
         if (j < nleaf) {
             leaves[j] = st;
-            S.loff[j] = carry + incl - c;
+            St.loff[j] = carry + incl - c;
         }
         carry += __shfl(incl, 63, 64);
     }
@@ -149,56 +193,36 @@ __device__ void eval_lists(int ncell, int nleaf, const int* cells, int* leaves, 
             int a = 0, b = nleaf - 1;
             while (a < b) {  // largest j with loff[j] <= p
                 const int mid = (a + b + 1) >> 1;
-                if (S.loff[mid] <= p) a = mid;
+                if (St.loff[mid] <= p) a = mid;
                 else b = mid - 1;
             }
-            const int src = leaves[a] + (p - S.loff[a]);
+            const int src = leaves[a] + (p - St.loff[a]);
             const double4 ps = pos4[src];
-            S.part.pm[lane] = make_double4(ps.x, ps.y, ps.z, m[src]);
-            S.part.src[lane] = src;
+            St.part.pm[lane] = make_double4(ps.x, ps.y, ps.z, m[src]);
+            St.part.src[lane] = src;
         }
         __syncthreads();
         const int tn = total - p0 < 64 ? total - p0 : 64;
-        if (!tv) continue;
-        float tx = 0.0f, ty = 0.0f, tz = 0.0f, tph = 0.0f;
-        for (int j = phi; j < tn; j += P_) {
-            const double4 sb = S.part.pm[j];
-            if (!soft && S.part.src[j] == q) continue;
-            if (!FP32C) {
-                const double dx = me.x - sb.x, dy = me.y - sb.y, dz = me.z - sb.z;
-                const double s2 = fma(dx, dx, fma(dy, dy, fma(dz, dz, e2)));
-                const double i1 = rsq_nr(s2);
-                const double mi3 = sb.w * i1 * i1 * i1;
-                cgx = fma(-mi3, dx, cgx);
-                cgy = fma(-mi3, dy, cgy);
-                cgz = fma(-mi3, dz, cgz);
-                cph = fma(-sb.w, i1, cph);
-            } else {
-                const float dx = (float)(me.x - sb.x), dy = (float)(me.y - sb.y), dz = (float)(me.z - sb.z);
-                const float s2 = fmaf(dx, dx, fmaf(dy, dy, fmaf(dz, dz, (float)e2)));
-                const float i1 = __builtin_amdgcn_rsqf(s2);
-                const float mb = (float)sb.w;
-                const float mi3 = mb * i1 * i1 * i1;
-                tx = fmaf(-mi3, dx, tx);
-                ty = fmaf(-mi3, dy, ty);
-                tz = fmaf(-mi3, dz, tz);
-                tph = fmaf(-mb, i1, tph);
+        if (!any) continue;
+        if (soft) {
+            for (int j = T.phi; j < tn; j += T.P) {
+                const double4 sb = St.part.pm[j];
+                part_term<FP32C>(T.a, sb, e2, A);
+                part_term<FP32C>(T.b, sb, e2, B);
+            }
+        } else {
+            for (int j = T.phi; j < tn; j += T.P) {
+                const double4 sb = St.part.pm[j];
+                const int s = St.part.src[j];
+                if (s != T.qa) part_term<FP32C>(T.a, sb, e2, A);
+                if (s != T.qb) part_term<FP32C>(T.b, sb, e2, B);
             }
         }
         if (FP32C) {
-            kx.add(tx); ky.add(ty); kz.add(tz); kp.add(tph);
+            A.flush_tile();
+            B.flush_tile();
         }
     }
-    if (FP32C) {
-        cgx = kx.value();
-        cgy = ky.value();
-        cgz = kz.value();
-        cph = kp.value();
-    }
-    acc.gx += G * cgx;
-    acc.gy += G * cgy;
-    acc.gz += G * cgz;
-    acc.ph += G * cph;
 }
 
 template <bool FP32C>
@@ -213,102 +237,124 @@ __global__ void __launch_bounds__(64) k_gravity(DevCtl* ctl, const int4* __restr
     __shared__ int stack[GW_STACK];
     __shared__ int cells[GW_CELLS];
     __shared__ int leaves[GW_LEAVES];
-    __shared__ GravStage S;
+    __shared__ GravStage St;
     const int lane = lane_id();
-    const int t = lane & (gsz - 1), phi = lane / gsz, P_ = 64 / gsz;
+    GravTargets T;
+    T.TP = gsz >> 1;
+    T.P = 64 / T.TP;
+    T.tp = lane & (T.TP - 1);
+    T.phi = lane / T.TP;
     int g0, g1, gstep;
     group_range(ctl->n_groups, g0, g1, gstep);
     for (int gi = g0; gi < g1; gi += gstep) {
-    const int4 g = group[gi];
-    const bool tv = t < g.y;
-    const int q = g.x + t;
-    const double4 me = tv ? pos4[q] : make_double4(0, 0, 0, 0);
-    double lo[3], hi[3];
-    lo[0] = wave_min(tv ? me.x : INFINITY); hi[0] = wave_max(tv ? me.x : -INFINITY);
-    lo[1] = wave_min(tv ? me.y : INFINITY); hi[1] = wave_max(tv ? me.y : -INFINITY);
-    lo[2] = wave_min(tv ? me.z : INFINITY); hi[2] = wave_max(tv ? me.z : -INFINITY);
-    const double th2 = theta * theta;
-    const u64 lt = lanemask_lt();
-    GravAcc acc;
-    const int root = g.z < 0 ? 0 : ctl->level_off[3] + g.z;
-    __syncthreads();
-    if (lane == 0) stack[0] = root;
-    int sp = 1, nc = 0, nl = 0, iters = 0;
-    __syncthreads();
-    while (sp > 0) {
-        if (++iters > (1 << 22)) {  // bounded: every wave leaves the loop
-            if (lane == 0) set_err(ctl, ERR_GRAV_LIST);
-            break;
-        }
-        if (nc + 64 > GW_CELLS || nl + 64 > GW_LEAVES) {
-            eval_lists<FP32C>(nc, nl, cells, leaves, S, topo, mom0, mom1, mom2, pos4, m, me, q, tv, phi, P_,
-                              G, eps, acc);
-            nc = nl = 0;
+        const int4 g = group[gi];
+        T.qa = g.x + T.tp;
+        T.qb = g.x + T.tp + T.TP;
+        T.va = T.tp < g.y;
+        T.vb = T.tp + T.TP < g.y;
+        T.a = T.va ? pos4[T.qa] : make_double4(0, 0, 0, 0);
+        T.b = T.vb ? pos4[T.qb] : make_double4(0, 0, 0, 0);
+        double lo[3], hi[3];
+        lo[0] = wave_min(fmin(T.va ? T.a.x : INFINITY, T.vb ? T.b.x : INFINITY));
+        lo[1] = wave_min(fmin(T.va ? T.a.y : INFINITY, T.vb ? T.b.y : INFINITY));
+        lo[2] = wave_min(fmin(T.va ? T.a.z : INFINITY, T.vb ? T.b.z : INFINITY));
+        hi[0] = wave_max(fmax(T.va ? T.a.x : -INFINITY, T.vb ? T.b.x : -INFINITY));
+        hi[1] = wave_max(fmax(T.va ? T.a.y : -INFINITY, T.vb ? T.b.y : -INFINITY));
+        hi[2] = wave_max(fmax(T.va ? T.a.z : -INFINITY, T.vb ? T.b.z : -INFINITY));
+        const double th2 = theta * theta;
+        const u64 lt = lanemask_lt();
+        TargetSums A, B;
+        const int root = g.z < 0 ? 0 : ctl->level_off[3] + g.z;
+        __syncthreads();
+        if (lane == 0) stack[0] = root;
+        int sp = 1, nc = 0, nl = 0, iters = 0;
+        __syncthreads();
+        while (sp > 0) {
+            if (++iters > (1 << 22)) {  // bounded: every wave leaves the loop
+                if (lane == 0) set_err(ctl, ERR_GRAV_LIST);
+                break;
+            }
+            if (nc + 64 > GW_CELLS || nl + 64 > GW_LEAVES) {
+                eval_lists<FP32C>(nc, nl, cells, leaves, St, topo, mom0, mom1, mom2, pos4, m, T, eps, A, B);
+                nc = nl = 0;
+                __syncthreads();
+            }
+            int k = sp < 64 ? sp : 64;
+            const int room = (GW_STACK - sp) / 8;
+            if (k > room) k = room > 1 ? room : 1;
+            const int node = lane < k ? stack[sp - k + lane] : -1;
+            __syncthreads();
+            sp -= k;
+            int kind = 0;  // 1 = accepted cell, 2 = leaf to open, 3 = open children
+            int4 tp = make_int4(0, 0, 0, 0);
+            if (node >= 0) {
+                tp = topo[node];
+                const double4 a = nbox_lo[node], b = nbox_hi[node], m0 = mom0[node];
+                const double com[3] = {m0.y, m0.z, m0.w};
+                double d2 = 0.0;
+#pragma unroll
+                for (int c = 0; c < 3; ++c) {
+                    const double gp = com[c] < lo[c] ? lo[c] - com[c] : (com[c] > hi[c] ? com[c] - hi[c] : 0.0);
+                    d2 += gp * gp;
+                }
+                const bool apart =
+                    a.x > hi[0] || b.x < lo[0] || a.y > hi[1] || b.y < lo[1] || a.z > hi[2] || b.z < lo[2];
+                const double side = b.w;
+                if (apart && side * side < th2 * d2) kind = 1;
+                else kind = tp.w ? 2 : 3;
+            }
+            const u64 bc = __ballot(kind == 1), bl = __ballot(kind == 2);
+            if (kind == 1) cells[nc + __popcll(bc & lt)] = node;
+            if (kind == 2) leaves[nl + __popcll(bl & lt)] = node;
+            nc += __popcll(bc);
+            nl += __popcll(bl);
+            const int nch = kind == 3 ? tp.y : 0;
+            const int incl = wave_incl_scan(nch);
+            const int tot = __shfl(incl, 63, 64);
+            if (sp + tot > GW_STACK) {
+                if (lane == 0) set_err(ctl, ERR_GRAV_LIST);
+                break;
+            }
+            for (int j = 0; j < nch; ++j) stack[sp + incl - nch + j] = tp.x + j;
+            sp += tot;
             __syncthreads();
         }
-        int k = sp < 64 ? sp : 64;
-        const int room = (GW_STACK - sp) / 8;
-        if (k > room) k = room > 1 ? room : 1;
-        const int node = lane < k ? stack[sp - k + lane] : -1;
         __syncthreads();
-        sp -= k;
-        int kind = 0;  // 1 = accepted cell, 2 = leaf to open, 3 = open children
-        int4 tp = make_int4(0, 0, 0, 0);
-        if (node >= 0) {
-            tp = topo[node];
-            const double4 a = nbox_lo[node], b = nbox_hi[node], m0 = mom0[node];
-            const double com[3] = {m0.y, m0.z, m0.w};
-            double d2 = 0.0;
+        eval_lists<FP32C>(nc, nl, cells, leaves, St, topo, mom0, mom1, mom2, pos4, m, T, eps, A, B);
+        // per target: lanes tp + TP*phi combine in a fixed butterfly order
+        double r[8];
+        r[0] = FP32C ? A.kx.value() : A.gx;
+        r[1] = FP32C ? A.ky.value() : A.gy;
+        r[2] = FP32C ? A.kz.value() : A.gz;
+        r[3] = FP32C ? A.kp.value() : A.ph;
+        r[4] = FP32C ? B.kx.value() : B.gx;
+        r[5] = FP32C ? B.ky.value() : B.gy;
+        r[6] = FP32C ? B.kz.value() : B.gz;
+        r[7] = FP32C ? B.kp.value() : B.ph;
 #pragma unroll
-            for (int c = 0; c < 3; ++c) {
-                const double gp = com[c] < lo[c] ? lo[c] - com[c] : (com[c] > hi[c] ? com[c] - hi[c] : 0.0);
-                d2 += gp * gp;
+        for (int i = 0; i < 8; ++i) r[i] = G * lanes_sum_d(r[i], T.TP);
+        if (T.phi == 0) {
+            for (int s = 0; s < 2; ++s) {
+                if (!(s ? T.vb : T.va)) continue;
+                const int q = s ? T.qb : T.qa;
+                double gx = r[4 * s], gy = r[4 * s + 1], gz = r[4 * s + 2], ph = r[4 * s + 3];
+                if (eps > 0.0) {  // take out the self pair's potential term (see eval_lists)
+                    const double e2 = eps * eps;
+                    const double is = FP32C ? (double)__builtin_amdgcn_rsqf((float)e2) : rsq_nr(e2);
+                    ph += G * (m[q] * is);
+                }
+                if (accumulate) {
+                    gxo[q] += gx;
+                    gyo[q] += gy;
+                    gzo[q] += gz;
+                } else {
+                    gxo[q] = gx;
+                    gyo[q] = gy;
+                    gzo[q] = gz;
+                }
+                if (pho) pho[q] = ph;
             }
-            const bool apart = a.x > hi[0] || b.x < lo[0] || a.y > hi[1] || b.y < lo[1] || a.z > hi[2] || b.z < lo[2];
-            const double side = b.w;
-            if (apart && side * side < th2 * d2) kind = 1;
-            else kind = tp.w ? 2 : 3;
         }
-        const u64 bc = __ballot(kind == 1), bl = __ballot(kind == 2);
-        if (kind == 1) cells[nc + __popcll(bc & lt)] = node;
-        if (kind == 2) leaves[nl + __popcll(bl & lt)] = node;
-        nc += __popcll(bc);
-        nl += __popcll(bl);
-        const int nch = kind == 3 ? tp.y : 0;
-        const int incl = wave_incl_scan(nch);
-        const int tot = __shfl(incl, 63, 64);
-        if (sp + tot > GW_STACK) {
-            if (lane == 0) set_err(ctl, ERR_GRAV_LIST);
-            break;
-        }
-        for (int j = 0; j < nch; ++j) stack[sp + incl - nch + j] = tp.x + j;
-        sp += tot;
-        __syncthreads();
-    }
-    __syncthreads();
-    eval_lists<FP32C>(nc, nl, cells, leaves, S, topo, mom0, mom1, mom2, pos4, m, me, q, tv, phi, P_, G, eps,
-                      acc);
-    acc.gx = lanes_sum_d(acc.gx, gsz);
-    acc.gy = lanes_sum_d(acc.gy, gsz);
-    acc.gz = lanes_sum_d(acc.gz, gsz);
-    acc.ph = lanes_sum_d(acc.ph, gsz);
-    if (tv && phi == 0) {
-        if (eps > 0.0) {  // take out the self pair's potential term (see eval_lists)
-            const double e2 = eps * eps;
-            const double is = FP32C ? (double)__builtin_amdgcn_rsqf((float)e2) : rsq_nr(e2);
-            acc.ph += G * (m[q] * is);
-        }
-        if (accumulate) {
-            gxo[q] += acc.gx;
-            gyo[q] += acc.gy;
-            gzo[q] += acc.gz;
-        } else {
-            gxo[q] = acc.gx;
-            gyo[q] = acc.gy;
-            gzo[q] = acc.gz;
-        }
-        if (pho) pho[q] = acc.ph;
-    }
     }
 }
 
