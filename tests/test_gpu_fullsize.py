@@ -7,13 +7,20 @@
   those values come from the density field whose sample passed).
 * The n = 1 polytrope at 4,194,304 particles: theta = 0.5 quadrupole gravity within 1e-3
   RMS relative of the direct sum on 1024 sampled targets.
+* The batched ensemble (256 boxes, 4,879,340 particles, one context as the benchmark runs
+  it): keys and order bit-exact; per-set neighbour sets bit-exact and density, forces
+  (layered) for sampled targets across many sets, FP64 within 1e-12 and FP32C within the
+  stated 2e-6 budget.
+* The Evrard-style sphere at 16,777,216 particles (FP32C as configured, and FP64): keys and
+  order bit-exact; sampled neighbour sets bit-exact, density and forces (layered) within
+  the FP64 / FP32C bounds; theta = 0.5 gravity within 1e-3 RMS of the direct sum.
 """
 import math
 
 import numpy as np
 import pytest
 
-from workloads import polytrope_n1, sod_tube
+from workloads import ensemble, evrard, polytrope_n1, sod_tube
 
 from gpu_helpers import gpu_density, gpu_gravity, gpu_keys_order, gpu_tree, make_ctx, parts, rel_err, to_np
 
@@ -76,5 +83,90 @@ def test_polytrope_4m_gravity_sampled(orc, capsys):
         with capsys.disabled():
             print(f"\n4M polytrope gravity prec={prec}: RMS {rms:.3e} median {np.median(e):.2e} max {e.max():.2e}",
                   flush=True)
+        assert rms <= 1e-3
+        ctx.close()
+
+
+def _sampled_sph(orc, ctx, ps, tg, seg, prec, say):
+    """Neighbour sets of the targets bit-exact; density and (layered) forces within the
+    FP64 or FP32C bound."""
+    import torch
+    import paper_2007_03097_amd as sph
+    n = ps.n
+    off = torch.zeros(n + 1, dtype=torch.int64, device="cuda")
+    total = sph.sph_find_neighbors(ctx.h, off, None, 0)
+    idx = torch.zeros(total, dtype=torch.int32, device="cuda")
+    sph.sph_find_neighbors(ctx.h, off, idx, total)
+    off, idx = to_np(off), to_np(idx)
+    roff, ridx = orc.neighbors(ps.x, ps.y, ps.z, ps.h, targets=tg, seg=seg)
+    for j, a in enumerate(tg):
+        assert np.array_equal(idx[off[a]:off[a + 1]], ridx[roff[j]:roff[j + 1]]), a
+    say(f"neighbour sets of {tg.size} targets bit-exact ({total} pairs in all)")
+    rho, P, c, hn = gpu_density(ctx, n)
+    r_rho, r_P, r_c, r_hn = orc.density(ps.fields(), (roff, ridx), targets=tg)
+    outs = [torch.zeros(n, dtype=torch.float64, device="cuda") for _ in range(4)]
+    sph.sph_compute_forces(ctx.h, *outs)
+    ax, ay, az, du = [to_np(x) for x in outs]
+    r_ax, r_ay, r_az, r_du, Sa, Su = orc.forces(ps.fields(), rho, P, c, (roff, ridx), targets=tg)
+    e_rho = np.abs(rho[tg] - r_rho) / r_rho
+    e_a = np.sqrt((ax[tg] - r_ax) ** 2 + (ay[tg] - r_ay) ** 2 + (az[tg] - r_az) ** 2) / Sa
+    e_u = np.abs(du[tg] - r_du) / np.maximum(Su, 1e-300)
+    say(f"prec={prec}: max rel. err rho {e_rho.max():.2e} a {e_a.max():.2e} du {e_u.max():.2e}")
+    bound = 1e-12 if prec == 0 else 2e-6
+    assert e_rho.max() <= bound and e_a.max() <= bound and e_u.max() <= bound
+
+
+@pytest.mark.timeout(900)
+def test_ensemble_full_size_sampled(orc, capsys):
+    def say(s):
+        with capsys.disabled():
+            print(f"\n[ensemble] {s}", flush=True)
+    ps = ensemble(256, seed=1004)
+    n, so = ps.n, ps.seg_offsets
+    seg = orc.seg_ids(n, so)
+    rng = np.random.default_rng(11)
+    tg = np.sort(rng.choice(n, 1536, replace=False))
+    k_ref = orc.keys(ps.x, ps.y, ps.z, seg_offsets=so)
+    o_ref = orc.order(k_ref)
+    say(f"n={n} in 256 sets, oracle keys and order ready")
+    for prec in (0, 1):
+        ctx = make_ctx(n, seg_cap=256, precision=prec)
+        k, o = gpu_keys_order(ctx, parts(ps))
+        assert np.array_equal(k, k_ref) and np.array_equal(o, o_ref)
+        say(f"prec={prec}: keys and order bit-exact")
+        _sampled_sph(orc, ctx, ps, tg, seg, prec, say)
+        ctx.close()
+
+
+@pytest.mark.timeout(1200)
+def test_evrard_16m_sampled(orc, capsys):
+    import math as _m
+
+    def say(s):
+        with capsys.disabled():
+            print(f"\n[evrard] {s}", flush=True)
+    n = 16777216
+    ps = evrard(n, seed=1005)
+    say(f"n={n} generated")
+    k_ref = orc.keys(ps.x, ps.y, ps.z)
+    o_ref = orc.order(k_ref)
+    say("oracle keys and order ready")
+    rng = np.random.default_rng(13)
+    r = np.sqrt(ps.x ** 2 + ps.y ** 2 + ps.z ** 2)
+    tg = np.unique(np.concatenate([rng.choice(n, 384, replace=False), np.argsort(r)[:64:4]]))  # + the centre
+    gt = np.sort(rng.choice(n, 256, replace=False))
+    dx, dy, dz, dp = orc.gravity_direct(ps.x, ps.y, ps.z, ps.m, 1.0, 0.005, targets=gt)
+    gd = np.sqrt(dx ** 2 + dy ** 2 + dz ** 2)
+    say("oracle direct gravity on 256 targets ready")
+    for prec in (1, 0):
+        ctx = make_ctx(n, precision=prec, adaptive_h=1, G=1.0, soft_eps=0.005, theta=0.5, nbr_capacity=256)
+        k, o = gpu_keys_order(ctx, parts(ps))
+        assert np.array_equal(k, k_ref) and np.array_equal(o, o_ref)
+        say(f"prec={prec}: keys and order bit-exact")
+        _sampled_sph(orc, ctx, ps, tg, None, prec, say)
+        gx, gy, gz, phi = gpu_gravity(ctx, n)
+        e = np.sqrt((gx[gt] - dx) ** 2 + (gy[gt] - dy) ** 2 + (gz[gt] - dz) ** 2) / gd
+        rms = _m.sqrt((e ** 2).mean())
+        say(f"prec={prec}: gravity RMS {rms:.3e} median {np.median(e):.2e} max {e.max():.2e}")
         assert rms <= 1e-3
         ctx.close()
