@@ -122,7 +122,9 @@ __global__ void k_emit_groups(int n, int gsz, int batched, DevCtl* ctl, const in
     }
 }
 
-// Pre-order node records, leaf table and per-level node counts.
+// Pre-order node records, leaf table and per-level node counts.  A grid-stride loop over
+// positions; the level counts are wave-aggregated into LDS and added to the global counts
+// once per workgroup, so the 24 global counters see few atomics.
 __global__ void __launch_bounds__(256) k_emit_nodes(int n, const signed char* __restrict__ lcp,
                                                      const unsigned char* __restrict__ lvl,
                                                      const u64* __restrict__ scan, unsigned char* pre_level,
@@ -131,11 +133,16 @@ __global__ void __launch_bounds__(256) k_emit_nodes(int n, const signed char* __
     __shared__ int hist[24];
     if (threadIdx.x < 24) hist[threadIdx.x] = 0;
     __syncthreads();
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
     const u64 tot = scan[n];
     const int n_nodes = (int)(tot >> 32), n_leaves = (int)(tot & 0xffffffffu);
-    if (i < n) {
-        const int c = lcp[i], L = lvl[i];
+    const int stride = gridDim.x * blockDim.x;
+    for (int i0 = blockIdx.x * blockDim.x; i0 < n; i0 += stride) {
+        const int i = i0 + threadIdx.x;
+        int c = MAX_LEVEL, L = -1;
+        if (i < n) {
+            c = lcp[i];
+            L = lvl[i];
+        }
         if (L > c) {
             const u64 sv = scan[i];
             const int base = (int)(sv >> 32), lf = (int)(sv & 0xffffffffu);
@@ -146,13 +153,20 @@ __global__ void __launch_bounds__(256) k_emit_nodes(int n, const signed char* __
                     pre_leaf[idx] = (unsigned char)(l == L);
                     pre_start[idx] = i;
                 }
-                atomicAdd(&hist[l], 1);
             }
             leaf_start[lf] = i;
             leaf_pre[lf] = base + (L - c - 1);
         }
+        // nodes per level: position i starts one node at each level c+1 .. L
+        const u64 any = __ballot(L > c);
+        if (any) {
+            for (int l = 0; l <= MAX_LEVEL; ++l) {
+                const int k = __popcll(__ballot(c < l && l <= L));
+                if (k && lane_id() == 0) atomicAdd(&hist[l], k);
+            }
+        }
     }
-    if (i == 0) {
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
         ctl->n_nodes = n_nodes < node_cap ? n_nodes : node_cap;
         ctl->n_leaves = n_leaves;
         leaf_start[n_leaves] = n;
@@ -462,7 +476,7 @@ void build_octree(hipStream_t s, const DevPtrs& d, const Dims& dm) {
     hipLaunchKernelGGL(k_leaf_levels, dim3((n + TB - 1) / TB), dim3(TB), 0, s, d.key_a, n, dm.leaf_size, dm.min_level,
                        d.lcp, d.lvl, d.scan_in);
     scan_u64(s, d.scan_in, d.scan_out, n, d.scan_tmp);
-    hipLaunchKernelGGL(k_emit_nodes, dim3((n + 255) / 256), dim3(256), 0, s, n, d.lcp, d.lvl, d.scan_out,
+    hipLaunchKernelGGL(k_emit_nodes, dim3(grid_cap(n, 256, 512)), dim3(256), 0, s, n, d.lcp, d.lvl, d.scan_out,
                        d.pre_level, d.pre_leaf, d.pre_start, d.leaf_start, d.leaf_pre, d.ctl, dm.node_cap);
     hipLaunchKernelGGL(k_level_offsets, dim3(1), dim3(64), 0, s, d.ctl);
     const int tiles_cap = grid_cap(dm.node_cap, LS_TILE, 1024);
