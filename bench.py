@@ -27,6 +27,9 @@ sys.path.insert(0, ROOT)
 
 FP64_PEAK_TFLOPS = 78.6     # MI355X FP64 vector, 256 CU x 64 lanes x 2 flop x 2.4 GHz
 HBM_PEAK_GBS = 8000.0
+# leaf / group sizes chosen by sph_autotune on MI355X, keyed by workload; missing keys are
+# tuned on the spot (and appended to this file)
+TUNING_CACHE = os.path.join(ROOT, "paper_2007_03097_amd", "tuning_gfx950.json")
 
 # Algorithmic operation counts per true pair (see the design notes): one flop per IEEE
 # add, subtract, multiply, divide, square root or comparison in the definition.
@@ -64,13 +67,15 @@ def dt_for(ps, gamma=5.0 / 3.0):
     return 0.25 * float(np.min(ps.h / c))
 
 
-def run_gpu(ps, prec, steps, warmup, reps):
+def run_gpu(ps, prec, steps, warmup, reps, autotune=True):
     import torch
     import paper_2007_03097_amd as sph
     n = ps.n
     ctx = sph.Context(n, adaptive_h=1, precision=prec)
     pa = sph.ParticleArrays.from_numpy(ps)
     dt = dt_for(ps)
+    if autotune:
+        sph.sph_autotune(ctx.h, pa, dt, TUNING_CACHE)    # leaf and group size by timed steps (untimed here)
     sph.sph_step(ctx.h, pa, dt, max(warmup, 1), 0)       # load, prime, warm up, capture graphs
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -124,6 +129,7 @@ def run_polytrope(ps, steps, prec):
     n = ps.n
     ctx = sph.Context(n, adaptive_h=1, precision=prec, G=1.0, soft_eps=0.01, theta=0.5, nbr_capacity=2048)
     pa = sph.ParticleArrays.from_numpy(ps, with_accel=True)
+    sph.sph_autotune(ctx.h, pa, 1e-4, TUNING_CACHE)
     sph.sph_step(ctx.h, pa, 1e-9, 0, 0)                  # prime: accelerations of the initial state
     a = np.sqrt(sum(pa[k].cpu().numpy() ** 2 for k in ("ax", "ay", "az")))
     c = np.sqrt((5.0 / 3.0) * (2.0 / 3.0) * ps.u)
@@ -135,9 +141,11 @@ def run_polytrope(ps, steps, prec):
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     pairs = _pairs(ctx, pa, n)
+    leaf, group = sph.sph_get_tuning(ctx.h)
     ctx.close()
     torch.cuda.empty_cache()
-    return dict(ms_per_step=wall / steps * 1e3, steps_per_s=steps / wall, value=pairs * steps / wall, dt=dt)
+    return dict(ms_per_step=wall / steps * 1e3, steps_per_s=steps / wall, value=pairs * steps / wall, dt=dt,
+                leaf_size=leaf, group_size=group)
 
 
 def run_ensemble(steps):
@@ -155,6 +163,7 @@ def run_ensemble(steps):
     for prec, key in ((1, "batched_fp32c"), (0, "batched_fp64")):
         ctx = sph.Context(n, seg_capacity=256, precision=prec)
         pa = sph.ParticleArrays.from_numpy(ps)
+        sph.sph_autotune(ctx.h, pa, dt, TUNING_CACHE)
         sph.sph_step(ctx.h, pa, dt, 1, 0)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
@@ -162,7 +171,8 @@ def run_ensemble(steps):
         torch.cuda.synchronize()
         wall = time.perf_counter() - t0
         pairs = _pairs(ctx, pa, n)
-        out[key] = {"ms_per_step": wall / steps * 1e3, "value": pairs * steps / wall}
+        out[key] = {"ms_per_step": wall / steps * 1e3, "value": pairs * steps / wall,
+                    "leaf_size": sph.sph_get_tuning(ctx.h)[0], "group_size": sph.sph_get_tuning(ctx.h)[1]}
         ctx.close()
         del pa
         torch.cuda.empty_cache()
@@ -224,6 +234,7 @@ def main():
     ap.add_argument("--reps", type=int, default=20, help="repetitions of the per-kernel timing")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-extra", action="store_true", help="skip the polytrope and ensemble workloads")
+    ap.add_argument("--no-autotune", action="store_true", help="keep the default leaf and group sizes")
     ap.add_argument("--copy-calib-mib", type=int, default=0,
                     help="first run one device-to-device copy of this many MiB (hardware-counter calibration)")
     args = ap.parse_args()
@@ -241,8 +252,8 @@ def main():
         torch.cuda.synchronize()
         del src, dst
     ps = sod_tube(args.ny)
-    r64 = run_gpu(ps, 0, args.steps, args.warmup, args.reps)
-    r32 = run_gpu(ps, 1, args.steps, args.warmup, args.reps)
+    r64 = run_gpu(ps, 0, args.steps, args.warmup, args.reps, not args.no_autotune)
+    r32 = run_gpu(ps, 1, args.steps, args.warmup, args.reps, not args.no_autotune)
     n = ps.n
     kernels = {"k_nbr_lists": (r64["t_list"], r64["pairs_dens"], FLOP_PRED_PAIR),
                "k_density<false>": (r64["t_dens"], r64["pairs_dens"], FLOP_DENS_PAIR),
@@ -272,7 +283,8 @@ def main():
         "warmup": args.warmup, "ms_per_step": r64["ms_per_step"], "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": "f64", "data": "synthetic",
         "config": {"workload": f"3D Sod-type tube, {n} particles, adaptive h, Monaghan AV, KDK leapfrog",
-                   "n_particles": n, "dt": r64["dt"], "leaf_size": r64["leaf"], "group_size": r64["group"]},
+                   "n_particles": n, "dt": r64["dt"], "leaf_size": r64["leaf"], "group_size": r64["group"],
+                   "fp32c_leaf_size": r32["leaf"], "fp32c_group_size": r32["group"]},
         "steps_per_s": r64["steps_per_s"],
         "pairs_per_step": r64["pairs_dens"] + r64["pairs_force"],
         "pass_rate": r64["pass_rate"],
