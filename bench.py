@@ -28,8 +28,8 @@ sys.path.insert(0, ROOT)
 FP64_PEAK_TFLOPS = 78.6     # MI355X FP64 vector, 256 CU x 64 lanes x 2 flop x 2.4 GHz
 HBM_PEAK_GBS = 8000.0
 # leaf / group sizes chosen by sph_autotune on MI355X, keyed by workload; missing keys are
-# tuned on the spot (and appended to this file)
-TUNING_CACHE = os.path.join(ROOT, "paper_2007_03097_amd", "tuning_gfx950.json")
+# tuned on the spot (and appended to that file)
+TUNING_CACHE = os.path.join(ROOT, "paper_2007_03097_amd", "tuning_gfx950.json")  # = paper_2007_03097_amd.TUNING_CACHE
 
 # Algorithmic operation counts per true pair (see the design notes): one flop per IEEE
 # add, subtract, multiply, divide, square root or comparison in the definition.

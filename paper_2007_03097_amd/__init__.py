@@ -5,6 +5,7 @@ include/sph.h).  ``api`` exposes the same entry points for torch tensors; PyTorc
 provides device memory and streams.
 """
 from .api import (  # noqa: F401
+    TUNING_CACHE,
     SPHError,
     Context,
     ParticleArrays,

@@ -7,6 +7,7 @@ libsph_gfx950.so; tensors must be contiguous CUDA/HIP tensors of the stated dtyp
 from __future__ import annotations
 
 import ctypes
+import os
 
 import numpy as np
 
@@ -159,6 +160,11 @@ def sph_step(ctx, parts: ParticleArrays | None, dt: float, nsteps: int, flags: i
     _check(ctx, _lib().sph_step(ctx, ctypes.byref(s) if s is not None else None, float(dt), int(nsteps), int(flags),
                                 diag.ctypes.data_as(ctypes.POINTER(ctypes.c_double))))
     return diag
+
+
+# Leaf and group sizes measured by sph_autotune on MI355X, keyed by workload (n, sets,
+# precision, gravity, adaptive h); sph_autotune reads a key when present.
+TUNING_CACHE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "tuning_gfx950.json")
 
 
 def sph_autotune(ctx, parts: ParticleArrays, dt: float, cache_path: str | None = None):

@@ -14,6 +14,13 @@ def make_ctx(n_cap, seg_cap=1, **cfg):
     return sph.Context(max(int(n_cap), 1), seg_cap, **cfg)
 
 
+def tuned(ctx, pa, dt=1e-4):
+    """Leaf and group sizes the benchmark uses for this workload (the package's tuning file)."""
+    import paper_2007_03097_amd as sph
+    sph.sph_autotune(ctx.h, pa, dt, sph.TUNING_CACHE)
+    return sph.sph_get_tuning(ctx.h)
+
+
 def parts(ps, with_accel=False):
     import paper_2007_03097_amd as sph
     return sph.ParticleArrays.from_numpy(ps, with_accel=with_accel)

@@ -22,7 +22,7 @@ import pytest
 
 from workloads import ensemble, evrard, polytrope_n1, sod_tube
 
-from gpu_helpers import gpu_density, gpu_gravity, gpu_keys_order, gpu_tree, make_ctx, parts, rel_err, to_np
+from gpu_helpers import gpu_density, gpu_gravity, gpu_keys_order, gpu_tree, make_ctx, parts, rel_err, to_np, tuned
 
 pytestmark = pytest.mark.gpu
 
@@ -34,12 +34,14 @@ def test_sod_full_size_sampled(orc):
     n = ps.n
     assert n == 987840
     ctx = make_ctx(n, adaptive_h=1)
-    k, o = gpu_keys_order(ctx, parts(ps))
-    print(f"\nfull-size tube: n={n}", flush=True)
+    pa = parts(ps)
+    leaf, group = tuned(ctx, pa)
+    k, o = gpu_keys_order(ctx, pa)
+    print(f"\nfull-size tube: n={n} leaf {leaf} group {group}", flush=True)
     assert np.array_equal(k, orc.keys(ps.x, ps.y, ps.z))
     assert np.array_equal(o, orc.order(k))
     t = gpu_tree(ctx)
-    ref = orc.octree(k[o], ctx.cfg.leaf_size)
+    ref = orc.octree(k[o], leaf)
     assert len(t["key"]) == len(ref["key"])
     assert np.array_equal(np.sort(t["key"]), np.sort(ref["key"]))
     off = torch.zeros(n + 1, dtype=torch.int64, device="cuda")
@@ -71,8 +73,10 @@ def test_polytrope_4m_gravity_sampled(orc, capsys):
     n = 4194304
     ps = polytrope_n1(n, seed=1003)
     for prec in (0, 1):
-        ctx = make_ctx(n, G=1.0, soft_eps=0.01, theta=0.5, precision=prec)
-        gpu_keys_order(ctx, parts(ps))
+        ctx = make_ctx(n, G=1.0, soft_eps=0.01, theta=0.5, precision=prec, adaptive_h=1, nbr_capacity=2048)
+        pa = parts(ps)
+        tuned(ctx, pa)
+        gpu_keys_order(ctx, pa)
         gx, gy, gz, phi = gpu_gravity(ctx, n)
         rng = np.random.default_rng(7)
         tg = np.sort(rng.choice(n, 1024, replace=False))
@@ -131,7 +135,10 @@ def test_ensemble_full_size_sampled(orc, capsys):
     say(f"n={n} in 256 sets, oracle keys and order ready")
     for prec in (0, 1):
         ctx = make_ctx(n, seg_cap=256, precision=prec)
-        k, o = gpu_keys_order(ctx, parts(ps))
+        pa = parts(ps)
+        leaf, group = tuned(ctx, pa)
+        k, o = gpu_keys_order(ctx, pa)
+        say(f"prec={prec}: leaf {leaf} group {group}")
         assert np.array_equal(k, k_ref) and np.array_equal(o, o_ref)
         say(f"prec={prec}: keys and order bit-exact")
         _sampled_sph(orc, ctx, ps, tg, seg, prec, say)
