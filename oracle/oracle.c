@@ -323,6 +323,53 @@ void orc_forces(const double* x, const double* y, const double* z, const double*
 }
 
 /* ------------------------------------------------------------------------------------ */
+/* Thermokinetic energy equation (Sec. 2.2.1, eq. (8)): the total specific energy
+ * e_a = u_a + v_a^2 / 2 evolves as
+ *   de_a/dt = -sum_{b != a} m_b (P_a v_b / rho_a^2 + P_b v_a / rho_b^2
+ *                                + (v_a + v_b)/2 Pi_ab) . grad_a W_ab,
+ * with W, h_ab and Pi_ab exactly as in orc_forces.  Se: the absolute-sum scale of the
+ * three terms (for relative error bounds).                                             */
+void orc_dedt(const double* x, const double* y, const double* z, const double* vx, const double* vy,
+              const double* vz, const double* h, const double* m, const double* rho, const double* P,
+              const double* c, double alpha, double beta, double eps_av, int64_t ntgt, const int64_t* tgt,
+              const int64_t* offsets, const int64_t* idx, double* dedt, double* Se)
+{
+#pragma omp parallel for schedule(dynamic, 64)
+    for (int64_t t = 0; t < ntgt; ++t) {
+        int64_t a = tgt ? tgt[t] : t;
+        double pa = P[a] / (rho[a] * rho[a]);
+        double de = 0, se = 0;
+        for (int64_t k = offsets[t]; k < offsets[t + 1]; ++k) {
+            int64_t b = idx[k];
+            if (b == a) continue;
+            double dx = x[a] - x[b], dy = y[a] - y[b], dz = z[a] - z[b];
+            double r2 = dx * dx + dy * dy + dz * dz;
+            double r = sqrt(r2);
+            double hab = 0.5 * (h[a] + h[b]);
+            double q = r / hab;
+            double gw = orc_dw_over_q(q) / (ORC_PI * hab * hab * hab * hab * hab);
+            double gx = dx * gw, gy = dy * gw, gz = dz * gw;  /* grad_a W_ab */
+            double wx = vx[a] - vx[b], wy = vy[a] - vy[b], wz = vz[a] - vz[b];
+            double vr = wx * dx + wy * dy + wz * dz;
+            double Pi = 0.0;
+            if (vr < 0.0) {
+                double mu = hab * vr / (r2 + eps_av * hab * hab);
+                double cbar = 0.5 * (c[a] + c[b]), rbar = 0.5 * (rho[a] + rho[b]);
+                Pi = (-alpha * cbar * mu + beta * mu * mu) / rbar;
+            }
+            double pb = P[b] / (rho[b] * rho[b]);
+            double vag = vx[a] * gx + vy[a] * gy + vz[a] * gz;   /* v_a . grad_a W_ab */
+            double vbg = vx[b] * gx + vy[b] * gy + vz[b] * gz;   /* v_b . grad_a W_ab */
+            double t1 = pa * vbg, t2 = pb * vag, t3 = 0.5 * Pi * (vag + vbg);
+            de -= m[b] * (t1 + t2 + t3);
+            se += m[b] * (fabs(t1) + fabs(t2) + fabs(t3));
+        }
+        dedt[t] = de;
+        if (Se) Se[t] = se;
+    }
+}
+
+/* ------------------------------------------------------------------------------------ */
 /* Direct-sum self-gravity (eq. (10) with theta_MAC = 0: every cell opened down to single
  * particles), Plummer softened:
  *   g_a = -G sum_{b != a} m_b r_ab / (r_ab^2 + eps^2)^{3/2},

@@ -56,6 +56,7 @@ def lib():
         L.orc_dw_over_q.restype = DBL
         L.orc_density.argtypes = [_d, _d, _d, _d, _d, _d, DBL, DBL, I64, _i64, _i64, _i64, _d, _d, _d, _d]
         L.orc_forces.argtypes = [_d] * 11 + [DBL, DBL, DBL, I64, _i64, _i64, _i64] + [_d] * 6
+        L.orc_dedt.argtypes = [_d] * 11 + [DBL, DBL, DBL, I64, _i64, _i64, _i64] + [_d] * 2
         L.orc_gravity_direct.argtypes = [I64, _d, _d, _d, _d, DBL, DBL, I64, _i64, _d, _d, _d, _d]
         L.orc_moments.argtypes = [I64, I64, _i64, _d, _d, _d, _d, _d]
         L.orc_quad_field.argtypes = [_d, DBL, DBL, DBL, DBL, DBL, _d, _d]
@@ -199,6 +200,22 @@ def forces(ps_or_arrays, rho, P, c, csr, alpha=1.0, beta=2.0, eps_av=0.01, targe
     return tuple(out)
 
 
+def dedt(ps_or_arrays, rho, P, c, csr, alpha=1.0, beta=2.0, eps_av=0.01, targets=None, vel=None):
+    """Eq. (8), thermokinetic energy rate: returns dedt, Se indexed by target.  rho, P, c
+    indexed by particle; vel: optional (vx, vy, vz) overriding the state's velocities."""
+    x, y, z, h, m = (_f64(ps_or_arrays[k]) for k in ("x", "y", "z", "h", "m"))
+    vx, vy, vz = (_f64(v) for v in (vel if vel is not None else
+                                     (ps_or_arrays["vx"], ps_or_arrays["vy"], ps_or_arrays["vz"])))
+    rho, P, c = _f64(rho), _f64(P), _f64(c)
+    off, idx = csr
+    tg = _ii(targets)
+    nt = x.size if tg is None else tg.size
+    de, se = np.empty(nt), np.empty(nt)
+    lib().orc_dedt(_p(x), _p(y), _p(z), _p(vx), _p(vy), _p(vz), _p(h), _p(m), _p(rho), _p(P), _p(c),
+                   alpha, beta, eps_av, nt, _p(tg, _i64), _p(_ii(off), _i64), _p(_ii(idx), _i64), _p(de), _p(se))
+    return de, se
+
+
 def gravity_direct(x, y, z, m, G=1.0, eps=0.0, targets=None):
     x, y, z, m = _f64(x), _f64(y), _f64(z), _f64(m)
     tg = _ii(targets)
@@ -245,24 +262,35 @@ def tree_gravity(xs, ys, zs, ms, tree, L, theta, G, eps, gstart, gcount):
 # Leapfrog (kick-drift-kick) with velocity and energy predictors, lagged adaptive h
 
 class Params:
+    """thermokinetic: evolve e = u + v^2/2 with eq. (8) instead of u with eq. (5); the state
+    keeps the thermal u, and its "dudt" entry holds de/dt."""
+
     def __init__(self, gamma=5.0 / 3.0, alpha=1.0, beta=2.0, eps_av=0.01, h_coeff=1.2, adaptive_h=False,
-                 G=0.0, soft_eps=0.0):
+                 G=0.0, soft_eps=0.0, thermokinetic=False):
         self.gamma, self.alpha, self.beta, self.eps_av = gamma, alpha, beta, eps_av
         self.h_coeff, self.adaptive_h, self.G, self.soft_eps = h_coeff, adaptive_h, G, soft_eps
+        self.thermokinetic = thermokinetic
 
 
 def accelerations(st: dict, prm: Params, vel=None, u=None, seg=None):
     """Hydro (+ direct gravity) accelerations for the whole set.  Returns
-    (ax, ay, az, dudt, rho, P, c, h_next).  u overrides the state's energy in the EOS."""
+    (ax, ay, az, dudt, rho, P, c, h_next).  u overrides the state's thermal energy in the EOS.
+    Thermokinetic: the fourth value is de/dt of eq. (8), plus v . g with gravity (the work of
+    gravity on e = u + v^2/2)."""
     csr = neighbors(st["x"], st["y"], st["z"], st["h"], seg=seg)
     d = dict(st)
     if u is not None:
         d["u"] = u
     rho, P, c, hn = density(d, csr, prm.gamma, prm.h_coeff)
     ax, ay, az, du, _, _ = forces(d, rho, P, c, csr, prm.alpha, prm.beta, prm.eps_av, vel=vel)
+    if prm.thermokinetic:
+        du, _ = dedt(d, rho, P, c, csr, prm.alpha, prm.beta, prm.eps_av, vel=vel)
     if prm.G != 0.0:
         gx, gy, gz, _ = gravity_direct(st["x"], st["y"], st["z"], st["m"], prm.G, prm.soft_eps)
         ax, ay, az = ax + gx, ay + gy, az + gz
+        if prm.thermokinetic:
+            v = vel if vel is not None else (st["vx"], st["vy"], st["vz"])
+            du = du + (v[0] * gx + v[1] * gy + v[2] * gz)
     return ax, ay, az, du, rho, P, c, hn
 
 
@@ -278,6 +306,8 @@ def prime(st: dict, prm: Params, seg=None):
 
 def kdk_step(st: dict, dt: float, prm: Params, seg=None):
     """One step from a primed state (dict with x..u, ax, ay, az, dudt)."""
+    if prm.thermokinetic:
+        return _kdk_step_thermokinetic(st, dt, prm, seg)
     s = {k: np.array(v, dtype=np.float64) for k, v in st.items()}
     half = 0.5 * dt
     vhx, vhy, vhz = s["vx"] + half * s["ax"], s["vy"] + half * s["ay"], s["vz"] + half * s["az"]
@@ -289,6 +319,29 @@ def kdk_step(st: dict, dt: float, prm: Params, seg=None):
     s["vx"], s["vy"], s["vz"] = vhx + half * ax, vhy + half * ay, vhz + half * az
     s["u"] = uh + half * du
     s.update(ax=ax, ay=ay, az=az, dudt=du, rho=rho)
+    if prm.adaptive_h:
+        s["h"] = hn
+    return s
+
+
+def _kdk_step_thermokinetic(st: dict, dt: float, prm: Params, seg=None):
+    """The same kick-drift-kick with the total energy e = u + v^2/2 in place of u:
+    e' = e + dt/2 de; predictor e^ = e' + dt/2 de and u^ = e^ - |v^|^2/2 for the EOS;
+    e = e' + dt/2 de_new; the returned state holds u = e - |v|^2/2."""
+    s = {k: np.array(v, dtype=np.float64) for k, v in st.items()}
+    half = 0.5 * dt
+    e = s["u"] + 0.5 * (s["vx"] ** 2 + s["vy"] ** 2 + s["vz"] ** 2)
+    vhx, vhy, vhz = s["vx"] + half * s["ax"], s["vy"] + half * s["ay"], s["vz"] + half * s["az"]
+    eh = e + half * s["dudt"]
+    s["x"], s["y"], s["z"] = s["x"] + dt * vhx, s["y"] + dt * vhy, s["z"] + dt * vhz
+    vpx, vpy, vpz = vhx + half * s["ax"], vhy + half * s["ay"], vhz + half * s["az"]
+    ep = eh + half * s["dudt"]
+    up = ep - 0.5 * (vpx ** 2 + vpy ** 2 + vpz ** 2)
+    ax, ay, az, de, rho, P, c, hn = accelerations(s, prm, vel=(vpx, vpy, vpz), u=up, seg=seg)
+    s["vx"], s["vy"], s["vz"] = vhx + half * ax, vhy + half * ay, vhz + half * az
+    e = eh + half * de
+    s["u"] = e - 0.5 * (s["vx"] ** 2 + s["vy"] ** 2 + s["vz"] ** 2)
+    s.update(ax=ax, ay=ay, az=az, dudt=de, rho=rho)
     if prm.adaptive_h:
         s["h"] = hn
     return s

@@ -246,6 +246,63 @@ def test_energy_rate_vanishes(orc):
     assert np.abs(du - du0).max() > 1e-3 * np.abs(du).max()
 
 
+def test_thermokinetic_rate_is_thermal_plus_kinetic(orc):
+    """Eq. (8) against eq. (5) and (6): per particle, de_a/dt = du_a/dt + v_a . dv_a/dt (no
+    gravity) -- the pressure parts recombine as P_a v_b/rho_a^2 + P_b v_a/rho_b^2 and the
+    viscous parts as (v_a + v_b)/2 Pi_ab.  A swapped P_a/P_b, a wrong sign or a dropped
+    viscous half breaks it."""
+    ps, csr, rho, P, c = _random_state(orc)
+    ax, ay, az, du, Sa, Su = orc.forces(ps.fields(), rho, P, c, csr)
+    de, Se = orc.dedt(ps.fields(), rho, P, c, csr)
+    vmag = np.sqrt(ps.vx ** 2 + ps.vy ** 2 + ps.vz ** 2)
+    ref = du + ps.vx * ax + ps.vy * ay + ps.vz * az
+    assert np.all(np.abs(de - ref) <= 1e-13 * (Se + Su + vmag * Sa))
+    assert np.abs(de).max() > 1e-3 * np.abs(Se).max()       # the rate is not trivially zero
+
+
+def test_thermokinetic_rate_conserves_total_energy(orc):
+    """Eq. (8)'s pair terms are antisymmetric: sum m_a de_a/dt = 0 to rounding, viscosity
+    included; with v = 0 every term vanishes."""
+    ps, csr, rho, P, c = _random_state(orc)
+    de, Se = orc.dedt(ps.fields(), rho, P, c, csr)
+    assert abs((ps.m * de).sum()) < 1e-14 * (ps.m * Se).sum()
+    z = np.zeros(ps.n)
+    de0, _ = orc.dedt(ps.fields(), rho, P, c, csr, vel=(z, z, z))
+    assert np.all(de0 == 0.0)
+
+
+def test_thermokinetic_kdk_conserves_energy_each_step(orc):
+    """With e = u + v^2/2 integrated by the kick-drift-kick, sum m e changes only by rounding
+    per step (sum m de/dt = 0 at every evaluation), while the eq. (5) integrator's error is
+    of third order in dt; momentum is conserved to rounding in both."""
+    ps = lattice_box(8, v_sigma=0.05, jitter=0.2)
+    prm = orc.Params(adaptive_h=False, thermokinetic=True)
+    st = orc.prime(ps.fields(), prm)
+    E0 = orc.diagnostics(st)
+    for _ in range(3):
+        st = orc.kdk_step(st, 0.02, prm)
+        E = orc.diagnostics(st)
+        assert abs((E[6] + E[7]) - (E0[6] + E0[7])) <= 1e-13 * (E0[6] + E0[7])
+        assert np.abs(E[:3] - E0[:3]).max() < 1e-15
+    st5 = orc.kdk_step(orc.prime(ps.fields(), orc.Params(adaptive_h=False)), 0.02, orc.Params(adaptive_h=False))
+    E5 = orc.diagnostics(st5)
+    assert abs((E5[6] + E5[7]) - (E0[6] + E0[7])) > 1e-10 * (E0[6] + E0[7])
+
+
+def test_thermokinetic_step_agrees_with_thermal_to_third_order(orc):
+    """Both energy forms discretise the same equations, so one step of each differs by the
+    local error only: the difference in u and v falls by ~2^3 per halving of dt (a predictor
+    or EOS-input mistake in either form leaves a second-order difference)."""
+    ps = lattice_box(8, v_sigma=0.05, jitter=0.2)
+    pt, pk = orc.Params(adaptive_h=False), orc.Params(adaptive_h=False, thermokinetic=True)
+    st_t, st_k = orc.prime(ps.fields(), pt), orc.prime(ps.fields(), pk)
+    diffs = []
+    for dt in (0.02, 0.01, 0.005):
+        a, b = orc.kdk_step(st_t, dt, pt), orc.kdk_step(st_k, dt, pk)
+        diffs.append(max(np.abs(a["u"] - b["u"]).max(), np.abs(a["vx"] - b["vx"]).max()))
+    assert 7.0 < diffs[0] / diffs[1] < 20.0 and 7.0 < diffs[1] / diffs[2] < 20.0
+
+
 def _thermal_energy(orc, ps, K, gamma):
     csr = orc.neighbors(ps.x, ps.y, ps.z, ps.h)
     rho, _, _, _ = orc.density(ps.fields(), csr)
