@@ -68,7 +68,16 @@ typedef struct {
     int32_t group_size;  /* target particles per walk group: 8, 16, 32 or 64 (0 = 32)        */
     int32_t nbr_capacity;/* maximum neighbours per particle, 16..4096 (0 = 160)              */
     void* stream;        /* hipStream_t to run on; NULL = the null stream                    */
+    int32_t energy_form; /* SPH_ENERGY_THERMAL: u evolves with eq. (5) (default).
+                            SPH_ENERGY_THERMOKINETIC: Sec. 2.2.1, eq. (8) -- the total
+                            energy e = u + v^2/2 evolves; sph_compute_forces and sph_step's
+                            dudt array then carry de/dt (plus v.g when G != 0), and sph_step
+                            still takes and returns the thermal u.                      */
 } sph_config;
+
+/* Values of sph_config.energy_form. */
+#define SPH_ENERGY_THERMAL 0
+#define SPH_ENERGY_THERMOKINETIC 1
 
 /* A particle set.  Segments: n_seg > 1 independent sets stored back to back, set s being
  * particles [seg_offsets[s], seg_offsets[s+1]); pairs and tree nodes never cross sets. */
@@ -80,9 +89,9 @@ typedef struct {
     double *vx, *vy, *vz;         /* device: velocities                                     */
     double *m, *h, *u;            /* device: masses (> 0), smoothing lengths (> 0),
                                      specific internal energy                               */
-    double *ax, *ay, *az, *dudt;  /* device, sph_step only: accelerations and du/dt of the
-                                     current state (read when SPH_STEP_PRIMED, written on
-                                     return when non-NULL)                                  */
+    double *ax, *ay, *az, *dudt;  /* device, sph_step only: accelerations and du/dt (de/dt
+                                     in the thermokinetic form) of the current state (read
+                                     when SPH_STEP_PRIMED, written on return when non-NULL)  */
 } sph_particles;
 
 /* Flags of sph_step. */
@@ -156,6 +165,8 @@ sph_status sph_compute_density(sph_ctx* ctx, double* rho, double* P, double* cs,
  * mu = h_ab v_ab . r_ab / (r^2 + eps h_ab^2).  rho, P, cs: device double[n] in caller order,
  * or all NULL to use the values of the last sph_compute_density (SPH_E_STATE if none
  * since the last sph_build_tree, or if the last sph_compute_forces was given values).
+ * With energy_form = SPH_ENERGY_THERMOKINETIC, dudt receives eq. (8) instead:
+ * de_a/dt = -sum_b m_b (P_a v_b/rho_a^2 + P_b v_a/rho_b^2 + (v_a + v_b)/2 Pi_ab) . grad_a W_ab.
  * Outputs: device double[n] in caller order; any may be NULL (not copied out). */
 sph_status sph_compute_forces(sph_ctx* ctx, const double* rho, const double* P, const double* cs,
                               double* ax, double* ay, double* az, double* dudt);
@@ -170,6 +181,9 @@ sph_status sph_compute_gravity(sph_ctx* ctx, double* gx, double* gy, double* gz,
  *   v' = v + dt/2 a;  u' = u + dt/2 du;  x += dt v';  predictors v^ = v' + dt/2 a, u^ = u' + dt/2 du;
  *   rebuild keys, tree and neighbours; density, EOS(u^), forces with v^ (+ gravity if G != 0);
  *   v = v' + dt/2 a_new;  u = u' + dt/2 du_new;  adaptive_h: h = h_coeff (m/rho)^(1/3).
+ * Thermokinetic form: the same scheme integrates e = u + v^2/2 with de/dt (eq. (8), plus
+ * v^.g with gravity) in place of u; the EOS takes u^ = e^ - |v^|^2/2, and the returned u is
+ * e - |v|^2/2.
  * Without SPH_STEP_PRIMED the accelerations of the input state are computed first (and,
  * with adaptive_h, h is reset from that density).  The state stays on the device in key
  * order between steps; on return x, v, u, h (and ax..dudt when given) are written back in

@@ -198,6 +198,8 @@ static sph_status check_config(sph_ctx* c, const sph_config* f) {
     if (g != 8 && g != 16 && g != 32 && g != 64) return fail(c, SPH_E_ARG, "group_size must be 8, 16, 32 or 64");
     const int k = f->nbr_capacity ? f->nbr_capacity : 160;
     if (k < 16 || k > 4096) return fail(c, SPH_E_ARG, "nbr_capacity must be in 16..4096");
+    if (f->energy_form != SPH_ENERGY_THERMAL && f->energy_form != SPH_ENERGY_THERMOKINETIC)
+        return fail(c, SPH_E_ARG, "energy_form must be 0 or 1");
     return SPH_OK;
 }
 
@@ -342,6 +344,7 @@ void sph_config_default(sph_config* f) {
     f->leaf_size = 16;
     f->group_size = 32;
     f->nbr_capacity = 160;
+    f->energy_form = SPH_ENERGY_THERMAL;
     f->stream = nullptr;
 }
 
@@ -480,7 +483,7 @@ sph_status sph_compute_density(sph_ctx* c, double* rho, double* P, double* cs, d
     if (st != SPH_OK) return st;
     const DevPtrs& d = c->d[c->parity];
     const int n = c->dm.n;
-    launch_density(c->stream, d, c->dm, c->cfg.precision == SPH_FP32C, c->cfg.gamma, c->cfg.h_coeff, d.u);
+    launch_density(c->stream, d, c->dm, c->cfg.precision == SPH_FP32C, c->cfg.gamma, c->cfg.h_coeff, d.u, 0);
     launch_scatter_caller(c->stream, d, n, d.rho, rho);
     launch_scatter_caller(c->stream, d, n, d.P, P);
     launch_scatter_caller(c->stream, d, n, d.cs, cs);
@@ -506,7 +509,7 @@ sph_status sph_compute_forces(sph_ctx* c, const double* rho, const double* P, co
         return fail(c, SPH_E_STATE, "sph_compute_density has not been called");
     }
     launch_forces(c->stream, d, c->dm, c->cfg.precision == SPH_FP32C, c->cfg.av_alpha, c->cfg.av_beta, c->cfg.av_eps,
-                  nullptr, nullptr, nullptr);
+                  c->cfg.energy_form == SPH_ENERGY_THERMOKINETIC);
     launch_scatter_caller(c->stream, d, n, d.ax, ax);
     launch_scatter_caller(c->stream, d, n, d.ay, ay);
     launch_scatter_caller(c->stream, d, n, d.az, az);
@@ -520,7 +523,7 @@ sph_status sph_compute_gravity(sph_ctx* c, double* gx, double* gy, double* gz, d
     const int n = c->dm.n;
     if (!c->tree_ok) return fail(c, SPH_E_STATE, "sph_build_tree has not been called");
     const DevPtrs& d = c->d[c->parity];
-    launch_gravity(c->stream, d, c->dm, c->cfg.precision == SPH_FP32C, c->cfg.G, c->cfg.soft_eps, c->cfg.theta, 0);
+    launch_gravity(c->stream, d, c->dm, c->cfg.precision == SPH_FP32C, c->cfg.G, c->cfg.soft_eps, c->cfg.theta, 0, 0);
     launch_scatter_caller(c->stream, d, n, d.gx, gx);
     launch_scatter_caller(c->stream, d, n, d.gy, gy);
     launch_scatter_caller(c->stream, d, n, d.gz, gz);
@@ -535,12 +538,14 @@ sph_status sph_compute_gravity(sph_ctx* c, double* gx, double* gy, double* gz, d
 // leapfrog driver
 
 // Accelerations of the resident state in buffer set p (tree already built).
-static void accel_pass(sph_ctx* c, hipStream_t s, const DevPtrs& d, const double* u_eos) {
+// u_eos holds e = u + v^2/2 when kin (thermokinetic steps), the thermal u otherwise.
+static void accel_pass(sph_ctx* c, hipStream_t s, const DevPtrs& d, const double* u_eos, int kin) {
     const int fp32c = c->cfg.precision == SPH_FP32C;
+    const int thermo = c->cfg.energy_form == SPH_ENERGY_THERMOKINETIC;
     launch_nbr_lists(s, d, c->dm);
-    launch_density(s, d, c->dm, fp32c, c->cfg.gamma, c->cfg.h_coeff, u_eos);
-    launch_forces(s, d, c->dm, fp32c, c->cfg.av_alpha, c->cfg.av_beta, c->cfg.av_eps, nullptr, nullptr, nullptr);
-    if (c->cfg.G != 0.0) launch_gravity(s, d, c->dm, fp32c, c->cfg.G, c->cfg.soft_eps, c->cfg.theta, 1);
+    launch_density(s, d, c->dm, fp32c, c->cfg.gamma, c->cfg.h_coeff, u_eos, kin);
+    launch_forces(s, d, c->dm, fp32c, c->cfg.av_alpha, c->cfg.av_beta, c->cfg.av_eps, thermo);
+    if (c->cfg.G != 0.0) launch_gravity(s, d, c->dm, fp32c, c->cfg.G, c->cfg.soft_eps, c->cfg.theta, 1, thermo);
 }
 
 // One KDK step from buffer set p into buffer set 1 - p.
@@ -555,7 +560,7 @@ static void step_launches(sph_ctx* c, hipStream_t s, int p) {
     radix_sort(s, a, n);
     launch_step_permute(s, a, n);         // also writes the pair records
     build_octree(s, b, c->dm);
-    accel_pass(c, s, b, b.up);
+    accel_pass(c, s, b, b.up, c->cfg.energy_form == SPH_ENERGY_THERMOKINETIC);
     launch_kick(s, b, n, dt, c->cfg.adaptive_h);
 }
 
@@ -617,9 +622,10 @@ static sph_status step_impl(sph_ctx* c, sph_particles* p, double dt, int32_t nst
             if (flags & SPH_STEP_PRIMED) {
                 launch_load_accel(c->stream, d, n, p->ax, p->ay, p->az, p->dudt);
             } else {
-                accel_pass(c, c->stream, d, d.u);
+                accel_pass(c, c->stream, d, d.u, 0);
                 if (c->cfg.adaptive_h) launch_set_hnext(c->stream, d, n);
             }
+            if (c->cfg.energy_form == SPH_ENERGY_THERMOKINETIC) launch_add_kinetic(c->stream, d, n);
         }
         HIPCHK(c, hipGetLastError());
         c->resident_ok = true;
@@ -630,12 +636,12 @@ static sph_status step_impl(sph_ctx* c, sph_particles* p, double dt, int32_t nst
     const DevPtrs& d = c->d[c->parity];
     const int n = c->dm.n;
     if (diag) {
-        launch_diag(c->stream, d, n, c->cfg.G != 0.0);
+        launch_diag(c->stream, d, n, c->cfg.G != 0.0, c->cfg.energy_form == SPH_ENERGY_THERMOKINETIC);
         HIPCHK(c, hipMemcpyAsync(diag, d.ctl->diag, 9 * sizeof(double), hipMemcpyDeviceToHost, c->stream));
     }
     if (write_back && p && p->x && n > 0)
         launch_write_back(c->stream, d, n, p->x, p->y, p->z, p->vx, p->vy, p->vz, p->h, p->u, p->ax, p->ay, p->az,
-                          p->dudt);
+                          p->dudt, c->cfg.energy_form == SPH_ENERGY_THERMOKINETIC);
     HIPCHK(c, hipGetLastError());
     HIPCHK(c, hipStreamSynchronize(c->stream));
     return read_err(c);

@@ -321,7 +321,7 @@ void launch_tree_export(hipStream_t s, const DevPtrs& d, const Dims& dm, u64* ke
 // neighbour lists + density, EOS and h_next (u_eos: the energy the EOS uses)
 void launch_nbr_lists(hipStream_t s, const DevPtrs& d, const Dims& dm);
 void launch_density(hipStream_t s, const DevPtrs& d, const Dims& dm, int fp32c, double gamma, double h_coeff,
-                    const double* u_eos);
+                    const double* u_eos, int kinetic_in_u);
 void launch_csr_count(hipStream_t s, const DevPtrs& d, const Dims& dm, int64_t* counts_caller);
 void scan_i64_inplace(hipStream_t s, int64_t* a, int n, void* tmp);
 void launch_csr_fill(hipStream_t s, const DevPtrs& d, const Dims& dm, const int64_t* offsets, int32_t* idx);
@@ -329,10 +329,10 @@ void launch_csr_fill(hipStream_t s, const DevPtrs& d, const Dims& dm, const int6
 void launch_thermo_from_caller(hipStream_t s, const DevPtrs& d, const Dims& dm, const double* rho,
                                const double* P, const double* cs);
 void launch_forces(hipStream_t s, const DevPtrs& d, const Dims& dm, int fp32c, double alpha, double beta,
-                   double eps_av, const double* vx, const double* vy, const double* vz);
+                  double eps_av, int thermokinetic);
 // k_grav.hip
 void launch_gravity(hipStream_t s, const DevPtrs& d, const Dims& dm, int fp32c, double G, double eps,
-                    double theta, int accumulate);
+                    double theta, int accumulate, int thermokinetic);
 // k_step.hip
 void launch_scatter_caller(hipStream_t s, const DevPtrs& d, int n, const double* src, double* dst);
 void launch_gather_caller(hipStream_t s, const DevPtrs& d, int n, const double* src_caller, double* dst);
@@ -342,9 +342,10 @@ void launch_step_keys(hipStream_t s, const DevPtrs& d, const Dims& dm);
 void launch_step_permute(hipStream_t s, const DevPtrs& d, int n);
 void launch_kick(hipStream_t s, const DevPtrs& d, int n, double dt, int adaptive_h);
 void launch_set_hnext(hipStream_t s, const DevPtrs& d, int n);
-void launch_diag(hipStream_t s, const DevPtrs& d, int n, int with_phi);
+void launch_diag(hipStream_t s, const DevPtrs& d, int n, int with_phi, int kinetic_in_u);
 void launch_write_back(hipStream_t s, const DevPtrs& d, int n, double* x, double* y, double* z, double* vx,
                        double* vy, double* vz, double* h, double* u, double* ax, double* ay, double* az,
-                       double* du);
+                       double* du, int kinetic_in_u);
+void launch_add_kinetic(hipStream_t s, const DevPtrs& d, int n);
 void launch_load_accel(hipStream_t s, const DevPtrs& d, int n, const double* ax, const double* ay,
                        const double* az, const double* du);

@@ -233,7 +233,8 @@ __global__ void __launch_bounds__(64) k_gravity(DevCtl* ctl, const int4* __restr
                                                 const double4* __restrict__ pos4, const double* __restrict__ m,
                                                 double G, double eps, double theta, int accumulate,
                                                 double* __restrict__ gxo, double* __restrict__ gyo,
-                                                double* __restrict__ gzo, double* __restrict__ pho) {
+                                                double* __restrict__ gzo, double* __restrict__ pho,
+                                                const double4* __restrict__ vel4, double* __restrict__ deo) {
     __shared__ int stack[GW_STACK];
     __shared__ int cells[GW_CELLS];
     __shared__ int leaves[GW_LEAVES];
@@ -347,6 +348,10 @@ __global__ void __launch_bounds__(64) k_gravity(DevCtl* ctl, const int4* __restr
                     gxo[q] += gx;
                     gyo[q] += gy;
                     gzo[q] += gz;
+                    if (deo) {  // thermokinetic form: the work of gravity on e = u + v^2/2
+                        const double4 v = vel4[q];
+                        deo[q] += fma(v.x, gx, fma(v.y, gy, v.z * gz));
+                    }
                 } else {
                     gxo[q] = gx;
                     gyo[q] = gy;
@@ -359,17 +364,18 @@ __global__ void __launch_bounds__(64) k_gravity(DevCtl* ctl, const int4* __restr
 }
 
 void launch_gravity(hipStream_t s, const DevPtrs& d, const Dims& dm, int fp32c, double G, double eps, double theta,
-                    int accumulate) {
+                    int accumulate, int thermo) {
     if (dm.n <= 0) return;
     double* gx = accumulate ? d.ax : d.gx;
     double* gy = accumulate ? d.ay : d.gy;
     double* gz = accumulate ? d.az : d.gz;
+    double* de = (accumulate && thermo) ? d.du : nullptr;
     if (fp32c)
         hipLaunchKernelGGL(k_gravity<true>, dim3(dm.group_grid), dim3(64), 0, s, d.ctl, d.group, dm.group_size, d.topo,
                            d.nbox_lo, d.nbox_hi, d.mom0, d.mom1, d.mom2, d.pos4, d.m, G, eps, theta, accumulate, gx, gy,
-                           gz, d.phi);
+                           gz, d.phi, d.vel4, de);
     else
         hipLaunchKernelGGL(k_gravity<false>, dim3(dm.group_grid), dim3(64), 0, s, d.ctl, d.group, dm.group_size, d.topo,
                            d.nbox_lo, d.nbox_hi, d.mom0, d.mom1, d.mom2, d.pos4, d.m, G, eps, theta, accumulate, gx, gy,
-                           gz, d.phi);
+                           gz, d.phi, d.vel4, de);
 }

@@ -3,6 +3,9 @@
 //                       P = (gamma - 1) rho u, c = sqrt(gamma P / rho); h_next (eq. (9))
 //   momentum (eq. (6)): dv_a/dt = -sum_b m_b ((P_a/rho_a^2 + P_b/rho_b^2) + Pi_ab) grad_a W_ab
 //   energy (eq. (5)):   du_a/dt =  sum_b m_b (P_a/rho_a^2 + Pi_ab/2) v_ab . grad_a W_ab
+//   or, thermokinetic (eq. (8)), e = u + v^2/2:
+//                       de_a/dt = -sum_b m_b (P_a v_b/rho_a^2 + P_b v_a/rho_b^2
+//                                             + (v_a + v_b)/2 Pi_ab) . grad_a W_ab
 //   viscosity:          Pi_ab = (-alpha cbar mu + beta mu^2)/rhobar if v_ab . r_ab < 0,
 //                       mu = h_ab v_ab . r_ab / (r^2 + eps h_ab^2)
 // with the M4 cubic spline, W = w(q)/(pi h^3), grad_a W_ab = r_ab g(q)/(pi h^5), g = w'(q)/q.
@@ -81,7 +84,7 @@ __global__ void __launch_bounds__(PAIR_THREADS) k_density(
     const DevCtl* __restrict__ ctl, const int4* __restrict__ group, int gsz, int cap, const int* __restrict__ nbr,
     const int* __restrict__ nbr_cnt, const int* __restrict__ uni, const int* __restrict__ ucnt,
     const double4* __restrict__ pos4, const double4* __restrict__ vel4, const double* __restrict__ m,
-    const double* __restrict__ u_eos, double gamma, double h_coeff, double* __restrict__ rho,
+    const double* __restrict__ u_eos, int kin, double gamma, double h_coeff, double* __restrict__ rho,
     double* __restrict__ P, double* __restrict__ cs, double* __restrict__ hnext, double4* __restrict__ thr4,
     float4* __restrict__ thrf) {
     __shared__ double4 spos[DENS_CHUNK];
@@ -128,7 +131,11 @@ __global__ void __launch_bounds__(PAIR_THREADS) k_density(
             double sum = red[t];
             for (int f = 1; f < PL; ++f) sum += red[t + gsz * f];
             const double r_ = sum * M_1_PI_D;
-            const double ue = u_eos[q];
+            double ue = u_eos[q];
+            if (kin) {  // u_eos holds the total energy e = u + v^2/2 (thermokinetic form)
+                const double4 v = vel4[q];
+                ue -= 0.5 * (v.x * v.x + v.y * v.y + v.z * v.z);
+            }
             const double p_ = (gamma - 1.0) * r_ * ue;
             const double c_ = sqrt(gamma * p_ / r_);
             const double pr2 = p_ / (r_ * r_);
@@ -143,16 +150,16 @@ __global__ void __launch_bounds__(PAIR_THREADS) k_density(
 }
 
 void launch_density(hipStream_t s, const DevPtrs& d, const Dims& dm, int fp32c, double gamma, double h_coeff,
-                    const double* u_eos) {
+                    const double* u_eos, int kin) {
     if (dm.n <= 0) return;
     if (fp32c)
         hipLaunchKernelGGL(k_density<true>, dim3(dm.group_grid), dim3(PAIR_THREADS), 0, s, d.ctl, d.group,
                            dm.group_size, dm.nbr_cap, d.nbr, d.nbr_cnt, d.uni, d.ucnt, d.pos4, d.vel4, d.m, u_eos,
-                           gamma, h_coeff, d.rho, d.P, d.cs, d.hnext, d.thr4, d.thrf);
+                           kin, gamma, h_coeff, d.rho, d.P, d.cs, d.hnext, d.thr4, d.thrf);
     else
         hipLaunchKernelGGL(k_density<false>, dim3(dm.group_grid), dim3(PAIR_THREADS), 0, s, d.ctl, d.group,
                            dm.group_size, dm.nbr_cap, d.nbr, d.nbr_cnt, d.uni, d.ucnt, d.pos4, d.vel4, d.m, u_eos,
-                           gamma, h_coeff, d.rho, d.P, d.cs, d.hnext, d.thr4, d.thrf);
+                           kin, gamma, h_coeff, d.rho, d.P, d.cs, d.hnext, d.thr4, d.thrf);
 }
 
 // Source records in LDS for the force sums: FP64 (x, h), (v, m), (rho, P/rho^2, c), or
@@ -172,7 +179,7 @@ struct ForceSrc<true> {
     float4 thr[FORCE_CHUNK];
 };
 
-template <bool FP32C>
+template <bool FP32C, bool THERMO>
 __global__ void __launch_bounds__(PAIR_THREADS) k_forces(
     const DevCtl* __restrict__ ctl, const int4* __restrict__ group, int gsz, int cap, const int* __restrict__ nbr,
     const int* __restrict__ nbr_cnt, const int* __restrict__ uni, const int* __restrict__ ucnt,
@@ -237,7 +244,13 @@ __global__ void __launch_bounds__(PAIR_THREADS) k_forces(
                     sx = fma(-term, dx, sx);
                     sy = fma(-term, dy, sy);
                     sz = fma(-term, dz, sz);
-                    su = fma(vb.w * fma(0.5, Pi, mt.y) * gw, vr, su);
+                    if (THERMO) {  // eq. (8): P_a v_b/rho_a^2 + P_b v_a/rho_b^2 + (v_a + v_b)/2 Pi
+                        const double var = fma(mv.x, dx, fma(mv.y, dy, mv.z * dz));
+                        const double vbr = fma(vb.x, dx, fma(vb.y, dy, vb.z * dz));
+                        su = fma(-vb.w * gw, fma(mt.y, vbr, fma(tb.y, var, 0.5 * Pi * (var + vbr))), su);
+                    } else {
+                        su = fma(vb.w * fma(0.5, Pi, mt.y) * gw, vr, su);
+                    }
                     k = kn;
                     e = en;
                 }
@@ -287,7 +300,13 @@ __global__ void __launch_bounds__(PAIR_THREADS) k_forces(
                     sx.add(-term * dx);
                     sy.add(-term * dy);
                     sz.add(-term * dz);
-                    su.add(vb.w * fmaf(0.5f, Pi, mt.y) * gw * vr);
+                    if (THERMO) {
+                        const float var = fmaf(mv.x, dx, fmaf(mv.y, dy, mv.z * dz));
+                        const float vbr = fmaf(vb.x, dx, fmaf(vb.y, dy, vb.z * dz));
+                        su.add(-vb.w * gw * fmaf(mt.y, vbr, fmaf(tb.y, var, 0.5f * Pi * (var + vbr))));
+                    } else {
+                        su.add(vb.w * fmaf(0.5f, Pi, mt.y) * gw * vr);
+                    }
                     k = kn;
                     e = en;
                 }
@@ -319,14 +338,18 @@ __global__ void __launch_bounds__(PAIR_THREADS) k_forces(
 }
 
 void launch_forces(hipStream_t s, const DevPtrs& d, const Dims& dm, int fp32c, double alpha, double beta,
-                   double eps_av, const double*, const double*, const double*) {
+                   double eps_av, int thermo) {
     if (dm.n <= 0) return;
-    if (fp32c)
-        hipLaunchKernelGGL(k_forces<true>, dim3(dm.group_grid), dim3(PAIR_THREADS), 0, s, d.ctl, d.group,
-                           dm.group_size, dm.nbr_cap, d.nbr, d.nbr_cnt, d.uni, d.ucnt, d.pos4, d.vel4, d.thr4,
-                           d.velf, d.thrf, alpha, beta, eps_av, d.ax, d.ay, d.az, d.du);
-    else
-        hipLaunchKernelGGL(k_forces<false>, dim3(dm.group_grid), dim3(PAIR_THREADS), 0, s, d.ctl, d.group,
-                           dm.group_size, dm.nbr_cap, d.nbr, d.nbr_cnt, d.uni, d.ucnt, d.pos4, d.vel4, d.thr4,
-                           d.velf, d.thrf, alpha, beta, eps_av, d.ax, d.ay, d.az, d.du);
+    auto go = [&](auto kern) {
+        hipLaunchKernelGGL(kern, dim3(dm.group_grid), dim3(PAIR_THREADS), 0, s, d.ctl, d.group, dm.group_size,
+                           dm.nbr_cap, d.nbr, d.nbr_cnt, d.uni, d.ucnt, d.pos4, d.vel4, d.thr4, d.velf, d.thrf, alpha,
+                           beta, eps_av, d.ax, d.ay, d.az, d.du);
+    };
+    if (fp32c) {
+        if (thermo) go(k_forces<true, true>);
+        else go(k_forces<true, false>);
+    } else {
+        if (thermo) go(k_forces<false, true>);
+        else go(k_forces<false, false>);
+    }
 }

@@ -111,16 +111,17 @@ __global__ void __launch_bounds__(256) k_diag1(int n, const double* __restrict__
                                                 const double* __restrict__ z, const double* __restrict__ vx,
                                                 const double* __restrict__ vy, const double* __restrict__ vz,
                                                 const double* __restrict__ m, const double* __restrict__ u,
-                                                const double* __restrict__ phi, double* part) {
+                                                const double* __restrict__ phi, int kin, double* part) {
     double a[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
     for (int q = blockIdx.x * blockDim.x + threadIdx.x; q < n; q += gridDim.x * blockDim.x) {
         const double mm = m[q], px = x[q], py = y[q], pz = z[q], wx = vx[q], wy = vy[q], wz = vz[q];
+        const double uq = kin ? u[q] - 0.5 * (wx * wx + wy * wy + wz * wz) : u[q];
         a[0] += mm * wx; a[1] += mm * wy; a[2] += mm * wz;
         a[3] += mm * (py * wz - pz * wy);
         a[4] += mm * (pz * wx - px * wz);
         a[5] += mm * (px * wy - py * wx);
         a[6] += 0.5 * mm * (wx * wx + wy * wy + wz * wz);
-        a[7] += mm * u[q];
+        a[7] += mm * uq;
         if (phi) a[8] += 0.5 * mm * phi[q];
     }
     __shared__ double red[4][9];
@@ -141,27 +142,42 @@ __global__ void k_diag2(const double* __restrict__ part, DevCtl* ctl) {
         ctl->diag[threadIdx.x] = s;
     }
 }
-void launch_diag(hipStream_t s, const DevPtrs& d, int n, int with_phi) {
+void launch_diag(hipStream_t s, const DevPtrs& d, int n, int with_phi, int kin) {
     hipLaunchKernelGGL(k_diag1, dim3(DIAG_BLOCKS), dim3(256), 0, s, n, d.x, d.y, d.z, d.vx, d.vy, d.vz, d.m, d.u,
-                       with_phi ? d.phi : nullptr, d.diag_part);
+                       with_phi ? d.phi : nullptr, kin, d.diag_part);
     hipLaunchKernelGGL(k_diag2, dim3(1), dim3(64), 0, s, d.diag_part, d.ctl);
 }
 
-// Resident key-ordered state -> caller order.
+// Resident key-ordered state -> caller order (kin: the resident u is e = u + v^2/2).
 __global__ void k_write_back(int n, DevPtrs d, double* x, double* y, double* z, double* vx, double* vy, double* vz,
-                             double* h, double* u, double* ax, double* ay, double* az, double* du) {
+                             double* h, double* u, double* ax, double* ay, double* az, double* du, int kin) {
     const int q = blockIdx.x * blockDim.x + threadIdx.x;
     if (q >= n) return;
     const u32 i = d.id[q];
+    const double wx = d.vx[q], wy = d.vy[q], wz = d.vz[q];
     x[i] = d.x[q]; y[i] = d.y[q]; z[i] = d.z[q];
-    vx[i] = d.vx[q]; vy[i] = d.vy[q]; vz[i] = d.vz[q];
-    h[i] = d.h[q]; u[i] = d.u[q];
+    vx[i] = wx; vy[i] = wy; vz[i] = wz;
+    h[i] = d.h[q];
+    u[i] = kin ? d.u[q] - 0.5 * (wx * wx + wy * wy + wz * wz) : d.u[q];
     if (ax) { ax[i] = d.ax[q]; ay[i] = d.ay[q]; az[i] = d.az[q]; du[i] = d.du[q]; }
 }
 void launch_write_back(hipStream_t s, const DevPtrs& d, int n, double* x, double* y, double* z, double* vx, double* vy,
-                       double* vz, double* h, double* u, double* ax, double* ay, double* az, double* du) {
+                       double* vz, double* h, double* u, double* ax, double* ay, double* az, double* du, int kin) {
     if (n > 0)
-        hipLaunchKernelGGL(k_write_back, g256(n), dim3(256), 0, s, n, d, x, y, z, vx, vy, vz, h, u, ax, ay, az, du);
+        hipLaunchKernelGGL(k_write_back, g256(n), dim3(256), 0, s, n, d, x, y, z, vx, vy, vz, h, u, ax, ay, az, du,
+                           kin);
+}
+
+// Thermokinetic form: the resident thermal u becomes the total energy e = u + v^2/2.
+__global__ void k_add_kinetic(int n, const double* __restrict__ vx, const double* __restrict__ vy,
+                              const double* __restrict__ vz, double* u) {
+    const int q = blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= n) return;
+    const double wx = vx[q], wy = vy[q], wz = vz[q];
+    u[q] = u[q] + 0.5 * (wx * wx + wy * wy + wz * wz);
+}
+void launch_add_kinetic(hipStream_t s, const DevPtrs& d, int n) {
+    if (n > 0) hipLaunchKernelGGL(k_add_kinetic, g256(n), dim3(256), 0, s, n, d.vx, d.vy, d.vz, d.u);
 }
 
 // Caller-supplied accelerations of the input state -> key order.

@@ -263,6 +263,74 @@ def test_step_lockstep(orc, case, adaptive, dt):
         flags = sph.SPH_STEP_PRIMED
 
 
+# ---------------------------------------------------------------------------- thermokinetic form (eq. (8))
+@pytest.mark.parametrize("prec", [0, 1])
+@pytest.mark.parametrize("case", ["random_varh", "sod_small", "duplicates"])
+def test_thermokinetic_rate(orc, case, prec):
+    """de/dt of eq. (8) against the oracle with random velocities (viscosity active): FP64
+    within 1e-12 of the absolute-sum scale, FP32C within the stated 2e-6."""
+    import torch
+    import paper_2007_03097_amd as sph
+    ps = CASES[case]()
+    rng = np.random.default_rng(3)
+    ps.vx, ps.vy, ps.vz = (rng.normal(0.0, 0.3, ps.n) for _ in range(3))
+    ctx = make_ctx(ps.n, precision=prec, energy_form=sph.SPH_ENERGY_THERMOKINETIC, nbr_capacity=4096)
+    gpu_keys_order(ctx, parts(ps))
+    gpu_density(ctx, ps.n)
+    ax, ay, az, de = gpu_forces(ctx, ps.n)
+    csr = orc.neighbors(ps.x, ps.y, ps.z, ps.h)
+    rho, P, c, _ = orc.density(ps.fields(), csr)
+    r_de, Se = orc.dedt(ps.fields(), rho, P, c, csr)
+    r_ax, r_ay, r_az, _, Sa, _ = orc.forces(ps.fields(), rho, P, c, csr)
+    bound = TOL if prec == 0 else 2e-6
+    assert np.all(np.abs(de - r_de) <= bound * Se + 1e-300)
+    assert np.all(np.sqrt((ax - r_ax) ** 2 + (ay - r_ay) ** 2 + (az - r_az) ** 2) <= bound * Sa + 1e-300)
+
+
+@pytest.mark.parametrize("case,adaptive,dt,G", [("lattice4096", 0, 0.0178, 0.0), ("sod_small", 1, 4.0e-4, 0.0),
+                                                ("polytrope", 1, 2.0e-3, 1.0)])
+def test_thermokinetic_step_lockstep(orc, case, adaptive, dt, G):
+    """Thermokinetic KDK steps in lockstep with the oracle (each GPU step starts from the GPU
+    state); with gravity (theta = 0: the direct sum) de/dt includes the work v.g."""
+    import paper_2007_03097_amd as sph
+    ps = CASES[case]()
+    if case == "lattice4096":
+        rng = np.random.default_rng(9)
+        ps.vx, ps.vy, ps.vz = (rng.normal(0.0, 0.2, ps.n) for _ in range(3))
+    ctx = make_ctx(ps.n, adaptive_h=adaptive, energy_form=sph.SPH_ENERGY_THERMOKINETIC, G=G, soft_eps=0.01,
+                   theta=0.0, nbr_capacity=1024)
+    pa = parts(ps, with_accel=True)
+    prm = orc.Params(adaptive_h=bool(adaptive), thermokinetic=True, G=G, soft_eps=0.01)
+    st = orc.prime(ps.fields(), prm)
+    flags = 0
+    for step in range(3):
+        start = st if step == 0 else dict(_state_from(ps, pa))
+        sph.sph_step(ctx.h, pa, dt, 1, flags)
+        got = _state_from(ps, pa)
+        ref = orc.kdk_step(start, dt, prm)
+        for k in ("x", "y", "z", "vx", "vy", "vz", "u", "h", "ax", "ay", "az", "dudt"):
+            scale = max(np.abs(ref[k]).max(), 1e-300)
+            assert np.abs(got[k] - ref[k]).max() <= 1e-11 * scale, (step, k)
+        flags = sph.SPH_STEP_PRIMED
+
+
+def test_thermokinetic_energy_conserved_on_gpu():
+    """Resident thermokinetic steps conserve E_kin + E_th to rounding (sum m de/dt = 0 at every
+    evaluation), far better than the thermal form over the same steps."""
+    import paper_2007_03097_amd as sph
+    ps = lattice_box(16, v_sigma=0.2)
+    out = {}
+    for form in (sph.SPH_ENERGY_THERMAL, sph.SPH_ENERGY_THERMOKINETIC):
+        ctx = make_ctx(ps.n, energy_form=form)
+        pa = parts(ps)
+        d0 = sph.sph_step(ctx.h, pa, 1e-12, 0, 0)
+        d1 = sph.sph_step(ctx.h, pa, 0.01, 10, sph.SPH_STEP_RESUME)
+        out[form] = abs((d1[6] + d1[7]) - (d0[6] + d0[7])) / (d0[6] + d0[7])
+        ctx.close()
+    assert out[sph.SPH_ENERGY_THERMOKINETIC] <= 1e-13
+    assert out[sph.SPH_ENERGY_THERMAL] > 100 * out[sph.SPH_ENERGY_THERMOKINETIC]
+
+
 def test_graph_replay_matches_eager(monkeypatch):
     """Steps replayed from the captured HIP graphs equal eager launches bit for bit."""
     import paper_2007_03097_amd as sph
