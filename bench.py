@@ -235,6 +235,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-extra", action="store_true", help="skip the polytrope and ensemble workloads")
     ap.add_argument("--no-autotune", action="store_true", help="keep the default leaf and group sizes")
+    ap.add_argument("--sweep", action="store_true",
+                    help="instead of the benchmark: gravity time/accuracy vs theta and time vs N (one JSON line)")
     ap.add_argument("--copy-calib-mib", type=int, default=0,
                     help="first run one device-to-device copy of this many MiB (hardware-counter calibration)")
     args = ap.parse_args()
@@ -245,6 +247,9 @@ def main():
     import torch
     from workloads import sod_tube
     assert torch.cuda.is_available(), "needs a GPU"
+    if args.sweep:
+        print(json.dumps(run_sweeps()), flush=True)
+        return
     if args.copy_calib_mib > 0:
         src = torch.empty(args.copy_calib_mib << 20, dtype=torch.uint8, device="cuda")
         dst = torch.empty_like(src)
