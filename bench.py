@@ -201,6 +201,73 @@ def run_ensemble(steps):
     return out
 
 
+def run_sweeps():
+    """Gravity time and accuracy against the opening angle (n = 1 polytrope, 262,144
+    particles; the theta = 0 result of the same kernel -- the direct sum -- is the reference)
+    and time against N at theta = 0.5 (gravity and the SPH passes), with power-law fits."""
+    import numpy as np
+    import torch
+    import paper_2007_03097_amd as sph
+    from workloads import polytrope_n1
+
+    def timed(fn, reps=3):
+        fn()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(reps):
+            fn()
+        e1.record()
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / reps
+
+    out = {"metric": "gravity time and accuracy vs opening angle; time vs N", "data": "synthetic",
+           "workload": "n = 1 polytrope, G = 1, eps = 0.01, quadrupole cells, FP64"}
+    ps = polytrope_n1(262144, seed=1003)
+    n = ps.n
+    pa = sph.ParticleArrays.from_numpy(ps)
+    ref = None
+    rows = []
+    for theta in (0.0, 0.2, 0.3, 0.4, 0.5, 0.6, 0.7, 0.8, 0.9, 1.0):
+        ctx = sph.Context(n, G=1.0, soft_eps=0.01, theta=theta)
+        sph.sph_build_tree(ctx.h, pa)
+        g = [torch.zeros(n, dtype=torch.float64, device="cuda") for _ in range(3)]
+        ms = timed(lambda: sph.sph_compute_gravity(ctx.h, *g), reps=1 if theta == 0.0 else 3)
+        gv = torch.stack(g, 1).cpu().numpy()
+        if ref is None:
+            ref = gv
+        e = np.linalg.norm(gv - ref, axis=1) / np.linalg.norm(ref, axis=1)
+        rows.append({"theta": theta, "gravity_ms": ms, "rms_rel_err": float(np.sqrt((e ** 2).mean())),
+                     "p99_rel_err": float(np.quantile(e, 0.99))})
+        print(json.dumps(rows[-1]), file=sys.stderr, flush=True)
+        ctx.close()
+    out["theta_sweep_n262144"] = rows
+    del pa
+    rows = []
+    for n in (65536, 262144, 1048576, 4194304):
+        ps = polytrope_n1(n, seed=1003)
+        pa = sph.ParticleArrays.from_numpy(ps)
+        ctx = sph.Context(n, G=1.0, soft_eps=0.01, theta=0.5, nbr_capacity=2048)
+        sph.sph_build_tree(ctx.h, pa)
+        g = [torch.zeros(n, dtype=torch.float64, device="cuda") for _ in range(3)]
+        tg = timed(lambda: sph.sph_compute_gravity(ctx.h, *g))
+        tl = timed(lambda: sph.sph_find_neighbors(ctx.h, count=False))
+        td = timed(lambda: sph.sph_compute_density(ctx.h, None, None, None, None))
+        tf = timed(lambda: sph.sph_compute_forces(ctx.h, None, None, None, None))
+        rows.append({"n": n, "gravity_ms": tg, "lists_ms": tl, "density_ms": td, "forces_ms": tf})
+        print(json.dumps(rows[-1]), file=sys.stderr, flush=True)
+        ctx.close()
+        del pa, g
+        torch.cuda.empty_cache()
+    out["n_sweep_theta0.5"] = rows
+    ns = np.array([r["n"] for r in rows], dtype=float)
+    for key in ("gravity_ms", "lists_ms", "density_ms", "forces_ms"):
+        t = np.array([r[key] for r in rows])
+        out[f"{key}_exponent"] = float(np.polyfit(np.log(ns[1:]), np.log(t[1:]), 1)[0])
+        out[f"{key}_per_nlogn_ns"] = [float(x * 1e6 / (m * np.log2(m))) for x, m in zip(t, ns)]
+    return out
+
+
 def cpu_baseline(ps, reps=10):
     """The CPU FP64 reference on a bounded sample: the slab 0.42 < x < 0.58 of the same tube
     (both lattices and the interface).  Brute-force neighbours are built once (reported,
