@@ -113,8 +113,8 @@ static size_t layout(const sph_ctx* c, char* base, DevPtrs* out) {
     d.key_b = cv.take<u64>(N);
     d.val_a = cv.take<u32>(N);
     d.val_b = cv.take<u32>(N);
-    d.rs_hist = cv.take<u32>(8 * 256 * RSB);
-    d.rs_dtot = cv.take<u32>(8 * 256 + 64);
+    d.rs_hist = cv.take<u32>(256 * RSB);
+    d.rs_dtot = cv.take<u32>(256);
     d.scan_tmp = cv.take<u64>(SCB);
     double** f1[] = {&d.x, &d.y, &d.z, &d.vx, &d.vy, &d.vz, &d.m, &d.h, &d.u, &d.vpx, &d.vpy, &d.vpz, &d.up,
                      &d.ax, &d.ay, &d.az, &d.du, &d.rho, &d.P, &d.cs, &d.hnext, &d.gx, &d.gy, &d.gz, &d.phi,
@@ -283,7 +283,6 @@ static sph_status read_err(sph_ctx* c) {
     if (e & ERR_WALK_STACK) return fail(c, SPH_E_CAPACITY, "device: tree-walk stack or candidate list overflow");
     if (e & ERR_NODE_CAP) return fail(c, SPH_E_CAPACITY, "device: octree node capacity exceeded");
     if (e & ERR_GRAV_LIST) return fail(c, SPH_E_CAPACITY, "device: gravity walk stack overflow");
-    if (e & ERR_SORT_WAIT) return fail(c, SPH_E_DEVICE, "device: radix sort look-back did not complete");
     return fail(c, SPH_E_DEVICE, "device error word 0x%x", e);
 }
 

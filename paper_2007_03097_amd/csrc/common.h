@@ -17,7 +17,6 @@ enum : u32 {
     ERR_WALK_STACK = 8u,     // tree-walk stack or candidate list overflow
     ERR_NODE_CAP = 16u,      // octree node capacity exceeded
     ERR_GRAV_LIST = 32u,     // gravity walk stack overflow
-    ERR_SORT_WAIT = 64u,     // radix sort: a tile's predecessor never published its counts
 };
 
 constexpr int MAX_LEVEL = 21;   // 21 three-bit digits below the sentinel bit 63
@@ -46,8 +45,8 @@ struct DevPtrs {
     // sort
     u64 *key_a, *key_b;           // n_cap
     u32 *val_a, *val_b;           // n_cap
-    u32* rs_hist;                 // radix sort look-back words: 8 passes x tiles x 256 digits
-    u32* rs_dtot;                 // radix sort: 8 x 256 digit totals, then 8 tile counters
+    u32* rs_hist;                 // 256 * rs_blocks_cap
+    u32* rs_dtot;                 // 256 digit totals of the current pass
     void* scan_tmp;               // 8 * scan_blocks_cap (u64)
     // Morton-ordered particle data (SoA FP64)
     double *x, *y, *z, *vx, *vy, *vz, *m, *h, *u;

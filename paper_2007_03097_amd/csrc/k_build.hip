@@ -3,8 +3,7 @@
 //  * k_bbox      exact per-segment bounding box (ordered-integer atomics, order independent)
 //  * k_keys      quantise to B bits inside the cubic root cell, interleave (x lowest),
 //                sentinel bit 63, segment number in bits 54..62 for segmented sets
-//  * radix sort  stable LSD, 8 passes of 8-bit digits over (key, caller index), one launch
-//                per pass with decoupled look-back; stability
+//  * radix sort  stable LSD, 8 passes of 8-bit digits over (key, caller index); stability
 //                plus an identity initial order gives the (key, ID) order of the paper
 //  * gather      caller-order input -> key-ordered SoA + AoS records
 #include "common.h"
@@ -312,55 +311,45 @@ static void scan_u32(hipStream_t s, u32* a, int n, void* tmp) { scan_impl<u32>(s
 void scan_u32_total(hipStream_t s, const u32* in, u32* out, int n, void* tmp) { scan_impl<u32>(s, in, out, n, tmp, 1); }
 
 // ---------------------------------------------------------------------------------------
-// LSD radix sort of (u64 key, u32 value), 8-bit digits, 8 passes, one launch per pass.
-//  * k_rs_count: the digit counts of all eight passes in one read of the keys.
-//  * k_rs_pass: each workgroup takes the next 2048-key tile (an atomic ticket, so tiles
-//    start in order), ranks its keys per digit (wave w owns keys [w*512, w*512 + 512) of the
-//    tile in 8 rounds of 64, so (wave, round, lane) order is index order: stable), publishes
-//    its per-digit counts, and finds the counts of all earlier tiles by looking back over
-//    their published words (decoupled look-back; a word holds a status and a count, so one
-//    atomic access carries both).  Every tile publishes before it looks back, and a tile
-//    only waits for tiles that started earlier, so the waits end; each wait is also bounded
-//    (ERR_SORT_WAIT).  The keys are then placed in LDS in sorted order and written out
-//    from there, so consecutive lanes write consecutive addresses of a digit's run.
+// LSD radix sort of (u64 key, u32 value), 8-bit digits, 8 passes.  Each block owns a tile
+// of 2048 keys; wave w of the block owns keys [w*512, w*512 + 512) of the tile in 8 rounds
+// of 64, so (wave, round, lane) order is index order and ranks are stable.
 constexpr int RS_THREADS = 256, RS_ITEMS = 8, RS_TILE = RS_THREADS * RS_ITEMS, RS_WAVES = RS_THREADS / 64;
-constexpr u32 LB_AGG = 1u << 30, LB_INC = 2u << 30, LB_VAL = (1u << 30) - 1u;
-constexpr int LB_SPIN = 1 << 16;
 
-__global__ void __launch_bounds__(RS_THREADS) k_rs_count(const u64* __restrict__ key, int n, u32* counts) {
-    __shared__ u32 h[8][256];
-    for (int j = threadIdx.x; j < 8 * 256; j += RS_THREADS) (&h[0][0])[j] = 0;
+__global__ void __launch_bounds__(RS_THREADS) k_rs_hist(const u64* __restrict__ key, int n, int shift, u32* hist,
+                                                        int nb) {
+    __shared__ u32 h[RS_WAVES][256];
+    const int w = threadIdx.x >> 6, lane = lane_id();
+    for (int i = threadIdx.x; i < RS_WAVES * 256; i += RS_THREADS) (&h[0][0])[i] = 0;
     __syncthreads();
-    for (int i = blockIdx.x * RS_THREADS + threadIdx.x; i < n; i += gridDim.x * RS_THREADS) {
-        const u64 k = key[i];
+    const int base = blockIdx.x * RS_TILE + w * (64 * RS_ITEMS) + lane;
 #pragma unroll
-        for (int p = 0; p < 8; ++p) atomicAdd(&h[p][(u32)(k >> (8 * p)) & 255u], 1u);
+    for (int r = 0; r < RS_ITEMS; ++r) {
+        int i = base + r * 64;
+        if (i < n) atomicAdd(&h[w][(key[i] >> shift) & 255u], 1u);
     }
     __syncthreads();
-    for (int j = threadIdx.x; j < 8 * 256; j += RS_THREADS) {
-        const u32 v = (&h[0][0])[j];
-        if (v) atomicAdd(&counts[j], v);
-    }
+    u32 t = 0;
+    for (int k = 0; k < RS_WAVES; ++k) t += h[k][threadIdx.x];
+    hist[threadIdx.x * nb + blockIdx.x] = t;
 }
 
-__global__ void __launch_bounds__(RS_THREADS) k_rs_pass(const u64* __restrict__ kin, const u32* __restrict__ vin,
-                                                        u64* __restrict__ kout, u32* __restrict__ vout, int n, int pass,
-                                                        const u32* __restrict__ counts, u32* lookback, u32* ticket,
-                                                        DevCtl* ctl) {
+__global__ void __launch_bounds__(RS_THREADS) k_rs_scatter(const u64* __restrict__ kin, const u32* __restrict__ vin,
+                                                           u64* __restrict__ kout, u32* __restrict__ vout, int n,
+                                                           int shift, const u32* __restrict__ offs, int nb,
+                                                           const u32* __restrict__ digit_tot) {
     __shared__ u32 wcnt[RS_WAVES][256];
-    __shared__ u32 loff[256];
-    __shared__ u32 gbase[256];
-    __shared__ u64 sk[RS_TILE];
-    __shared__ u32 sv[RS_TILE];
-    __shared__ int s_tile;
+    __shared__ u32 woff[RS_WAVES][256];
+    __shared__ u32 dbase[256];
     const int w = threadIdx.x >> 6, lane = lane_id();
-    const int shift = 8 * pass;
-    if (threadIdx.x == 0) s_tile = (int)atomicAdd(ticket, 1u);
     for (int i = threadIdx.x; i < RS_WAVES * 256; i += RS_THREADS) (&wcnt[0][0])[i] = 0;
+    {   // exclusive scan of the digit totals
+        u32 tot;
+        const u32 e = block_excl_scan<u32>(digit_tot[threadIdx.x], &tot);
+        dbase[threadIdx.x] = e;
+    }
     __syncthreads();
-    const int tile = s_tile;
-    const int t0 = tile * RS_TILE;
-    const int base = t0 + w * (64 * RS_ITEMS) + lane;
+    const int base = blockIdx.x * RS_TILE + w * (64 * RS_ITEMS) + lane;
     u64 k[RS_ITEMS];
     u32 v[RS_ITEMS], rank[RS_ITEMS];
     const u64 lt = lanemask_lt();
@@ -384,83 +373,68 @@ __global__ void __launch_bounds__(RS_THREADS) k_rs_pass(const u64* __restrict__ 
         if (leader) wcnt[w][dg] = before + (u32)__popcll(peers);
     }
     __syncthreads();
-    // per digit (thread d): tile count, local offset, per-wave offsets; publish and look back
-    const int d = threadIdx.x;
-    const u32 c0 = wcnt[0][d], c1 = wcnt[1][d], c2 = wcnt[2][d], c3 = wcnt[3][d];
-    const u32 cnt = c0 + c1 + c2 + c3;
-    u32 tot;
-    const u32 lo = block_excl_scan<u32>(cnt, &tot);
-    const u32 gdig = block_excl_scan<u32>(counts[pass * 256 + d], &tot);
-    u32* my = lookback + (size_t)tile * 256 + d;
-    __hip_atomic_store(my, (tile == 0 ? LB_INC : LB_AGG) | cnt, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    u32 excl = 0;
-    if (tile > 0) {
-        int t = tile - 1, spins = 0;
-        while (t >= 0) {
-            const u32 word = __hip_atomic_load(lookback + (size_t)t * 256 + d, __ATOMIC_RELAXED,
-                                               __HIP_MEMORY_SCOPE_AGENT);
-            const u32 st = word & ~LB_VAL;
-            if (st == 0u) {
-                if (++spins > LB_SPIN) {
-                    set_err(ctl, ERR_SORT_WAIT);
-                    break;
-                }
-                continue;
-            }
-            excl += word & LB_VAL;
-            if (st == LB_INC) break;
-            --t;
+    {
+        const int dg = threadIdx.x;
+        u32 acc = 0;
+        const u32 base = dbase[dg] + offs[dg * nb + blockIdx.x];
+        for (int q = 0; q < RS_WAVES; ++q) {
+            woff[q][dg] = acc + base;
+            acc += wcnt[q][dg];
         }
-        __hip_atomic_store(my, LB_INC | (excl + cnt), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
-    loff[d] = lo;
-    gbase[d] = gdig + excl;
-    wcnt[0][d] = lo;
-    wcnt[1][d] = lo + c0;
-    wcnt[2][d] = lo + c0 + c1;
-    wcnt[3][d] = lo + c0 + c1 + c2;
     __syncthreads();
-    // keys into LDS at their position within the tile's sorted order
 #pragma unroll
     for (int r = 0; r < RS_ITEMS; ++r) {
-        if (base + r * 64 < n) {
+        const int i = base + r * 64;
+        if (i < n) {
             const u32 dg = (u32)(k[r] >> shift) & 255u;
-            const u32 pl = wcnt[w][dg] + rank[r];
-            sk[pl] = k[r];
-            sv[pl] = v[r];
+            const u32 pos = woff[w][dg] + rank[r];
+            kout[pos] = k[r];
+            vout[pos] = v[r];
         }
     }
-    __syncthreads();
-    // write out: consecutive threads take consecutive sorted positions
-    const int tn = n - t0 < RS_TILE ? n - t0 : RS_TILE;
+}
+
+// Per-digit exclusive scan of the per-block counts: one workgroup per digit scans that
+// digit's contiguous row (digit-major table) and records the digit total.
+__global__ void __launch_bounds__(SC_THREADS) k_rs_digit_scan(u32* hist, int nb, u32* digit_tot) {
+    u32* h = hist + (size_t)blockIdx.x * nb;
+    u32 carry = 0;
+    for (int b0 = 0; b0 < nb; b0 += SC_TILE) {
+        u32 v[SC_ITEMS];
+        u32 s = 0;
 #pragma unroll
-    for (int r = 0; r < RS_ITEMS; ++r) {
-        const int j = threadIdx.x + r * RS_THREADS;
-        if (j < tn) {
-            const u64 kk = sk[j];
-            const u32 dg = (u32)(kk >> shift) & 255u;
-            const u32 pos = gbase[dg] + ((u32)j - loff[dg]);
-            kout[pos] = kk;
-            vout[pos] = sv[j];
+        for (int k = 0; k < SC_ITEMS; ++k) {
+            const int i = b0 + threadIdx.x * SC_ITEMS + k;
+            v[k] = i < nb ? h[i] : 0u;
+            s += v[k];
         }
+        u32 tot;
+        u32 e = block_excl_scan<u32>(s, &tot) + carry;
+#pragma unroll
+        for (int k = 0; k < SC_ITEMS; ++k) {
+            const int i = b0 + threadIdx.x * SC_ITEMS + k;
+            if (i < nb) h[i] = e;
+            e += v[k];
+        }
+        carry += tot;
+        __syncthreads();
     }
+    if (threadIdx.x == 0) digit_tot[blockIdx.x] = carry;
 }
 
 // Sorts (key_a, val_a) in place (ping-pong through key_b / val_b; 8 passes end in _a).
 void radix_sort(hipStream_t s, const DevPtrs& d, int n) {
     if (n <= 1) return;
     const int nb = (n + RS_TILE - 1) / RS_TILE;
-    u32* counts = d.rs_dtot;
-    u32* tickets = d.rs_dtot + 8 * 256;
-    launch_fill_u32(s, d.rs_dtot, 0u, 8 * 256 + 8);
-    launch_fill_u32(s, d.rs_hist, 0u, 8 * 256 * nb);
-    const int gc = nb < 1024 ? nb : 1024;
-    hipLaunchKernelGGL(k_rs_count, dim3(gc), dim3(RS_THREADS), 0, s, d.key_a, n, counts);
     u64 *ki = d.key_a, *ko = d.key_b;
     u32 *vi = d.val_a, *vo = d.val_b;
     for (int pass = 0; pass < 8; ++pass) {
-        hipLaunchKernelGGL(k_rs_pass, dim3(nb), dim3(RS_THREADS), 0, s, ki, vi, ko, vo, n, pass, counts,
-                           d.rs_hist + (size_t)pass * 256 * nb, tickets + pass, d.ctl);
+        const int shift = 8 * pass;
+        hipLaunchKernelGGL(k_rs_hist, dim3(nb), dim3(RS_THREADS), 0, s, ki, n, shift, d.rs_hist, nb);
+        hipLaunchKernelGGL(k_rs_digit_scan, dim3(256), dim3(SC_THREADS), 0, s, d.rs_hist, nb, d.rs_dtot);
+        hipLaunchKernelGGL(k_rs_scatter, dim3(nb), dim3(RS_THREADS), 0, s, ki, vi, ko, vo, n, shift, d.rs_hist, nb,
+                           d.rs_dtot);
         u64* tk = ki; ki = ko; ko = tk;
         u32* tv = vi; vi = vo; vo = tv;
     }
