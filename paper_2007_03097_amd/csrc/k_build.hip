@@ -341,6 +341,10 @@ __global__ void __launch_bounds__(RS_THREADS) k_rs_scatter(const u64* __restrict
     __shared__ u32 wcnt[RS_WAVES][256];
     __shared__ u32 woff[RS_WAVES][256];
     __shared__ u32 dbase[256];
+    __shared__ u32 loff[256];
+    __shared__ u32 gbase[256];
+    __shared__ u64 sk[RS_TILE];
+    __shared__ u32 sv[RS_TILE];
     const int w = threadIdx.x >> 6, lane = lane_id();
     for (int i = threadIdx.x; i < RS_WAVES * 256; i += RS_THREADS) (&wcnt[0][0])[i] = 0;
     {   // exclusive scan of the digit totals
@@ -373,24 +377,42 @@ __global__ void __launch_bounds__(RS_THREADS) k_rs_scatter(const u64* __restrict
         if (leader) wcnt[w][dg] = before + (u32)__popcll(peers);
     }
     __syncthreads();
-    {
+    {   // per digit: local offsets of the tile's sorted order, per-wave offsets, global base
         const int dg = threadIdx.x;
-        u32 acc = 0;
-        const u32 base = dbase[dg] + offs[dg * nb + blockIdx.x];
-        for (int q = 0; q < RS_WAVES; ++q) {
-            woff[q][dg] = acc + base;
-            acc += wcnt[q][dg];
+        const u32 c0 = wcnt[0][dg], c1 = wcnt[1][dg], c2 = wcnt[2][dg], c3 = wcnt[3][dg];
+        u32 tot;
+        const u32 lo = block_excl_scan<u32>(c0 + c1 + c2 + c3, &tot);
+        loff[dg] = lo;
+        gbase[dg] = dbase[dg] + offs[dg * nb + blockIdx.x];
+        woff[0][dg] = lo;
+        woff[1][dg] = lo + c0;
+        woff[2][dg] = lo + c0 + c1;
+        woff[3][dg] = lo + c0 + c1 + c2;
+    }
+    __syncthreads();
+    // keys into LDS in the tile's sorted order, then written out from there so that
+    // consecutive lanes write consecutive addresses of a digit's run
+#pragma unroll
+    for (int r = 0; r < RS_ITEMS; ++r) {
+        if (base + r * 64 < n) {
+            const u32 dg = (u32)(k[r] >> shift) & 255u;
+            const u32 pl = woff[w][dg] + rank[r];
+            sk[pl] = k[r];
+            sv[pl] = v[r];
         }
     }
     __syncthreads();
+    const int t0 = blockIdx.x * RS_TILE;
+    const int tn = n - t0 < RS_TILE ? n - t0 : RS_TILE;
 #pragma unroll
     for (int r = 0; r < RS_ITEMS; ++r) {
-        const int i = base + r * 64;
-        if (i < n) {
-            const u32 dg = (u32)(k[r] >> shift) & 255u;
-            const u32 pos = woff[w][dg] + rank[r];
-            kout[pos] = k[r];
-            vout[pos] = v[r];
+        const int j = threadIdx.x + r * RS_THREADS;
+        if (j < tn) {
+            const u64 kk = sk[j];
+            const u32 dg = (u32)(kk >> shift) & 255u;
+            const u32 pos = gbase[dg] + ((u32)j - loff[dg]);
+            kout[pos] = kk;
+            vout[pos] = sv[j];
         }
     }
 }
