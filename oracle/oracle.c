@@ -110,6 +110,62 @@ void orc_keys(int64_t n, const double* x, const double* y, const double* z, int3
     }
 }
 
+/* 3D Hilbert index of grid cell (kx, ky, kz) on a 2^bits grid, by Skilling's transposition
+ * (J. Skilling, "Programming the Hilbert curve", AIP Conf. Proc. 707, 381 (2004)): the
+ * coordinates are transformed into the "transposed" index in place, whose bits read out
+ * level by level (x, then y, then z within a level) give the index.  One 3-bit digit per
+ * level, so every octree cell is one contiguous run of indices.                          */
+uint64_t orc_hilbert(uint32_t kx, uint32_t ky, uint32_t kz, int bits)
+{
+    uint32_t X[3] = {kx, ky, kz};
+    const uint32_t M = 1u << (bits - 1);
+    for (uint32_t Q = M; Q > 1; Q >>= 1) {      /* inverse undo */
+        const uint32_t P = Q - 1;
+        for (int i = 0; i < 3; ++i) {
+            if (X[i] & Q) {
+                X[0] ^= P;                        /* invert the low bits of x */
+            } else {
+                uint32_t t = (X[0] ^ X[i]) & P;   /* exchange low bits of x and axis i */
+                X[0] ^= t;
+                X[i] ^= t;
+            }
+        }
+    }
+    for (int i = 1; i < 3; ++i) X[i] ^= X[i - 1]; /* Gray encode */
+    uint32_t t = 0;
+    for (uint32_t Q = M; Q > 1; Q >>= 1)
+        if (X[2] & Q) t ^= Q - 1;
+    for (int i = 0; i < 3; ++i) X[i] ^= t;
+    uint64_t h = 0;
+    for (int b = bits - 1; b >= 0; --b)
+        for (int i = 0; i < 3; ++i) h = (h << 1) | ((X[i] >> b) & 1u);
+    return h;
+}
+
+/* orc_keys with the Hilbert index in place of the bit interleave (same quantisation,
+ * sentinel and segment prefix).                                                          */
+void orc_keys_hilbert(int64_t n, const double* x, const double* y, const double* z, int32_t nseg,
+                      const int64_t* seg_off, const double* box, uint64_t* keys)
+{
+    int batched = (nseg > 1);
+    int bits = batched ? 18 : 21;
+    int32_t ns = batched ? nseg : 1;
+    for (int32_t s = 0; s < ns; ++s) {
+        int64_t b = batched ? seg_off[s] : 0, e = batched ? seg_off[s + 1] : n;
+        double bb[6];
+        if (box) memcpy(bb, box + 6 * s, sizeof bb);
+        else orc_bbox(b, e, x, y, z, bb);
+        double S = orc_scale(bb, bits);
+        uint64_t prefix = (1ull << 63) | (batched ? ((uint64_t)s << 54) : 0ull);
+        for (int64_t i = b; i < e; ++i) {
+            uint32_t kx = orc_quantise(x[i], bb[0], S, bits);
+            uint32_t ky = orc_quantise(y[i], bb[1], S, bits);
+            uint32_t kz = orc_quantise(z[i], bb[2], S, bits);
+            keys[i] = prefix | orc_hilbert(kx, ky, kz, bits);
+        }
+    }
+}
+
 /* ------------------------------------------------------------------------------------ */
 /* Order: sort by (key, caller index); the caller index is the paper's unique particle ID
  * that resolves key collisions (Sec. 2.1).                                               */

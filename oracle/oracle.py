@@ -45,6 +45,9 @@ def lib():
             build(force=False)
         L = ctypes.CDLL(_LIB)
         L.orc_keys.argtypes = [I64, _d, _d, _d, I32, _i64, _d, _u64]
+        L.orc_keys_hilbert.argtypes = [I64, _d, _d, _d, I32, _i64, _d, _u64]
+        L.orc_hilbert.argtypes = [ctypes.c_uint32, ctypes.c_uint32, ctypes.c_uint32, ctypes.c_int]
+        L.orc_hilbert.restype = ctypes.c_uint64
         L.orc_order.argtypes = [I64, _u64, _i64]
         L.orc_octree.argtypes = [I64, _u64, ctypes.c_int, ctypes.c_int, I64, _u64, _i32, _i32, _i64, _i64]
         L.orc_octree.restype = I64
@@ -84,15 +87,23 @@ def _ii(a):
 # ---------------------------------------------------------------------------------------
 # Keys, order, tree (Sec. 2.1 "Tree topology", Fig. 1)
 
-def keys(x, y, z, seg_offsets=None, box=None):
+def keys(x, y, z, seg_offsets=None, box=None, curve="morton"):
+    """Sentinel-prefixed keys of the quantised positions: the Morton bit interleave
+    (Fig. 1), or the Hilbert index (curve="hilbert")."""
     x, y, z = _f64(x), _f64(y), _f64(z)
     n = x.size
     out = np.empty(n, dtype=np.uint64)
     nseg = 1 if seg_offsets is None else len(seg_offsets) - 1
     so = _ii(seg_offsets)
     bx = None if box is None else _f64(box)
-    lib().orc_keys(n, _p(x), _p(y), _p(z), nseg, _p(so, _i64), _p(bx), _p(out, _u64))
+    fn = lib().orc_keys_hilbert if curve == "hilbert" else lib().orc_keys
+    fn(n, _p(x), _p(y), _p(z), nseg, _p(so, _i64), _p(bx), _p(out, _u64))
     return out
+
+
+def hilbert(kx, ky, kz, bits):
+    """Hilbert index of one grid cell (for pins)."""
+    return int(lib().orc_hilbert(int(kx), int(ky), int(kz), int(bits)))
 
 
 def order(k):

@@ -83,6 +83,48 @@ def test_key_segments(orc):
     assert (k & np.uint64((1 << 54) - 1)).max() < (1 << 54)
 
 
+def test_hilbert_index_is_a_hilbert_curve(orc):
+    """Skilling's Hilbert index on 2^b grids (b = 1..4): a bijection onto 0 .. 8^b - 1 that
+    starts at the origin, moves to a face neighbour at every step, and maps every octree
+    cell (equal leading 3-bit digits) onto an aligned cube -- the properties that make it a
+    Hilbert curve and make octree cells contiguous runs of keys."""
+    import itertools
+    for b in (1, 2, 3, 4):
+        N = 1 << b
+        at = {}
+        for x, y, z in itertools.product(range(N), repeat=3):
+            at[orc.hilbert(x, y, z, b)] = (x, y, z)
+        assert sorted(at) == list(range(N ** 3))
+        assert at[0] == (0, 0, 0)
+        for h in range(N ** 3 - 1):
+            assert sum(abs(p - q) for p, q in zip(at[h], at[h + 1])) == 1, (b, h)
+        for lev in range(1, b + 1):
+            sh = 3 * (b - lev)
+            cells = {}
+            for h, c in at.items():
+                cells.setdefault(h >> sh, set()).add(tuple(v >> (b - lev) for v in c))
+            assert all(len(s) == 1 for s in cells.values())
+
+
+def test_hilbert_keys_give_the_same_octree_cells(orc):
+    """The octree over Hilbert-sorted keys has the same cells (as particle sets, per level)
+    as the one over Morton-sorted keys; keys keep the sentinel and segment prefix."""
+    ps = uniform_random(3000, seed=31, h=0.05)
+    ps.x[:40] = ps.x[0]; ps.y[:40] = ps.y[0]; ps.z[:40] = ps.z[0]   # a run of equal keys
+    cells = []
+    for curve in ("morton", "hilbert"):
+        k = orc.keys(ps.x, ps.y, ps.z, curve=curve)
+        assert np.all(k >> np.uint64(63) == 1)
+        o = orc.order(k)
+        t = orc.octree(k[o], 8)
+        cells.append(sorted((int(l), tuple(sorted(o[s:s + c].tolist())))
+                            for l, s, c in zip(t["level"], t["start"], t["count"])))
+    assert cells[0] == cells[1]
+    so = np.array([0, 1000, 3000])
+    kh = orc.keys(ps.x, ps.y, ps.z, seg_offsets=so, curve="hilbert")
+    assert np.all((kh[1000:] >> np.uint64(54)) & np.uint64(511) == 1) and np.all(kh >> np.uint64(63) == 1)
+
+
 def test_order_matches_lexsort(orc):
     """Stable order by (key, caller index) equals numpy.lexsort, including many ties."""
     rng = np.random.default_rng(7)
