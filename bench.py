@@ -67,11 +67,11 @@ def dt_for(ps, gamma=5.0 / 3.0):
     return 0.25 * float(np.min(ps.h / c))
 
 
-def run_gpu(ps, prec, steps, warmup, reps, autotune=True, energy_form=0):
+def run_gpu(ps, prec, steps, warmup, reps, autotune=True, energy_form=0, key_curve=0):
     import torch
     import paper_2007_03097_amd as sph
     n = ps.n
-    ctx = sph.Context(n, adaptive_h=1, precision=prec, energy_form=energy_form)
+    ctx = sph.Context(n, adaptive_h=1, precision=prec, energy_form=energy_form, key_curve=key_curve)
     pa = sph.ParticleArrays.from_numpy(ps)
     dt = dt_for(ps)
     if autotune:
@@ -354,6 +354,13 @@ def main():
             tk[key] = {"ms_per_step": r["ms_per_step"], "steps_per_s": r["steps_per_s"], "value": r["value"],
                        "forces_ms": r["t_force"] * 1e3}
         extra["thermokinetic_tube"] = tk
+        hk = {}
+        for prec, key in ((0, "fp64"), (1, "fp32c")):
+            r = run_gpu(ps, prec, args.steps, args.warmup, args.reps, not args.no_autotune, key_curve=1)
+            hk[key] = {"ms_per_step": r["ms_per_step"], "steps_per_s": r["steps_per_s"], "value": r["value"],
+                       "kernel_ms": {"nbr_lists": r["t_list"] * 1e3, "density": r["t_dens"] * 1e3,
+                                     "forces": r["t_force"] * 1e3}}
+        extra["hilbert_keys_tube"] = hk
     cpu = None if args.no_cpu else cpu_baseline(ps)
     out = {
         "metric": "pair interactions/sec (density+force) and steps/sec, FP64 vs FP32-comp, 1 GPU",

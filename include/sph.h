@@ -73,11 +73,20 @@ typedef struct {
                             energy e = u + v^2/2 evolves; sph_compute_forces and sph_step's
                             dudt array then carry de/dt (plus v.g when G != 0), and sph_step
                             still takes and returns the thermal u.                      */
+    int32_t key_curve;   /* SPH_CURVE_MORTON: Sec. 2.1 / Fig. 1 bit interleave (default).
+                            SPH_CURVE_HILBERT: the Hilbert index of the same quantised cell
+                            (Skilling's transposition; x, y, z from the high bit of each
+                            3-bit digit).  Either way a key's leading 3l bits name its
+                            level-l octree cell, so the tree cells, neighbour sets and
+                            sums are the same; the sorted order and keys_out differ.    */
 } sph_config;
 
 /* Values of sph_config.energy_form. */
 #define SPH_ENERGY_THERMAL 0
 #define SPH_ENERGY_THERMOKINETIC 1
+/* Values of sph_config.key_curve. */
+#define SPH_CURVE_MORTON 0
+#define SPH_CURVE_HILBERT 1
 
 /* A particle set.  Segments: n_seg > 1 independent sets stored back to back, set s being
  * particles [seg_offsets[s], seg_offsets[s+1]); pairs and tree nodes never cross sets. */

@@ -26,5 +26,5 @@ from .api import (  # noqa: F401
     sph_sync,
     sph_last_error,
 )
-from ._abi import (SPH_ENERGY_THERMAL, SPH_ENERGY_THERMOKINETIC, SPH_FP32C, SPH_FP64, SPH_STEP_PRIMED,  # noqa: F401
+from ._abi import (SPH_CURVE_HILBERT, SPH_CURVE_MORTON, SPH_ENERGY_THERMAL, SPH_ENERGY_THERMOKINETIC, SPH_FP32C, SPH_FP64, SPH_STEP_PRIMED,  # noqa: F401
                    SPH_STEP_RESUME)

@@ -16,6 +16,7 @@ SPH_OK, SPH_E_ARG, SPH_E_STATE, SPH_E_NOMEM, SPH_E_CAPACITY, SPH_E_DEVICE, SPH_E
 SPH_FP64, SPH_FP32C = 0, 1
 SPH_STEP_PRIMED, SPH_STEP_RESUME = 1, 2
 SPH_ENERGY_THERMAL, SPH_ENERGY_THERMOKINETIC = 0, 1
+SPH_CURVE_MORTON, SPH_CURVE_HILBERT = 0, 1
 
 STATUS_NAMES = {0: "SPH_OK", -1: "SPH_E_ARG", -2: "SPH_E_STATE", -3: "SPH_E_NOMEM", -4: "SPH_E_CAPACITY",
                 -5: "SPH_E_DEVICE", -6: "SPH_E_NONFINITE"}
@@ -30,7 +31,8 @@ class sph_config(ctypes.Structure):
                 ("av_beta", ctypes.c_double), ("av_eps", ctypes.c_double), ("h_coeff", ctypes.c_double),
                 ("adaptive_h", ctypes.c_int32), ("G", ctypes.c_double), ("soft_eps", ctypes.c_double),
                 ("theta", ctypes.c_double), ("leaf_size", ctypes.c_int32), ("group_size", ctypes.c_int32),
-                ("nbr_capacity", ctypes.c_int32), ("stream", ctypes.c_void_p), ("energy_form", ctypes.c_int32)]
+                ("nbr_capacity", ctypes.c_int32), ("stream", ctypes.c_void_p), ("energy_form", ctypes.c_int32),
+                ("key_curve", ctypes.c_int32)]
 
 
 _dp = ctypes.c_void_p  # device pointers are passed as integers

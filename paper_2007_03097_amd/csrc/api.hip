@@ -200,6 +200,8 @@ static sph_status check_config(sph_ctx* c, const sph_config* f) {
     if (k < 16 || k > 4096) return fail(c, SPH_E_ARG, "nbr_capacity must be in 16..4096");
     if (f->energy_form != SPH_ENERGY_THERMAL && f->energy_form != SPH_ENERGY_THERMOKINETIC)
         return fail(c, SPH_E_ARG, "energy_form must be 0 or 1");
+    if (f->key_curve != SPH_CURVE_MORTON && f->key_curve != SPH_CURVE_HILBERT)
+        return fail(c, SPH_E_ARG, "key_curve must be 0 or 1");
     return SPH_OK;
 }
 
@@ -236,6 +238,7 @@ static sph_status prepare(sph_ctx* c, const sph_particles* p) {
     dm.nbr_cap = c->nbr_cap;
     dm.node_cap = (int)node_cap_for(c->n_cap > 0 ? c->n_cap : 1, c->leaf_min);
     dm.min_level = dm.batched ? 3 : 0;
+    dm.curve = c->cfg.key_curve;
     const bool same = c->tab.n == p->n && c->tab.n_seg == n_seg && c->tab.seg == seg;
     std::vector<int4> chunks;
     std::vector<int> rank(n_seg, 0);
@@ -345,6 +348,7 @@ void sph_config_default(sph_config* f) {
     f->group_size = 32;
     f->nbr_capacity = 160;
     f->energy_form = SPH_ENERGY_THERMAL;
+    f->key_curve = SPH_CURVE_MORTON;
     f->stream = nullptr;
 }
 

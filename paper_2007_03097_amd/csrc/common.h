@@ -118,6 +118,7 @@ struct Dims {
     int n_chunks;
     int node_cap;
     int min_level;    // 3 when batched, else 0
+    int curve;        // 0 Morton, 1 Hilbert keys
 };
 
 // ---------------------------------------------------------------------------------------

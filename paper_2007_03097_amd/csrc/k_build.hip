@@ -1,8 +1,9 @@
 // Keys, sort and snapshot (Sec. 2.1 "Tree topology" of arXiv:2007.03097, Fig. 1).
 //
 //  * k_bbox      exact per-segment bounding box (ordered-integer atomics, order independent)
-//  * k_keys      quantise to B bits inside the cubic root cell, interleave (x lowest),
-//                sentinel bit 63, segment number in bits 54..62 for segmented sets
+//  * k_keys      quantise to B bits inside the cubic root cell, interleave (x lowest) or
+//                Hilbert index, sentinel bit 63, segment number in bits 54..62 for
+//                segmented sets
 //  * radix sort  stable LSD, 8 passes of 8-bit digits over (key, caller index); stability
 //                plus an identity initial order gives the (key, ID) order of the paper
 //  * gather      caller-order input -> key-ordered SoA + AoS records
@@ -110,19 +111,53 @@ __device__ __forceinline__ u32 quantise(double x, double lo, double S, u32 top) 
     return (u32)t;
 }
 
+// Hilbert index of grid cell (x, y, z) on a 2^bits grid: Skilling's transposition
+// (J. Skilling, AIP Conf. Proc. 707, 381 (2004)) unrolled for three axes, then one 3-bit
+// digit per level with x in its high bit.
+__device__ __forceinline__ u64 hilbert3(u32 x, u32 y, u32 z, int bits) {
+    const u32 top = 1u << (bits - 1);
+    for (u32 q = top; q > 1u; q >>= 1) {
+        const u32 low = q - 1u;
+        if (x & q) x ^= low;
+        if (y & q) {
+            x ^= low;
+        } else {
+            const u32 t = (x ^ y) & low;
+            x ^= t;
+            y ^= t;
+        }
+        if (z & q) {
+            x ^= low;
+        } else {
+            const u32 t = (x ^ z) & low;
+            x ^= t;
+            z ^= t;
+        }
+    }
+    y ^= x;
+    z ^= y;
+    u32 flip = 0u;
+    for (u32 q = top; q > 1u; q >>= 1)
+        if (z & q) flip ^= q - 1u;
+    x ^= flip;
+    y ^= flip;
+    z ^= flip;
+    return spread3(z) | (spread3(y) << 1) | (spread3(x) << 2);
+}
+
 __device__ __forceinline__ u64 make_key(double x, double y, double z, const double* lo, double S, int seg,
-                                        int batched) {
+                                        int batched, int curve) {
     const int bits = batched ? 18 : 21;
     const u32 top = (1u << bits) - 1u;
-    u64 m = spread3(quantise(x, lo[0], S, top)) | (spread3(quantise(y, lo[1], S, top)) << 1) |
-            (spread3(quantise(z, lo[2], S, top)) << 2);
+    const u32 qx = quantise(x, lo[0], S, top), qy = quantise(y, lo[1], S, top), qz = quantise(z, lo[2], S, top);
+    const u64 m = curve ? hilbert3(qx, qy, qz, bits) : (spread3(qx) | (spread3(qy) << 1) | (spread3(qz) << 2));
     u64 k = (1ull << 63) | m;
     if (batched) k |= (u64)seg << 54;
     return k;
 }
 
 // Caller-order keys + input validation.  val = caller index (identity).
-__global__ void __launch_bounds__(256) k_keys(DevCtl* ctl, const int4* chunk, int batched,
+__global__ void __launch_bounds__(256) k_keys(DevCtl* ctl, const int4* chunk, int batched, int curve,
                                                const double* __restrict__ x, const double* __restrict__ y,
                                                const double* __restrict__ z, const double* __restrict__ vx,
                                                const double* __restrict__ vy, const double* __restrict__ vz,
@@ -136,7 +171,7 @@ __global__ void __launch_bounds__(256) k_keys(DevCtl* ctl, const int4* chunk, in
             !isfinite(vz[i]) || !isfinite(u[i]))
             bad |= ERR_NONFINITE;
         if (!(h[i] > 0.0) || !(m[i] > 0.0) || !isfinite(h[i]) || !isfinite(m[i])) bad |= ERR_NONPOSITIVE;
-        u64 k = make_key(px, py, pz, ctl->box + 6 * ch.z, ctl->scale[ch.z], ch.z, batched);
+        u64 k = make_key(px, py, pz, ctl->box + 6 * ch.z, ctl->scale[ch.z], ch.z, batched, curve);
         key[i] = k;
         val[i] = (u32)i;
         if (key_out) key_out[i] = k;
@@ -148,14 +183,14 @@ void launch_keys(hipStream_t s, const DevPtrs& d, const Dims& dm, const double* 
                  const double* z, const double* vx, const double* vy, const double* vz, const double* m,
                  const double* h, const double* u, u64* keys_out_caller, int) {
     if (dm.n_chunks > 0)
-        hipLaunchKernelGGL(k_keys, dim3(dm.n_chunks), dim3(256), 0, s, d.ctl, d.chunk, dm.batched, x, y, z, vx, vy,
+        hipLaunchKernelGGL(k_keys, dim3(dm.n_chunks), dim3(256), 0, s, d.ctl, d.chunk, dm.batched, dm.curve, x, y, z, vx, vy,
                            vz, m, h, u, d.key_a, d.val_a, keys_out_caller);
 }
 
 // Step-loop keys: positions are in the previous key order; write the key at the caller
 // index (so the sort input is again in caller order) and remember where each caller
 // index sat.
-__global__ void __launch_bounds__(256) k_step_keys(DevCtl* ctl, const int4* chunk, int batched,
+__global__ void __launch_bounds__(256) k_step_keys(DevCtl* ctl, const int4* chunk, int batched, int curve,
                                                     const double* __restrict__ x, const double* __restrict__ y,
                                                     const double* __restrict__ z, const double* __restrict__ vx,
                                                     const double* __restrict__ vy, const double* __restrict__ vz,
@@ -187,7 +222,7 @@ __global__ void __launch_bounds__(256) k_step_keys(DevCtl* ctl, const int4* chun
             !isfinite(vz[p]) || !isfinite(u[p]))
             bad |= ERR_NONFINITE;
         const u32 i = id[p];
-        key[i] = make_key(px, py, pz, box, S, ch.z, batched);
+        key[i] = make_key(px, py, pz, box, S, ch.z, batched, curve);
         val[i] = i;
         inv[i] = (u32)p;
     }
@@ -196,7 +231,7 @@ __global__ void __launch_bounds__(256) k_step_keys(DevCtl* ctl, const int4* chun
 
 void launch_step_keys(hipStream_t s, const DevPtrs& d, const Dims& dm) {
     if (dm.n_chunks > 0)
-        hipLaunchKernelGGL(k_step_keys, dim3(dm.n_chunks), dim3(256), 0, s, d.ctl, d.chunk, dm.batched, d.x, d.y,
+        hipLaunchKernelGGL(k_step_keys, dim3(dm.n_chunks), dim3(256), 0, s, d.ctl, d.chunk, dm.batched, dm.curve, d.x, d.y,
                            d.z, d.vx, d.vy, d.vz, d.u, d.id, d.key_a, d.val_a, d.inv);
 }
 

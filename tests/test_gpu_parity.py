@@ -263,6 +263,66 @@ def test_step_lockstep(orc, case, adaptive, dt):
         flags = sph.SPH_STEP_PRIMED
 
 
+# ---------------------------------------------------------------------------- Hilbert keys
+@pytest.mark.parametrize("case", ["random_varh", "duplicates", "clustered", "sod_small", "polytrope", "n1", "n2"])
+def test_hilbert_keys_order_tree(orc, case):
+    """Hilbert keys: keys and order bit-exact; the octree over them equals the oracle's."""
+    import paper_2007_03097_amd as sph
+    ps = CASES[case]()
+    ctx = make_ctx(ps.n, leaf_size=5, key_curve=sph.SPH_CURVE_HILBERT)
+    k, o = gpu_keys_order(ctx, parts(ps))
+    assert np.array_equal(k, orc.keys(ps.x, ps.y, ps.z, curve="hilbert"))
+    assert np.array_equal(o, orc.order(k))
+    t = gpu_tree(ctx)
+    ref = orc.octree(k[o], 5)
+    got = sorted(zip(t["key"].tolist(), t["level"].tolist(), t["leaf"].tolist(), t["start"].tolist(), t["count"].tolist()))
+    exp = sorted(zip(ref["key"].tolist(), ref["level"].tolist(), ref["leaf"].tolist(), ref["start"].tolist(),
+                     ref["count"].tolist()))
+    assert got == exp
+
+
+def test_hilbert_batched_and_physics(orc):
+    """Hilbert keys with segments (set number in bits 54..62), and neighbour sets, density and
+    forces unchanged by the curve."""
+    import paper_2007_03097_amd as sph
+    ps = ensemble(n_boxes=5, seed=35, n_min=150, n_max=1500, side_lo=5, side_hi=11)
+    so = ps.seg_offsets
+    ctx = make_ctx(ps.n, seg_cap=8, key_curve=sph.SPH_CURVE_HILBERT)
+    k, o = gpu_keys_order(ctx, parts(ps))
+    assert np.array_equal(k, orc.keys(ps.x, ps.y, ps.z, seg_offsets=so, curve="hilbert"))
+    assert np.array_equal(o, orc.order(k))
+    off, idx = gpu_neighbors(ctx, ps.n)
+    roff, ridx = orc.neighbors(ps.x, ps.y, ps.z, ps.h, seg=orc.seg_ids(ps.n, so))
+    assert np.array_equal(off, roff) and np.array_equal(idx, ridx)
+    rho, P, c, hn = gpu_density(ctx, ps.n)
+    r = orc.density(ps.fields(), (roff, ridx))
+    assert rel_err(rho, r[0], r[0]) <= TOL
+    ax, ay, az, du = gpu_forces(ctx, ps.n)
+    r_ax, r_ay, r_az, r_du, Sa, Su = orc.forces(ps.fields(), r[0], r[1], r[2], (roff, ridx))
+    assert np.all(np.sqrt((ax - r_ax) ** 2 + (ay - r_ay) ** 2 + (az - r_az) ** 2) <= TOL * Sa + 1e-300)
+
+
+def test_hilbert_step_lockstep(orc):
+    """Leapfrog steps with Hilbert ordering agree with the oracle (the curve changes only the
+    summation order)."""
+    import paper_2007_03097_amd as sph
+    ps = CASES["sod_small"]()
+    ctx = make_ctx(ps.n, adaptive_h=1, key_curve=sph.SPH_CURVE_HILBERT)
+    pa = parts(ps, with_accel=True)
+    prm = orc.Params(adaptive_h=True)
+    st = orc.prime(ps.fields(), prm)
+    flags = 0
+    for step in range(2):
+        start = st if step == 0 else dict(_state_from(ps, pa))
+        sph.sph_step(ctx.h, pa, 4.0e-4, 1, flags)
+        got = _state_from(ps, pa)
+        ref = orc.kdk_step(start, 4.0e-4, prm)
+        for k in ("x", "vx", "u", "h", "ax", "dudt"):
+            scale = max(np.abs(ref[k]).max(), 1e-300)
+            assert np.abs(got[k] - ref[k]).max() <= 1e-11 * scale, (step, k)
+        flags = sph.SPH_STEP_PRIMED
+
+
 # ---------------------------------------------------------------------------- thermokinetic form (eq. (8))
 @pytest.mark.parametrize("prec", [0, 1])
 @pytest.mark.parametrize("case", ["random_varh", "sod_small", "duplicates"])
