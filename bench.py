@@ -41,8 +41,8 @@ FLOP_FORCE_PAIR = 54     # momentum + energy without the viscosity branch (69 wi
 def measured_traffic(kernel):
     """HBM bytes per launch of `kernel` from the committed hardware-counter summary, or None
     when there is none or the kernel's source has changed since the counters were taken.
-    Summary lines read: 'traffic: <kernel> <source files, comma-separated> <sha256 of their
-    concatenated contents> <bytes per launch>'."""
+    Summary lines read: 'traffic: <kernel, spaces removed> <source files, comma-separated>
+    <sha256 of their concatenated contents> <bytes per launch>'."""
     import hashlib
     prof = os.path.join(ROOT, "profiles")
     if not os.path.isdir(prof):
@@ -52,7 +52,7 @@ def measured_traffic(kernel):
             continue
         for line in open(os.path.join(prof, fn)):
             f = line.split()
-            if len(f) == 5 and f[0] == "traffic:" and f[1] == kernel:
+            if len(f) == 5 and f[0] == "traffic:" and f[1] == kernel.replace(" ", ""):
                 srcs = [os.path.join(ROOT, s) for s in f[2].split(",")]
                 if all(os.path.isfile(s) for s in srcs):
                     h = hashlib.sha256(b"".join(open(s, "rb").read() for s in srcs)).hexdigest()
@@ -329,7 +329,7 @@ def main():
     n = ps.n
     kernels = {"k_nbr_lists": (r64["t_list"], r64["pairs_dens"], FLOP_PRED_PAIR),
                "k_density<false>": (r64["t_dens"], r64["pairs_dens"], FLOP_DENS_PAIR),
-               "k_forces<false>": (r64["t_force"], r64["pairs_force"], FLOP_FORCE_PAIR)}
+               "k_forces<false, false>": (r64["t_force"], r64["pairs_force"], FLOP_FORCE_PAIR)}
     rooflines = {}
     for name, (t, pairs, fpp) in kernels.items():
         ach = pairs * fpp / t / 1e12
