@@ -578,3 +578,206 @@ void orc_tree_gravity(int64_t n, int64_t n_nodes, const int32_t* nlevel, const i
     }
     free(child); free(nch); free(mom); free(nbox);
 }
+
+/* ------------------------------------------------------------------------------------ */
+/* Symmetric node-node gravity (the paper's own scheme, Sec. 2.2.2 and eq. (10), after
+ * Dehnen 2000): a mutual recursion over pairs of nodes of the octree above.
+ *
+ *   interact(A, A): a leaf sums all its particle pairs directly; an internal node
+ *                   interacts every child with itself and every unordered pair of children.
+ *   interact(A, B): if the MAC accepts (A, B), one node-node term; else, if both are
+ *                   leaves, every particle pair directly; else the larger node (lower level;
+ *                   on equal levels the one whose particles come first in key order) is
+ *                   split -- unless it is a leaf, then the other one -- and each of its
+ *                   children interacts with the other node.
+ *
+ * MAC: every cell is enclosed by the sphere of radius (sqrt 3 / 2) side about its centre;
+ * (A, B) is accepted when r_A + r_B < theta |c_A - c_B|.  The cells are the octree cells of
+ * the quantised keys (cell of node j: the quantised coordinates of its first particle,
+ * shifted to its level), so in units of half the finest cell every quantity is an integer:
+ *   T = 2 (s_A + s_B),  D = 2 (c_A - c_B),  accept  <=>  3 T^2 < 4 theta^2 |D|^2.
+ * theta = 0 never accepts: the result is the direct sum.
+ *
+ * Node-node term (first order in the Taylor expansion of the potential about each
+ * centre of mass, with monopole sources, so the field is constant across a node; eq. (10)
+ * with R_AB = R_A - R_B, Plummer softened, s^2 = |R_AB|^2 + eps^2):
+ *   node A:  g += -G M_B R_AB / s^3,  phi(R_A) += -G M_B / s
+ *   node B:  g += +G M_A R_AB / s^3,  phi(R_B) += -G M_A / s
+ * Particle pair (a, b), b != a, evaluated once and applied to both (d = r_a - r_b):
+ *   g_a += -G m_b d / s^3,  g_b += +G m_a d / s^3,  phi_a += -G m_b / s,  phi_b += -G m_a / s
+ * Particle a finally sums, over every node X that contains it, g_X and the first-order
+ * potential phi_X(R_X) - g_X . (r_a - R_X).
+ *
+ * Particles in key order (x, y, z, m); tree from orc_octree (pre-order).  lo, S, bits: the
+ * key quantisation (orc_quantise).  Outputs (per particle): g, phi; sg = sum of the norms
+ * of the acceleration terms, sp = sum of the magnitudes of the potential terms (the
+ * absolute-sum scales), cover = how many other particles reached a through some term
+ * (n - 1 when the interactions partition all pairs).  Returns 0, or -1 on a bad tree. */
+typedef struct {
+    const int32_t* level; const int32_t* leaf; const int64_t* start; const int64_t* count;
+    const double *x, *y, *z, *m;
+    int64_t* child; int32_t* nch;
+    double* mom;          /* 10 per node (orc_moments) */
+    int64_t* cell;        /* 3 per node */
+    double th4;           /* 4 theta^2 */
+    int bits;
+    double G, e2;
+    double *ng, *nphi, *nsg, *nsp;   /* node accumulators (3, 1, 1, 1) */
+    int64_t* ncov;
+    double *gx, *gy, *gz, *phi, *sg, *sp;
+    int64_t* cover;
+} orc_fmm_ctx;
+
+static int orc_fmm_mac(const orc_fmm_ctx* f, int64_t A, int64_t B)
+{
+    int la = f->level[A], lb = f->level[B];
+    int64_t T = ((int64_t)1 << (f->bits - la + 1)) + ((int64_t)1 << (f->bits - lb + 1));
+    int64_t D2 = 0;
+    for (int d = 0; d < 3; ++d) {
+        int64_t ca = (2 * f->cell[3 * A + d] + 1) << (f->bits - la);
+        int64_t cb = (2 * f->cell[3 * B + d] + 1) << (f->bits - lb);
+        D2 += (ca - cb) * (ca - cb);
+    }
+    double lhs = 3.0 * (double)(T * T);
+    double rhs = f->th4 * (double)D2;
+    return lhs < rhs;
+}
+
+static void orc_fmm_pair(orc_fmm_ctx* f, int64_t a, int64_t b)
+{
+    double dx = f->x[a] - f->x[b], dy = f->y[a] - f->y[b], dz = f->z[a] - f->z[b];
+    double s = sqrt(dx * dx + dy * dy + dz * dz + f->e2);
+    double i1 = 1.0 / s;
+    double i3 = i1 * i1 * i1;
+    double ka = f->G * f->m[b] * i3, kb = f->G * f->m[a] * i3;
+    f->gx[a] -= ka * dx; f->gy[a] -= ka * dy; f->gz[a] -= ka * dz;
+    f->gx[b] += kb * dx; f->gy[b] += kb * dy; f->gz[b] += kb * dz;
+    f->phi[a] -= f->G * f->m[b] * i1;
+    f->phi[b] -= f->G * f->m[a] * i1;
+    double r = sqrt(dx * dx + dy * dy + dz * dz);
+    f->sg[a] += ka * r; f->sg[b] += kb * r;
+    f->sp[a] += f->G * f->m[b] * i1; f->sp[b] += f->G * f->m[a] * i1;
+    f->cover[a] += 1; f->cover[b] += 1;
+}
+
+static void orc_fmm_node_term(orc_fmm_ctx* f, int64_t A, int64_t B)
+{
+    const double* ma = f->mom + 10 * A;
+    const double* mb = f->mom + 10 * B;
+    double R[3] = {ma[1] - mb[1], ma[2] - mb[2], ma[3] - mb[3]};
+    double s = sqrt(R[0] * R[0] + R[1] * R[1] + R[2] * R[2] + f->e2);
+    double i1 = 1.0 / s;
+    double i3 = i1 * i1 * i1;
+    double kA = f->G * mb[0] * i3, kB = f->G * ma[0] * i3;
+    double r = sqrt(R[0] * R[0] + R[1] * R[1] + R[2] * R[2]);
+    for (int d = 0; d < 3; ++d) {
+        f->ng[3 * A + d] -= kA * R[d];
+        f->ng[3 * B + d] += kB * R[d];
+    }
+    f->nphi[A] -= f->G * mb[0] * i1;
+    f->nphi[B] -= f->G * ma[0] * i1;
+    f->nsg[A] += kA * r; f->nsg[B] += kB * r;
+    f->nsp[A] += f->G * mb[0] * i1; f->nsp[B] += f->G * ma[0] * i1;
+    f->ncov[A] += f->count[B];
+    f->ncov[B] += f->count[A];
+}
+
+static void orc_fmm_interact(orc_fmm_ctx* f, int64_t A, int64_t B)
+{
+    if (A == B) {
+        if (f->leaf[A]) {
+            int64_t s = f->start[A], e = s + f->count[A];
+            for (int64_t a = s; a < e; ++a)
+                for (int64_t b = a + 1; b < e; ++b) orc_fmm_pair(f, a, b);
+        } else {
+            const int64_t* c = f->child + 8 * A;
+            for (int i = 0; i < f->nch[A]; ++i) orc_fmm_interact(f, c[i], c[i]);
+            for (int i = 0; i < f->nch[A]; ++i)
+                for (int j = i + 1; j < f->nch[A]; ++j) orc_fmm_interact(f, c[i], c[j]);
+        }
+        return;
+    }
+    if (orc_fmm_mac(f, A, B)) {
+        orc_fmm_node_term(f, A, B);
+        return;
+    }
+    if (f->leaf[A] && f->leaf[B]) {
+        for (int64_t a = f->start[A]; a < f->start[A] + f->count[A]; ++a)
+            for (int64_t b = f->start[B]; b < f->start[B] + f->count[B]; ++b) orc_fmm_pair(f, a, b);
+        return;
+    }
+    int split_a = f->level[A] < f->level[B] || (f->level[A] == f->level[B] && f->start[A] < f->start[B]);
+    if (split_a ? f->leaf[A] : f->leaf[B]) split_a = !split_a;
+    if (split_a) {
+        for (int i = 0; i < f->nch[A]; ++i) orc_fmm_interact(f, f->child[8 * A + i], B);
+    } else {
+        for (int i = 0; i < f->nch[B]; ++i) orc_fmm_interact(f, A, f->child[8 * B + i]);
+    }
+}
+
+int orc_fmm_gravity(int64_t n, int64_t n_nodes, const int32_t* nlevel, const int32_t* nleaf,
+                    const int64_t* nstart, const int64_t* ncount, const double* x, const double* y,
+                    const double* z, const double* m, const double* lo3, double S, int bits, double theta,
+                    double G, double eps, double* gx, double* gy, double* gz, double* phi, double* sg,
+                    double* sp, int64_t* cover)
+{
+    for (int64_t a = 0; a < n; ++a) { gx[a] = gy[a] = gz[a] = phi[a] = sg[a] = sp[a] = 0.0; cover[a] = 0; }
+    if (n_nodes == 0) return 0;
+    orc_fmm_ctx f;
+    memset(&f, 0, sizeof f);
+    f.level = nlevel; f.leaf = nleaf; f.start = nstart; f.count = ncount;
+    f.x = x; f.y = y; f.z = z; f.m = m;
+    f.bits = bits; f.G = G; f.e2 = eps * eps; f.th4 = 4.0 * (theta * theta);
+    f.gx = gx; f.gy = gy; f.gz = gz; f.phi = phi; f.sg = sg; f.sp = sp; f.cover = cover;
+    f.child = (int64_t*)malloc(sizeof(int64_t) * 8 * (size_t)n_nodes);
+    f.nch = (int32_t*)calloc((size_t)n_nodes, sizeof(int32_t));
+    f.mom = (double*)malloc(sizeof(double) * 10 * (size_t)n_nodes);
+    f.cell = (int64_t*)malloc(sizeof(int64_t) * 3 * (size_t)n_nodes);
+    f.ng = (double*)calloc(3 * (size_t)n_nodes, sizeof(double));
+    f.nphi = (double*)calloc((size_t)n_nodes, sizeof(double));
+    f.nsg = (double*)calloc((size_t)n_nodes, sizeof(double));
+    f.nsp = (double*)calloc((size_t)n_nodes, sizeof(double));
+    f.ncov = (int64_t*)calloc((size_t)n_nodes, sizeof(int64_t));
+    int64_t parent_at[23];
+    int bad = 0;
+    for (int64_t j = 0; j < n_nodes; ++j) {   /* parent = latest node one level up (pre-order) */
+        int l = nlevel[j];
+        if (l < 0 || l > bits) { bad = 1; break; }
+        parent_at[l] = j;
+        if (j > 0) {
+            int64_t p = parent_at[l - 1];
+            if (f.nch[p] >= 8) { bad = 1; break; }
+            f.child[8 * p + f.nch[p]++] = j;
+        }
+        orc_moments(nstart[j], nstart[j] + ncount[j], NULL, x, y, z, m, f.mom + 10 * j);
+        const double* c[3] = {x, y, z};
+        for (int d = 0; d < 3; ++d)
+            f.cell[3 * j + d] = (int64_t)(orc_quantise(c[d][nstart[j]], lo3[d], S, bits) >> (bits - l));
+    }
+    if (!bad) {
+        orc_fmm_interact(&f, 0, 0);
+        /* every particle collects the terms of the nodes that contain it */
+        int64_t path[23];
+        for (int64_t j = 0; j < n_nodes; ++j) {
+            path[nlevel[j]] = j;
+            if (!nleaf[j]) continue;
+            for (int64_t a = nstart[j]; a < nstart[j] + ncount[j]; ++a) {
+                const double r[3] = {x[a], y[a], z[a]};
+                for (int l = nlevel[0]; l <= nlevel[j]; ++l) {
+                    int64_t X = path[l];
+                    const double* gX = f.ng + 3 * X;
+                    const double* R = f.mom + 10 * X + 1;
+                    double lin = gX[0] * (r[0] - R[0]) + gX[1] * (r[1] - R[1]) + gX[2] * (r[2] - R[2]);
+                    gx[a] += gX[0]; gy[a] += gX[1]; gz[a] += gX[2];
+                    phi[a] += f.nphi[X] - lin;
+                    sg[a] += f.nsg[X];
+                    sp[a] += f.nsp[X] + fabs(lin);
+                    cover[a] += f.ncov[X];
+                }
+            }
+        }
+    }
+    free(f.child); free(f.nch); free(f.mom); free(f.cell);
+    free(f.ng); free(f.nphi); free(f.nsg); free(f.nsp); free(f.ncov);
+    return bad ? -1 : 0;
+}

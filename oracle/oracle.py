@@ -65,6 +65,9 @@ def lib():
         L.orc_quad_field.argtypes = [_d, DBL, DBL, DBL, DBL, DBL, _d, _d]
         L.orc_tree_gravity.argtypes = ([I64, I64, _i32, _i32, _i64, _i64, _d, _d, _d, _d, DBL, DBL, DBL, DBL,
                                         I64, _i64, _i64, _d, _d, _d, _d])
+        L.orc_fmm_gravity.argtypes = ([I64, I64, _i32, _i32, _i64, _i64, _d, _d, _d, _d, _d, DBL, ctypes.c_int, DBL,
+                                       DBL, DBL, _d, _d, _d, _d, _d, _d, _i64])
+        L.orc_fmm_gravity.restype = ctypes.c_int
         L.orc_bbox.argtypes = [I64, I64, _d, _d, _d, _d]
         L.orc_scale.argtypes = [_d, ctypes.c_int]
         L.orc_scale.restype = DBL
@@ -267,6 +270,29 @@ def tree_gravity(xs, ys, zs, ms, tree, L, theta, G, eps, gstart, gcount):
                            _p(zs), _p(ms), L, theta, G, eps, gs.size, _p(gs, _i64), _p(gc, _i64), _p(gx), _p(gy),
                            _p(gz), _p(phi))
     return gx, gy, gz, phi
+
+
+def fmm_gravity(xs, ys, zs, ms, tree, lo, S, theta, G, eps, bits=21):
+    """Symmetric node-node gravity (Sec. 2.2.2, eq. (10)) over particles already in key order;
+    tree from octree(), lo/S the key quantisation.  Returns dict of g (x, y, z), phi, the
+    absolute-sum scales sg, sp and cover (other particles reached, n - 1 when every pair is
+    accounted for exactly once)."""
+    xs, ys, zs, ms = _f64(xs), _f64(ys), _f64(zs), _f64(ms)
+    n = xs.size
+    lev = np.ascontiguousarray(tree["level"], np.int32)
+    leaf = np.ascontiguousarray(tree["leaf"], np.int32)
+    st, ct = _ii(tree["start"]), _ii(tree["count"])
+    lo3 = _f64(np.asarray(lo, dtype=np.float64)[:3])
+    out = {k: np.empty(n) for k in ("gx", "gy", "gz", "phi", "sg", "sp")}
+    cover = np.empty(n, np.int64)
+    r = lib().orc_fmm_gravity(n, lev.size, _p(lev, _i32), _p(leaf, _i32), _p(st, _i64), _p(ct, _i64), _p(xs), _p(ys),
+                              _p(zs), _p(ms), _p(lo3), float(S), int(bits), float(theta), float(G), float(eps),
+                              _p(out["gx"]), _p(out["gy"]), _p(out["gz"]), _p(out["phi"]), _p(out["sg"]),
+                              _p(out["sp"]), _p(cover, _i64))
+    if r != 0:
+        raise RuntimeError("fmm_gravity: malformed tree")
+    out["cover"] = cover
+    return out
 
 
 # ---------------------------------------------------------------------------------------

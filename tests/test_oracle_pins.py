@@ -541,6 +541,115 @@ def test_tree_gravity_theta_half_accuracy(orc):
     assert rms[1] < rms[0]
 
 
+# ---------------------------------------------------------------------------- node-node (FMM) gravity
+def _fmm_setup(orc, ps, leaf_cap, min_level=0):
+    k = orc.keys(ps.x, ps.y, ps.z)
+    o = orc.order(k)
+    t = orc.octree(k[o], leaf_cap, min_level)
+    box = orc.bbox(ps.x, ps.y, ps.z)
+    return o, t, box, orc.scale(box, 21)
+
+
+def test_fmm_theta_zero_is_direct(orc):
+    """theta_MAC = 0 accepts no node pair: eq. (10) reduces to the exact particle sum (Sec.
+    2.2.2); the mutual recursion must still reach every pair exactly once."""
+    ps = polytrope_n1(1500, seed=9)
+    o, t, box, S = _fmm_setup(orc, ps, 8)
+    xs, ys, zs, ms = ps.x[o], ps.y[o], ps.z[o], ps.m[o]
+    r = orc.fmm_gravity(xs, ys, zs, ms, t, box, S, 0.0, 1.3, 0.01)
+    dx, dy, dz, dp = orc.gravity_direct(xs, ys, zs, ms, 1.3, 0.01)
+    assert np.all(r["cover"] == ps.n - 1)
+    d = np.sqrt((r["gx"] - dx) ** 2 + (r["gy"] - dy) ** 2 + (r["gz"] - dz) ** 2)
+    assert np.all(d <= 1e-13 * r["sg"])
+    assert np.all(np.abs(r["phi"] - dp) <= 1e-13 * r["sp"])
+
+
+@pytest.mark.parametrize("theta", [0.3, 0.5, 1.0])
+def test_fmm_partition_and_conservation(orc, theta):
+    """The node-pair recursion partitions all particle pairs (every particle is reached by
+    each other one exactly once), and the symmetric node-node terms conserve linear momentum
+    and -- at first order, with central forces between centres of mass -- angular momentum
+    to rounding (Sec. 2.2.2).  The particle-cell quadrupole walk misses both by ~1e-4."""
+    ps = polytrope_n1(6000, seed=31)
+    o, t, box, S = _fmm_setup(orc, ps, 12)
+    xs, ys, zs, ms = ps.x[o], ps.y[o], ps.z[o], ps.m[o]
+    r = orc.fmm_gravity(xs, ys, zs, ms, t, box, S, theta, 1.0, 0.01)
+    assert np.all(r["cover"] == ps.n - 1)
+    g = np.stack([r["gx"], r["gy"], r["gz"]], axis=1)
+    pos = np.stack([xs, ys, zs], axis=1)
+    gn = np.linalg.norm(g, axis=1)
+    P = (ms[:, None] * g).sum(axis=0)
+    Lm = (ms[:, None] * np.cross(pos, g)).sum(axis=0)
+    assert np.linalg.norm(P) <= 1e-14 * (ms * gn).sum()
+    assert np.linalg.norm(Lm) <= 1e-14 * (ms * np.linalg.norm(pos, axis=1) * gn).sum()
+
+
+def test_fmm_two_clusters_closed_form(orc):
+    """Two compact clusters in opposite corners of the root cell.  With leaf capacity 8 and
+    leaves from level 2, the level-2 cells holding the clusters pass the opening test for
+    theta > 1/3 (3 T^2 = 48 < 432 theta^2 in half-finest-cell units) but not below.  Above,
+    each particle feels its own cluster directly plus Newton's point-mass attraction of the
+    other cluster's mass at its centre of mass, evaluated at its own cluster's centre of mass,
+    and the first-order potential; below, everything is the direct sum."""
+    rng = np.random.default_rng(5)
+    a = rng.uniform(0.0, 0.01, size=(8, 3))
+    b = rng.uniform(0.99, 1.0, size=(8, 3))
+    a[0] = 0.0
+    b[0] = 1.0
+    p = np.vstack([a, b])
+    m = rng.uniform(0.5, 2.0, size=16)
+    ps = uniform_random(16, seed=1)
+    ps.x, ps.y, ps.z = [np.ascontiguousarray(p[:, i]) for i in range(3)]
+    ps.m = m
+    o, t, box, S = _fmm_setup(orc, ps, 8, min_level=2)
+    assert o[:8].max() < 8 <= o[8:].min()  # cluster A sorts first
+    G, eps = 1.7, 0.003
+    xs, ys, zs, ms = ps.x[o], ps.y[o], ps.z[o], ps.m[o]
+    pos = np.stack([xs, ys, zs], axis=1)
+    dx, dy, dz, dp = orc.gravity_direct(xs, ys, zs, ms, G, eps)
+    r = orc.fmm_gravity(xs, ys, zs, ms, t, box, S, 0.3, G, eps)
+    assert np.allclose(r["gx"], dx, rtol=0, atol=1e-13 * np.abs(dx).max())
+    assert np.allclose(r["phi"], dp, rtol=0, atol=1e-13 * np.abs(dp).max())
+    r = orc.fmm_gravity(xs, ys, zs, ms, t, box, S, 0.5, G, eps)
+    for own, other in ((slice(0, 8), slice(8, 16)), (slice(8, 16), slice(0, 8))):
+        jx, jy, jz, jp = orc.gravity_direct(xs[own], ys[own], zs[own], ms[own], G, eps)
+        MA, MB = ms[own].sum(), ms[other].sum()
+        RA = (ms[own, None] * pos[own]).sum(axis=0) / MA
+        RB = (ms[other, None] * pos[other]).sum(axis=0) / MB
+        R = RA - RB
+        s = math.sqrt(R @ R + eps * eps)
+        gfar = -G * MB * R / s ** 3
+        want_g = np.stack([jx, jy, jz], axis=1) + gfar
+        want_p = jp - G * MB / s - (pos[own] - RA) @ gfar
+        got_g = np.stack([r["gx"][own], r["gy"][own], r["gz"][own]], axis=1)
+        assert np.abs(got_g - want_g).max() <= 1e-12 * np.abs(want_g).max()
+        assert np.abs(r["phi"][own] - want_p).max() <= 1e-12 * np.abs(want_p).max()
+
+
+def test_fmm_error_orders(orc):
+    """First order in the Taylor expansion of the potential: the acceleration (constant
+    across a node) errs at first order in the opening angle, the potential (with its linear
+    term) at second order.  Halving theta from 1 to 0.5 must shrink the RMS acceleration
+    error by 1.6-3x and the potential error by at least 3x (a tidal term in the acceleration
+    would make the first ratio ~4, a missing linear potential term the second ~2); at 0.25
+    the error keeps falling."""
+    ps = polytrope_n1(8192, seed=10)
+    o, t, box, S = _fmm_setup(orc, ps, 16)
+    xs, ys, zs, ms = ps.x[o], ps.y[o], ps.z[o], ps.m[o]
+    dx, dy, dz, dp = orc.gravity_direct(xs, ys, zs, ms, 1.0, 0.01)
+    gd = np.sqrt(dx ** 2 + dy ** 2 + dz ** 2)
+    eg, ep = [], []
+    for th in (1.0, 0.5, 0.25):
+        r = orc.fmm_gravity(xs, ys, zs, ms, t, box, S, th, 1.0, 0.01)
+        e = np.sqrt((r["gx"] - dx) ** 2 + (r["gy"] - dy) ** 2 + (r["gz"] - dz) ** 2) / gd
+        eg.append(math.sqrt((e ** 2).mean()))
+        ep.append(math.sqrt((((r["phi"] - dp) / dp) ** 2).mean()))
+    assert eg[1] < 0.1
+    assert 1.6 < eg[0] / eg[1] < 3.0
+    assert ep[0] / ep[1] > 3.0
+    assert eg[2] < eg[1] and ep[2] < ep[1]
+
+
 # ---------------------------------------------------------------------------- integrator
 def test_kdk_momentum_and_energy_order(orc):
     """KDK leapfrog: momentum is conserved to rounding; the one-step energy error falls by
