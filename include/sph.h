@@ -79,6 +79,15 @@ typedef struct {
                             3-bit digit).  Either way a key's leading 3l bits name its
                             level-l octree cell, so the tree cells, neighbour sets and
                             sums are the same; the sorted order and keys_out differ.    */
+    int32_t gravity_scheme; /* SPH_GRAVITY_QUADRUPOLE: particle-cell walk with monopole +
+                            quadrupole cells and the cell-side test above (default).
+                            SPH_GRAVITY_FMM: the paper's symmetric node-node scheme (Sec.
+                            2.2.2, eq. (10), after Dehnen 2000): node pairs accepted when
+                            r_A + r_B < theta |c_A - c_B| (r = sqrt(3)/2 side, c = cell
+                            centre) interact through their masses at their centres of mass,
+                            first order in the potential (field constant across a node);
+                            linear and angular momentum are conserved to rounding.  One set
+                            only (n_seg == 1).                                       */
 } sph_config;
 
 /* Values of sph_config.energy_form. */
@@ -87,6 +96,9 @@ typedef struct {
 /* Values of sph_config.key_curve. */
 #define SPH_CURVE_MORTON 0
 #define SPH_CURVE_HILBERT 1
+/* Values of sph_config.gravity_scheme. */
+#define SPH_GRAVITY_QUADRUPOLE 0
+#define SPH_GRAVITY_FMM 1
 
 /* A particle set.  Segments: n_seg > 1 independent sets stored back to back, set s being
  * particles [seg_offsets[s], seg_offsets[s+1]); pairs and tree nodes never cross sets. */
@@ -183,6 +195,9 @@ sph_status sph_compute_forces(sph_ctx* ctx, const double* rho, const double* P, 
 /* Sec. 2.2.2, eq. (10): self-gravity on the last tree.  Cells accepted by the opening test
  * (see sph_config.theta) act through monopole + quadrupole moments about their centre of
  * mass, with Plummer softening; other leaves by direct softened sums (self excluded).
+ * With gravity_scheme = SPH_GRAVITY_FMM: the symmetric node-node scheme instead (see
+ * sph_config.gravity_scheme); particle pairs of unaccepted leaf pairs are summed directly,
+ * and phi is the first-order potential.  SPH_E_ARG if the last tree holds several sets.
  * Outputs: device double[n] in caller order; any may be NULL (not copied out). */
 sph_status sph_compute_gravity(sph_ctx* ctx, double* gx, double* gy, double* gz, double* phi);
 

@@ -27,4 +27,4 @@ from .api import (  # noqa: F401
     sph_last_error,
 )
 from ._abi import (SPH_CURVE_HILBERT, SPH_CURVE_MORTON, SPH_ENERGY_THERMAL, SPH_ENERGY_THERMOKINETIC, SPH_FP32C, SPH_FP64, SPH_STEP_PRIMED,  # noqa: F401
-                   SPH_STEP_RESUME)
+                   SPH_GRAVITY_FMM, SPH_GRAVITY_QUADRUPOLE, SPH_STEP_RESUME)

@@ -17,6 +17,7 @@ SPH_FP64, SPH_FP32C = 0, 1
 SPH_STEP_PRIMED, SPH_STEP_RESUME = 1, 2
 SPH_ENERGY_THERMAL, SPH_ENERGY_THERMOKINETIC = 0, 1
 SPH_CURVE_MORTON, SPH_CURVE_HILBERT = 0, 1
+SPH_GRAVITY_QUADRUPOLE, SPH_GRAVITY_FMM = 0, 1
 
 STATUS_NAMES = {0: "SPH_OK", -1: "SPH_E_ARG", -2: "SPH_E_STATE", -3: "SPH_E_NOMEM", -4: "SPH_E_CAPACITY",
                 -5: "SPH_E_DEVICE", -6: "SPH_E_NONFINITE"}
@@ -32,7 +33,7 @@ class sph_config(ctypes.Structure):
                 ("adaptive_h", ctypes.c_int32), ("G", ctypes.c_double), ("soft_eps", ctypes.c_double),
                 ("theta", ctypes.c_double), ("leaf_size", ctypes.c_int32), ("group_size", ctypes.c_int32),
                 ("nbr_capacity", ctypes.c_int32), ("stream", ctypes.c_void_p), ("energy_form", ctypes.c_int32),
-                ("key_curve", ctypes.c_int32)]
+                ("key_curve", ctypes.c_int32), ("gravity_scheme", ctypes.c_int32)]
 
 
 _dp = ctypes.c_void_p  # device pointers are passed as integers

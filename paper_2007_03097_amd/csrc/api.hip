@@ -202,6 +202,8 @@ static sph_status check_config(sph_ctx* c, const sph_config* f) {
         return fail(c, SPH_E_ARG, "energy_form must be 0 or 1");
     if (f->key_curve != SPH_CURVE_MORTON && f->key_curve != SPH_CURVE_HILBERT)
         return fail(c, SPH_E_ARG, "key_curve must be 0 or 1");
+    if (f->gravity_scheme != SPH_GRAVITY_QUADRUPOLE && f->gravity_scheme != SPH_GRAVITY_FMM)
+        return fail(c, SPH_E_ARG, "gravity_scheme must be 0 or 1");
     return SPH_OK;
 }
 
@@ -328,6 +330,16 @@ static sph_status ensure_lists(sph_ctx* c) {
     return SPH_OK;
 }
 
+// Self-gravity of the resident state with the configured scheme; accumulate adds it to
+// a (and v.g to du when thermo), else it goes to g and phi.
+static void gravity_pass(sph_ctx* c, hipStream_t s, const DevPtrs& d, int accumulate, int thermo) {
+    const int fp32c = c->cfg.precision == SPH_FP32C;
+    if (c->cfg.gravity_scheme == SPH_GRAVITY_FMM)
+        launch_fmm(s, d, c->dm, fp32c, c->cfg.G, c->cfg.soft_eps, c->cfg.theta, accumulate, thermo);
+    else
+        launch_gravity(s, d, c->dm, fp32c, c->cfg.G, c->cfg.soft_eps, c->cfg.theta, accumulate, thermo);
+}
+
 // ---------------------------------------------------------------------------------------
 extern "C" {
 
@@ -349,6 +361,7 @@ void sph_config_default(sph_config* f) {
     f->nbr_capacity = 160;
     f->energy_form = SPH_ENERGY_THERMAL;
     f->key_curve = SPH_CURVE_MORTON;
+    f->gravity_scheme = SPH_GRAVITY_QUADRUPOLE;
     f->stream = nullptr;
 }
 
@@ -526,8 +539,10 @@ sph_status sph_compute_gravity(sph_ctx* c, double* gx, double* gy, double* gz, d
     if (!c) return SPH_E_ARG;
     const int n = c->dm.n;
     if (!c->tree_ok) return fail(c, SPH_E_STATE, "sph_build_tree has not been called");
+    if (c->cfg.gravity_scheme == SPH_GRAVITY_FMM && c->dm.batched)
+        return fail(c, SPH_E_ARG, "gravity_scheme SPH_GRAVITY_FMM needs a single set (n_seg == 1)");
     const DevPtrs& d = c->d[c->parity];
-    launch_gravity(c->stream, d, c->dm, c->cfg.precision == SPH_FP32C, c->cfg.G, c->cfg.soft_eps, c->cfg.theta, 0, 0);
+    gravity_pass(c, c->stream, d, 0, 0);
     launch_scatter_caller(c->stream, d, n, d.gx, gx);
     launch_scatter_caller(c->stream, d, n, d.gy, gy);
     launch_scatter_caller(c->stream, d, n, d.gz, gz);
@@ -549,7 +564,7 @@ static void accel_pass(sph_ctx* c, hipStream_t s, const DevPtrs& d, const double
     launch_nbr_lists(s, d, c->dm);
     launch_density(s, d, c->dm, fp32c, c->cfg.gamma, c->cfg.h_coeff, u_eos, kin);
     launch_forces(s, d, c->dm, fp32c, c->cfg.av_alpha, c->cfg.av_beta, c->cfg.av_eps, thermo);
-    if (c->cfg.G != 0.0) launch_gravity(s, d, c->dm, fp32c, c->cfg.G, c->cfg.soft_eps, c->cfg.theta, 1, thermo);
+    if (c->cfg.G != 0.0) gravity_pass(c, s, d, 1, thermo);
 }
 
 // One KDK step from buffer set p into buffer set 1 - p.
@@ -616,6 +631,8 @@ static sph_status step_impl(sph_ctx* c, sph_particles* p, double dt, int32_t nst
     } else {
         st = check_particles(c, p);
         if (st != SPH_OK) return st;
+        if (c->cfg.G != 0.0 && c->cfg.gravity_scheme == SPH_GRAVITY_FMM && p->n_seg > 1)
+            return fail(c, SPH_E_ARG, "gravity_scheme SPH_GRAVITY_FMM needs a single set (n_seg == 1)");
         if ((flags & SPH_STEP_PRIMED) && p->n > 0 && (!p->ax || !p->ay || !p->az || !p->dudt))
             return fail(c, SPH_E_ARG, "SPH_STEP_PRIMED needs ax, ay, az and dudt");
         st = build_from_caller(c, p, nullptr, nullptr, nullptr);
@@ -670,8 +687,9 @@ sph_status sph_autotune(sph_ctx* c, const sph_particles* p, double dt, const cha
     sph_status st = check_particles(c, p);
     if (st != SPH_OK) return st;
     char keybuf[160];
-    snprintf(keybuf, sizeof keybuf, "n%lld_s%d_p%d_g%d_a%d", (long long)p->n, p->n_seg, c->cfg.precision,
-             c->cfg.G != 0.0, c->cfg.adaptive_h);
+    snprintf(keybuf, sizeof keybuf, "n%lld_s%d_p%d_g%d_a%d%s", (long long)p->n, p->n_seg, c->cfg.precision,
+             c->cfg.G != 0.0, c->cfg.adaptive_h,
+             c->cfg.G != 0.0 && c->cfg.gravity_scheme == SPH_GRAVITY_FMM ? "_fmm" : "");
     const std::string key(keybuf);
     if (cache) {  // tiny JSON reader: "key": [leaf, group]
         std::ifstream f(cache);

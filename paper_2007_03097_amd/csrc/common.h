@@ -121,6 +121,15 @@ struct Dims {
     int curve;        // 0 Morton, 1 Hilbert keys
 };
 
+// Key quantisation of one coordinate (Sec. 2.1): one subtraction, one multiplication, then
+// truncation into 0 .. top (the cell index inside the cubic root cell at the finest level).
+__device__ __forceinline__ u32 quantise(double x, double lo, double S, u32 top) {
+    double t = (x - lo) * S;
+    if (!(t > 0.0)) return 0u;
+    if (t >= (double)top) return top;
+    return (u32)t;
+}
+
 // ---------------------------------------------------------------------------------------
 // Wave helpers (wave64 on gfx950)
 
@@ -334,6 +343,8 @@ void launch_forces(hipStream_t s, const DevPtrs& d, const Dims& dm, int fp32c, d
 // k_grav.hip
 void launch_gravity(hipStream_t s, const DevPtrs& d, const Dims& dm, int fp32c, double G, double eps,
                     double theta, int accumulate, int thermokinetic);
+void launch_fmm(hipStream_t s, const DevPtrs& d, const Dims& dm, int fp32c, double G, double eps, double theta,
+                int accumulate, int thermokinetic);
 // k_step.hip
 void launch_scatter_caller(hipStream_t s, const DevPtrs& d, int n, const double* src, double* dst);
 void launch_gather_caller(hipStream_t s, const DevPtrs& d, int n, const double* src_caller, double* dst);

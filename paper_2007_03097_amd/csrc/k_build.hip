@@ -104,13 +104,6 @@ __device__ __forceinline__ u64 spread3(u32 v) {
     return x;
 }
 
-__device__ __forceinline__ u32 quantise(double x, double lo, double S, u32 top) {
-    double t = (x - lo) * S;
-    if (!(t > 0.0)) return 0u;
-    if (t >= (double)top) return top;
-    return (u32)t;
-}
-
 // Hilbert index of grid cell (x, y, z) on a 2^bits grid: Skilling's transposition
 // (J. Skilling, AIP Conf. Proc. 707, 381 (2004)) unrolled for three axes, then one 3-bit
 // digit per level with x in its high bit.

@@ -129,21 +129,14 @@ struct GravTargets {
     int tp, phi, TP, P;
 };
 
-// Accepted cells (monopole + quadrupole) and unaccepted leaves (softened particle sums,
-// self excluded) for the lane's targets.  Cells are staged 64 at a time (one lane loads
-// one cell); the leaves' particles are concatenated and staged 64 at a time, so every
-// staging round is one load per lane.  With softening the self pair is evaluated like any
-// other (it adds no force) and its potential term -m_q/eps is taken out at the end.
+// Accepted cells (monopole + quadrupole) for the lane's targets, staged 64 at a time (one
+// lane loads one cell).
 template <bool FP32C>
-__device__ void eval_lists(int ncell, int nleaf, const int* cells, int* leaves, GravStage& St,
-                           const int4* __restrict__ topo, const double4* __restrict__ mom0,
-                           const double4* __restrict__ mom1, const double4* __restrict__ mom2,
-                           const double4* __restrict__ pos4, const double* __restrict__ m, const GravTargets& T,
-                           double eps, TargetSums& A, TargetSums& B) {
+__device__ void eval_cells(int ncell, const int* cells, GravStage& St, const double4* __restrict__ mom0,
+                           const double4* __restrict__ mom1, const double4* __restrict__ mom2, const GravTargets& T,
+                           double e2, TargetSums& A, TargetSums& B) {
     const int lane = lane_id();
-    const double e2 = eps * eps;
     const bool any = T.va || T.vb;
-    // ---- cells
     for (int k0 = 0; k0 < ncell; k0 += 64) {
         __syncthreads();
         if (k0 + lane < ncell) {
@@ -165,6 +158,19 @@ __device__ void eval_lists(int ncell, int nleaf, const int* cells, int* leaves, 
             B.flush_tile();
         }
     }
+}
+
+// Leaves evaluated by softened particle sums (self excluded) for the lane's targets.  The
+// leaves' particles are concatenated and staged 64 at a time, so every staging round is
+// one load per lane.  With softening the self pair is evaluated like any other (it adds no
+// force) and its potential term -m_q/eps is taken out by the caller.  leaves[] is
+// overwritten with the leaves' first particles.
+template <bool FP32C>
+__device__ void eval_leaves(int nleaf, int* leaves, GravStage& St, const int4* __restrict__ topo,
+                            const double4* __restrict__ pos4, const double* __restrict__ m, const GravTargets& T,
+                            double e2, TargetSums& A, TargetSums& B) {
+    const int lane = lane_id();
+    const bool any = T.va || T.vb;
     // ---- leaves: offsets of their particles, then the particles 64 at a time
     int carry = 0;
     for (int j0 = 0; j0 < nleaf; j0 += 64) {
@@ -223,6 +229,16 @@ __device__ void eval_lists(int ncell, int nleaf, const int* cells, int* leaves, 
             B.flush_tile();
         }
     }
+}
+
+template <bool FP32C>
+__device__ void eval_lists(int ncell, int nleaf, const int* cells, int* leaves, GravStage& St,
+                           const int4* __restrict__ topo, const double4* __restrict__ mom0,
+                           const double4* __restrict__ mom1, const double4* __restrict__ mom2,
+                           const double4* __restrict__ pos4, const double* __restrict__ m, const GravTargets& T,
+                           double eps, TargetSums& A, TargetSums& B) {
+    eval_cells<FP32C>(ncell, cells, St, mom0, mom1, mom2, T, eps * eps, A, B);
+    eval_leaves<FP32C>(nleaf, leaves, St, topo, pos4, m, T, eps * eps, A, B);
 }
 
 template <bool FP32C>
@@ -378,4 +394,322 @@ void launch_gravity(hipStream_t s, const DevPtrs& d, const Dims& dm, int fp32c, 
         hipLaunchKernelGGL(k_gravity<false>, dim3(dm.group_grid), dim3(64), 0, s, d.ctl, d.group, dm.group_size, d.topo,
                            d.nbox_lo, d.nbox_hi, d.mom0, d.mom1, d.mom2, d.pos4, d.m, G, eps, theta, accumulate, gx, gy,
                            gz, d.phi, d.vel4, de);
+}
+
+// ---------------------------------------------------------------------------------------
+// Symmetric node-node gravity: the paper's own scheme (Sec. 2.2.2, eq. (10), after Dehnen
+// 2000).
+//
+// Interaction set: the mutual recursion over node pairs.  A node paired with itself splits
+// into its children's self pairs and every unordered pair of children (a leaf sums its
+// particle pairs).  A pair (A, B) of distinct nodes is one node-node term when the opening
+// test accepts it; else every particle pair when both are leaves; else the larger node
+// (lower level; on equal levels the one whose particles come first in key order) is split,
+// unless it is a leaf, in which case the other one is.
+//
+// Opening test: every octree cell (the cells of the key quantisation) lies inside the
+// sphere of radius (sqrt 3 / 2) side about its centre; (A, B) is accepted when
+// r_A + r_B < theta |c_A - c_B|.  In integer units of half the finest cell this reads
+// 3 T^2 < 4 theta^2 |D|^2 with T = 2 (s_A + s_B) and D = 2 (c_A - c_B), so every decision is
+// exact and independent of rounding.  theta = 0 accepts nothing: the direct sum.
+//
+// Node-node term: first order in the Taylor expansion of the potential about each centre
+// of mass, with monopole sources.  Node Y acts on node X through g = -G M_Y R / s^3 at R_X
+// (R = R_X - R_Y, s^2 = |R|^2 + eps^2), constant across X, and the potential
+// -G M_Y / s - g . (r - R_X).  R flips sign bit for bit between the two directions of a
+// pair, so the forces two nodes exert on each other are opposite and central: linear and
+// angular momentum are conserved up to rounding.
+//
+// GPU form: every leaf of the tree is a target of one wavefront, which replays the part of
+// the recursion that involves the leaf's ancestors X_0 (root) .. X_D (the leaf): each self
+// pair (X_e, X_e) yields the pairs (X_e+1, C) for the other children C of X_e, and a pair
+// (X_e, Y) either ends (term or particle pairs), moves down the path (X split) or fans out
+// over Y's children.  Every node-node term of an ancestor is evaluated once per leaf below
+// it -- no scatter, no atomics, a fixed summation order.  The lanes evaluate 64 accepted
+// pairs at a time (one each) and sum the constant fields across the wave at the end;
+// unaccepted leaf pairs go through eval_leaves.  The potential's linear part is referred
+// to the leaf's centre of mass.
+constexpr int FM_STACK = 512;
+constexpr int FM_TERMS = 512;
+constexpr int FM_LEAVES = 256;
+constexpr int FM_TARGETS = 128;   // targets per pass over a leaf (two per lane)
+static_assert(7 * MAX_LEVEL <= FM_STACK, "the initial pairs of a path fit the stack");
+static_assert(FM_LEAVES <= GW_LEAVES, "leaf offsets live in GravStage");
+
+struct FmmPath {
+    double4 com[MAX_LEVEL + 1];  // (M, centre of mass) of the ancestor at each depth
+    int4 topo[MAX_LEVEL + 1];    // its topology record
+    int node[MAX_LEVEL + 1];
+    int start[MAX_LEVEL + 1];    // its first particle (key order)
+    int cell[MAX_LEVEL + 1][3];  // its integer cell coordinates at its level
+};
+
+// Integer coordinates of the cell of a node: its first particle, quantised as for the keys
+// and truncated to the node's level.
+__device__ __forceinline__ void fmm_cell(const double4* __restrict__ pos4, int start, int level, const double* lo,
+                                         double S, int* c) {
+    const double4 p = pos4[start];
+    const u32 top = (1u << MAX_LEVEL) - 1u;
+    const int sh = MAX_LEVEL - level;
+    c[0] = (int)(quantise(p.x, lo[0], S, top) >> sh);
+    c[1] = (int)(quantise(p.y, lo[1], S, top) >> sh);
+    c[2] = (int)(quantise(p.z, lo[2], S, top) >> sh);
+}
+
+__device__ __forceinline__ bool fmm_accept(int la, const int* ca, int lb, const int* cb, double th4) {
+    const long long T = (1ll << (MAX_LEVEL - la + 1)) + (1ll << (MAX_LEVEL - lb + 1));
+    long long D2 = 0;
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+        const long long a = (2ll * ca[d] + 1) << (MAX_LEVEL - la);
+        const long long b = (2ll * cb[d] + 1) << (MAX_LEVEL - lb);
+        D2 += (a - b) * (a - b);
+    }
+    return 3.0 * (double)(T * T) < th4 * (double)D2;
+}
+
+// Accepted pairs (tnode[k], depth tdep[k]): lane k evaluates pair k, k + 64, ... and keeps
+// its own partial sums of the field (fg) and of the potential referred to the leaf's
+// centre of mass (fc); the caller sums them across the wave.
+__device__ __forceinline__ void fmm_eval_terms(int nt, const int* tnode, const unsigned char* tdep, const FmmPath& P,
+                                               int D, const double4* __restrict__ mom0, double e2, double& fgx,
+                                               double& fgy, double& fgz, double& fc) {
+    const double4 cl = P.com[D];
+    for (int k = lane_id(); k < nt; k += 64) {
+        const double4 cx = P.com[tdep[k]];
+        const double4 cy = mom0[tnode[k]];
+        const double Rx = cx.y - cy.y, Ry = cx.z - cy.z, Rz = cx.w - cy.w;
+        const double s2 = fma(Rx, Rx, fma(Ry, Ry, fma(Rz, Rz, e2)));
+        const double i1 = rsq_nr(s2);
+        const double mi1 = cy.x * i1;
+        const double mi3 = mi1 * i1 * i1;
+        const double gx = -mi3 * Rx, gy = -mi3 * Ry, gz = -mi3 * Rz;
+        fgx += gx;
+        fgy += gy;
+        fgz += gz;
+        fc -= mi1 + fma(gx, cl.y - cx.y, fma(gy, cl.z - cx.z, gz * (cl.w - cx.w)));
+    }
+}
+
+template <bool FP32C>
+__global__ void __launch_bounds__(64) k_fmm(DevCtl* ctl, const int* __restrict__ leaf_pre,
+                                            const int* __restrict__ pre_to_bfs, const int* __restrict__ parent,
+                                            const int4* __restrict__ topo, const int2* __restrict__ range,
+                                            const double4* __restrict__ mom0, const double4* __restrict__ pos4,
+                                            const double* __restrict__ m, double G, double eps, double th4,
+                                            int accumulate, double* __restrict__ gxo, double* __restrict__ gyo,
+                                            double* __restrict__ gzo, double* __restrict__ pho,
+                                            const double4* __restrict__ vel4, double* __restrict__ deo) {
+    __shared__ int stk[FM_STACK];
+    __shared__ unsigned char sdep[FM_STACK];
+    __shared__ int tnode[FM_TERMS];
+    __shared__ unsigned char tdep[FM_TERMS];
+    __shared__ int leaves[FM_LEAVES];
+    __shared__ GravStage St;
+    __shared__ FmmPath Pth;
+    const int lane = lane_id();
+    const double e2 = eps * eps;
+    const double lo[3] = {ctl->box[0], ctl->box[1], ctl->box[2]};
+    const double S = ctl->scale[0];
+    const u64 lt = lanemask_lt();
+    int l0, l1, lstep;
+    group_range(ctl->n_leaves, l0, l1, lstep);
+    for (int li = l0; li < l1; li += lstep) {
+        const int L = pre_to_bfs[leaf_pre[li]];
+        const int4 tl = topo[L];
+        const int D = tl.z;  // one set: the root is at level 0
+        __syncthreads();
+        if (lane == 0) {
+            int b = L;
+            for (int e = D; e >= 0; --e) {
+                Pth.node[e] = b;
+                b = e > 0 ? parent[b] : -1;
+            }
+        }
+        __syncthreads();
+        if (lane <= D) {
+            const int b = Pth.node[lane];
+            const int4 t = topo[b];
+            const int st = range[b].x;
+            Pth.topo[lane] = t;
+            Pth.start[lane] = st;
+            Pth.com[lane] = mom0[b];
+            fmm_cell(pos4, st, t.z, lo, S, Pth.cell[lane]);
+        }
+        __syncthreads();
+        const double4 cl = Pth.com[D];
+        for (int t0 = 0; t0 < tl.y; t0 += FM_TARGETS) {
+            const int cc = min(FM_TARGETS, tl.y - t0);
+            GravTargets T;
+            T.TP = 1;
+            while (2 * T.TP < cc) T.TP <<= 1;
+            T.P = 64 / T.TP;
+            T.tp = lane & (T.TP - 1);
+            T.phi = lane / T.TP;
+            T.qa = tl.x + t0 + T.tp;
+            T.qb = T.qa + T.TP;
+            T.va = T.tp < cc;
+            T.vb = T.tp + T.TP < cc;
+            T.a = T.va ? pos4[T.qa] : make_double4(0, 0, 0, 0);
+            T.b = T.vb ? pos4[T.qb] : make_double4(0, 0, 0, 0);
+            // initial pairs: (X_e+1, C) for every other child C of every ancestor X_e
+            const int n0 = lane < D ? Pth.topo[lane].y - 1 : 0;
+            const int incl = wave_incl_scan(n0);
+            int sp = __shfl(incl, 63, 64);
+            if (lane < D) {
+                const int4 t = Pth.topo[lane];
+                const int nxt = Pth.node[lane + 1];
+                int o = incl - n0;
+                for (int j = 0; j < t.y; ++j) {
+                    const int ch = t.x + j;
+                    if (ch != nxt) {
+                        stk[o] = ch;
+                        sdep[o] = (unsigned char)(lane + 1);
+                        ++o;
+                    }
+                }
+            }
+            if (lane == 0) leaves[0] = L;  // the leaf's own particle pairs
+            int nt = 0, nl = 1, iters = 0;
+            TargetSums A, B;
+            double fgx = 0.0, fgy = 0.0, fgz = 0.0, fc = 0.0;
+            __syncthreads();
+            while (sp > 0) {
+                if (++iters > (1 << 22)) {  // bounded: every wave leaves the loop
+                    if (lane == 0) set_err(ctl, ERR_GRAV_LIST);
+                    break;
+                }
+                if (nt + 64 > FM_TERMS) {
+                    fmm_eval_terms(nt, tnode, tdep, Pth, D, mom0, e2, fgx, fgy, fgz, fc);
+                    nt = 0;
+                    __syncthreads();
+                }
+                if (nl + 64 > FM_LEAVES) {
+                    eval_leaves<FP32C>(nl, leaves, St, topo, pos4, m, T, e2, A, B);
+                    nl = 0;
+                    __syncthreads();
+                }
+                int k = sp < 64 ? sp : 64;
+                const int room = (FM_STACK - sp) / 8;
+                if (k > room) k = room > 1 ? room : 1;
+                int Y = -1, e = 0;
+                if (lane < k) {
+                    Y = stk[sp - k + lane];
+                    e = sdep[sp - k + lane];
+                }
+                __syncthreads();
+                sp -= k;
+                int kind = 0;  // 1 = node-node term, 2 = leaf pair, 3 = split X, 4 = split Y
+                int4 ty = make_int4(0, 0, 0, 0);
+                if (Y >= 0) {
+                    ty = topo[Y];
+                    const int sy = range[Y].x;
+                    int cy[3];
+                    fmm_cell(pos4, sy, ty.z, lo, S, cy);
+                    const int4 tx = Pth.topo[e];
+                    if (fmm_accept(tx.z, Pth.cell[e], ty.z, cy, th4)) {
+                        kind = 1;
+                    } else if (tx.w && ty.w) {
+                        kind = 2;
+                    } else {
+                        bool split_x = tx.z < ty.z || (tx.z == ty.z && Pth.start[e] < sy);
+                        if (split_x ? tx.w : ty.w) split_x = !split_x;
+                        kind = split_x ? 3 : 4;
+                    }
+                }
+                const u64 bt = __ballot(kind == 1), bl = __ballot(kind == 2);
+                if (kind == 1) {
+                    const int o = nt + __popcll(bt & lt);
+                    tnode[o] = Y;
+                    tdep[o] = (unsigned char)e;
+                }
+                if (kind == 2) leaves[nl + __popcll(bl & lt)] = Y;
+                nt += __popcll(bt);
+                nl += __popcll(bl);
+                const int np = kind == 3 ? 1 : (kind == 4 ? ty.y : 0);
+                const int pin = wave_incl_scan(np);
+                const int tot = __shfl(pin, 63, 64);
+                if (sp + tot > FM_STACK) {
+                    if (lane == 0) set_err(ctl, ERR_GRAV_LIST);
+                    break;
+                }
+                if (kind == 3) {
+                    stk[sp + pin - 1] = Y;
+                    sdep[sp + pin - 1] = (unsigned char)(e + 1);
+                } else if (kind == 4) {
+                    for (int j = 0; j < np; ++j) {
+                        stk[sp + pin - np + j] = ty.x + j;
+                        sdep[sp + pin - np + j] = (unsigned char)e;
+                    }
+                }
+                sp += tot;
+                __syncthreads();
+            }
+            __syncthreads();
+            fmm_eval_terms(nt, tnode, tdep, Pth, D, mom0, e2, fgx, fgy, fgz, fc);
+            eval_leaves<FP32C>(nl, leaves, St, topo, pos4, m, T, e2, A, B);
+            fgx = lanes_sum_d(fgx, 1);
+            fgy = lanes_sum_d(fgy, 1);
+            fgz = lanes_sum_d(fgz, 1);
+            fc = lanes_sum_d(fc, 1);
+            double r[8];
+            r[0] = FP32C ? A.kx.value() : A.gx;
+            r[1] = FP32C ? A.ky.value() : A.gy;
+            r[2] = FP32C ? A.kz.value() : A.gz;
+            r[3] = FP32C ? A.kp.value() : A.ph;
+            r[4] = FP32C ? B.kx.value() : B.gx;
+            r[5] = FP32C ? B.ky.value() : B.gy;
+            r[6] = FP32C ? B.kz.value() : B.gz;
+            r[7] = FP32C ? B.kp.value() : B.ph;
+#pragma unroll
+            for (int i = 0; i < 8; ++i) r[i] = lanes_sum_d(r[i], T.TP);
+            if (T.phi == 0) {
+                for (int s = 0; s < 2; ++s) {
+                    if (!(s ? T.vb : T.va)) continue;
+                    const int q = s ? T.qb : T.qa;
+                    const double4 me = s ? T.b : T.a;
+                    const double lin = fma(fgx, me.x - cl.y, fma(fgy, me.y - cl.z, fgz * (me.z - cl.w)));
+                    const double gx = G * (r[4 * s] + fgx), gy = G * (r[4 * s + 1] + fgy),
+                                 gz = G * (r[4 * s + 2] + fgz);
+                    double ph = G * (r[4 * s + 3] + (fc - lin));
+                    if (eps > 0.0) {  // take out the self pair's potential term (see eval_leaves)
+                        const double is = FP32C ? (double)__builtin_amdgcn_rsqf((float)e2) : rsq_nr(e2);
+                        ph += G * (m[q] * is);
+                    }
+                    if (accumulate) {
+                        gxo[q] += gx;
+                        gyo[q] += gy;
+                        gzo[q] += gz;
+                        if (deo) {  // thermokinetic form: the work of gravity on e = u + v^2/2
+                            const double4 v = vel4[q];
+                            deo[q] += fma(v.x, gx, fma(v.y, gy, v.z * gz));
+                        }
+                    } else {
+                        gxo[q] = gx;
+                        gyo[q] = gy;
+                        gzo[q] = gz;
+                    }
+                    if (pho) pho[q] = ph;
+                }
+            }
+        }
+    }
+}
+
+void launch_fmm(hipStream_t s, const DevPtrs& d, const Dims& dm, int fp32c, double G, double eps, double theta,
+                int accumulate, int thermo) {
+    if (dm.n <= 0) return;
+    double* gx = accumulate ? d.ax : d.gx;
+    double* gy = accumulate ? d.ay : d.gy;
+    double* gz = accumulate ? d.az : d.gz;
+    double* de = (accumulate && thermo) ? d.du : nullptr;
+    const double th4 = 4.0 * (theta * theta);
+    if (fp32c)
+        hipLaunchKernelGGL(k_fmm<true>, dim3(dm.group_grid), dim3(64), 0, s, d.ctl, d.leaf_pre, d.pre_to_bfs, d.parent,
+                           d.topo, d.range, d.mom0, d.pos4, d.m, G, eps, th4, accumulate, gx, gy, gz, d.phi, d.vel4,
+                           de);
+    else
+        hipLaunchKernelGGL(k_fmm<false>, dim3(dm.group_grid), dim3(64), 0, s, d.ctl, d.leaf_pre, d.pre_to_bfs,
+                           d.parent, d.topo, d.range, d.mom0, d.pos4, d.m, G, eps, th4, accumulate, gx, gy, gz, d.phi,
+                           d.vel4, de);
 }

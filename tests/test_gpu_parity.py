@@ -229,6 +229,134 @@ def test_gravity_theta_half(orc, prec, capsys):
         assert np.quantile(d, 0.99) <= 1e-9 and d.max() <= 1e-3
 
 
+# ---------------------------------------------------------------------------- node-node (FMM) gravity
+def _two_clusters():
+    rng = np.random.default_rng(5)
+    p = np.vstack([rng.uniform(0.0, 0.01, size=(8, 3)), rng.uniform(0.99, 1.0, size=(8, 3))])
+    ps = uniform_random(16, seed=1)
+    ps.x, ps.y, ps.z = [np.ascontiguousarray(p[:, i]) for i in range(3)]
+    ps.m = rng.uniform(0.5, 2.0, size=16)
+    return ps
+
+
+FMM_CASES = {
+    "polytrope": lambda: polytrope_n1(12000, seed=41),
+    "clustered": _clustered,
+    "duplicates": _dup_set,
+    "random_varh": lambda: uniform_random(3333, seed=4, h=(0.02, 0.08)),
+    "two_clusters": _two_clusters,
+    "n1": lambda: uniform_random(1, seed=1),
+    "n2": lambda: uniform_random(2, seed=2, h=0.5),
+}
+
+
+def _fmm_oracle(orc, ps, k, o, leaf, theta, G, eps):
+    """The oracle's symmetric node-node gravity on the oracle's own tree of the GPU's keys
+    (keys and order are checked bit-exact elsewhere), scattered back to caller order."""
+    t = orc.octree(k[o], leaf)
+    box = orc.bbox(ps.x, ps.y, ps.z)
+    r = orc.fmm_gravity(ps.x[o], ps.y[o], ps.z[o], ps.m[o], t, box, orc.scale(box, 21), theta, G, eps)
+    out = {}
+    for f in ("gx", "gy", "gz", "phi", "sg", "sp"):
+        a = np.empty(ps.n)
+        a[o] = r[f]
+        out[f] = a
+    assert np.all(r["cover"] == ps.n - 1)
+    return out
+
+
+@pytest.mark.parametrize("case,theta,leaf,eps", [("polytrope", 0.5, 16, 0.01), ("polytrope", 0.0, 16, 0.01),
+                                                 ("polytrope", 1.0, 8, 0.01), ("polytrope", 0.3, 24, 0.01),
+                                                 ("polytrope", 0.5, 64, 0.01), ("clustered", 0.5, 12, 0.01),
+                                                 ("duplicates", 0.7, 16, 0.01), ("random_varh", 0.5, 16, 0.0),
+                                                 ("two_clusters", 0.5, 8, 0.003), ("n1", 0.5, 16, 0.01),
+                                                 ("n2", 0.5, 16, 0.0)])
+def test_fmm_matches_oracle(orc, case, theta, leaf, eps):
+    """The GPU's per-leaf replay of the node-pair recursion against the oracle's mutual
+    recursion (Sec. 2.2.2, eq. (10)): the opening decisions are exact integer tests, so the
+    same node and particle terms are summed and every particle agrees to 1e-12 of its
+    absolute-sum scale, in g and in the first-order potential."""
+    import paper_2007_03097_amd as sph
+    ps = FMM_CASES[case]()
+    ctx = make_ctx(ps.n, theta=theta, G=1.3, soft_eps=eps, leaf_size=leaf, gravity_scheme=sph.SPH_GRAVITY_FMM)
+    k, o = gpu_keys_order(ctx, parts(ps))
+    gx, gy, gz, phi = gpu_gravity(ctx, ps.n)
+    r = _fmm_oracle(orc, ps, k, o, leaf, theta, 1.3, eps)
+    assert vec_rel_err((gx, gy, gz), (r["gx"], r["gy"], r["gz"]), r["sg"]) <= TOL
+    assert rel_err(phi, r["phi"], r["sp"]) <= TOL
+
+
+def test_fmm_fp32c_and_conservation(orc, capsys):
+    """FP32C particle pairs (node-node terms stay FP64): within 1e-6 of the scale per particle
+    (median below 1e-7).  Both precisions conserve momentum and angular momentum of the
+    gravitational forces to rounding; the quadrupole particle-cell walk on the same set does
+    not (reported)."""
+    import paper_2007_03097_amd as sph
+    ps = FMM_CASES["polytrope"]()
+    k = o = None
+    res = {}
+    for prec in (0, 1):
+        ctx = make_ctx(ps.n, theta=0.5, G=1.0, soft_eps=0.01, leaf_size=16, precision=prec,
+                       gravity_scheme=sph.SPH_GRAVITY_FMM)
+        k, o = gpu_keys_order(ctx, parts(ps))
+        res[prec] = gpu_gravity(ctx, ps.n)
+    ctx = make_ctx(ps.n, theta=0.5, G=1.0, soft_eps=0.01, leaf_size=16)
+    gpu_keys_order(ctx, parts(ps))
+    res["quad"] = gpu_gravity(ctx, ps.n)
+    r = _fmm_oracle(orc, ps, k, o, 16, 0.5, 1.0, 0.01)
+    g32 = np.stack(res[1][:3], axis=1)
+    d = np.linalg.norm(g32 - np.stack([r["gx"], r["gy"], r["gz"]], axis=1), axis=1) / r["sg"]
+    pos = np.stack([ps.x, ps.y, ps.z], axis=1)
+    cons = {}
+    for key in (0, 1, "quad"):
+        g = np.stack(res[key][:3], axis=1)
+        gn = np.linalg.norm(g, axis=1)
+        P = np.linalg.norm((ps.m[:, None] * g).sum(axis=0)) / (ps.m * gn).sum()
+        Lm = np.linalg.norm((ps.m[:, None] * np.cross(pos, g)).sum(axis=0)) / (
+            ps.m * np.linalg.norm(pos, axis=1) * gn).sum()
+        cons[key] = (P, Lm)
+    with capsys.disabled():
+        print(f"\nFMM FP32C |dg|/S median {np.median(d):.2e} max {d.max():.2e}; |P|/S, |L|/S: "
+              + ", ".join(f"{k}: {a:.1e} {b:.1e}" for k, (a, b) in cons.items()))
+    assert np.median(d) <= 1e-7 and d.max() <= 1e-6
+    assert cons[0][0] <= 1e-14 and cons[0][1] <= 1e-14
+    assert cons[1][0] <= 1e-8 and cons[1][1] <= 1e-8
+
+
+def test_fmm_step_conserves_momentum():
+    """Resident KDK steps with SPH forces and node-node gravity: every pair term (SPH pairs,
+    particle pairs, node pairs) is antisymmetric and central, so total momentum and angular
+    momentum stay at rounding level while the star moves."""
+    import paper_2007_03097_amd as sph
+    from gpu_helpers import to_np
+    ps = polytrope_n1(20000, seed=8)
+    ctx = make_ctx(ps.n, G=1.0, soft_eps=0.01, theta=0.5, adaptive_h=1, nbr_capacity=512,
+                   gravity_scheme=sph.SPH_GRAVITY_FMM)
+    pa = parts(ps)
+    sph.sph_step(ctx.h, pa, 2e-3, 5, 0)
+    v = np.stack([to_np(pa[k]) for k in ("vx", "vy", "vz")], axis=1)
+    x = np.stack([to_np(pa[k]) for k in ("x", "y", "z")], axis=1)
+    vn = np.linalg.norm(v, axis=1)
+    assert vn.max() > 0.0
+    P = np.linalg.norm((ps.m[:, None] * v).sum(axis=0))
+    Lm = np.linalg.norm((ps.m[:, None] * np.cross(x, v)).sum(axis=0))
+    assert P <= 1e-13 * (ps.m * vn).sum()
+    assert Lm <= 1e-13 * (ps.m * np.linalg.norm(x, axis=1) * vn).sum()
+
+
+def test_fmm_rejects_segments():
+    import paper_2007_03097_amd as sph
+    ps = ensemble(3, seed=2, n_min=64, n_max=216, side_lo=4, side_hi=6)
+    ctx = make_ctx(ps.n, seg_cap=4, G=1.0, soft_eps=0.01, gravity_scheme=sph.SPH_GRAVITY_FMM)
+    pa = parts(ps)
+    sph.sph_build_tree(ctx.h, pa)
+    with pytest.raises(sph.SPHError) as e:
+        gpu_gravity(ctx, ps.n)
+    assert e.value.status == -1  # SPH_E_ARG
+    with pytest.raises(sph.SPHError):
+        sph.sph_step(ctx.h, pa, 1e-4, 1, 0)
+
+
 # ---------------------------------------------------------------------------- leapfrog
 def _state_from(ps, pa):
     from gpu_helpers import to_np
