@@ -121,13 +121,16 @@ def _pairs(ctx, pa, n):
     return total + (total - n)
 
 
-def run_polytrope(ps, steps, prec):
-    """n = 1 polytrope with self-gravity (theta = 0.5 quadrupole, eps = 0.01, G = 1), adaptive h."""
+def run_polytrope(ps, steps, prec, scheme=0):
+    """n = 1 polytrope with self-gravity (theta = 0.5, eps = 0.01, G = 1), adaptive h; scheme 0 =
+    quadrupole particle-cell walk, 1 = symmetric node-node (FMM) gravity.  Also times one
+    gravity pass on the final state (HIP events on the context's stream)."""
     import numpy as np
     import torch
     import paper_2007_03097_amd as sph
     n = ps.n
-    ctx = sph.Context(n, adaptive_h=1, precision=prec, G=1.0, soft_eps=0.01, theta=0.5, nbr_capacity=2048)
+    ctx = sph.Context(n, adaptive_h=1, precision=prec, G=1.0, soft_eps=0.01, theta=0.5, nbr_capacity=2048,
+                      gravity_scheme=scheme)
     pa = sph.ParticleArrays.from_numpy(ps, with_accel=True)
     sph.sph_autotune(ctx.h, pa, 1e-4, TUNING_CACHE)
     sph.sph_step(ctx.h, pa, 1e-9, 0, 0)                  # prime: accelerations of the initial state
@@ -141,11 +144,22 @@ def run_polytrope(ps, steps, prec):
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     pairs = _pairs(ctx, pa, n)
+    g = [torch.zeros(n, dtype=torch.float64, device="cuda") for _ in range(3)]
+    sph.sph_compute_gravity(ctx.h, *g)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(3):
+        sph.sph_compute_gravity(ctx.h, *g)
+    e1.record()
+    torch.cuda.synchronize()
+    grav_ms = e0.elapsed_time(e1) / 3
     leaf, group = sph.sph_get_tuning(ctx.h)
     ctx.close()
+    del g
     torch.cuda.empty_cache()
     return dict(ms_per_step=wall / steps * 1e3, steps_per_s=steps / wall, value=pairs * steps / wall, dt=dt,
-                leaf_size=leaf, group_size=group)
+                leaf_size=leaf, group_size=group, gravity_ms=grav_ms)
 
 
 def run_ensemble(steps):
@@ -203,8 +217,10 @@ def run_ensemble(steps):
 
 def run_sweeps():
     """Gravity time and accuracy against the opening angle (n = 1 polytrope, 262,144
-    particles; the theta = 0 result of the same kernel -- the direct sum -- is the reference)
-    and time against N at theta = 0.5 (gravity and the SPH passes), with power-law fits."""
+    particles; the theta = 0 result of the quadrupole walk -- the direct sum -- is the
+    reference), for the quadrupole particle-cell walk and the node-node (FMM) scheme, and
+    time against N at theta = 0.5 (both gravity schemes and the SPH passes), with power-law
+    fits."""
     import numpy as np
     import torch
     import paper_2007_03097_amd as sph
@@ -242,6 +258,19 @@ def run_sweeps():
         print(json.dumps(rows[-1]), file=sys.stderr, flush=True)
         ctx.close()
     out["theta_sweep_n262144"] = rows
+    rows = []
+    for theta in (0.0, 0.1, 0.2, 0.3, 0.4, 0.5, 0.6, 0.7, 0.8, 0.9, 1.0):
+        ctx = sph.Context(n, G=1.0, soft_eps=0.01, theta=theta, gravity_scheme=1)
+        sph.sph_build_tree(ctx.h, pa)
+        g = [torch.zeros(n, dtype=torch.float64, device="cuda") for _ in range(3)]
+        ms = timed(lambda: sph.sph_compute_gravity(ctx.h, *g), reps=1 if theta < 0.15 else 3)
+        gv = torch.stack(g, 1).cpu().numpy()
+        e = np.linalg.norm(gv - ref, axis=1) / np.linalg.norm(ref, axis=1)
+        rows.append({"theta": theta, "gravity_ms": ms, "rms_rel_err": float(np.sqrt((e ** 2).mean())),
+                     "p99_rel_err": float(np.quantile(e, 0.99))})
+        print(json.dumps(rows[-1]), file=sys.stderr, flush=True)
+        ctx.close()
+    out["fmm_theta_sweep_n262144"] = rows
     del pa
     rows = []
     for n in (65536, 262144, 1048576, 4194304):
@@ -251,17 +280,22 @@ def run_sweeps():
         sph.sph_build_tree(ctx.h, pa)
         g = [torch.zeros(n, dtype=torch.float64, device="cuda") for _ in range(3)]
         tg = timed(lambda: sph.sph_compute_gravity(ctx.h, *g))
+        cf = sph.Context(n, G=1.0, soft_eps=0.01, theta=0.5, gravity_scheme=1)
+        sph.sph_build_tree(cf.h, pa)
+        tfmm = timed(lambda: sph.sph_compute_gravity(cf.h, *g))
+        cf.close()
         tl = timed(lambda: sph.sph_find_neighbors(ctx.h, count=False))
         td = timed(lambda: sph.sph_compute_density(ctx.h, None, None, None, None))
         tf = timed(lambda: sph.sph_compute_forces(ctx.h, None, None, None, None))
-        rows.append({"n": n, "gravity_ms": tg, "lists_ms": tl, "density_ms": td, "forces_ms": tf})
+        rows.append({"n": n, "gravity_ms": tg, "fmm_gravity_ms": tfmm, "lists_ms": tl, "density_ms": td,
+                     "forces_ms": tf})
         print(json.dumps(rows[-1]), file=sys.stderr, flush=True)
         ctx.close()
         del pa, g
         torch.cuda.empty_cache()
     out["n_sweep_theta0.5"] = rows
     ns = np.array([r["n"] for r in rows], dtype=float)
-    for key in ("gravity_ms", "lists_ms", "density_ms", "forces_ms"):
+    for key in ("gravity_ms", "fmm_gravity_ms", "lists_ms", "density_ms", "forces_ms"):
         t = np.array([r[key] for r in rows])
         out[f"{key}_exponent"] = float(np.polyfit(np.log(ns[1:]), np.log(t[1:]), 1)[0])
         out[f"{key}_per_nlogn_ns"] = [float(x * 1e6 / (m * np.log2(m))) for x, m in zip(t, ns)]
@@ -346,6 +380,8 @@ def main():
         pp = polytrope_n1(4194304, seed=1003)
         extra["polytrope_4m_gravity"] = {"n_particles": pp.n, "fp64": run_polytrope(pp, 5, 0),
                                          "fp32c": run_polytrope(pp, 5, 1)}
+        extra["polytrope_4m_fmm_gravity"] = {"n_particles": pp.n, "fp64": run_polytrope(pp, 5, 0, scheme=1),
+                                             "fp32c": run_polytrope(pp, 5, 1, scheme=1)}
         del pp
         extra["ensemble_256"] = run_ensemble(5)
         tk = {}

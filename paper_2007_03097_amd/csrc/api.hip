@@ -709,7 +709,9 @@ sph_status sph_autotune(sph_ctx* c, const sph_particles* p, double dt, const cha
             }
         }
     }
-    const int leaves[] = {8, 12, 16, 24, 32};
+    // the node-node gravity favours larger leaves (its particle sums fill more lanes)
+    const bool fmm = c->cfg.G != 0.0 && c->cfg.gravity_scheme == SPH_GRAVITY_FMM;
+    const std::vector<int> leaves = fmm ? std::vector<int>{16, 24, 32, 48, 64} : std::vector<int>{8, 12, 16, 24, 32};
     const int groups[] = {16, 32, 64};
     double best = 1e300;
     int bL = c->leaf_size, bG = c->group_size;

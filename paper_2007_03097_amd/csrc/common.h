@@ -85,7 +85,7 @@ struct DevPtrs {
     double4* nbox_hi;             // node_cap: hi.xyz, cell side
     double4* mom0;                // node_cap: M, com.xyz
     double4* mom1;                // node_cap: Ixx, Iyy, Izz, tr I
-    double4* mom2;                // node_cap: Ixy, Ixz, Iyz, 0
+    double4* mom2;                // node_cap: Ixy, Ixz, Iyz, cell (bits; node-node gravity only)
     // groups and neighbour lists
     int4* group;                  // group_cap: {start, count, segment root rank (-1 = root), 0}
     u32* gflag;                   // n_cap + 1: 1 where a group cell starts

@@ -444,16 +444,29 @@ struct FmmPath {
     int cell[MAX_LEVEL + 1][3];  // its integer cell coordinates at its level
 };
 
-// Integer coordinates of the cell of a node: its first particle, quantised as for the keys
-// and truncated to the node's level.
-__device__ __forceinline__ void fmm_cell(const double4* __restrict__ pos4, int start, int level, const double* lo,
-                                         double S, int* c) {
-    const double4 p = pos4[start];
+// Integer coordinates of the cell of every node: its first particle, quantised as for the
+// keys and truncated to the node's level; packed 21 bits per axis into the free fourth
+// component of mom2 (the walk then reads them with the node's topology, not after it).
+__global__ void __launch_bounds__(256) k_fmm_cells(const DevCtl* __restrict__ ctl, const int4* __restrict__ topo,
+                                                    const int2* __restrict__ range, const double4* __restrict__ pos4,
+                                                    double4* mom2) {
+    const double lo[3] = {ctl->box[0], ctl->box[1], ctl->box[2]};
+    const double S = ctl->scale[0];
     const u32 top = (1u << MAX_LEVEL) - 1u;
-    const int sh = MAX_LEVEL - level;
-    c[0] = (int)(quantise(p.x, lo[0], S, top) >> sh);
-    c[1] = (int)(quantise(p.y, lo[1], S, top) >> sh);
-    c[2] = (int)(quantise(p.z, lo[2], S, top) >> sh);
+    const int nn = ctl->n_nodes;
+    for (int b = blockIdx.x * blockDim.x + threadIdx.x; b < nn; b += gridDim.x * blockDim.x) {
+        const double4 p = pos4[range[b].x];
+        const int sh = MAX_LEVEL - topo[b].z;
+        const u64 c = (u64)(quantise(p.x, lo[0], S, top) >> sh) | ((u64)(quantise(p.y, lo[1], S, top) >> sh) << 21) |
+                      ((u64)(quantise(p.z, lo[2], S, top) >> sh) << 42);
+        mom2[b].w = __longlong_as_double((long long)c);
+    }
+}
+
+__device__ __forceinline__ void fmm_unpack(u64 c, int* v) {
+    v[0] = (int)(c & 0x1fffff);
+    v[1] = (int)((c >> 21) & 0x1fffff);
+    v[2] = (int)(c >> 42);
 }
 
 __device__ __forceinline__ bool fmm_accept(int la, const int* ca, int lb, const int* cb, double th4) {
@@ -495,8 +508,9 @@ template <bool FP32C>
 __global__ void __launch_bounds__(64) k_fmm(DevCtl* ctl, const int* __restrict__ leaf_pre,
                                             const int* __restrict__ pre_to_bfs, const int* __restrict__ parent,
                                             const int4* __restrict__ topo, const int2* __restrict__ range,
-                                            const double4* __restrict__ mom0, const double4* __restrict__ pos4,
-                                            const double* __restrict__ m, double G, double eps, double th4,
+                                            const double4* __restrict__ mom0, const double* __restrict__ ncell,
+                                            const double4* __restrict__ pos4, const double* __restrict__ m, double G,
+                                            double eps, double th4,
                                             int accumulate, double* __restrict__ gxo, double* __restrict__ gyo,
                                             double* __restrict__ gzo, double* __restrict__ pho,
                                             const double4* __restrict__ vel4, double* __restrict__ deo) {
@@ -509,8 +523,6 @@ __global__ void __launch_bounds__(64) k_fmm(DevCtl* ctl, const int* __restrict__
     __shared__ FmmPath Pth;
     const int lane = lane_id();
     const double e2 = eps * eps;
-    const double lo[3] = {ctl->box[0], ctl->box[1], ctl->box[2]};
-    const double S = ctl->scale[0];
     const u64 lt = lanemask_lt();
     int l0, l1, lstep;
     group_range(ctl->n_leaves, l0, l1, lstep);
@@ -534,7 +546,7 @@ __global__ void __launch_bounds__(64) k_fmm(DevCtl* ctl, const int* __restrict__
             Pth.topo[lane] = t;
             Pth.start[lane] = st;
             Pth.com[lane] = mom0[b];
-            fmm_cell(pos4, st, t.z, lo, S, Pth.cell[lane]);
+            fmm_unpack((u64)__double_as_longlong(ncell[4 * b]), Pth.cell[lane]);
         }
         __syncthreads();
         const double4 cl = Pth.com[D];
@@ -605,7 +617,7 @@ __global__ void __launch_bounds__(64) k_fmm(DevCtl* ctl, const int* __restrict__
                     ty = topo[Y];
                     const int sy = range[Y].x;
                     int cy[3];
-                    fmm_cell(pos4, sy, ty.z, lo, S, cy);
+                    fmm_unpack((u64)__double_as_longlong(ncell[4 * Y]), cy);
                     const int4 tx = Pth.topo[e];
                     if (fmm_accept(tx.z, Pth.cell[e], ty.z, cy, th4)) {
                         kind = 1;
@@ -704,12 +716,16 @@ void launch_fmm(hipStream_t s, const DevPtrs& d, const Dims& dm, int fp32c, doub
     double* gz = accumulate ? d.az : d.gz;
     double* de = (accumulate && thermo) ? d.du : nullptr;
     const double th4 = 4.0 * (theta * theta);
+    const double* ncell = &d.mom2[0].w;  // stride 4 doubles
+    const int cg = std::min(2048, (dm.node_cap + 255) / 256);
+    hipLaunchKernelGGL(k_fmm_cells, dim3(cg), dim3(256), 0, s, d.ctl, d.topo, d.range,
+                       d.pos4, d.mom2);
     if (fp32c)
         hipLaunchKernelGGL(k_fmm<true>, dim3(dm.group_grid), dim3(64), 0, s, d.ctl, d.leaf_pre, d.pre_to_bfs, d.parent,
-                           d.topo, d.range, d.mom0, d.pos4, d.m, G, eps, th4, accumulate, gx, gy, gz, d.phi, d.vel4,
-                           de);
+                           d.topo, d.range, d.mom0, ncell, d.pos4, d.m, G, eps, th4, accumulate, gx, gy, gz, d.phi,
+                           d.vel4, de);
     else
         hipLaunchKernelGGL(k_fmm<false>, dim3(dm.group_grid), dim3(64), 0, s, d.ctl, d.leaf_pre, d.pre_to_bfs,
-                           d.parent, d.topo, d.range, d.mom0, d.pos4, d.m, G, eps, th4, accumulate, gx, gy, gz, d.phi,
-                           d.vel4, de);
+                           d.parent, d.topo, d.range, d.mom0, ncell, d.pos4, d.m, G, eps, th4, accumulate, gx, gy, gz,
+                           d.phi, d.vel4, de);
 }

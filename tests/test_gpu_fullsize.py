@@ -6,7 +6,9 @@
   targets within 1e-12 given the GPU's rho, P, c of their neighbours (a layered check:
   those values come from the density field whose sample passed).
 * The n = 1 polytrope at 4,194,304 particles: theta = 0.5 quadrupole gravity within 1e-3
-  RMS relative of the direct sum on 1024 sampled targets.
+  RMS relative of the direct sum on 1024 sampled targets; the node-node scheme conserves
+  momentum and angular momentum to rounding over all particles and keeps its first-order
+  accuracy on the same targets.
 * The batched ensemble (256 boxes, 4,879,340 particles, one context as the benchmark runs
   it): keys and order bit-exact; per-set neighbour sets bit-exact and density, forces
   (layered) for sampled targets across many sets, FP64 within 1e-12 and FP32C within the
@@ -88,6 +90,42 @@ def test_polytrope_4m_gravity_sampled(orc, capsys):
             print(f"\n4M polytrope gravity prec={prec}: RMS {rms:.3e} median {np.median(e):.2e} max {e.max():.2e}",
                   flush=True)
         assert rms <= 1e-3
+        ctx.close()
+
+
+def test_polytrope_4m_fmm_sampled(orc, capsys):
+    """The symmetric node-node gravity at 4,194,304 particles as the benchmark runs it (theta
+    = 0.5, the tuned leaf size, FP64 and FP32C): linear and angular momentum of the
+    gravitational forces over all particles at rounding level (1e-13 FP64, 1e-8 FP32C, of
+    sum m|g| and sum m|r||g|), and the first-order accuracy the oracle shows at small N on
+    1024 sampled targets against the direct sum (RMS below 0.1)."""
+    import paper_2007_03097_amd as sph
+    n = 4194304
+    ps = polytrope_n1(n, seed=1003)
+    rng = np.random.default_rng(7)
+    tg = np.sort(rng.choice(n, 1024, replace=False))
+    dx, dy, dz, dp = orc.gravity_direct(ps.x, ps.y, ps.z, ps.m, 1.0, 0.01, targets=tg)
+    gd = np.sqrt(dx ** 2 + dy ** 2 + dz ** 2)
+    pos = np.stack([ps.x, ps.y, ps.z], axis=1)
+    rn = np.linalg.norm(pos, axis=1)
+    for prec, bound in ((0, 1e-13), (1, 1e-8)):
+        ctx = make_ctx(n, G=1.0, soft_eps=0.01, theta=0.5, precision=prec, adaptive_h=1, nbr_capacity=2048,
+                       gravity_scheme=sph.SPH_GRAVITY_FMM)
+        pa = parts(ps)
+        leaf, _ = tuned(ctx, pa)
+        gpu_keys_order(ctx, pa)
+        gx, gy, gz, phi = gpu_gravity(ctx, n)
+        g = np.stack([gx, gy, gz], axis=1)
+        gn = np.linalg.norm(g, axis=1)
+        P = np.linalg.norm((ps.m[:, None] * g).sum(axis=0)) / (ps.m * gn).sum()
+        Lm = np.linalg.norm((ps.m[:, None] * np.cross(pos, g)).sum(axis=0)) / (ps.m * rn * gn).sum()
+        e = np.sqrt((gx[tg] - dx) ** 2 + (gy[tg] - dy) ** 2 + (gz[tg] - dz) ** 2) / gd
+        rms = math.sqrt((e ** 2).mean())
+        with capsys.disabled():
+            print(f"\n4M polytrope node-node gravity prec={prec} leaf {leaf}: |P|/S {P:.1e} |L|/S {Lm:.1e} "
+                  f"RMS {rms:.3e} median {np.median(e):.2e}", flush=True)
+        assert P <= bound and Lm <= bound
+        assert rms <= 0.1
         ctx.close()
 
 
