@@ -338,6 +338,9 @@ def main():
     ap.add_argument("--no-autotune", action="store_true", help="keep the default leaf and group sizes")
     ap.add_argument("--sweep", action="store_true",
                     help="instead of the benchmark: gravity time/accuracy vs theta and time vs N (one JSON line)")
+    ap.add_argument("--polytrope", action="store_true",
+                    help="instead of the benchmark: the 4M polytrope with both gravity schemes, FP64 and FP32C "
+                         "(one JSON line; --steps timed steps each)")
     ap.add_argument("--copy-calib-mib", type=int, default=0,
                     help="first run one device-to-device copy of this many MiB (hardware-counter calibration)")
     args = ap.parse_args()
@@ -350,6 +353,16 @@ def main():
     assert torch.cuda.is_available(), "needs a GPU"
     if args.sweep:
         print(json.dumps(run_sweeps()), flush=True)
+        return
+    if args.polytrope:
+        from workloads import polytrope_n1
+        pp = polytrope_n1(4194304, seed=1003)
+        out = {"workload": "n = 1 polytrope, 4,194,304 particles, G = 1, eps = 0.01, theta = 0.5, adaptive h",
+               "steps": args.steps}
+        for scheme, name in ((0, "quadrupole"), (1, "node_node")):
+            out[name] = {"fp64": run_polytrope(pp, args.steps, 0, scheme),
+                         "fp32c": run_polytrope(pp, args.steps, 1, scheme)}
+        print(json.dumps(out), flush=True)
         return
     if args.copy_calib_mib > 0:
         src = torch.empty(args.copy_calib_mib << 20, dtype=torch.uint8, device="cuda")
