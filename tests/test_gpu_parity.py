@@ -286,6 +286,22 @@ def test_fmm_matches_oracle(orc, case, theta, leaf, eps):
     assert rel_err(phi, r["phi"], r["sp"]) <= TOL
 
 
+def test_fmm_hilbert_keys(orc):
+    """Node-node gravity over a tree of Hilbert keys: the cells and their integer coordinates
+    are the Morton build's, only the order of children (and so the equal-level tie rule's
+    'first in key order') follows the curve; parity as for Morton keys."""
+    import paper_2007_03097_amd as sph
+    ps = polytrope_n1(9000, seed=44)
+    ctx = make_ctx(ps.n, theta=0.5, G=1.0, soft_eps=0.01, leaf_size=12, gravity_scheme=sph.SPH_GRAVITY_FMM,
+                   key_curve=sph.SPH_CURVE_HILBERT)
+    k, o = gpu_keys_order(ctx, parts(ps))
+    assert np.array_equal(k, orc.keys(ps.x, ps.y, ps.z, curve="hilbert"))
+    gx, gy, gz, phi = gpu_gravity(ctx, ps.n)
+    r = _fmm_oracle(orc, ps, k, o, 12, 0.5, 1.0, 0.01)
+    assert vec_rel_err((gx, gy, gz), (r["gx"], r["gy"], r["gz"]), r["sg"]) <= TOL
+    assert rel_err(phi, r["phi"], r["sp"]) <= TOL
+
+
 def test_fmm_fp32c_and_conservation(orc, capsys):
     """FP32C particle pairs (node-node terms stay FP64): within 1e-6 of the scale per particle
     (median below 1e-7).  Both precisions conserve momentum and angular momentum of the
@@ -485,18 +501,21 @@ def test_thermokinetic_rate(orc, case, prec):
             assert np.median(e) <= 2e-7 and e.max() <= 3e-5
 
 
-@pytest.mark.parametrize("case,adaptive,dt,G", [("lattice4096", 0, 0.0178, 0.0), ("sod_small", 1, 4.0e-4, 0.0),
-                                                ("polytrope", 1, 2.0e-3, 1.0)])
-def test_thermokinetic_step_lockstep(orc, case, adaptive, dt, G):
+@pytest.mark.parametrize("case,adaptive,dt,G,scheme", [("lattice4096", 0, 0.0178, 0.0, 0),
+                                                       ("sod_small", 1, 4.0e-4, 0.0, 0),
+                                                       ("polytrope", 1, 2.0e-3, 1.0, 0),
+                                                       ("polytrope", 1, 2.0e-3, 1.0, 1)])
+def test_thermokinetic_step_lockstep(orc, case, adaptive, dt, G, scheme):
     """Thermokinetic KDK steps in lockstep with the oracle (each GPU step starts from the GPU
-    state); with gravity (theta = 0: the direct sum) de/dt includes the work v.g."""
+    state); with gravity (theta = 0: the direct sum, through either gravity scheme) de/dt
+    includes the work v.g."""
     import paper_2007_03097_amd as sph
     ps = CASES[case]()
     if case == "lattice4096":
         rng = np.random.default_rng(9)
         ps.vx, ps.vy, ps.vz = (rng.normal(0.0, 0.2, ps.n) for _ in range(3))
     ctx = make_ctx(ps.n, adaptive_h=adaptive, energy_form=sph.SPH_ENERGY_THERMOKINETIC, G=G, soft_eps=0.01,
-                   theta=0.0, nbr_capacity=1024)
+                   theta=0.0, nbr_capacity=1024, gravity_scheme=scheme)
     pa = parts(ps, with_accel=True)
     prm = orc.Params(adaptive_h=bool(adaptive), thermokinetic=True, G=G, soft_eps=0.01)
     st = orc.prime(ps.fields(), prm)
