@@ -10,8 +10,8 @@
 //   lcp[i]   = leading equal digits of keys i-1 and i (-1 at i = 0 and i = n): cell
 //              boundaries at level l are the positions with lcp < l.
 //   lvl[i]   = level of the leaf holding i = 1 + min{v : the nearest boundaries with
-//              lcp <= v on both sides of i are at most leaf_size apart}, found by a binary
-//              search over v with windowed scans in LDS.
+//              lcp <= v on both sides of i are at most leaf_size apart}, found in one
+//              pass over a window of lcp values in LDS (see window_level).
 //   position i starts the nodes of levels lcp[i]+1 .. lvl[i]; an exclusive scan of those
 //   counts numbers the nodes in pre-order.  A stable counting sort by level turns that
 //   into breadth-first order, where the children of a node are a contiguous run of the
@@ -22,22 +22,31 @@
 #include "common.h"
 
 constexpr int TB = 256;          // positions per block in the leaf-level kernel
-constexpr int MAX_WIN = 256;     // largest supported leaf_size
+constexpr int MAX_WIN = 64;      // largest supported leaf_size
 
 // Level of the smallest cell around position ci that holds at most win particles:
 // 1 + min{v : the nearest boundaries with lcp <= v on both sides are at most win apart}.
-__device__ __forceinline__ int window_level(const signed char* c, int ci, int win) {
-    int vlo = -1, vhi = MAX_LEVEL;
-    while (vlo < vhi) {
-        const int v = (vlo + vhi) >> 1;
-        int t = 0;
-        while (t < win && c[ci - t] > v) ++t;
-        int k = 1;
-        while (k <= win && c[ci + k] > v) ++k;
-        if (t < win && k <= win && t + k <= win) vhi = v;
-        else vlo = v + 1;
+// With ML(t) = min c[ci-t .. ci] and MR(k) = min c[ci+1 .. ci+k], a level v qualifies
+// exactly when ML(t) <= v and MR(k) <= v for some t < win, k >= 1, t + k <= win; both
+// minima only fall as t, k grow, so the smallest v is min over t of max(ML(t), MR(win - t)).
+// One branch-free pass; this thread's MR(k) sits at mr[(k - 1) * TB] in LDS (threads of a
+// wave write neighbouring bytes).
+__device__ __forceinline__ int window_level(const signed char* c, int ci, int win, signed char* mr) {
+    int m = 127;
+    for (int k = 1; k <= win; ++k) {
+        const int v = c[ci + k];
+        m = v < m ? v : m;
+        mr[(k - 1) * TB] = (signed char)m;
     }
-    const int L = vlo + 1;
+    int best = 127, ml = 127;
+    for (int t = 0; t < win; ++t) {
+        const int v = c[ci - t];
+        ml = v < ml ? v : ml;
+        const int r = mr[(win - 1 - t) * TB];
+        const int x = ml > r ? ml : r;
+        best = x < best ? x : best;
+    }
+    const int L = best + 1;
     return L > MAX_LEVEL ? MAX_LEVEL : L;
 }
 
@@ -47,6 +56,7 @@ __device__ __forceinline__ int window_level(const signed char* c, int ci, int wi
 __global__ void __launch_bounds__(TB) k_leaf_levels(const u64* __restrict__ key, int n, int win, int min_level,
                                                     signed char* lcp, unsigned char* lvl, u64* scan_in) {
     __shared__ signed char c[TB + 2 * MAX_WIN + 2];
+    __shared__ signed char mrow[TB * MAX_WIN];
     const int b0 = blockIdx.x * TB;
     const int lo = b0 - win;                      // c[j] holds position lo + j
     const int cnt = TB + 2 * win + 1;
@@ -60,7 +70,7 @@ __global__ void __launch_bounds__(TB) k_leaf_levels(const u64* __restrict__ key,
     const int i = b0 + threadIdx.x;
     if (i >= n) return;
     const int ci = i - lo;
-    int L = window_level(c, ci, win);
+    int L = window_level(c, ci, win, mrow + threadIdx.x);
     if (L < min_level) L = min_level;
     const int cc = c[ci];
     const int nodes = L > cc ? L - cc : 0;
