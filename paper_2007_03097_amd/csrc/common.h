@@ -281,6 +281,19 @@ __device__ __forceinline__ double sqrt_nr(double a) {
     r = fma(d, h, r);
     return a > 0.0 ? r : 0.0;
 }
+// sqrt(a) and 1/sqrt(a) together, a >= 0: the Goldschmidt step of sqrt_nr refines both;
+// the inverse to about 1e-14 relative (a == 0 gives sqrt 0 and a non-finite inverse).
+__device__ __forceinline__ double sqrt_rsq_nr(double a, double& inv) {
+    const double y = __builtin_amdgcn_rsq(a);
+    double r = a * y, h = 0.5 * y;
+    const double e = fma(-r, h, 0.5);
+    r = fma(r, e, r);
+    h = fma(h, e, h);
+    const double d = fma(-r, r, a);
+    r = fma(d, h, r);
+    inv = 2.0 * h;
+    return a > 0.0 ? r : 0.0;
+}
 
 // Kahan / Neumaier accumulators (explicit operation order; the library is built without
 // floating-point contraction, so these are not fused).

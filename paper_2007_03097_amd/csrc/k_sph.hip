@@ -227,18 +227,22 @@ __global__ void __launch_bounds__(PAIR_THREADS) k_forces(
                     const double4 tb = reinterpret_cast<const double4*>(S.thr)[j];
                     const double dx = me.x - sb.x, dy = me.y - sb.y, dz = me.z - sb.z;
                     const double r2 = fma(dx, dx, fma(dy, dy, dz * dz));
-                    const double r = sqrt_nr(r2);
+                    double ir;
+                    const double r = sqrt_rsq_nr(r2, ir);
                     const double hab = 0.5 * (me.w + sb.w);
                     const double ih = rcp_nr(hab);
                     const double ih2 = ih * ih;
                     const double qq = r * ih;
-                    const double gw = m4_g(qq, hab * rcp_nr(r)) * (ih2 * ih2 * ih) * M_1_PI_D;
+                    const double gw = m4_g(qq, hab * ir) * (ih2 * ih2 * ih) * M_1_PI_D;
                     const double wx = mv.x - vb.x, wy = mv.y - vb.y, wz = mv.z - vb.z;
                     const double vr = fma(wx, dx, fma(wy, dy, wz * dz));
                     double Pi = 0.0;
-                    if (vr < 0.0) {
-                        const double mu = hab * vr * rcp_nr(fma(eps_av * hab, hab, r2));
-                        Pi = fma(-alpha * 0.5 * (mt.z + tb.z), mu, beta * mu * mu) * rcp_nr(0.5 * (mt.x + tb.x));
+                    if (vr < 0.0) {  // one reciprocal of den * rhobar gives 1/den and 1/rhobar
+                        const double den = fma(eps_av * hab, hab, r2);
+                        const double rb = 0.5 * (mt.x + tb.x);
+                        const double inv = rcp_nr(den * rb);
+                        const double mu = hab * vr * (rb * inv);
+                        Pi = fma(-alpha * 0.5 * (mt.z + tb.z), mu, beta * mu * mu) * (den * inv);
                     }
                     const double term = vb.w * ((mt.y + tb.y) + Pi) * gw;
                     sx = fma(-term, dx, sx);
