@@ -68,7 +68,7 @@ __device__ __forceinline__ void cell_term(const double4 me, const double4 a, con
         const double IRz = fma(d.y, Rx, fma(d.z, Ry, b.z * Rz));
         const double RIR = fma(Rx, IRx, fma(Ry, IRy, Rz * IRz));
         const double s2 = fma(Rx, Rx, fma(Ry, Ry, fma(Rz, Rz, e2)));
-        const double i1 = rsq_nr(s2);
+        const double i1 = rsq_nr1(s2);
         const double i2 = i1 * i1, i3 = i1 * i2, i5 = i3 * i2, i7 = i5 * i2;
         const double cR = -a.x * i3 + 1.5 * b.w * i5 - 7.5 * RIR * i7;
         S.gx = fma(cR, Rx, fma(3.0 * i5, IRx, S.gx));
@@ -100,7 +100,7 @@ __device__ __forceinline__ void part_term(const double4 me, const double4 sb, do
     if (!FP32C) {
         const double dx = me.x - sb.x, dy = me.y - sb.y, dz = me.z - sb.z;
         const double s2 = fma(dx, dx, fma(dy, dy, fma(dz, dz, e2)));
-        const double i1 = rsq_nr(s2);
+        const double i1 = rsq_nr1(s2);
         const double mi3 = sb.w * i1 * i1 * i1;
         S.gx = fma(-mi3, dx, S.gx);
         S.gy = fma(-mi3, dy, S.gy);
@@ -357,7 +357,7 @@ __global__ void __launch_bounds__(64) k_gravity(DevCtl* ctl, const int4* __restr
                 double gx = r[4 * s], gy = r[4 * s + 1], gz = r[4 * s + 2], ph = r[4 * s + 3];
                 if (eps > 0.0) {  // take out the self pair's potential term (see eval_lists)
                     const double e2 = eps * eps;
-                    const double is = FP32C ? (double)__builtin_amdgcn_rsqf((float)e2) : rsq_nr(e2);
+                    const double is = FP32C ? (double)__builtin_amdgcn_rsqf((float)e2) : rsq_nr1(e2);
                     ph += G * (m[q] * is);
                 }
                 if (accumulate) {
@@ -493,7 +493,7 @@ __device__ __forceinline__ void fmm_eval_terms(int nt, const int* tnode, const u
         const double4 cy = mom0[tnode[k]];
         const double Rx = cx.y - cy.y, Ry = cx.z - cy.z, Rz = cx.w - cy.w;
         const double s2 = fma(Rx, Rx, fma(Ry, Ry, fma(Rz, Rz, e2)));
-        const double i1 = rsq_nr(s2);
+        const double i1 = rsq_nr1(s2);
         const double mi1 = cy.x * i1;
         const double mi3 = mi1 * i1 * i1;
         const double gx = -mi3 * Rx, gy = -mi3 * Ry, gz = -mi3 * Rz;
@@ -685,7 +685,7 @@ __global__ void __launch_bounds__(64) k_fmm(DevCtl* ctl, const int* __restrict__
                                  gz = G * (r[4 * s + 2] + fgz);
                     double ph = G * (r[4 * s + 3] + (fc - lin));
                     if (eps > 0.0) {  // take out the self pair's potential term (see eval_leaves)
-                        const double is = FP32C ? (double)__builtin_amdgcn_rsqf((float)e2) : rsq_nr(e2);
+                        const double is = FP32C ? (double)__builtin_amdgcn_rsqf((float)e2) : rsq_nr1(e2);
                         ph += G * (m[q] * is);
                     }
                     if (accumulate) {
