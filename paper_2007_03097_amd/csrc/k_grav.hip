@@ -160,20 +160,15 @@ __device__ void eval_cells(int ncell, const int* cells, GravStage& St, const dou
     }
 }
 
-// Leaves evaluated by softened particle sums (self excluded) for the lane's targets.  The
-// leaves' particles are concatenated and staged 64 at a time, so every staging round is
-// one load per lane.  With softening the self pair is evaluated like any other (it adds no
-// force) and its potential term -m_q/eps is taken out by the caller.  leaves[] is
-// overwritten with the leaves' first particles.
-template <bool FP32C>
-__device__ void eval_leaves(int nleaf, int* leaves, GravStage& St, const int4* __restrict__ topo,
-                            const double4* __restrict__ pos4, const double* __restrict__ m, const GravTargets& T,
-                            double e2, TargetSums& A, TargetSums& B) {
+// Particles of the listed leaves, concatenated and staged through LDS 64 at a time (one
+// load per lane per round); tile(tn) evaluates each staged tile of tn particles.  leaves[]
+// is overwritten with the leaves' first particles.
+template <typename Stage, typename Tile>
+__device__ void stage_leaves(int nleaf, int* leaves, Stage& St, const int4* __restrict__ topo,
+                             const double4* __restrict__ pos4, const double* __restrict__ m, Tile&& tile) {
     const int lane = lane_id();
-    const bool any = T.va || T.vb;
-    // ---- leaves: offsets of their particles, then the particles 64 at a time
     int carry = 0;
-    for (int j0 = 0; j0 < nleaf; j0 += 64) {
+    for (int j0 = 0; j0 < nleaf; j0 += 64) {  // particle offsets of the leaves
         const int j = j0 + lane;
         int c = 0, st = 0;
         if (j < nleaf) {
@@ -191,7 +186,6 @@ __device__ void eval_leaves(int nleaf, int* leaves, GravStage& St, const int4* _
     }
     __syncthreads();
     const int total = carry;
-    const bool soft = e2 > 0.0;
     for (int p0 = 0; p0 < total; p0 += 64) {
         const int p = p0 + lane;
         __syncthreads();
@@ -208,8 +202,21 @@ __device__ void eval_leaves(int nleaf, int* leaves, GravStage& St, const int4* _
             St.part.src[lane] = src;
         }
         __syncthreads();
-        const int tn = total - p0 < 64 ? total - p0 : 64;
-        if (!any) continue;
+        tile(total - p0 < 64 ? total - p0 : 64);
+    }
+}
+
+// Leaves evaluated by softened particle sums (self excluded) for the lane's two targets.
+// With softening the self pair is evaluated like any other (it adds no force) and its
+// potential term -m_q/eps is taken out by the caller.
+template <bool FP32C>
+__device__ void eval_leaves(int nleaf, int* leaves, GravStage& St, const int4* __restrict__ topo,
+                            const double4* __restrict__ pos4, const double* __restrict__ m, const GravTargets& T,
+                            double e2, TargetSums& A, TargetSums& B) {
+    const bool any = T.va || T.vb;
+    const bool soft = e2 > 0.0;
+    stage_leaves(nleaf, leaves, St, topo, pos4, m, [&](int tn) {
+        if (!any) return;
         if (soft) {
             for (int j = T.phi; j < tn; j += T.P) {
                 const double4 sb = St.part.pm[j];
@@ -228,7 +235,33 @@ __device__ void eval_leaves(int nleaf, int* leaves, GravStage& St, const int4* _
             A.flush_tile();
             B.flush_tile();
         }
-    }
+    });
+}
+
+// One target per lane: target t of c (lanes t + c ph, ph < P = 64 / c, split the staged
+// sources), for targets that fill a wave poorly (the particles of one octree leaf).
+struct LaneTarget {
+    double4 a;
+    int q;
+    bool v;
+    int ph, P;
+};
+
+template <bool FP32C, typename Stage>
+__device__ void eval_leaves1(int nleaf, int* leaves, Stage& St, const int4* __restrict__ topo,
+                             const double4* __restrict__ pos4, const double* __restrict__ m, const LaneTarget& T,
+                             double e2, TargetSums& A) {
+    const bool soft = e2 > 0.0;
+    stage_leaves(nleaf, leaves, St, topo, pos4, m, [&](int tn) {
+        if (!T.v) return;
+        if (soft) {
+            for (int j = T.ph; j < tn; j += T.P) part_term<FP32C>(T.a, St.part.pm[j], e2, A);
+        } else {
+            for (int j = T.ph; j < tn; j += T.P)
+                if (St.part.src[j] != T.q) part_term<FP32C>(T.a, St.part.pm[j], e2, A);
+        }
+        if (FP32C) A.flush_tile();
+    });
 }
 
 template <bool FP32C>
@@ -430,11 +463,19 @@ void launch_gravity(hipStream_t s, const DevPtrs& d, const Dims& dm, int fp32c, 
 // unaccepted leaf pairs go through eval_leaves.  The potential's linear part is referred
 // to the leaf's centre of mass.
 constexpr int FM_STACK = 512;
-constexpr int FM_TERMS = 512;
+constexpr int FM_TERMS = 256;
 constexpr int FM_LEAVES = 256;
-constexpr int FM_TARGETS = 128;   // targets per pass over a leaf (two per lane)
+constexpr int FM_TARGETS = 64;    // targets per pass over a leaf (one per lane)
 static_assert(7 * MAX_LEVEL <= FM_STACK, "the initial pairs of a path fit the stack");
-static_assert(FM_LEAVES <= GW_LEAVES, "leaf offsets live in GravStage");
+
+// LDS staging of the particle sums (the node-node walk has no cell tiles).
+struct FmmStage {
+    struct {
+        double4 pm[64];  // (x, y, z, m)
+        int src[64];     // particle index (self test without softening)
+    } part;
+    int loff[FM_LEAVES + 1];  // particle offsets of the staged leaves
+};
 
 struct FmmPath {
     double4 com[MAX_LEVEL + 1];  // (M, centre of mass) of the ancestor at each depth
@@ -519,7 +560,7 @@ __global__ void __launch_bounds__(64) k_fmm(DevCtl* ctl, const int* __restrict__
     __shared__ int tnode[FM_TERMS];
     __shared__ unsigned char tdep[FM_TERMS];
     __shared__ int leaves[FM_LEAVES];
-    __shared__ GravStage St;
+    __shared__ FmmStage St;
     __shared__ FmmPath Pth;
     const int lane = lane_id();
     const double e2 = eps * eps;
@@ -552,18 +593,12 @@ __global__ void __launch_bounds__(64) k_fmm(DevCtl* ctl, const int* __restrict__
         const double4 cl = Pth.com[D];
         for (int t0 = 0; t0 < tl.y; t0 += FM_TARGETS) {
             const int cc = min(FM_TARGETS, tl.y - t0);
-            GravTargets T;
-            T.TP = 1;
-            while (2 * T.TP < cc) T.TP <<= 1;
-            T.P = 64 / T.TP;
-            T.tp = lane & (T.TP - 1);
-            T.phi = lane / T.TP;
-            T.qa = tl.x + t0 + T.tp;
-            T.qb = T.qa + T.TP;
-            T.va = T.tp < cc;
-            T.vb = T.tp + T.TP < cc;
-            T.a = T.va ? pos4[T.qa] : make_double4(0, 0, 0, 0);
-            T.b = T.vb ? pos4[T.qb] : make_double4(0, 0, 0, 0);
+            LaneTarget T;
+            T.P = 64 / cc;
+            T.ph = lane / cc;
+            T.q = tl.x + t0 + (lane - T.ph * cc);
+            T.v = T.ph < T.P;
+            T.a = T.v ? pos4[T.q] : make_double4(0, 0, 0, 0);
             // initial pairs: (X_e+1, C) for every other child C of every ancestor X_e
             const int n0 = lane < D ? Pth.topo[lane].y - 1 : 0;
             const int incl = wave_incl_scan(n0);
@@ -583,7 +618,7 @@ __global__ void __launch_bounds__(64) k_fmm(DevCtl* ctl, const int* __restrict__
             }
             if (lane == 0) leaves[0] = L;  // the leaf's own particle pairs
             int nt = 0, nl = 1, iters = 0;
-            TargetSums A, B;
+            TargetSums A;
             double fgx = 0.0, fgy = 0.0, fgz = 0.0, fc = 0.0;
             __syncthreads();
             while (sp > 0) {
@@ -597,7 +632,7 @@ __global__ void __launch_bounds__(64) k_fmm(DevCtl* ctl, const int* __restrict__
                     __syncthreads();
                 }
                 if (nl + 64 > FM_LEAVES) {
-                    eval_leaves<FP32C>(nl, leaves, St, topo, pos4, m, T, e2, A, B);
+                    eval_leaves1<FP32C>(nl, leaves, St, topo, pos4, m, T, e2, A);
                     nl = 0;
                     __syncthreads();
                 }
@@ -659,32 +694,32 @@ __global__ void __launch_bounds__(64) k_fmm(DevCtl* ctl, const int* __restrict__
             }
             __syncthreads();
             fmm_eval_terms(nt, tnode, tdep, Pth, D, mom0, e2, fgx, fgy, fgz, fc);
-            eval_leaves<FP32C>(nl, leaves, St, topo, pos4, m, T, e2, A, B);
+            eval_leaves1<FP32C>(nl, leaves, St, topo, pos4, m, T, e2, A);
             fgx = lanes_sum_d(fgx, 1);
             fgy = lanes_sum_d(fgy, 1);
             fgz = lanes_sum_d(fgz, 1);
             fc = lanes_sum_d(fc, 1);
-            double r[8];
-            r[0] = FP32C ? A.kx.value() : A.gx;
-            r[1] = FP32C ? A.ky.value() : A.gy;
-            r[2] = FP32C ? A.kz.value() : A.gz;
-            r[3] = FP32C ? A.kp.value() : A.ph;
-            r[4] = FP32C ? B.kx.value() : B.gx;
-            r[5] = FP32C ? B.ky.value() : B.gy;
-            r[6] = FP32C ? B.kz.value() : B.gz;
-            r[7] = FP32C ? B.kp.value() : B.ph;
-#pragma unroll
-            for (int i = 0; i < 8; ++i) r[i] = lanes_sum_d(r[i], T.TP);
-            if (T.phi == 0) {
-                for (int s = 0; s < 2; ++s) {
-                    if (!(s ? T.vb : T.va)) continue;
-                    const int q = s ? T.qb : T.qa;
-                    const double4 me = s ? T.b : T.a;
+            // each target's P partial sums (lanes t + cc ph) combined in phase order
+            __syncthreads();
+            St.part.pm[lane] = FP32C ? make_double4(A.kx.value(), A.ky.value(), A.kz.value(), A.kp.value())
+                                     : make_double4(A.gx, A.gy, A.gz, A.ph);
+            __syncthreads();
+            if (T.v && T.ph == 0) {
+                double4 r = St.part.pm[lane];
+                for (int k = 1; k < T.P; ++k) {
+                    const double4 o = St.part.pm[lane + k * cc];
+                    r.x += o.x;
+                    r.y += o.y;
+                    r.z += o.z;
+                    r.w += o.w;
+                }
+                {
+                    const int q = T.q;
+                    const double4 me = T.a;
                     const double lin = fma(fgx, me.x - cl.y, fma(fgy, me.y - cl.z, fgz * (me.z - cl.w)));
-                    const double gx = G * (r[4 * s] + fgx), gy = G * (r[4 * s + 1] + fgy),
-                                 gz = G * (r[4 * s + 2] + fgz);
-                    double ph = G * (r[4 * s + 3] + (fc - lin));
-                    if (eps > 0.0) {  // take out the self pair's potential term (see eval_leaves)
+                    const double gx = G * (r.x + fgx), gy = G * (r.y + fgy), gz = G * (r.z + fgz);
+                    double ph = G * (r.w + (fc - lin));
+                    if (eps > 0.0) {  // take out the self pair's potential term (see eval_leaves1)
                         const double is = FP32C ? (double)__builtin_amdgcn_rsqf((float)e2) : rsq_nr1(e2);
                         ph += G * (m[q] * is);
                     }

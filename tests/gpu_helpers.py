@@ -83,10 +83,13 @@ def gpu_forces(ctx, n, thermo=None):
 
 
 def gpu_gravity(ctx, n):
+    """g and phi in caller order; sph_sync surfaces any device-side error (e.g. a walk list
+    overflow) as an exception instead of leaving partial sums."""
     import torch
     import paper_2007_03097_amd as sph
     out = [torch.zeros(max(n, 1), dtype=torch.float64, device="cuda") for _ in range(4)]
     sph.sph_compute_gravity(ctx.h, *out)
+    sph.sph_sync(ctx.h)
     torch.cuda.synchronize()
     return [to_np(o)[:n] for o in out]
 
