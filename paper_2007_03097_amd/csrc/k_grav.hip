@@ -15,9 +15,14 @@
 // the evaluation stages cell moments and leaf particles through LDS 64 at a time.
 #include "common.h"
 
-constexpr int GW_STACK = 512;
+constexpr int GW_STACK = 768;
 constexpr int GW_CELLS = 512;
 constexpr int GW_LEAVES = 256;
+// Stack headroom kept free of wide rounds: popping one entry at a time (depth first), the
+// stack grows by at most 7 per tree level below the popped node, so rounds of 64 entries
+// stop DFS_HEADROOM entries short of the top and single-entry rounds cannot overflow it.
+constexpr int DFS_HEADROOM = 7 * MAX_LEVEL + 8;
+static_assert(GW_STACK > 2 * DFS_HEADROOM, "room for wide rounds above the headroom");
 
 // LDS staging of one evaluation: cell moments in the cell phase, particles in the leaf phase.
 struct GravStage {
@@ -329,8 +334,10 @@ __global__ void __launch_bounds__(64) k_gravity(DevCtl* ctl, const int4* __restr
                 nc = nl = 0;
                 __syncthreads();
             }
+            // pop as many nodes as the stack can take the children of (8 each) while keeping
+            // the depth-first headroom; past it, one node per round
             int k = sp < 64 ? sp : 64;
-            const int room = (GW_STACK - sp) / 8;
+            const int room = (GW_STACK - DFS_HEADROOM - sp) / 8;
             if (k > room) k = room > 1 ? room : 1;
             const int node = lane < k ? stack[sp - k + lane] : -1;
             __syncthreads();
@@ -462,11 +469,11 @@ void launch_gravity(hipStream_t s, const DevPtrs& d, const Dims& dm, int fp32c, 
 // pairs at a time (one each) and sum the constant fields across the wave at the end;
 // unaccepted leaf pairs go through eval_leaves.  The potential's linear part is referred
 // to the leaf's centre of mass.
-constexpr int FM_STACK = 512;
-constexpr int FM_TERMS = 256;
-constexpr int FM_LEAVES = 256;
+constexpr int FM_STACK = 672;
+constexpr int FM_TERMS = 192;
+constexpr int FM_LEAVES = 192;
 constexpr int FM_TARGETS = 64;    // targets per pass over a leaf (one per lane)
-static_assert(7 * MAX_LEVEL <= FM_STACK, "the initial pairs of a path fit the stack");
+static_assert(7 * MAX_LEVEL + DFS_HEADROOM <= FM_STACK, "the initial pairs of a path and the headroom fit");
 
 // LDS staging of the particle sums (the node-node walk has no cell tiles).
 struct FmmStage {
@@ -636,8 +643,8 @@ __global__ void __launch_bounds__(64) k_fmm(DevCtl* ctl, const int* __restrict__
                     nl = 0;
                     __syncthreads();
                 }
-                int k = sp < 64 ? sp : 64;
-                const int room = (FM_STACK - sp) / 8;
+                int k = sp < 64 ? sp : 64;  // wide rounds only above the depth-first headroom
+                const int room = (FM_STACK - DFS_HEADROOM - sp) / 8;
                 if (k > room) k = room > 1 ? room : 1;
                 int Y = -1, e = 0;
                 if (lane < k) {
