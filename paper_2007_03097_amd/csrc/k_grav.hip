@@ -467,8 +467,9 @@ void launch_gravity(hipStream_t s, const DevPtrs& d, const Dims& dm, int fp32c, 
 // over Y's children.  Every node-node term of an ancestor is evaluated once per leaf below
 // it -- no scatter, no atomics, a fixed summation order.  The lanes evaluate 64 accepted
 // pairs at a time (one each) and sum the constant fields across the wave at the end;
-// unaccepted leaf pairs go through eval_leaves.  The potential's linear part is referred
-// to the leaf's centre of mass.
+// the particle pairs of unaccepted leaf pairs go through eval_leaves1, one target per lane
+// (a leaf fills a wave poorly; 64 / c lanes share each of its c targets).  The
+// potential's linear part is referred to the leaf's centre of mass.
 constexpr int FM_STACK = 672;
 constexpr int FM_TERMS = 192;
 constexpr int FM_LEAVES = 192;
