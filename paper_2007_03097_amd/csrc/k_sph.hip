@@ -19,9 +19,11 @@
 // contraction (each target has its own irregular list), so they run on the vector ALUs,
 // not on the matrix cores.
 //
-// FP32C: the position difference is formed in FP64 and rounded to FP32; everything else
-// of the pair term is FP32, summed per thread with Kahan (density) or Neumaier (forces)
-// compensation; the partial sums combine in FP64 and results are stored in FP64.
+// FP32C: positions enter as FP32 offsets from the group's first particle (each offset
+// formed in FP64, then rounded), so a pair's difference is one FP32 subtraction of two
+// nearby offsets; everything else of the pair term is FP32, summed per thread with Kahan
+// (density) or Neumaier (forces) compensation; the partial sums combine in FP64 and
+// results are stored in FP64.
 #include "common.h"
 
 // rho, P, c given by the caller (caller order) -> key-ordered thermo records
@@ -70,14 +72,49 @@ struct DensAcc<false> {
 template <>
 struct DensAcc<true> {
     Kahan k;
-    __device__ __forceinline__ void add(const double4 me, const double4 b, double mb) {
-        const float dx = (float)(me.x - b.x), dy = (float)(me.y - b.y), dz = (float)(me.z - b.z);
+    // me, b: (x, y, z offsets from the group origin, h) in FP32
+    __device__ __forceinline__ void add(const float4 me, const float4 b, float mb) {
+        const float dx = me.x - b.x, dy = me.y - b.y, dz = me.z - b.z;
         const float r = __builtin_amdgcn_sqrtf(fmaf(dx, dx, fmaf(dy, dy, dz * dz)));
-        const float ih = __builtin_amdgcn_rcpf(0.5f * ((float)me.w + (float)b.w));
-        k.add((float)mb * m4_wf(r * ih) * (ih * ih * ih));
+        const float ih = __builtin_amdgcn_rcpf(0.5f * (me.w + b.w));
+        k.add(mb * m4_wf(r * ih) * (ih * ih * ih));
     }
     __device__ __forceinline__ double value() const { return k.value(); }
 };
+
+// FP32 offset record of a position from the group origin o: (x - o, y - o, z - o, h).
+__device__ __forceinline__ float4 offset_rec(const double4 p, const double4 o) {
+    return make_float4((float)(p.x - o.x), (float)(p.y - o.y), (float)(p.z - o.z), (float)p.w);
+}
+
+// Density sources staged in LDS: FP64 (x, y, z, h) and m, or FP32 offset records and m.
+template <bool FP32C>
+struct DensSrc;
+template <>
+struct DensSrc<false> {
+    double4 pos[DENS_CHUNK];
+    double mass[DENS_CHUNK];
+    using Rec = double4;
+    using Mass = double;
+    __device__ __forceinline__ void put(int i, const double4 p, double mb, const double4&) {
+        pos[i] = p;
+        mass[i] = mb;
+    }
+    __device__ __forceinline__ static double4 target(const double4 p, const double4&) { return p; }
+};
+template <>
+struct DensSrc<true> {
+    float4 pos[DENS_CHUNK];
+    float mass[DENS_CHUNK];
+    using Rec = float4;
+    using Mass = float;
+    __device__ __forceinline__ void put(int i, const double4 p, double mb, const double4& o) {
+        pos[i] = offset_rec(p, o);
+        mass[i] = (float)mb;
+    }
+    __device__ __forceinline__ static float4 target(const double4 p, const double4& o) { return offset_rec(p, o); }
+};
+static_assert(sizeof(DensSrc<true>) >= PAIR_THREADS * sizeof(double), "the reduction reuses the staging");
 
 template <bool FP32C>
 __global__ void __launch_bounds__(PAIR_THREADS) k_density(
@@ -87,8 +124,7 @@ __global__ void __launch_bounds__(PAIR_THREADS) k_density(
     const double* __restrict__ u_eos, int kin, double gamma, double h_coeff, double* __restrict__ rho,
     double* __restrict__ P, double* __restrict__ cs, double* __restrict__ hnext, double4* __restrict__ thr4,
     float4* __restrict__ thrf) {
-    __shared__ double4 spos[DENS_CHUNK];
-    __shared__ double smass[DENS_CHUNK];
+    __shared__ DensSrc<FP32C> S;
     const int tid = threadIdx.x;
     const int t = tid & (gsz - 1), phi = tid / gsz, PL = PAIR_THREADS / gsz;
     int g0, g1, gstep;
@@ -97,7 +133,9 @@ __global__ void __launch_bounds__(PAIR_THREADS) k_density(
         const int4 g = group[gi];
         const bool tv = t < g.y;
         const int q = g.x + t;
-        const double4 me = tv ? pos4[q] : make_double4(0, 0, 0, 1);
+        const double4 org = pos4[g.x];  // group origin (FP32C offsets)
+        const double4 mp = tv ? pos4[q] : make_double4(org.x, org.y, org.z, 1);
+        const typename DensSrc<FP32C>::Rec me = DensSrc<FP32C>::target(mp, org);
         const int cnt = tv ? nbr_cnt[q] : 0;
         const int* lst = nbr + (size_t)g.x * cap + t;
         const int* un = uni + (size_t)g.x * cap;
@@ -105,26 +143,31 @@ __global__ void __launch_bounds__(PAIR_THREADS) k_density(
         DensAcc<FP32C> acc;
         int k = phi;
         int e = k < cnt ? lst[k * g.y] : INT_MAX;
+        int e1 = k + PL < cnt ? lst[(k + PL) * g.y] : INT_MAX;
+        int e2 = k + 2 * PL < cnt ? lst[(k + 2 * PL) * g.y] : INT_MAX;
+        int e3 = k + 3 * PL < cnt ? lst[(k + 3 * PL) * g.y] : INT_MAX;
         for (int c0 = 0; c0 < nu; c0 += DENS_CHUNK) {
             const int cn = nu - c0 < DENS_CHUNK ? nu - c0 : DENS_CHUNK;
             __syncthreads();
             for (int i = tid; i < cn; i += PAIR_THREADS) {
                 const int b = un[c0 + i];
-                spos[i] = pos4[b];
-                smass[i] = m[b];
+                S.put(i, pos4[b], m[b], org);
             }
             __syncthreads();
             const int ce = c0 + cn;
             while (e < ce) {
-                const int kn = k + PL;
+                const int kn = k + 4 * PL;
                 const int en = kn < cnt ? lst[kn * g.y] : INT_MAX;
-                acc.add(me, spos[e - c0], smass[e - c0]);
-                k = kn;
-                e = en;
+                acc.add(me, S.pos[e - c0], S.mass[e - c0]);
+                k += PL;
+                e = e1;
+                e1 = e2;
+                e2 = e3;
+                e3 = en;
             }
         }
         __syncthreads();
-        double* red = reinterpret_cast<double*>(spos);
+        double* red = reinterpret_cast<double*>(S.pos);
         red[tid] = acc.value();
         __syncthreads();
         if (tv && phi == 0) {
@@ -132,6 +175,7 @@ __global__ void __launch_bounds__(PAIR_THREADS) k_density(
             for (int f = 1; f < PL; ++f) sum += red[t + gsz * f];
             const double r_ = sum * M_1_PI_D;
             double ue = u_eos[q];
+            const double4 mpos = mp;
             if (kin) {  // u_eos holds the total energy e = u + v^2/2 (thermokinetic form)
                 const double4 v = vel4[q];
                 ue -= 0.5 * (v.x * v.x + v.y * v.y + v.z * v.z);
@@ -144,7 +188,7 @@ __global__ void __launch_bounds__(PAIR_THREADS) k_density(
             cs[q] = c_;
             hnext[q] = h_coeff * cbrt(m[q] / r_);
             thr4[q] = make_double4(r_, pr2, c_, ue);
-            thrf[q] = make_float4((float)r_, (float)pr2, (float)c_, (float)me.w);
+            thrf[q] = make_float4((float)r_, (float)pr2, (float)c_, (float)mpos.w);
         }
     }
 }
@@ -174,10 +218,11 @@ struct ForceSrc<false> {
 };
 template <>
 struct ForceSrc<true> {
-    double4 pos[FORCE_CHUNK];
+    float4 pos[FORCE_CHUNK];  // offsets from the group origin, h
     float4 vel[FORCE_CHUNK];
     float4 thr[FORCE_CHUNK];
 };
+static_assert(sizeof(ForceSrc<true>) >= 4 * PAIR_THREADS * sizeof(double), "the reduction reuses the staging");
 
 template <bool FP32C, bool THERMO>
 __global__ void __launch_bounds__(PAIR_THREADS) k_forces(
@@ -212,7 +257,7 @@ __global__ void __launch_bounds__(PAIR_THREADS) k_forces(
                 __syncthreads();
                 for (int i = tid; i < cn; i += PAIR_THREADS) {
                     const int b = un[c0 + i];
-                    S.pos[i] = pos4[b];
+                    reinterpret_cast<double4*>(S.pos)[i] = pos4[b];
                     reinterpret_cast<double4*>(S.vel)[i] = vel4[b];
                     reinterpret_cast<double4*>(S.thr)[i] = thr4[b];
                 }
@@ -222,7 +267,7 @@ __global__ void __launch_bounds__(PAIR_THREADS) k_forces(
                     const int kn = k + PL;
                     const int en = kn < cnt ? lst[kn * g.y] : INT_MAX;
                     const int j = e - c0;
-                    const double4 sb = S.pos[j];
+                    const double4 sb = reinterpret_cast<const double4*>(S.pos)[j];
                     const double4 vb = reinterpret_cast<const double4*>(S.vel)[j];
                     const double4 tb = reinterpret_cast<const double4*>(S.thr)[j];
                     const double dx = me.x - sb.x, dy = me.y - sb.y, dz = me.z - sb.z;
@@ -263,6 +308,8 @@ __global__ void __launch_bounds__(PAIR_THREADS) k_forces(
         } else {
             const float4 mv = tv ? velf[q] : make_float4(0, 0, 0, 0);
             const float4 mt = tv ? thrf[q] : make_float4(1, 0, 0, 1);
+            const double4 org = pos4[g.x];  // group origin
+            const float4 mef = offset_rec(tv ? me : org, org);
             const float alf = (float)alpha, bef = (float)beta, epf = (float)eps_av;
             const float ipi = (float)M_1_PI_D;
             Neumaier sx, sy, sz, su;
@@ -271,7 +318,7 @@ __global__ void __launch_bounds__(PAIR_THREADS) k_forces(
                 __syncthreads();
                 for (int i = tid; i < cn; i += PAIR_THREADS) {
                     const int b = un[c0 + i];
-                    S.pos[i] = pos4[b];
+                    reinterpret_cast<float4*>(S.pos)[i] = offset_rec(pos4[b], org);
                     reinterpret_cast<float4*>(S.vel)[i] = velf[b];
                     reinterpret_cast<float4*>(S.thr)[i] = thrf[b];
                 }
@@ -281,10 +328,10 @@ __global__ void __launch_bounds__(PAIR_THREADS) k_forces(
                     const int kn = k + PL;
                     const int en = kn < cnt ? lst[kn * g.y] : INT_MAX;
                     const int j = e - c0;
-                    const double4 sb = S.pos[j];
+                    const float4 sb = reinterpret_cast<const float4*>(S.pos)[j];
                     const float4 vb = reinterpret_cast<const float4*>(S.vel)[j];
                     const float4 tb = reinterpret_cast<const float4*>(S.thr)[j];
-                    const float dx = (float)(me.x - sb.x), dy = (float)(me.y - sb.y), dz = (float)(me.z - sb.z);
+                    const float dx = mef.x - sb.x, dy = mef.y - sb.y, dz = mef.z - sb.z;
                     const float r2 = fmaf(dx, dx, fmaf(dy, dy, dz * dz));
                     const float r = __builtin_amdgcn_sqrtf(r2);
                     const float hab = 0.5f * (mt.w + tb.w);
