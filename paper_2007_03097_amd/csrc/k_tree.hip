@@ -51,10 +51,12 @@ __device__ __forceinline__ int window_level(const signed char* c, int ci, int wi
 }
 
 // Per sorted position: lcp, leaf level (leaf capacity win) and the node / leaf-start counts
-// for the pre-order scan.  The leaf level is at most max(lcp[i], lcp[i+1]) + 1 (the cell
-// holding i alone), which bounds the binary search.
+// for the pre-order scan.  Also clears the per-level node counters (block 0) and the
+// group-cell flags of every position, which later kernels of the build fill in.
 __global__ void __launch_bounds__(TB) k_leaf_levels(const u64* __restrict__ key, int n, int win, int min_level,
-                                                    signed char* lcp, unsigned char* lvl, u64* scan_in) {
+                                                    signed char* lcp, unsigned char* lvl, u64* scan_in, DevCtl* ctl,
+                                                    u32* gflag) {
+    if (blockIdx.x == 0 && threadIdx.x < 24) ctl->level_count[threadIdx.x] = 0;
     __shared__ signed char c[TB + 2 * MAX_WIN + 2];
     __shared__ signed char mrow[TB * MAX_WIN];
     const int b0 = blockIdx.x * TB;
@@ -77,7 +79,11 @@ __global__ void __launch_bounds__(TB) k_leaf_levels(const u64* __restrict__ key,
     lcp[i] = (signed char)cc;
     lvl[i] = (unsigned char)L;
     scan_in[i] = ((u64)nodes << 32) | (u64)(nodes > 0 ? 1u : 0u);
-    if (i == n - 1) lcp[n] = -1;
+    gflag[i] = 0u;
+    if (i == n - 1) {
+        lcp[n] = -1;
+        gflag[n] = 0u;
+    }
 }
 
 // Group cells: the largest nodes holding at most gcap particles (at or below min_level),
@@ -186,19 +192,6 @@ __global__ void __launch_bounds__(256) k_emit_nodes(int n, const signed char* __
     if (threadIdx.x < 24 && hist[threadIdx.x]) atomicAdd(&ctl->level_count[threadIdx.x], hist[threadIdx.x]);
 }
 
-__global__ void k_tree_reset(DevCtl* ctl) {
-    if (threadIdx.x < 24) ctl->level_count[threadIdx.x] = 0;
-}
-
-__global__ void k_level_offsets(DevCtl* ctl) {
-    if (threadIdx.x == 0) {
-        int acc = 0;
-        for (int l = 0; l < 24; ++l) {
-            ctl->level_off[l] = acc;
-            acc += ctl->level_count[l];
-        }
-    }
-}
 
 // Stable counting sort of pre-order nodes by level (2048-node tiles, 5-bit digit).
 constexpr int LS_THREADS = 256, LS_ITEMS = 8, LS_TILE = LS_THREADS * LS_ITEMS, LS_WAVES = LS_THREADS / 64;
@@ -221,12 +214,16 @@ __global__ void __launch_bounds__(LS_THREADS) k_lsort_hist(const DevCtl* __restr
     }
 }
 
-// One wave per level: exclusive scan of that level's tile counts, offset by level_off.
-__global__ void __launch_bounds__(64) k_lsort_scan(const DevCtl* __restrict__ ctl, int* hist) {
+// One wave per level (24): the level's first breadth-first index (level_off, the prefix of
+// the level counts; written here for every later kernel), then the exclusive scan of that
+// level's tile counts offset by it.
+__global__ void __launch_bounds__(64) k_lsort_scan(DevCtl* ctl, int* hist) {
     const int l = blockIdx.x;
     const int nn = ctl->n_nodes;
     const int ntiles = (nn + LS_TILE - 1) / LS_TILE;
-    int carry = ctl->level_off[l];
+    int carry = 0;
+    for (int k = 0; k < l; ++k) carry += ctl->level_count[k];
+    if (lane_id() == 0) ctl->level_off[l] = carry;
     for (int t0 = 0; t0 < ntiles; t0 += 64) {
         const int t = t0 + lane_id();
         const int v = t < ntiles ? hist[t * 24 + l] : 0;
@@ -482,16 +479,14 @@ static int grid_cap(int n, int bs, int cap) {
 void build_octree(hipStream_t s, const DevPtrs& d, const Dims& dm) {
     const int n = dm.n;
     if (n <= 0) return;
-    hipLaunchKernelGGL(k_tree_reset, dim3(1), dim3(64), 0, s, d.ctl);
     hipLaunchKernelGGL(k_leaf_levels, dim3((n + TB - 1) / TB), dim3(TB), 0, s, d.key_a, n, dm.leaf_size, dm.min_level,
-                       d.lcp, d.lvl, d.scan_in);
+                       d.lcp, d.lvl, d.scan_in, d.ctl, d.gflag);
     scan_u64(s, d.scan_in, d.scan_out, n, d.scan_tmp);
     hipLaunchKernelGGL(k_emit_nodes, dim3(grid_cap(n, 256, 512)), dim3(256), 0, s, n, d.lcp, d.lvl, d.scan_out,
                        d.pre_level, d.pre_leaf, d.pre_start, d.leaf_start, d.leaf_pre, d.ctl, dm.node_cap);
-    hipLaunchKernelGGL(k_level_offsets, dim3(1), dim3(64), 0, s, d.ctl);
     const int tiles_cap = grid_cap(dm.node_cap, LS_TILE, 1024);
     hipLaunchKernelGGL(k_lsort_hist, dim3(tiles_cap), dim3(LS_THREADS), 0, s, d.ctl, d.pre_level, d.lsort_hist);
-    hipLaunchKernelGGL(k_lsort_scan, dim3(22), dim3(64), 0, s, d.ctl, d.lsort_hist);
+    hipLaunchKernelGGL(k_lsort_scan, dim3(24), dim3(64), 0, s, d.ctl, d.lsort_hist);
     hipLaunchKernelGGL(k_lsort_scatter, dim3(tiles_cap), dim3(LS_THREADS), 0, s, d.ctl, d.pre_level, d.lsort_hist,
                        d.pre_to_bfs, d.bfs_to_pre);
     const int g = grid_cap(dm.node_cap, 256, 2048);
@@ -507,7 +502,6 @@ void build_octree(hipStream_t s, const DevPtrs& d, const Dims& dm) {
     hipLaunchKernelGGL(k_top_moments, dim3(1), dim3(1024), 0, s, A);
     // target groups: cells of at most 4 * group_size particles, cut into runs of group_size
     const int gcap = 4 * dm.group_size;
-    launch_fill_u32(s, d.gflag, 0u, n + 1);
     hipLaunchKernelGGL(k_gcell_flags, dim3(g), dim3(256), 0, s, d.ctl, gcap, dm.min_level, d.topo, d.parent, d.range,
                        d.gflag);
     scan_u32_total(s, d.gflag, d.gscan, n, d.scan_tmp);
