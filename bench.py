@@ -321,9 +321,29 @@ def cpu_baseline(ps, reps=10):
         oracle.forces(sub.fields(), rho, P, c, csr)
         best = min(best, time.perf_counter() - t0)
     cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    # direct-sum gravity on 1,024 sampled targets of a 262,144-particle n = 1 polytrope
+    from workloads import lattice_box, polytrope_n1
+    pp = polytrope_n1(262144, seed=1003)
+    tg = np.sort(np.random.default_rng(3).choice(pp.n, 1024, replace=False))
+    t0 = time.perf_counter()
+    oracle.gravity_direct(pp.x, pp.y, pp.z, pp.m, 1.0, 0.01, targets=tg)
+    t_grav = time.perf_counter() - t0
+    # whole KDK steps of the 4,096-particle jittered lattice (brute-force neighbours each step)
+    lb = lattice_box(16)
+    prm = oracle.Params()
+    st = oracle.prime(lb.fields(), prm)
+    t0 = time.perf_counter()
+    for _ in range(3):
+        st = oracle.kdk_step(st, 0.0178, prm)
+    t_steps = time.perf_counter() - t0
     return dict(value=pairs / best, unit="pair interactions/s", cores=cores, kind="oracle",
                 sample=f"slab 0.42<x<0.58 of the tube: {sub.n} particles, {pairs} density+force pairs; "
-                       f"best of {reps}: {best:.3f} s; brute-force neighbour search {t_nbr:.1f} s not counted")
+                       f"best of {reps}: {best:.3f} s; brute-force neighbour search {t_nbr:.1f} s not counted",
+                neighbor_search_s=t_nbr,
+                gravity_direct={"value": tg.size * (pp.n - 1) / t_grav, "unit": "particle-particle interactions/s",
+                                "sample": f"1,024 targets of a 262,144-particle polytrope, {t_grav:.2f} s"},
+                steps_per_s_lattice_4096={"value": 3 / t_steps, "unit": "steps/s",
+                                          "sample": f"3 KDK steps of the 4,096-particle lattice, {t_steps:.2f} s"})
 
 
 def main():
