@@ -239,8 +239,16 @@ def _two_clusters():
     return ps
 
 
+def _coincident_block():
+    """150 particles at one point (one level-21 leaf of more than 64 targets) among others."""
+    ps = uniform_random(650, seed=15, h=0.05)
+    ps.x[:150] = 0.3; ps.y[:150] = 0.6; ps.z[:150] = 0.45
+    return ps
+
+
 FMM_CASES = {
     "polytrope": lambda: polytrope_n1(12000, seed=41),
+    "coincident150": _coincident_block,
     "clustered": _clustered,
     "duplicates": _dup_set,
     "random_varh": lambda: uniform_random(3333, seed=4, h=(0.02, 0.08)),
@@ -270,7 +278,8 @@ def _fmm_oracle(orc, ps, k, o, leaf, theta, G, eps):
                                                  ("polytrope", 0.5, 64, 0.01), ("clustered", 0.5, 12, 0.01),
                                                  ("duplicates", 0.7, 16, 0.01), ("random_varh", 0.5, 16, 0.0),
                                                  ("two_clusters", 0.5, 8, 0.003), ("n1", 0.5, 16, 0.01),
-                                                 ("n2", 0.5, 16, 0.0)])
+                                                 ("n2", 0.5, 16, 0.0), ("coincident150", 0.5, 8, 0.01),
+                                                 ("polytrope", 0.6, 1, 0.01)])
 def test_fmm_matches_oracle(orc, case, theta, leaf, eps):
     """The GPU's per-leaf replay of the node-pair recursion against the oracle's mutual
     recursion (Sec. 2.2.2, eq. (10)): the opening decisions are exact integer tests, so the
