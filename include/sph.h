@@ -126,7 +126,9 @@ typedef struct {
 void sph_config_default(sph_config* cfg);
 
 /* Creates a context for up to n_capacity particles in up to seg_capacity segments
- * (1..512).  Validates cfg (SPH_E_ARG).  Allocates host memory only. */
+ * (1..512).  Validates cfg (SPH_E_ARG).  n_capacity must keep the octree's node capacity
+ * (about 4.4 n_capacity) within 32-bit indices, i.e. n_capacity <= ~4.9e8 (SPH_E_ARG
+ * otherwise).  Allocates host memory only. */
 sph_status sph_create(const sph_config* cfg, int64_t n_capacity, int32_t seg_capacity, sph_ctx** out);
 
 /* Destroys the context (synchronises its stream, frees the HIP graph). NULL is a no-op. */

@@ -382,6 +382,10 @@ sph_status sph_create(const sph_config* cfg, int64_t n_capacity, int32_t seg_cap
     c->seg_cap = seg_capacity;
     c->leaf_size = cfg->leaf_size ? cfg->leaf_size : 16;
     c->leaf_min = std::min(c->leaf_size, 8);
+    if (node_cap_for(std::max<int64_t>(n_capacity, 1), c->leaf_min) >= (int64_t)INT32_MAX) {
+        delete c;  // node indices are 32-bit
+        return SPH_E_ARG;
+    }
     c->group_size = cfg->group_size ? cfg->group_size : 32;
     c->nbr_cap = cfg->nbr_capacity ? cfg->nbr_capacity : 160;
     c->stream = (hipStream_t)cfg->stream;

@@ -50,6 +50,11 @@ def test_host_validation_without_gpu():
         sph.sph_create(cfg, -1, 1)
     with pytest.raises(sph.SPHError):
         sph.sph_create(cfg, 10, 513)
+    with pytest.raises(sph.SPHError):  # the octree's node indices would overflow 32 bits
+        sph.sph_create(cfg, 600_000_000, 1)
+    for bad in (dict(gravity_scheme=2), dict(key_curve=5), dict(energy_form=-1)):
+        with pytest.raises(sph.SPHError):
+            sph.sph_create(sph.sph_config_default(**bad), 10, 1)
     lib = _abi.load()
     # calls on a context without workspace fail with SPH_E_NOMEM / SPH_E_STATE, no GPU touched
     h = sph.sph_create(cfg, 10, 1)
