@@ -408,23 +408,26 @@ __device__ __forceinline__ void node_moments(const MomArgs& A, int b) {
         aggregate_node(b, tp, A.nbox_lo, A.nbox_hi, A.mom0, A.mom1, A.mom2, A.range, side);
 }
 
-// Every node at level >= CUT_LEVEL: one wavefront per level-CUT_LEVEL cell finishes its
-// whole subtree bottom-up.  A subtree's nodes at each level are one contiguous run in
-// breadth-first order (from the first child of its first internal node to the last child
-// of its last internal node), so the runs are found top-down, then the levels are done
-// deepest first with the wavefront's own results as inputs.
-constexpr int CUT_LEVEL = 6;
-__global__ void __launch_bounds__(64) k_subtree_moments(MomArgs A) {
+// Every node at level >= cut: one wavefront per level-cut cell finishes its whole subtree
+// bottom-up.  A subtree's nodes at each level are one contiguous run in breadth-first
+// order (from the first child of its first internal node to the last child of its last
+// internal node), so the runs are found top-down, then the levels are done deepest first
+// with the wavefront's own results as inputs.  The levels between the cut and the top
+// block go one launch each; large sets cut deeper, so that centrally concentrated ones do
+// not leave a few waves with very deep subtrees.
+constexpr int TOP_LEVELS = 5;
+static int subtree_cut(int n) { return n >= (1 << 21) ? 8 : 6; }
+__global__ void __launch_bounds__(64) k_subtree_moments(MomArgs A, int cut) {
     __shared__ int run_lo[MAX_LEVEL + 1], run_hi[MAX_LEVEL + 1];
     const int lane = lane_id();
-    const int nroot = A.ctl->level_count[CUT_LEVEL], r0 = A.ctl->level_off[CUT_LEVEL];
+    const int nroot = A.ctl->level_count[cut], r0 = A.ctl->level_off[cut];
     for (int ri = blockIdx.x; ri < nroot; ri += gridDim.x) {
-        int lo = r0 + ri, hi = lo, deep = CUT_LEVEL;
+        int lo = r0 + ri, hi = lo, deep = cut;
         if (lane == 0) {
-            run_lo[CUT_LEVEL] = lo;
-            run_hi[CUT_LEVEL] = hi;
+            run_lo[cut] = lo;
+            run_hi[cut] = hi;
         }
-        for (int l = CUT_LEVEL; l < MAX_LEVEL; ++l) {
+        for (int l = cut; l < MAX_LEVEL; ++l) {
             int first = -1, last = -1;
             for (int k0 = lo; k0 <= hi && first < 0; k0 += 64) {  // first internal node
                 const int k = k0 + lane;
@@ -447,7 +450,7 @@ __global__ void __launch_bounds__(64) k_subtree_moments(MomArgs A) {
             }
         }
         __syncthreads();
-        for (int l = deep; l >= CUT_LEVEL; --l) {
+        for (int l = deep; l >= cut; --l) {
             const int a = run_lo[l], e = run_hi[l];
             for (int k = a + lane; k <= e; k += 64) node_moments(A, k);
             __syncthreads();
@@ -462,7 +465,6 @@ __global__ void __launch_bounds__(256) k_level_moments(MomArgs A, int level) {
 }
 
 // Levels TOP_LEVELS - 1 .. 0 in one workgroup, a barrier between levels (their nodes are few).
-constexpr int TOP_LEVELS = 5;
 __global__ void __launch_bounds__(1024) k_top_moments(MomArgs A) {
     for (int level = TOP_LEVELS - 1; level >= 0; --level) {
         const int b0 = A.ctl->level_off[level], nb = A.ctl->level_count[level];
@@ -493,12 +495,13 @@ void build_octree(hipStream_t s, const DevPtrs& d, const Dims& dm) {
     hipLaunchKernelGGL(k_finalize, dim3(g), dim3(256), 0, s, d.ctl, d.pre_level, d.pre_leaf, d.pre_start,
                        d.pre_to_bfs, d.bfs_to_pre, d.lcp, d.scan_out, d.leaf_start, d.topo, d.parent, d.counter,
                        d.range);
-    // moments: subtrees below CUT_LEVEL, then the levels between, then the top levels
-    static_assert(CUT_LEVEL == TOP_LEVELS + 1, "one wide level between the top block and the subtrees");
+    // moments: subtrees below the cut, then the levels between, then the top levels
+    const int cut = subtree_cut(n);
     const MomArgs A{d.ctl, dm.batched, d.key_a, d.topo, d.pos4, d.m, d.nbox_lo, d.nbox_hi, d.mom0, d.mom1, d.mom2,
                     d.range};
-    hipLaunchKernelGGL(k_subtree_moments, dim3(grid_cap(n, 64, 8192)), dim3(64), 0, s, A);
-    hipLaunchKernelGGL(k_level_moments, dim3(grid_cap(n / 2 + 1, 256, 256)), dim3(256), 0, s, A, TOP_LEVELS);
+    hipLaunchKernelGGL(k_subtree_moments, dim3(grid_cap(n, 64, 8192)), dim3(64), 0, s, A, cut);
+    for (int lv = cut - 1; lv >= TOP_LEVELS; --lv)
+        hipLaunchKernelGGL(k_level_moments, dim3(grid_cap(n / 2 + 1, 256, 256)), dim3(256), 0, s, A, lv);
     hipLaunchKernelGGL(k_top_moments, dim3(1), dim3(1024), 0, s, A);
     // target groups: cells of at most 4 * group_size particles, cut into runs of group_size
     const int gcap = 4 * dm.group_size;
