@@ -416,7 +416,7 @@ __device__ __forceinline__ void node_moments(const MomArgs& A, int b) {
 // block go one launch each; large sets cut deeper, so that centrally concentrated ones do
 // not leave a few waves with very deep subtrees.
 constexpr int TOP_LEVELS = 5;
-static int subtree_cut(int n) { return n >= (1 << 21) ? 8 : 6; }
+static int subtree_cut(int n) { return n >= (1 << 21) ? 9 : 6; }
 __global__ void __launch_bounds__(64) k_subtree_moments(MomArgs A, int cut) {
     __shared__ int run_lo[MAX_LEVEL + 1], run_hi[MAX_LEVEL + 1];
     const int lane = lane_id();
