@@ -123,7 +123,6 @@ static size_t layout(const sph_ctx* c, char* base, DevPtrs* out) {
     for (double** p : f1) *p = cv.take<double>(N);
     d.id = cv.take<u32>(N);
     d.id2 = cv.take<u32>(N);
-    d.inv = cv.take<u32>(N);
     d.pos4 = cv.take<double4>(N);
     d.vel4 = cv.take<double4>(N);
     d.thr4 = cv.take<double4>(N);

@@ -58,7 +58,6 @@ struct DevPtrs {
     double *x2, *y2, *z2, *vx2, *vy2, *vz2, *m2, *h2, *u2, *vpx2, *vpy2, *vpz2, *up2;
     u32* id;                      // caller index of each Morton position
     u32* id2;
-    u32* inv;                     // caller index -> Morton position of the previous order
     double4* pos4;                // x, y, z, h (Morton order)
     double4* vel4;                // vx(pred), vy, vz, m
     double4* thr4;                // rho, P/rho^2, c, u

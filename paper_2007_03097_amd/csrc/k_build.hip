@@ -188,7 +188,7 @@ __global__ void __launch_bounds__(256) k_step_keys(DevCtl* ctl, const int4* chun
                                                     const double* __restrict__ z, const double* __restrict__ vx,
                                                     const double* __restrict__ vy, const double* __restrict__ vz,
                                                     const double* __restrict__ u, const u32* __restrict__ id,
-                                                    u64* key, u32* val, u32* inv) {
+                                                    u64* key, u32* val) {
     const int4 ch = chunk[blockIdx.x];
     // the segment's box from the merged encodings, L and S = 2^B / L (one IEEE division);
     // the segment's first chunk publishes them for the tree build
@@ -214,10 +214,9 @@ __global__ void __launch_bounds__(256) k_step_keys(DevCtl* ctl, const int4* chun
         if (!isfinite(px) || !isfinite(py) || !isfinite(pz) || !isfinite(vx[p]) || !isfinite(vy[p]) ||
             !isfinite(vz[p]) || !isfinite(u[p]))
             bad |= ERR_NONFINITE;
-        const u32 i = id[p];
+        const u32 i = id[p];  // keys go to caller order, so the stable sort orders ties by ID
         key[i] = make_key(px, py, pz, box, S, ch.z, batched, curve);
-        val[i] = i;
-        inv[i] = (u32)p;
+        val[i] = (u32)p;      // the sort carries each particle's current position
     }
     if (bad) set_err(ctl, bad);
 }
@@ -225,7 +224,7 @@ __global__ void __launch_bounds__(256) k_step_keys(DevCtl* ctl, const int4* chun
 void launch_step_keys(hipStream_t s, const DevPtrs& d, const Dims& dm) {
     if (dm.n_chunks > 0)
         hipLaunchKernelGGL(k_step_keys, dim3(dm.n_chunks), dim3(256), 0, s, d.ctl, d.chunk, dm.batched, dm.curve, d.x, d.y,
-                           d.z, d.vx, d.vy, d.vz, d.u, d.id, d.key_a, d.val_a, d.inv);
+                           d.z, d.vx, d.vy, d.vz, d.u, d.id, d.key_a, d.val_a);
 }
 
 // ---------------------------------------------------------------------------------------

@@ -56,14 +56,14 @@ void launch_kick_drift(hipStream_t s, const DevPtrs& d, const Dims& dm, double d
                            d.vy, d.vz, d.u, d.ax, d.ay, d.az, d.du, d.vpx, d.vpy, d.vpz, d.up);
 }
 
-// New key order: q <- old position inv[val[q]]; the second buffer set receives the data,
-// and the pair kernels' records pos4 = (x, h), vel4 = (predicted v, m) are written too.
-__global__ void k_step_permute(int n, const u32* __restrict__ val, const u32* __restrict__ inv, DevPtrs d) {
+// New key order: q <- old position val[q] (the sort carried the positions); the second
+// buffer set receives the data, and the pair kernels' records pos4 = (x, h),
+// vel4 = (predicted v, m) are written too.
+__global__ void k_step_permute(int n, const u32* __restrict__ val, DevPtrs d) {
     const int q = blockIdx.x * blockDim.x + threadIdx.x;
     if (q >= n) return;
-    const u32 i = val[q];
-    const u32 p = inv[i];
-    d.id2[q] = i;
+    const u32 p = val[q];
+    d.id2[q] = d.id[p];
     const double px = d.x[p], py = d.y[p], pz = d.z[p], hh = d.h[p], mm = d.m[p];
     const double wx = d.vpx[p], wy = d.vpy[p], wz = d.vpz[p];
     d.x2[q] = px; d.y2[q] = py; d.z2[q] = pz;
@@ -75,7 +75,7 @@ __global__ void k_step_permute(int n, const u32* __restrict__ val, const u32* __
     d.velf[q] = make_float4((float)wx, (float)wy, (float)wz, (float)mm);
 }
 void launch_step_permute(hipStream_t s, const DevPtrs& d, int n) {
-    if (n > 0) hipLaunchKernelGGL(k_step_permute, g256(n), dim3(256), 0, s, n, d.val_a, d.inv, d);
+    if (n > 0) hipLaunchKernelGGL(k_step_permute, g256(n), dim3(256), 0, s, n, d.val_a, d);
 }
 
 // v = v' + dt/2 a_new;  u = u' + dt/2 du_new;  optional lagged h update.
