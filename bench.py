@@ -302,6 +302,41 @@ def run_sweeps():
     return out
 
 
+def measure_peaks():
+    """Sustained rates measured on this GPU: FP64 and unpacked-FP32 FMA chains (the library's
+    probe) and a 1 GiB device-to-device copy (read + write bytes)."""
+    import torch
+    import paper_2007_03097_amd as sph
+    s = torch.cuda.current_stream()
+    out = {}
+    nt, iters, reps = 256 * 8192, 2048, 5
+    buf = torch.empty(nt, dtype=torch.float64, device="cuda")
+    for kind, name in ((0, "fp64_fma_tflops"), (1, "fp32_fma_tflops")):
+        sph.sph_peak_probe(kind, buf, iters, s.cuda_stream)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(s)
+        for _ in range(reps):
+            sph.sph_peak_probe(kind, buf, iters, s.cuda_stream)
+        e1.record(s)
+        torch.cuda.synchronize()
+        out[name] = 16.0 * iters * nt / (e0.elapsed_time(e1) / reps * 1e-3) / 1e12
+    del buf
+    nb = 1 << 30
+    src = torch.empty(nb, dtype=torch.uint8, device="cuda")
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(s)
+    for _ in range(reps):
+        dst.copy_(src)
+    e1.record(s)
+    torch.cuda.synchronize()
+    out["copy_tb_per_s"] = 2.0 * nb / (e0.elapsed_time(e1) / reps * 1e-3) / 1e12
+    del src, dst
+    torch.cuda.empty_cache()
+    return out
+
+
 def cpu_baseline(ps, reps=10):
     """The CPU FP64 reference on a bounded sample: the slab 0.42 < x < 0.58 of the same tube
     (both lattices and the interface).  Brute-force neighbours are built once (reported,
@@ -404,8 +439,11 @@ def main():
                            "frac": ach / FP64_PEAK_TFLOPS, "traffic": None,
                            "per_launch": {"pairs": pairs, "flop_per_pair": fpp, "avg_ms": t * 1e3}}
     dom = max(kernels, key=lambda k: kernels[k][0])
+    peaks = measure_peaks()
     for name in rooflines:
         rooflines[name]["traffic"] = measured_traffic(name)
+        rooflines[name]["measured_peak"] = peaks["fp64_fma_tflops"]
+        rooflines[name]["frac_measured"] = rooflines[name]["achieved"] / peaks["fp64_fma_tflops"]
     roof = dict(rooflines[dom], kernel=dom)
     extra = {}
     if not args.no_extra:
@@ -451,6 +489,7 @@ def main():
                                 "forces": r32["t_force"] * 1e3}},
         "roofline": roof,
         "rooflines_pair_kernels": rooflines,
+        "device_peaks_measured": peaks,
         "cpu_baseline": cpu,
         **extra,
     }

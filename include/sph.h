@@ -235,6 +235,17 @@ sph_status sph_sync(sph_ctx* ctx);
 /* Message for the last failed call on ctx (static text for ctx == NULL). */
 const char* sph_last_error(const sph_ctx* ctx);
 
+/* Device peak probe, for reading the kernels' arithmetic rates against a measured ceiling (no
+ * context, no SPH state).  Launches asynchronously on `stream` (a hipStream_t; NULL = the
+ * default stream) n_threads / 256 workgroups of 256 threads; each thread runs 8 independent
+ * fused-multiply-add chains of `iters` links in FP64 (kind 0) or unpacked FP32 (kind 1) and
+ * stores their sum to out_dev[thread].  One call performs 16 * iters * n_threads flops; timing
+ * it with events gives the sustained vector FMA rate.
+ *   out_dev  device double[n_threads], caller-owned, overwritten.
+ * SPH_E_ARG: kind not 0 or 1, out_dev NULL, n_threads <= 0 or not a multiple of 256, iters <= 0.
+ * SPH_E_DEVICE: the launch failed. */
+sph_status sph_peak_probe(int32_t kind, double* out_dev, int64_t n_threads, int32_t iters, void* stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -187,6 +187,15 @@ def sph_last_error(ctx) -> str:
     return m.decode() if m else ""
 
 
+def sph_peak_probe(kind: int, out, iters: int, stream=None):
+    """FMA-chain probe (kind 0 FP64, 1 FP32) over out.numel() threads; asynchronous."""
+    import torch
+    st = _lib().sph_peak_probe(int(kind), _ptr(out, torch.float64), out.numel(), int(iters),
+                               ctypes.c_void_p(stream) if stream else None)
+    if st != 0:
+        raise SPHError(st, "sph_peak_probe rejected its arguments or failed to launch")
+
+
 # ---------------------------------------------------------------------------------------
 class Context:
     """A context handle plus its workspace tensor (allocated once, as uint8 on the GPU)."""

@@ -19,7 +19,7 @@ def test_library_exports_every_declared_symbol():
     from paper_2007_03097_amd import _abi
     lib = _abi.load()
     decl = _declared()
-    assert len(decl) == 16
+    assert len(decl) == 17
     for name in decl:
         assert hasattr(lib, name), name
     assert sorted(_abi.EXPORTS) == decl
@@ -66,6 +66,9 @@ def test_host_validation_without_gpu():
     assert lib.sph_last_error(h)
     assert lib.sph_destroy(None) == 0
     sph.sph_destroy(h)
+    # the peak probe validates before launching
+    for args in ((2, 1, 256, 1), (0, None, 256, 1), (1, 1, 100, 1), (0, 1, 0, 1), (0, 1, 256, 0)):
+        assert lib.sph_peak_probe(args[0], args[1], args[2], args[3], None) == _abi.SPH_E_ARG
 
 
 def test_workspace_scales_with_capacity():
