@@ -17,7 +17,10 @@
 //     (tp, phi) tests the block of sources phi*T .. phi*T + T - 1 (T = group_size/2) against
 //     its two targets tp and tp + T with the exact predicate
 //     fl(fl(fl(dx dx) + fl(dy dy)) + fl(dz dz)) < fl(t t), recording hits as bits (two
-//     targets per lane halve the LDS reads per pair test).  The OR of all lanes' bits is the tile's part of the group's
+//     targets per lane halve the LDS reads per pair test).  The predicate is screened in FP32
+//     (fp32_screen below): the screen decides every pair outside a proven error margin, the
+//     few pairs inside it take the FP64 expression, so the lists are those of the FP64
+//     predicate bit for bit.  The OR of all lanes' bits is the tile's part of the group's
 //     source union U (sources that are a neighbour of at least one target), appended to
 //     U in staging order.  The 64/T lanes of a target then take consecutive slot ranges
 //     and write, for each hit, the source's index in U.
@@ -39,15 +42,64 @@ struct GroupBox {
     double lo[3], hi[3], hg;
 };
 
+// FP32 screen of the exact predicate.  Coordinates are offsets from the group origin o (the
+// group's first target), each formed in FP64 and rounded to FP32; h is rounded to FP32.
+// With u = 2^-24 and E the largest per-axis offset of a target from o, the screen values
+//   r2' = fma(dx', dx', fma(dy', dy', dz' dz')),  t2' = fl(fl(h_a' + h_b')^2)
+// (dx' = fl(x_a' - x_b') ...) differ from the exact r^2 and t^2 = (h_a + h_b)^2 by at most
+// 3.6u E^2 + 10.7u r^2 and 5.1u t^2 (offset errors grow with |x - o| <= E + |dx|), and the
+// FP64 expressions differ from them by O(2^-53).  Hence with
+//   M = 2^-21 E^2 + 2^-19 t2' + 2^-100   (about twice the bound; the last term covers FP32
+//                                          underflow)
+// the FP64 predicate holds when d' = t2' - r2' > M and fails when d' < -M.  Pairs with
+// |d'| <= M, and any NaN or overflow, are undecided and take the FP64 expression.  FP32
+// arithmetic issues at twice the FP64 rate on this GPU and the staged records halve.
+struct Screen {
+    double o[3];   // group origin
+    float me;      // 2^-21 E^2 + 2^-100, rounded up
+};
+
 // Each lane serves two targets of the group, tp and tp + TP (TP = group_size / 2), and a
 // block of B = TP staged sources; the P = 64 / TP lanes with the same tp cover the tile.
 // One LDS read of a source feeds two pair tests.
 struct LaneTargets {
-    double4 a, b;   // targets tp and tp + TP
+    float4 a, b;    // targets tp and tp + TP: FP32 offsets from the origin, h
     bool va, vb;    // they exist
     int tp, phi, TP, P;
     int cnt_a, cnt_b;
 };
+
+__device__ __forceinline__ float4 offset_rec(const double4& p, const Screen& S) {
+    return make_float4((float)(p.x - S.o[0]), (float)(p.y - S.o[1]), (float)(p.z - S.o[2]), (float)p.w);
+}
+
+// Screen of one pair: returns 1 (hit), 0 (miss) or -1 (undecided).
+__device__ __forceinline__ void screen_pair(const float4& a, const float4& s, float me, u32 bit, u32& hits,
+                                            u32& undecided) {
+    const float dx = a.x - s.x, dy = a.y - s.y, dz = a.z - s.z;
+    const float r2 = fmaf(dx, dx, fmaf(dy, dy, dz * dz));
+    const float tt = a.w + s.w;
+    const float t2 = tt * tt;
+    const float M = fmaf(t2, 0x1p-19f, me);
+    const float d = t2 - r2;
+    if (d > M) hits |= bit;
+    if (!(fabsf(d) > M)) undecided |= bit;
+}
+
+// The exact FP64 predicate for the pairs the screen left undecided (bit i = tile source i).
+__device__ void resolve_exact(u32 q, const double4& A, int head, int j0, const int* tsrc,
+                              const double4* __restrict__ pos4, u32& hits) {
+    while (q) {
+        const int it = __ffs(q) - 1;
+        q &= q - 1;
+        const double4 s = pos4[tsrc[(head + j0 + it) & (TILE_RING - 1)]];
+        const double dx = A.x - s.x, dy = A.y - s.y, dz = A.z - s.z;
+        double r2 = dx * dx + dy * dy;
+        r2 = r2 + dz * dz;
+        const double tt = A.w + s.w;
+        if (r2 < tt * tt) hits |= 1u << it;
+    }
+}
 
 // Slots for one target's hits: the P lanes of the target take consecutive slot ranges in
 // phi order, each in ascending source order; the entry is the source's index in the union.
@@ -74,33 +126,27 @@ __device__ __forceinline__ void append_hits(u32 bits, int t, int& cnt, const Lan
 }
 
 // Exact predicate fl(fl(fl(dx dx) + fl(dy dy)) + fl(dz dz)) < fl(t t), t = fl(h_a + h_b),
-// for the 64 (or, at the end, fewer) filtered sources at ring positions head .. head+tn-1;
-// hits go to the group's union and to the targets' lists.
-__device__ __forceinline__ void test_tile(int head, int tn, const double4* tile, const int* tsrc, LaneTargets& L,
-                                          int gy, int cap, int* mylist, int* myuni, int ulim, int& ucnt) {
+// for the 64 (or, at the end, fewer) filtered sources at ring positions head .. head+tn-1
+// (FP32 screen, FP64 for the undecided pairs); hits go to the group's union and to the
+// targets' lists.
+__device__ __forceinline__ void test_tile(int head, int tn, const float4* tile, const int* tsrc, LaneTargets& L,
+                                          float me, const double4* __restrict__ pos4, int gx, int gy, int cap,
+                                          int* mylist, int* myuni, int ulim, int& ucnt) {
     const int lane = lane_id();
     const int j0 = L.phi * L.TP;
     const int je = tn - j0 < L.TP ? tn - j0 : L.TP;
-    u32 ba = 0, bb = 0;
+    u32 ba = 0, bb = 0, qa = 0, qb = 0;
     for (int it = 0; it < je; ++it) {
-        const double4 s = tile[(head + j0 + it) & (TILE_RING - 1)];
-        {
-            const double dx = L.a.x - s.x, dy = L.a.y - s.y, dz = L.a.z - s.z;
-            double r2 = dx * dx + dy * dy;
-            r2 = r2 + dz * dz;
-            const double tt = L.a.w + s.w;
-            if (r2 < tt * tt) ba |= 1u << it;
-        }
-        {
-            const double dx = L.b.x - s.x, dy = L.b.y - s.y, dz = L.b.z - s.z;
-            double r2 = dx * dx + dy * dy;
-            r2 = r2 + dz * dz;
-            const double tt = L.b.w + s.w;
-            if (r2 < tt * tt) bb |= 1u << it;
-        }
+        const float4 s = tile[(head + j0 + it) & (TILE_RING - 1)];
+        screen_pair(L.a, s, me, 1u << it, ba, qa);
+        screen_pair(L.b, s, me, 1u << it, bb, qb);
     }
-    if (!L.va) ba = 0u;
-    if (!L.vb) bb = 0u;
+    if (!L.va) ba = qa = 0u;
+    if (!L.vb) bb = qb = 0u;
+    if (__ballot((qa | qb) != 0u)) {
+        if (qa) resolve_exact(qa, pos4[gx + L.tp], head, j0, tsrc, pos4, ba);
+        if (qb) resolve_exact(qb, pos4[gx + L.tp + L.TP], head, j0, tsrc, pos4, bb);
+    }
     // union of the tile, bit j = ring entry head + j
     u64 ub = (u64)(ba | bb) << j0;
     for (int d = 1; d < 64; d <<= 1) ub |= __shfl_xor(ub, d, 64);
@@ -119,10 +165,10 @@ __device__ __forceinline__ void test_tile(int head, int tn, const double4* tile,
 // test (gap^2 < (hmax_group + h_b)^2), so no true neighbour is dropped; survivors enter an
 // LDS ring and are matched 64 at a time.  Sources left in the ring (< 64) are matched by
 // the caller's final flush.
-__device__ void match_candidates(int nc, int* cand, int* coff, double4* tile, int* tsrc, int& head, int& tail,
-                                 const GroupBox& gb, const int4* __restrict__ topo,
-                                 const double4* __restrict__ pos4, LaneTargets& L, int gy, int cap, int* mylist,
-                                 int* myuni, int ulim, int& ucnt) {
+__device__ void match_candidates(int nc, int* cand, int* coff, float4* tile, int* tsrc, int& head, int& tail,
+                                 const GroupBox& gb, const Screen& S, const int4* __restrict__ topo,
+                                 const double4* __restrict__ pos4, LaneTargets& L, int gx, int gy, int cap,
+                                 int* mylist, int* myuni, int ulim, int& ucnt) {
     const int lane = lane_id();
     const u64 lt = lanemask_lt();
     int carry = 0;
@@ -170,13 +216,13 @@ __device__ void match_candidates(int nc, int* cand, int* coff, double4* tile, in
         const u64 bal = __ballot(pass);
         if (pass) {
             const int r = (tail + __popcll(bal & lt)) & (TILE_RING - 1);
-            tile[r] = b;
+            tile[r] = offset_rec(b, S);
             tsrc[r] = src;
         }
         tail += __popcll(bal);
         __syncthreads();
         if (tail - head >= 64) {
-            test_tile(head, 64, tile, tsrc, L, gy, cap, mylist, myuni, ulim, ucnt);
+            test_tile(head, 64, tile, tsrc, L, S.me, pos4, gx, gy, cap, mylist, myuni, ulim, ucnt);
             head += 64;
         }
         __syncthreads();
@@ -192,7 +238,7 @@ __global__ void __launch_bounds__(64) k_nbr_lists(DevCtl* ctl, const int4* __res
     __shared__ int stack[WALK_STACK];
     __shared__ int cand[WALK_CAND];
     __shared__ int coff[WALK_CAND + 1];
-    __shared__ double4 tile[TILE_RING];
+    __shared__ float4 tile[TILE_RING];
     __shared__ int tsrc[TILE_RING];
     const int lane = lane_id();
     const u64 lt = lanemask_lt();
@@ -207,17 +253,29 @@ __global__ void __launch_bounds__(64) k_nbr_lists(DevCtl* ctl, const int4* __res
         const int4 g = group[gi];
         L.va = L.tp < g.y;
         L.vb = L.tp + L.TP < g.y;
-        L.a = L.va ? pos4[g.x + L.tp] : make_double4(0, 0, 0, 0);
-        L.b = L.vb ? pos4[g.x + L.tp + L.TP] : make_double4(0, 0, 0, 0);
+        const double4 A = L.va ? pos4[g.x + L.tp] : make_double4(0, 0, 0, 0);
+        const double4 B = L.vb ? pos4[g.x + L.tp + L.TP] : make_double4(0, 0, 0, 0);
         L.cnt_a = L.cnt_b = 0;
         GroupBox gb;
-        gb.lo[0] = wave_min(fmin(L.va ? L.a.x : INFINITY, L.vb ? L.b.x : INFINITY));
-        gb.lo[1] = wave_min(fmin(L.va ? L.a.y : INFINITY, L.vb ? L.b.y : INFINITY));
-        gb.lo[2] = wave_min(fmin(L.va ? L.a.z : INFINITY, L.vb ? L.b.z : INFINITY));
-        gb.hi[0] = wave_max(fmax(L.va ? L.a.x : -INFINITY, L.vb ? L.b.x : -INFINITY));
-        gb.hi[1] = wave_max(fmax(L.va ? L.a.y : -INFINITY, L.vb ? L.b.y : -INFINITY));
-        gb.hi[2] = wave_max(fmax(L.va ? L.a.z : -INFINITY, L.vb ? L.b.z : -INFINITY));
-        gb.hg = wave_max(fmax(L.va ? L.a.w : 0.0, L.vb ? L.b.w : 0.0));
+        gb.lo[0] = wave_min(fmin(L.va ? A.x : INFINITY, L.vb ? B.x : INFINITY));
+        gb.lo[1] = wave_min(fmin(L.va ? A.y : INFINITY, L.vb ? B.y : INFINITY));
+        gb.lo[2] = wave_min(fmin(L.va ? A.z : INFINITY, L.vb ? B.z : INFINITY));
+        gb.hi[0] = wave_max(fmax(L.va ? A.x : -INFINITY, L.vb ? B.x : -INFINITY));
+        gb.hi[1] = wave_max(fmax(L.va ? A.y : -INFINITY, L.vb ? B.y : -INFINITY));
+        gb.hi[2] = wave_max(fmax(L.va ? A.z : -INFINITY, L.vb ? B.z : -INFINITY));
+        gb.hg = wave_max(fmax(L.va ? A.w : 0.0, L.vb ? B.w : 0.0));
+        Screen S;
+        {
+            const double4 o = pos4[g.x];
+            S.o[0] = o.x;
+            S.o[1] = o.y;
+            S.o[2] = o.z;
+            double E = 0.0;
+            for (int c = 0; c < 3; ++c) E = fmax(E, fmax(gb.hi[c] - S.o[c], S.o[c] - gb.lo[c]));
+            S.me = (float)((ldexp(E * E, -21) + 0x1p-100) * (1.0 + 0x1p-20));  // rounded up
+        }
+        L.a = offset_rec(A, S);
+        L.b = offset_rec(B, S);
         const double* lo = gb.lo;
         const double* hi = gb.hi;
         const double hg = gb.hg;
@@ -237,8 +295,8 @@ __global__ void __launch_bounds__(64) k_nbr_lists(DevCtl* ctl, const int4* __res
                 break;
             }
             if (nc + 64 > WALK_CAND) {
-                match_candidates(nc, cand, coff, tile, tsrc, head, tail, gb, topo, pos4, L, g.y, cap, mylist, myuni,
-                                 ulim, ucnt);
+                match_candidates(nc, cand, coff, tile, tsrc, head, tail, gb, S, topo, pos4, L, g.x, g.y, cap, mylist,
+                                 myuni, ulim, ucnt);
                 nc = 0;
             }
             // pop at most as many nodes as the free stack can take the children of (8 each)
@@ -278,9 +336,10 @@ __global__ void __launch_bounds__(64) k_nbr_lists(DevCtl* ctl, const int4* __res
         }
         __syncthreads();
         if (!overflow) {
-            match_candidates(nc, cand, coff, tile, tsrc, head, tail, gb, topo, pos4, L, g.y, cap, mylist, myuni, ulim,
-                             ucnt);
-            if (tail > head) test_tile(head, tail - head, tile, tsrc, L, g.y, cap, mylist, myuni, ulim, ucnt);
+            match_candidates(nc, cand, coff, tile, tsrc, head, tail, gb, S, topo, pos4, L, g.x, g.y, cap, mylist,
+                             myuni, ulim, ucnt);
+            if (tail > head)
+                test_tile(head, tail - head, tile, tsrc, L, S.me, pos4, g.x, g.y, cap, mylist, myuni, ulim, ucnt);
             __syncthreads();
         } else if (lane == 0)
             set_err(ctl, ERR_WALK_STACK);

@@ -40,6 +40,44 @@ def _clustered(n=3000, seed=12):
     return ps
 
 
+def _lattice_ties(seed=31):
+    """Unjittered lattice of spacing 1/16 (exact in binary) with h = s or s one ulp either
+    side: many pairs have r^2 exactly equal to, or one rounding away from, (h_a + h_b)^2."""
+    rng = np.random.default_rng(seed)
+    ps = lattice_box(12, seed=seed, jitter=0.0)
+    s = 1.0 / 16
+    i = np.arange(12) * s + 0.25
+    X, Y, Z = np.meshgrid(i, i, i, indexing="ij")
+    ps.x, ps.y, ps.z = (np.ascontiguousarray(A.ravel()) for A in (X, Y, Z))
+    ps.h = rng.choice(np.array([s, np.nextafter(s, 1.0), np.nextafter(s, 0.0)]), size=ps.n)
+    return ps
+
+
+def _near_ties(n_pairs=600, seed=32):
+    """Isolated pairs whose support t = h_a + h_b lies within a few ulps of their separation
+    (both sides of the strict inequality), at a spread of scales and offsets."""
+    rng = np.random.default_rng(seed)
+    ps = uniform_random(2 * n_pairs, seed=seed)
+    side = int(np.ceil(n_pairs ** (1 / 3)))
+    k = np.arange(n_pairs)
+    c = np.stack([k % side, (k // side) % side, k // (side * side)], 1) * 1.0 + 0.5
+    r = 10.0 ** rng.uniform(-3, -1, size=n_pairs)
+    d = rng.normal(size=(n_pairs, 3))
+    d /= np.linalg.norm(d, axis=1, keepdims=True)
+    a = c + 3.0 + rng.uniform(-0.2, 0.2, size=(n_pairs, 3))
+    b = a + d * r[:, None]
+    dist = np.sqrt(((a - b) ** 2).sum(1))
+    h = 0.5 * dist
+    for _ in range(3):
+        h = np.where(rng.random(n_pairs) < 0.5, np.nextafter(h, np.inf), np.nextafter(h, 0.0))
+    p = np.concatenate([a, b])
+    ps.x, ps.y, ps.z = (np.ascontiguousarray(p[:, i]) for i in range(3))
+    ps.h = np.concatenate([h, h])
+    return ps
+
+
+TIE_CASES = {"lattice_ties": _lattice_ties, "near_ties": _near_ties}
+
 CASES = {
     "lattice4096": lambda: lattice_box(16),
     "random_varh": lambda: uniform_random(3333, seed=4, h=(0.02, 0.08)),
@@ -94,10 +132,10 @@ def test_octree_matches_oracle(orc, case, leaf):
 
 
 # ---------------------------------------------------------------------------- neighbours
-@pytest.mark.parametrize("case", list(CASES))
+@pytest.mark.parametrize("case", list(CASES) + list(TIE_CASES))
 @pytest.mark.parametrize("group", [8, 32, 64])
 def test_neighbors_bitexact(orc, case, group):
-    ps = CASES[case]()
+    ps = (CASES.get(case) or TIE_CASES[case])()
     ctx = make_ctx(ps.n, group_size=group, leaf_size=12, nbr_capacity=4096)
     gpu_keys_order(ctx, parts(ps))
     off, idx = gpu_neighbors(ctx, ps.n)
