@@ -34,6 +34,13 @@ struct GravStage {
             double4 pm[64];  // (x, y, z, m)
             int src[64];     // particle index (self test without softening)
         } part;
+        struct {             // FP32C: the same with positions as offsets from the group origin
+            float4 c0[64], c1[64], c2[64];
+        } cellf;
+        struct {
+            float4 pm[64];
+            int src[64];
+        } partf;
     };
     int loff[GW_LEAVES + 1];  // particle offsets of the staged leaves
 };
@@ -124,11 +131,45 @@ __device__ __forceinline__ void part_term(const double4 me, const double4 sb, do
     }
 }
 
+// FP32C forms on group-origin offsets: the target and the cell's centre of mass (or the
+// source particle) are FP32 offsets from the group's first target, each formed in FP64 and
+// rounded once, so one FP32 subtraction gives R (its error is within u (|r_a - o| + |R_B - o|),
+// small against |R| for accepted cells, and softened for near particle pairs).
+__device__ __forceinline__ void cell_term_f(const float4 me, const float4 a, const float4 b, const float4 d, float e2,
+                                            TargetSums& S) {
+    const float Rx = me.x - a.y, Ry = me.y - a.z, Rz = me.z - a.w;
+    const float IRx = fmaf(b.x, Rx, fmaf(d.x, Ry, d.y * Rz));
+    const float IRy = fmaf(d.x, Rx, fmaf(b.y, Ry, d.z * Rz));
+    const float IRz = fmaf(d.y, Rx, fmaf(d.z, Ry, b.z * Rz));
+    const float RIR = fmaf(Rx, IRx, fmaf(Ry, IRy, Rz * IRz));
+    const float s2 = fmaf(Rx, Rx, fmaf(Ry, Ry, fmaf(Rz, Rz, e2)));
+    const float i1 = __builtin_amdgcn_rsqf(s2);
+    const float i2 = i1 * i1, i3 = i1 * i2, i5 = i3 * i2, i7 = i5 * i2;
+    const float cR = -a.x * i3 + 1.5f * b.w * i5 - 7.5f * RIR * i7;
+    S.tx = fmaf(cR, Rx, fmaf(3.0f * i5, IRx, S.tx));
+    S.ty = fmaf(cR, Ry, fmaf(3.0f * i5, IRy, S.ty));
+    S.tz = fmaf(cR, Rz, fmaf(3.0f * i5, IRz, S.tz));
+    S.tph -= a.x * i1 + 1.5f * RIR * i5 - 0.5f * b.w * i3;
+}
+
+__device__ __forceinline__ void part_term_f(const float4 me, const float4 sb, float e2, TargetSums& S) {
+    const float dx = me.x - sb.x, dy = me.y - sb.y, dz = me.z - sb.z;
+    const float s2 = fmaf(dx, dx, fmaf(dy, dy, fmaf(dz, dz, e2)));
+    const float i1 = __builtin_amdgcn_rsqf(s2);
+    const float mi3 = sb.w * i1 * i1 * i1;
+    S.tx = fmaf(-mi3, dx, S.tx);
+    S.ty = fmaf(-mi3, dy, S.ty);
+    S.tz = fmaf(-mi3, dz, S.tz);
+    S.tph = fmaf(-sb.w, i1, S.tph);
+}
+
 // Two targets per lane: tp and tp + TP (TP = group_size / 2); the P = 64 / TP lanes with
 // the same tp split every staged tile, so each LDS read of a cell or particle feeds two
 // evaluations.
 struct GravTargets {
     double4 a, b;
+    float4 fa, fb;  // FP32C: offsets from the group origin o
+    double o[3];
     int qa, qb;
     bool va, vb;
     int tp, phi, TP, P;
@@ -146,31 +187,48 @@ __device__ void eval_cells(int ncell, const int* cells, GravStage& St, const dou
         __syncthreads();
         if (k0 + lane < ncell) {
             const int c = cells[k0 + lane];
-            St.cell.c0[lane] = mom0[c];
-            St.cell.c1[lane] = mom1[c];
-            St.cell.c2[lane] = mom2[c];
+            const double4 c0 = mom0[c], c1 = mom1[c], c2 = mom2[c];
+            if (FP32C) {
+                St.cellf.c0[lane] = make_float4((float)c0.x, (float)(c0.y - T.o[0]), (float)(c0.z - T.o[1]),
+                                                (float)(c0.w - T.o[2]));
+                St.cellf.c1[lane] = make_float4((float)c1.x, (float)c1.y, (float)c1.z, (float)c1.w);
+                St.cellf.c2[lane] = make_float4((float)c2.x, (float)c2.y, (float)c2.z, 0.0f);
+            } else {
+                St.cell.c0[lane] = c0;
+                St.cell.c1[lane] = c1;
+                St.cell.c2[lane] = c2;
+            }
         }
         __syncthreads();
         const int cn = ncell - k0 < 64 ? ncell - k0 : 64;
         if (!any) continue;
-        for (int k = T.phi; k < cn; k += T.P) {
-            const double4 a = St.cell.c0[k], b = St.cell.c1[k], d = St.cell.c2[k];
-            cell_term<FP32C>(T.a, a, b, d, e2, A);
-            cell_term<FP32C>(T.b, a, b, d, e2, B);
-        }
         if (FP32C) {
+            const float e2f = (float)e2;
+            for (int k = T.phi; k < cn; k += T.P) {
+                const float4 a = St.cellf.c0[k], b = St.cellf.c1[k], d = St.cellf.c2[k];
+                cell_term_f(T.fa, a, b, d, e2f, A);
+                cell_term_f(T.fb, a, b, d, e2f, B);
+            }
             A.flush_tile();
             B.flush_tile();
+        } else {
+            for (int k = T.phi; k < cn; k += T.P) {
+                const double4 a = St.cell.c0[k], b = St.cell.c1[k], d = St.cell.c2[k];
+                cell_term<false>(T.a, a, b, d, e2, A);
+                cell_term<false>(T.b, a, b, d, e2, B);
+            }
         }
     }
 }
 
 // Particles of the listed leaves, concatenated and staged through LDS 64 at a time (one
-// load per lane per round); tile(tn) evaluates each staged tile of tn particles.  leaves[]
-// is overwritten with the leaves' first particles.
-template <typename Stage, typename Tile>
-__device__ void stage_leaves(int nleaf, int* leaves, Stage& St, const int4* __restrict__ topo,
-                             const double4* __restrict__ pos4, const double* __restrict__ m, Tile&& tile) {
+// load per lane per round): put(lane, position, mass, index) writes the staged record,
+// tile(tn) evaluates each staged tile of tn particles.  leaves[] is overwritten with the
+// leaves' first particles.
+template <typename Stage, typename Tile, typename Put>
+__device__ void stage_leaves_put(int nleaf, int* leaves, Stage& St, const int4* __restrict__ topo,
+                                 const double4* __restrict__ pos4, const double* __restrict__ m, Tile&& tile,
+                                 Put&& put) {
     const int lane = lane_id();
     int carry = 0;
     for (int j0 = 0; j0 < nleaf; j0 += 64) {  // particle offsets of the leaves
@@ -202,13 +260,21 @@ __device__ void stage_leaves(int nleaf, int* leaves, Stage& St, const int4* __re
                 else b = mid - 1;
             }
             const int src = leaves[a] + (p - St.loff[a]);
-            const double4 ps = pos4[src];
-            St.part.pm[lane] = make_double4(ps.x, ps.y, ps.z, m[src]);
-            St.part.src[lane] = src;
+            put(lane, pos4[src], m[src], src);
         }
         __syncthreads();
         tile(total - p0 < 64 ? total - p0 : 64);
     }
+}
+
+// stage_leaves_put with (x, y, z, m) records in FP64.
+template <typename Stage, typename Tile>
+__device__ void stage_leaves(int nleaf, int* leaves, Stage& St, const int4* __restrict__ topo,
+                             const double4* __restrict__ pos4, const double* __restrict__ m, Tile&& tile) {
+    stage_leaves_put(nleaf, leaves, St, topo, pos4, m, tile, [&](int lane, const double4& ps, double mass, int src) {
+        St.part.pm[lane] = make_double4(ps.x, ps.y, ps.z, mass);
+        St.part.src[lane] = src;
+    });
 }
 
 // Leaves evaluated by softened particle sums (self excluded) for the lane's two targets.
@@ -220,25 +286,51 @@ __device__ void eval_leaves(int nleaf, int* leaves, GravStage& St, const int4* _
                             double e2, TargetSums& A, TargetSums& B) {
     const bool any = T.va || T.vb;
     const bool soft = e2 > 0.0;
+    if (FP32C) {
+        const float e2f = (float)e2;
+        stage_leaves_put(
+            nleaf, leaves, St, topo, pos4, m,
+            [&](int tn) {
+                if (!any) return;
+                if (soft) {
+                    for (int j = T.phi; j < tn; j += T.P) {
+                        const float4 sb = St.partf.pm[j];
+                        part_term_f(T.fa, sb, e2f, A);
+                        part_term_f(T.fb, sb, e2f, B);
+                    }
+                } else {
+                    for (int j = T.phi; j < tn; j += T.P) {
+                        const float4 sb = St.partf.pm[j];
+                        const int s = St.partf.src[j];
+                        if (s != T.qa) part_term_f(T.fa, sb, e2f, A);
+                        if (s != T.qb) part_term_f(T.fb, sb, e2f, B);
+                    }
+                }
+                A.flush_tile();
+                B.flush_tile();
+            },
+            [&](int lane, const double4& ps, double mass, int src) {
+                St.partf.pm[lane] = make_float4((float)(ps.x - T.o[0]), (float)(ps.y - T.o[1]), (float)(ps.z - T.o[2]),
+                                                (float)mass);
+                St.partf.src[lane] = src;
+            });
+        return;
+    }
     stage_leaves(nleaf, leaves, St, topo, pos4, m, [&](int tn) {
         if (!any) return;
         if (soft) {
             for (int j = T.phi; j < tn; j += T.P) {
                 const double4 sb = St.part.pm[j];
-                part_term<FP32C>(T.a, sb, e2, A);
-                part_term<FP32C>(T.b, sb, e2, B);
+                part_term<false>(T.a, sb, e2, A);
+                part_term<false>(T.b, sb, e2, B);
             }
         } else {
             for (int j = T.phi; j < tn; j += T.P) {
                 const double4 sb = St.part.pm[j];
                 const int s = St.part.src[j];
-                if (s != T.qa) part_term<FP32C>(T.a, sb, e2, A);
-                if (s != T.qb) part_term<FP32C>(T.b, sb, e2, B);
+                if (s != T.qa) part_term<false>(T.a, sb, e2, A);
+                if (s != T.qb) part_term<false>(T.b, sb, e2, B);
             }
-        }
-        if (FP32C) {
-            A.flush_tile();
-            B.flush_tile();
         }
     });
 }
@@ -309,6 +401,14 @@ __global__ void __launch_bounds__(64) k_gravity(DevCtl* ctl, const int4* __restr
         T.vb = T.tp + T.TP < g.y;
         T.a = T.va ? pos4[T.qa] : make_double4(0, 0, 0, 0);
         T.b = T.vb ? pos4[T.qb] : make_double4(0, 0, 0, 0);
+        if (FP32C) {
+            const double4 o = pos4[g.x];
+            T.o[0] = o.x;
+            T.o[1] = o.y;
+            T.o[2] = o.z;
+            T.fa = make_float4((float)(T.a.x - o.x), (float)(T.a.y - o.y), (float)(T.a.z - o.z), 0.0f);
+            T.fb = make_float4((float)(T.b.x - o.x), (float)(T.b.y - o.y), (float)(T.b.z - o.z), 0.0f);
+        }
         double lo[3], hi[3];
         lo[0] = wave_min(fmin(T.va ? T.a.x : INFINITY, T.vb ? T.b.x : INFINITY));
         lo[1] = wave_min(fmin(T.va ? T.a.y : INFINITY, T.vb ? T.b.y : INFINITY));
