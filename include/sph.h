@@ -52,9 +52,10 @@ typedef struct sph_ctx sph_ctx;
 typedef struct {
     int32_t precision;   /* SPH_FP64: all pair arithmetic in FP64.  SPH_FP32C: density,
                             force and gravity pair arithmetic in FP32 (SPH positions as FP32
-                            offsets from the target group's first particle, gravity on FP64
-                            position differences), with compensated (Kahan/Neumaier) FP32
-                            sums; neighbour decisions, keys, tree, integration stay
+                            offsets from the target group's first particle; quadrupole
+                            gravity on FP32 offsets from the group's first target, node-node
+                            gravity on FP64 position differences), with Kahan-compensated
+                            FP32 sums; neighbour decisions, keys, tree, integration stay
                             FP64/integer.                                                */
     double gamma;        /* ideal-gas adiabatic index (> 1), default 5/3                     */
     double av_alpha;     /* Monaghan viscosity alpha (>= 0), default 1                       */

@@ -300,8 +300,8 @@ __device__ __forceinline__ double sqrt_rsq_nr(double a, double& inv) {
     return a > 0.0 ? r : 0.0;
 }
 
-// Kahan / Neumaier accumulators (explicit operation order; the library is built without
-// floating-point contraction, so these are not fused).
+// Kahan accumulator (explicit operation order; the library is built without floating-point
+// contraction, so it is not fused).
 struct Kahan {
     float s = 0.0f, c = 0.0f;
     __device__ __forceinline__ void add(float x) {
@@ -311,15 +311,6 @@ struct Kahan {
         s = t;
     }
     __device__ __forceinline__ double value() const { return (double)s - (double)c; }
-};
-struct Neumaier {
-    float s = 0.0f, c = 0.0f;
-    __device__ __forceinline__ void add(float x) {
-        const float t = s + x;
-        c += (fabsf(s) >= fabsf(x)) ? ((s - t) + x) : ((x - t) + s);
-        s = t;
-    }
-    __device__ __forceinline__ double value() const { return (double)s + (double)c; }
 };
 
 

@@ -22,8 +22,8 @@
 // FP32C: positions enter as FP32 offsets from the group's first particle (each offset
 // formed in FP64, then rounded), so a pair's difference is one FP32 subtraction of two
 // nearby offsets; everything else of the pair term is FP32, summed per thread with Kahan
-// (density) or Neumaier (forces) compensation; the partial sums combine in FP64 and
-// results are stored in FP64.
+// compensation (its error stays within about 2u times the sum of the terms' magnitudes,
+// whatever their signs); the partial sums combine in FP64 and results are stored in FP64.
 #include "common.h"
 
 // rho, P, c given by the caller (caller order) -> key-ordered thermo records
@@ -312,7 +312,7 @@ __global__ void __launch_bounds__(PAIR_THREADS) k_forces(
             const float4 mef = offset_rec(tv ? me : org, org);
             const float alf = (float)alpha, bef = (float)beta, epf = (float)eps_av;
             const float ipi = (float)M_1_PI_D;
-            Neumaier sx, sy, sz, su;
+            Kahan sx, sy, sz, su;
             for (int c0 = 0; c0 < nu; c0 += FORCE_CHUNK) {
                 const int cn = nu - c0 < FORCE_CHUNK ? nu - c0 : FORCE_CHUNK;
                 __syncthreads();
