@@ -52,9 +52,13 @@ void launch_thermo_from_caller(hipStream_t s, const DevPtrs& d, const Dims& dm, 
 
 constexpr int PAIR_THREADS = 256;
 constexpr int DENS_CHUNK = 512;
+// Union sources staged per round of the force pass: FP64 records are 96 bytes, so 256 keep six
+// workgroups per CU; the 48-byte FP32C records take 512, which covers most groups' union in one
+// round (a wave runs each round as long as its busiest target, so fewer rounds waste fewer lanes).
 constexpr int FORCE_CHUNK = 256;
+constexpr int FORCE_CHUNK_F = 512;
 
-// Density term of one pair: FP64, or FP32 on the FP64 position difference with Kahan
+// Density term of one pair: FP64, or FP32 on group-origin offsets with Kahan
 // compensation.  One term is m_b w(r/h_ab) / h_ab^3 (1/pi applied at the end).
 template <bool FP32C>
 struct DensAcc;
@@ -218,9 +222,9 @@ struct ForceSrc<false> {
 };
 template <>
 struct ForceSrc<true> {
-    float4 pos[FORCE_CHUNK];  // offsets from the group origin, h
-    float4 vel[FORCE_CHUNK];
-    float4 thr[FORCE_CHUNK];
+    float4 pos[FORCE_CHUNK_F];  // offsets from the group origin, h
+    float4 vel[FORCE_CHUNK_F];
+    float4 thr[FORCE_CHUNK_F];
 };
 static_assert(sizeof(ForceSrc<true>) >= 4 * PAIR_THREADS * sizeof(double), "the reduction reuses the staging");
 
@@ -313,8 +317,8 @@ __global__ void __launch_bounds__(PAIR_THREADS) k_forces(
             const float alf = (float)alpha, bef = (float)beta, epf = (float)eps_av;
             const float ipi = (float)M_1_PI_D;
             Kahan sx, sy, sz, su;
-            for (int c0 = 0; c0 < nu; c0 += FORCE_CHUNK) {
-                const int cn = nu - c0 < FORCE_CHUNK ? nu - c0 : FORCE_CHUNK;
+            for (int c0 = 0; c0 < nu; c0 += FORCE_CHUNK_F) {
+                const int cn = nu - c0 < FORCE_CHUNK_F ? nu - c0 : FORCE_CHUNK_F;
                 __syncthreads();
                 for (int i = tid; i < cn; i += PAIR_THREADS) {
                     const int b = un[c0 + i];
