@@ -311,6 +311,36 @@ __global__ void __launch_bounds__(SC_THREADS) k_scan_down(const T* __restrict__ 
     }
 }
 
+// Down-sweep that first sums the block totals of the blocks before it (sums[] holds the
+// totals of k_scan_reduce, not yet scanned): for up to SCAN_FUSE_MAX blocks this costs less
+// than a separate one-workgroup launch over the totals.
+constexpr int SCAN_FUSE_MAX = 4096;
+
+template <typename T>
+__global__ void __launch_bounds__(SC_THREADS) k_scan_down_fused(const T* __restrict__ in, T* out, int n,
+                                                                const T* __restrict__ sums, int write_total) {
+    T pre = 0;
+    for (int i = threadIdx.x; i < (int)blockIdx.x; i += SC_THREADS) pre += sums[i];
+    T pre_tot;
+    block_excl_scan<T>(pre, &pre_tot);
+    const int base = blockIdx.x * SC_TILE + threadIdx.x * SC_ITEMS;
+    T v[SC_ITEMS];
+    T s = 0;
+#pragma unroll
+    for (int k = 0; k < SC_ITEMS; ++k) {
+        v[k] = (base + k < n) ? in[base + k] : (T)0;
+        s += v[k];
+    }
+    T tot;
+    T e = block_excl_scan<T>(s, &tot) + pre_tot;
+#pragma unroll
+    for (int k = 0; k < SC_ITEMS; ++k) {
+        if (base + k < n) out[base + k] = e;
+        if (write_total && base + k == n - 1) out[n] = e + v[k];
+        e += v[k];
+    }
+}
+
 template <typename T>
 __global__ void k_zero_one(T* p) {
     if (threadIdx.x == 0) p[0] = (T)0;
@@ -325,6 +355,11 @@ static void scan_impl(hipStream_t s, const T* in, T* out, int n, void* tmp, int 
     const int nb = (n + SC_TILE - 1) / SC_TILE;
     T* sums = (T*)tmp;
     hipLaunchKernelGGL(k_scan_reduce<T>, dim3(nb), dim3(SC_THREADS), 0, s, in, n, sums);
+    if (nb <= SCAN_FUSE_MAX) {
+        hipLaunchKernelGGL(k_scan_down_fused<T>, dim3(nb), dim3(SC_THREADS), 0, s, in, out, n, (const T*)sums,
+                           write_total);
+        return;
+    }
     hipLaunchKernelGGL(k_scan_top<T>, dim3(1), dim3(SC_THREADS), 0, s, sums, nb);
     hipLaunchKernelGGL(k_scan_down<T>, dim3(nb), dim3(SC_THREADS), 0, s, in, out, n, (const T*)sums, write_total);
 }
