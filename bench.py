@@ -121,22 +121,28 @@ def _pairs(ctx, pa, n):
     return total + (total - n)
 
 
-def run_polytrope(ps, steps, prec, scheme=0):
-    """n = 1 polytrope with self-gravity (theta = 0.5, eps = 0.01, G = 1), adaptive h; scheme 0 =
-    quadrupole particle-cell walk, 1 = symmetric node-node (FMM) gravity.  Also times one
-    gravity pass on the final state (HIP events on the context's stream)."""
+def run_polytrope(ps, steps, prec, scheme=0, eps=0.01, sizes=None):
+    """Self-gravitating set (theta = 0.5, Plummer eps, G = 1), adaptive h: the n = 1 polytrope
+    (eps = 0.01) or the Evrard sphere (eps = 0.005); scheme 0 = quadrupole particle-cell walk,
+    1 = symmetric node-node (FMM) gravity.  Leaf and group sizes from the autotuner, or the
+    given (leaf, group).  dt = 0.25 min(h/c, sqrt(eps/|a|)) on the primed initial state.  Also
+    times one gravity pass on the final state (HIP events on the context's stream)."""
     import numpy as np
     import torch
     import paper_2007_03097_amd as sph
     n = ps.n
-    ctx = sph.Context(n, adaptive_h=1, precision=prec, G=1.0, soft_eps=0.01, theta=0.5, nbr_capacity=2048,
-                      gravity_scheme=scheme)
+    cfg = dict(adaptive_h=1, precision=prec, G=1.0, soft_eps=eps, theta=0.5, nbr_capacity=2048,
+               gravity_scheme=scheme)
+    if sizes:
+        cfg.update(leaf_size=sizes[0], group_size=sizes[1])
+    ctx = sph.Context(n, **cfg)
     pa = sph.ParticleArrays.from_numpy(ps, with_accel=True)
-    sph.sph_autotune(ctx.h, pa, 1e-4, TUNING_CACHE)
+    if not sizes:
+        sph.sph_autotune(ctx.h, pa, 1e-4, TUNING_CACHE)
     sph.sph_step(ctx.h, pa, 1e-9, 0, 0)                  # prime: accelerations of the initial state
     a = np.sqrt(sum(pa[k].cpu().numpy() ** 2 for k in ("ax", "ay", "az")))
     c = np.sqrt((5.0 / 3.0) * (2.0 / 3.0) * ps.u)
-    dt = 0.25 * min(float(np.min(pa["h"].cpu().numpy() / c)), float(np.sqrt(0.01 / a.max())))
+    dt = 0.25 * min(float(np.min(pa["h"].cpu().numpy() / c)), float(np.sqrt(eps / a.max())))
     sph.sph_step(ctx.h, pa, dt, 1, sph.SPH_STEP_PRIMED)  # warm up, capture graphs
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -396,6 +402,9 @@ def main():
     ap.add_argument("--polytrope", action="store_true",
                     help="instead of the benchmark: the 4M polytrope with both gravity schemes, FP64 and FP32C "
                          "(one JSON line; --steps timed steps each)")
+    ap.add_argument("--evrard", action="store_true",
+                    help="instead of the benchmark: the 16M Evrard sphere, FP32C and FP64, quadrupole gravity "
+                         "(one JSON line; --steps timed steps each)")
     ap.add_argument("--copy-calib-mib", type=int, default=0,
                     help="first run one device-to-device copy of this many MiB (hardware-counter calibration)")
     args = ap.parse_args()
@@ -417,6 +426,15 @@ def main():
         for scheme, name in ((0, "quadrupole"), (1, "node_node")):
             out[name] = {"fp64": run_polytrope(pp, args.steps, 0, scheme),
                          "fp32c": run_polytrope(pp, args.steps, 1, scheme)}
+        print(json.dumps(out), flush=True)
+        return
+    if args.evrard:
+        from workloads import evrard
+        pe = evrard(16777216, seed=1005)
+        out = {"workload": "Evrard sphere, 16,777,216 particles, u = 0.05, G = 1, eps = 0.005, theta = 0.5, "
+                           "adaptive h, quadrupole gravity, leaf 32 / group 64", "steps": args.steps}
+        for prec, key in ((1, "fp32c"), (0, "fp64")):
+            out[key] = run_polytrope(pe, args.steps, prec, 0, eps=0.005, sizes=(32, 64))
         print(json.dumps(out), flush=True)
         return
     if args.copy_calib_mib > 0:
