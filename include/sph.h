@@ -203,6 +203,8 @@ sph_status sph_compute_forces(sph_ctx* ctx, const double* rho, const double* P, 
  * With gravity_scheme = SPH_GRAVITY_FMM: the symmetric node-node scheme instead (see
  * sph_config.gravity_scheme); particle pairs of unaccepted leaf pairs are summed directly,
  * and phi is the first-order potential.  SPH_E_ARG if the last tree holds several sets.
+ * With G == 0 (gravity off) the outputs are filled with zeros: such a context builds its trees
+ * without node masses and moments, which only gravity reads.
  * Outputs: device double[n] in caller order; any may be NULL (not copied out). */
 sph_status sph_compute_gravity(sph_ctx* ctx, double* gx, double* gy, double* gz, double* phi);
 

@@ -240,6 +240,7 @@ static sph_status prepare(sph_ctx* c, const sph_particles* p) {
     dm.node_cap = (int)node_cap_for(c->n_cap > 0 ? c->n_cap : 1, c->leaf_min);
     dm.min_level = dm.batched ? 3 : 0;
     dm.curve = c->cfg.key_curve;
+    dm.mass_moments = c->cfg.G != 0.0;
     const bool same = c->tab.n == p->n && c->tab.n_seg == n_seg && c->tab.seg == seg;
     std::vector<int4> chunks;
     std::vector<int> rank(n_seg, 0);
@@ -544,6 +545,11 @@ sph_status sph_compute_gravity(sph_ctx* c, double* gx, double* gy, double* gz, d
     if (!c->tree_ok) return fail(c, SPH_E_STATE, "sph_build_tree has not been called");
     if (c->cfg.gravity_scheme == SPH_GRAVITY_FMM && c->dm.batched)
         return fail(c, SPH_E_ARG, "gravity_scheme SPH_GRAVITY_FMM needs a single set (n_seg == 1)");
+    if (c->cfg.G == 0.0) {  // no gravity: the tree carries no mass moments
+        for (double* o : {gx, gy, gz, phi}) launch_fill_zero(c->stream, n, o);
+        HIPCHK(c, hipGetLastError());
+        return SPH_OK;
+    }
     const DevPtrs& d = c->d[c->parity];
     gravity_pass(c, c->stream, d, 0, 0);
     launch_scatter_caller(c->stream, d, n, d.gx, gx);

@@ -118,6 +118,7 @@ struct Dims {
     int node_cap;
     int min_level;    // 3 when batched, else 0
     int curve;        // 0 Morton, 1 Hilbert keys
+    int mass_moments; // node masses and moments are built (only the gravity kernels read them)
 };
 
 // Key quantisation of one coordinate (Sec. 2.1): one subtraction, one multiplication, then
@@ -356,6 +357,7 @@ void launch_fmm(hipStream_t s, const DevPtrs& d, const Dims& dm, int fp32c, doub
                 int accumulate, int thermokinetic);
 // k_step.hip
 void launch_scatter_caller(hipStream_t s, const DevPtrs& d, int n, const double* src, double* dst);
+void launch_fill_zero(hipStream_t s, int n, double* dst);
 void launch_gather_caller(hipStream_t s, const DevPtrs& d, int n, const double* src_caller, double* dst);
 void launch_box_init(hipStream_t s, const DevPtrs& d, const Dims& dm);
 void launch_kick_drift(hipStream_t s, const DevPtrs& d, const Dims& dm, double dt);

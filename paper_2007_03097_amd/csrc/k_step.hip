@@ -12,6 +12,14 @@ void launch_scatter_caller(hipStream_t s, const DevPtrs& d, int n, const double*
     if (n > 0 && dst) hipLaunchKernelGGL(k_scatter_caller, g256(n), dim3(256), 0, s, n, d.id, src, dst);
 }
 
+__global__ void k_fill_zero(int n, double* dst) {
+    const int q = blockIdx.x * blockDim.x + threadIdx.x;
+    if (q < n) dst[q] = 0.0;
+}
+void launch_fill_zero(hipStream_t s, int n, double* dst) {
+    if (n > 0 && dst) hipLaunchKernelGGL(k_fill_zero, g256(n), dim3(256), 0, s, n, dst);
+}
+
 __global__ void k_gather_caller(int n, const u32* __restrict__ id, const double* __restrict__ src, double* dst) {
     const int q = blockIdx.x * blockDim.x + threadIdx.x;
     if (q < n) dst[q] = src[id[q]];

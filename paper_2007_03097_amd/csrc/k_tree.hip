@@ -320,20 +320,27 @@ __global__ void __launch_bounds__(256) k_finalize(DevCtl* ctl, const unsigned ch
 // Internal node from its children: box, largest h, mass, centre of mass, and second
 // moments about the centre of mass (parallel-axis shifts of the children's).
 __device__ void aggregate_node(int p, const int4 tp, double4* nbox_lo, double4* nbox_hi, double4* mom0,
-                               double4* mom1, double4* mom2, int2* range, double side) {
+                               double4* mom1, double4* mom2, int2* range, double side, bool mass) {
     double lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
     double hmax = 0.0, M = 0.0, sx = 0.0, sy = 0.0, sz = 0.0;
     int cnt = 0;
     for (int k = 0; k < tp.y; ++k) {
         const int c = tp.x + k;
-        const double4 a = nbox_lo[c], b = nbox_hi[c], m0 = mom0[c];
+        const double4 a = nbox_lo[c], b = nbox_hi[c];
         lo[0] = fmin(lo[0], a.x); lo[1] = fmin(lo[1], a.y); lo[2] = fmin(lo[2], a.z);
         hi[0] = fmax(hi[0], b.x); hi[1] = fmax(hi[1], b.y); hi[2] = fmax(hi[2], b.z);
         hmax = fmax(hmax, a.w);
-        M += m0.x;
-        sx += m0.x * m0.y; sy += m0.x * m0.z; sz += m0.x * m0.w;
+        if (mass) {
+            const double4 m0 = mom0[c];
+            M += m0.x;
+            sx += m0.x * m0.y; sy += m0.x * m0.z; sz += m0.x * m0.w;
+        }
         cnt += range[c].y;
     }
+    nbox_lo[p] = make_double4(lo[0], lo[1], lo[2], hmax);
+    nbox_hi[p] = make_double4(hi[0], hi[1], hi[2], side);
+    range[p] = make_int2(range[tp.x].x, cnt);
+    if (!mass) return;
     const double cx = sx / M, cy = sy / M, cz = sz / M;
     double I[6] = {0, 0, 0, 0, 0, 0};
     for (int k = 0; k < tp.y; ++k) {
@@ -343,21 +350,31 @@ __device__ void aggregate_node(int p, const int4 tp, double4* nbox_lo, double4* 
         I[0] += m1.x + m0.x * dx * dx; I[1] += m1.y + m0.x * dy * dy; I[2] += m1.z + m0.x * dz * dz;
         I[3] += m2.x + m0.x * dx * dy; I[4] += m2.y + m0.x * dx * dz; I[5] += m2.z + m0.x * dy * dz;
     }
-    nbox_lo[p] = make_double4(lo[0], lo[1], lo[2], hmax);
-    nbox_hi[p] = make_double4(hi[0], hi[1], hi[2], side);
     mom0[p] = make_double4(M, cx, cy, cz);
     mom1[p] = make_double4(I[0], I[1], I[2], I[0] + I[1] + I[2]);
     mom2[p] = make_double4(I[3], I[4], I[5], 0.0);
-    range[p] = make_int2(range[tp.x].x, cnt);
 }
 
 // Leaf geometry and moments from its particles [s, s + c).
 __device__ void leaf_node(int b, int s, int c, const double4* __restrict__ pos4, const double* __restrict__ m,
                           double4* nbox_lo, double4* nbox_hi, double4* mom0, double4* mom1, double4* mom2,
-                          int2* range, double side) {
+                          int2* range, double side, bool mass) {
     double lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
     double hmax = 0.0, M = 0.0, sx = 0.0, sy = 0.0, sz = 0.0;
     const int e = s + c;
+    if (!mass) {
+#pragma unroll 4
+        for (int j = s; j < e; ++j) {
+            const double4 p = pos4[j];
+            lo[0] = fmin(lo[0], p.x); lo[1] = fmin(lo[1], p.y); lo[2] = fmin(lo[2], p.z);
+            hi[0] = fmax(hi[0], p.x); hi[1] = fmax(hi[1], p.y); hi[2] = fmax(hi[2], p.z);
+            hmax = fmax(hmax, p.w);
+        }
+        nbox_lo[b] = make_double4(lo[0], lo[1], lo[2], hmax);
+        nbox_hi[b] = make_double4(hi[0], hi[1], hi[2], side);
+        range[b] = make_int2(s, c);
+        return;
+    }
 #pragma unroll 4
     for (int j = s; j < e; ++j) {
         const double4 p = pos4[j];
@@ -388,6 +405,7 @@ __device__ void leaf_node(int b, int s, int c, const double4* __restrict__ pos4,
 struct MomArgs {
     const DevCtl* ctl;
     int batched;
+    int mass;  // build masses and moments too (gravity on), else only boxes, h_max and ranges
     const u64* key;
     const int4* topo;
     const double4* pos4;
@@ -403,9 +421,9 @@ __device__ __forceinline__ void node_moments(const MomArgs& A, int b) {
     const int seg = A.batched ? (int)((A.key[s] >> 54) & 511ull) : 0;
     const double side = ldexp(A.ctl->side[seg], -tp.z);
     if (tp.w)
-        leaf_node(b, tp.x, tp.y, A.pos4, A.m, A.nbox_lo, A.nbox_hi, A.mom0, A.mom1, A.mom2, A.range, side);
+        leaf_node(b, tp.x, tp.y, A.pos4, A.m, A.nbox_lo, A.nbox_hi, A.mom0, A.mom1, A.mom2, A.range, side, A.mass);
     else
-        aggregate_node(b, tp, A.nbox_lo, A.nbox_hi, A.mom0, A.mom1, A.mom2, A.range, side);
+        aggregate_node(b, tp, A.nbox_lo, A.nbox_hi, A.mom0, A.mom1, A.mom2, A.range, side, A.mass);
 }
 
 // Every node at level >= cut: one wavefront per level-cut cell finishes its whole subtree
@@ -497,8 +515,8 @@ void build_octree(hipStream_t s, const DevPtrs& d, const Dims& dm) {
                        d.range);
     // moments: subtrees below the cut, then the levels between, then the top levels
     const int cut = subtree_cut(n);
-    const MomArgs A{d.ctl, dm.batched, d.key_a, d.topo, d.pos4, d.m, d.nbox_lo, d.nbox_hi, d.mom0, d.mom1, d.mom2,
-                    d.range};
+    const MomArgs A{d.ctl, dm.batched, dm.mass_moments, d.key_a, d.topo, d.pos4, d.m,
+                    d.nbox_lo, d.nbox_hi, d.mom0, d.mom1, d.mom2, d.range};
     hipLaunchKernelGGL(k_subtree_moments, dim3(grid_cap(n, 64, 8192)), dim3(64), 0, s, A, cut);
     for (int lv = cut - 1; lv >= TOP_LEVELS; --lv)
         hipLaunchKernelGGL(k_level_moments, dim3(grid_cap(n / 2 + 1, 256, 256)), dim3(256), 0, s, A, lv);

@@ -221,6 +221,15 @@ def test_lattice_pins_on_gpu():
 
 
 # ---------------------------------------------------------------------------- gravity
+def test_gravity_off_gives_zeros():
+    """G = 0: the tree carries no node masses or moments and sph_compute_gravity returns zeros."""
+    ps = uniform_random(2000, seed=9, h=(0.03, 0.06))
+    ctx = make_ctx(ps.n)
+    gpu_keys_order(ctx, parts(ps))
+    for o in gpu_gravity(ctx, ps.n):
+        assert np.all(o == 0.0)
+
+
 def test_gravity_theta0_equals_direct(orc):
     ps = polytrope_n1(4000, seed=5)
     ctx = make_ctx(ps.n, theta=0.0, G=1.0, soft_eps=0.01)
