@@ -105,13 +105,13 @@ def run_gpu(ps, prec, steps, warmup, reps, autotune=True, energy_form=0, key_cur
     t_list = ev[0].elapsed_time(ev[1]) / reps * 1e-3
     t_dens = ev[1].elapsed_time(ev[2]) / reps * 1e-3
     t_force = ev[2].elapsed_time(ev[3]) / reps * 1e-3
-    leaf, group = sph.sph_get_tuning(ctx.h)
+    leaf, group, waves = sph.sph_get_tuning(ctx.h)
     ctx.close()
     return dict(ms_per_step=wall / steps * 1e3, wall=wall, pairs_dens=pairs_dens, pairs_force=pairs_force,
                 value=(pairs_dens + pairs_force) * steps / wall, steps_per_s=steps / wall,
                 t_list=t_list, t_dens=t_dens, t_force=t_force,
                 pass_rate=(pairs_dens + pairs_force) / (t_dens + t_force),
-                diag=diag.tolist(), leaf=leaf, group=group, dt=dt)
+                diag=diag.tolist(), leaf=leaf, group=group, waves=waves, dt=dt)
 
 
 def _pairs(ctx, pa, n):
@@ -160,12 +160,12 @@ def run_polytrope(ps, steps, prec, scheme=0, eps=0.01, sizes=None):
     e1.record()
     torch.cuda.synchronize()
     grav_ms = e0.elapsed_time(e1) / 3
-    leaf, group = sph.sph_get_tuning(ctx.h)
+    leaf, group, waves = sph.sph_get_tuning(ctx.h)
     ctx.close()
     del g
     torch.cuda.empty_cache()
     return dict(ms_per_step=wall / steps * 1e3, steps_per_s=steps / wall, value=pairs * steps / wall, dt=dt,
-                leaf_size=leaf, group_size=group, gravity_ms=grav_ms)
+                leaf_size=leaf, group_size=group, waves_per_cu=waves, gravity_ms=grav_ms)
 
 
 def run_ensemble(steps):
@@ -192,7 +192,8 @@ def run_ensemble(steps):
         wall = time.perf_counter() - t0
         pairs = _pairs(ctx, pa, n)
         out[key] = {"ms_per_step": wall / steps * 1e3, "value": pairs * steps / wall,
-                    "leaf_size": sph.sph_get_tuning(ctx.h)[0], "group_size": sph.sph_get_tuning(ctx.h)[1]}
+                    "leaf_size": sph.sph_get_tuning(ctx.h)[0], "group_size": sph.sph_get_tuning(ctx.h)[1],
+                    "waves_per_cu": sph.sph_get_tuning(ctx.h)[2]}
         ctx.close()
         del pa
         torch.cuda.empty_cache()
@@ -494,7 +495,8 @@ def main():
         "vs_baseline": None, "dtype": "f64", "data": "synthetic",
         "config": {"workload": f"3D Sod-type tube, {n} particles, adaptive h, Monaghan AV, KDK leapfrog",
                    "n_particles": n, "dt": r64["dt"], "leaf_size": r64["leaf"], "group_size": r64["group"],
-                   "fp32c_leaf_size": r32["leaf"], "fp32c_group_size": r32["group"]},
+                   "waves_per_cu": r64["waves"], "fp32c_leaf_size": r32["leaf"], "fp32c_group_size": r32["group"],
+                   "fp32c_waves_per_cu": r32["waves"]},
         "steps_per_s": r64["steps_per_s"],
         "pairs_per_step": r64["pairs_dens"] + r64["pairs_force"],
         "pass_rate": r64["pass_rate"],

@@ -91,6 +91,12 @@ typedef struct {
                             first order in the potential (field constant across a node);
                             linear and angular momentum are conserved to rounding.  One set
                             only (n_seg == 1).                                       */
+    int32_t waves_per_cu; /* wavefronts per compute unit of the persistent per-group
+                            kernels (neighbour walk, density, forces, gravity): their grids
+                            hold at most waves_per_cu x 256 wavefronts (256 CUs), fewer when
+                            there are fewer groups; 1..32, or 0 (default) for one workgroup
+                            per group up to 8192 workgroups, as many resident per CU as
+                            registers and LDS allow.  Results do not depend on it.     */
 } sph_config;
 
 /* Values of sph_config.energy_form. */
@@ -225,12 +231,15 @@ sph_status sph_step(sph_ctx* ctx, sph_particles* ps, double dt, int32_t nsteps, 
                     double* diag_host);
 
 /* Times sph_step over candidate leaf_size x group_size settings on ps (which it leaves
- * unchanged), keeps the fastest in the context, and records it in a JSON cache file
- * (cache_json_path may be NULL).  Synchronous. */
+ * unchanged), then over waves_per_cu for the fastest pair, keeps the fastest in the context
+ * and records "key": [leaf_size, group_size, waves_per_cu] in a JSON cache file
+ * (cache_json_path may be NULL).  A cached entry is used as it is; an entry with only
+ * [leaf_size, group_size] keeps those and has its waves_per_cu searched and recorded.
+ * Synchronous. */
 sph_status sph_autotune(sph_ctx* ctx, const sph_particles* ps, double dt, const char* cache_json_path);
 
-/* Current tuning parameters (leaf_size, group_size) of the context. */
-sph_status sph_get_tuning(const sph_ctx* ctx, int32_t* leaf_size, int32_t* group_size);
+/* Current tuning parameters of the context; any pointer may be NULL. */
+sph_status sph_get_tuning(const sph_ctx* ctx, int32_t* leaf_size, int32_t* group_size, int32_t* waves_per_cu);
 
 /* Waits for the context's stream and returns (and clears) the sticky device error. */
 sph_status sph_sync(sph_ctx* ctx);

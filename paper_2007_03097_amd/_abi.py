@@ -34,7 +34,7 @@ class sph_config(ctypes.Structure):
                 ("adaptive_h", ctypes.c_int32), ("G", ctypes.c_double), ("soft_eps", ctypes.c_double),
                 ("theta", ctypes.c_double), ("leaf_size", ctypes.c_int32), ("group_size", ctypes.c_int32),
                 ("nbr_capacity", ctypes.c_int32), ("stream", ctypes.c_void_p), ("energy_form", ctypes.c_int32),
-                ("key_curve", ctypes.c_int32), ("gravity_scheme", ctypes.c_int32)]
+                ("key_curve", ctypes.c_int32), ("gravity_scheme", ctypes.c_int32), ("waves_per_cu", ctypes.c_int32)]
 
 
 _dp = ctypes.c_void_p  # device pointers are passed as integers
@@ -82,7 +82,7 @@ def load() -> ctypes.CDLL:
     L.sph_compute_gravity.argtypes = [ctx_p, _dp, _dp, _dp, _dp]
     L.sph_step.argtypes = [ctx_p, P(sph_particles), dbl, i32, u32, P(dbl)]
     L.sph_autotune.argtypes = [ctx_p, P(sph_particles), dbl, ctypes.c_char_p]
-    L.sph_get_tuning.argtypes = [ctx_p, P(i32), P(i32)]
+    L.sph_get_tuning.argtypes = [ctx_p, P(i32), P(i32), P(i32)]
     L.sph_sync.argtypes = [ctx_p]
     L.sph_last_error.argtypes = [ctx_p]
     L.sph_last_error.restype = ctypes.c_char_p

@@ -162,8 +162,8 @@ def sph_step(ctx, parts: ParticleArrays | None, dt: float, nsteps: int, flags: i
     return diag
 
 
-# Leaf and group sizes measured by sph_autotune on MI355X, keyed by workload (n, sets,
-# precision, gravity, adaptive h); sph_autotune reads a key when present.
+# Leaf size, group size and waves per CU measured by sph_autotune on MI355X, keyed by
+# workload (n, sets, precision, gravity, adaptive h); sph_autotune reads a key when present.
 TUNING_CACHE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "tuning_gfx950.json")
 
 
@@ -173,9 +173,10 @@ def sph_autotune(ctx, parts: ParticleArrays, dt: float, cache_path: str | None =
 
 
 def sph_get_tuning(ctx):
-    a, b = ctypes.c_int32(), ctypes.c_int32()
-    _check(ctx, _lib().sph_get_tuning(ctx, ctypes.byref(a), ctypes.byref(b)))
-    return int(a.value), int(b.value)
+    """(leaf_size, group_size, waves_per_cu) of the context."""
+    a, b, w = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
+    _check(ctx, _lib().sph_get_tuning(ctx, ctypes.byref(a), ctypes.byref(b), ctypes.byref(w)))
+    return int(a.value), int(b.value), int(w.value)
 
 
 def sph_sync(ctx):

@@ -39,6 +39,7 @@ struct sph_ctx {
     int leaf_min = 16;        // smallest leaf size the workspace is sized for
     int leaf_size = 16;
     int group_size = 32;
+    int waves = 0;            // waves per CU of the per-group kernels (0 = one workgroup per group)
     int nbr_cap = 160;
     char* ws = nullptr;
     size_t ws_bytes = 0;
@@ -54,7 +55,7 @@ struct sph_ctx {
     hipGraph_t graph[2] = {nullptr, nullptr};
     double g_dt = 0.0;
     int64_t g_n = -1;
-    int g_leaf = 0, g_gsz = 0, g_tabv = -1;
+    int g_leaf = 0, g_gsz = 0, g_waves = -1, g_tabv = -1;
     bool use_graph = true;
     std::string err;
 };
@@ -203,6 +204,7 @@ static sph_status check_config(sph_ctx* c, const sph_config* f) {
         return fail(c, SPH_E_ARG, "key_curve must be 0 or 1");
     if (f->gravity_scheme != SPH_GRAVITY_QUADRUPOLE && f->gravity_scheme != SPH_GRAVITY_FMM)
         return fail(c, SPH_E_ARG, "gravity_scheme must be 0 or 1");
+    if (f->waves_per_cu < 0 || f->waves_per_cu > 32) return fail(c, SPH_E_ARG, "waves_per_cu must be in 0..32");
     return SPH_OK;
 }
 
@@ -252,9 +254,17 @@ static sph_status prepare(sph_ctx* c, const sph_particles* p) {
             chunks.push_back(make_int4((int)b, (int)std::min<int64_t>(seg[s + 1], b + CHUNK), s, b == seg[s]));
     }
     dm.n_chunks = (int)chunks.size();
-    {   // persistent grid of the per-group kernels: a multiple of 8 (one share per XCD)
+    {   // persistent grids of the per-group kernels: multiples of 8 (one share per XCD); with
+        // waves_per_cu, at most that many wavefronts per CU (one-wave and four-wave workgroups)
         const int64_t est = p->n / std::max(1, c->group_size / 2) + 8;
-        dm.group_grid = (int)(8 * std::min<int64_t>(1024, (est + 7) / 8));
+        const int64_t units = std::min<int64_t>(1024, (est + 7) / 8);
+        int64_t u1 = units, u4 = units;
+        if (c->waves > 0) {
+            u1 = std::min<int64_t>(units, (int64_t)c->waves * 256 / 8);
+            u4 = std::min<int64_t>(units, std::max<int64_t>(1, (int64_t)c->waves * 256 / 4 / 8));
+        }
+        dm.group_grid = (int)(8 * u1);
+        dm.pair_grid = (int)(8 * u4);
     }
     if (!same) {
         if (!chunks.empty())
@@ -362,6 +372,7 @@ void sph_config_default(sph_config* f) {
     f->energy_form = SPH_ENERGY_THERMAL;
     f->key_curve = SPH_CURVE_MORTON;
     f->gravity_scheme = SPH_GRAVITY_QUADRUPOLE;
+    f->waves_per_cu = 0;
     f->stream = nullptr;
 }
 
@@ -387,6 +398,7 @@ sph_status sph_create(const sph_config* cfg, int64_t n_capacity, int32_t seg_cap
         return SPH_E_ARG;
     }
     c->group_size = cfg->group_size ? cfg->group_size : 32;
+    c->waves = cfg->waves_per_cu;
     c->nbr_cap = cfg->nbr_capacity ? cfg->nbr_capacity : 160;
     c->stream = (hipStream_t)cfg->stream;
     const char* ng = getenv("SPH_NO_GRAPH");
@@ -595,7 +607,7 @@ static void step_launches(sph_ctx* c, hipStream_t s, int p) {
 static sph_status run_steps(sph_ctx* c, double dt, int nsteps) {
     if (nsteps <= 0 || c->dm.n == 0) return SPH_OK;
     const bool regraph = c->g_dt != dt || c->g_n != c->dm.n || c->g_leaf != c->leaf_size ||
-                         c->g_gsz != c->group_size || c->g_tabv != c->tab.version;
+                         c->g_gsz != c->group_size || c->g_waves != c->waves || c->g_tabv != c->tab.version;
     c->g_dt = dt;
     if (!c->use_graph) {
         for (int k = 0; k < nsteps; ++k) {
@@ -620,6 +632,7 @@ static sph_status run_steps(sph_ctx* c, double dt, int nsteps) {
         c->g_tabv = c->tab.version;
         c->g_leaf = c->leaf_size;
         c->g_gsz = c->group_size;
+        c->g_waves = c->waves;
     }
     for (int k = 0; k < nsteps; ++k) {
         HIPCHK(c, hipGraphLaunch(c->gexec[c->parity], c->stream));
@@ -684,10 +697,11 @@ sph_status sph_step(sph_ctx* c, sph_particles* p, double dt, int32_t nsteps, uin
     return step_impl(c, p, dt, nsteps, flags, diag_host, true);
 }
 
-sph_status sph_get_tuning(const sph_ctx* c, int32_t* leaf_size, int32_t* group_size) {
+sph_status sph_get_tuning(const sph_ctx* c, int32_t* leaf_size, int32_t* group_size, int32_t* waves_per_cu) {
     if (!c) return SPH_E_ARG;
     if (leaf_size) *leaf_size = c->leaf_size;
     if (group_size) *group_size = c->group_size;
+    if (waves_per_cu) *waves_per_cu = c->waves;
     return SPH_OK;
 }
 
@@ -700,53 +714,82 @@ sph_status sph_autotune(sph_ctx* c, const sph_particles* p, double dt, const cha
              c->cfg.G != 0.0, c->cfg.adaptive_h,
              c->cfg.G != 0.0 && c->cfg.gravity_scheme == SPH_GRAVITY_FMM ? "_fmm" : "");
     const std::string key(keybuf);
-    if (cache) {  // tiny JSON reader: "key": [leaf, group]
+    std::string body;  // the cache file (tiny JSON object of "key": [leaf, group, waves])
+    if (cache) {
         std::ifstream f(cache);
         if (f) {
             std::stringstream ss;
             ss << f.rdbuf();
-            const std::string s = ss.str();
-            const size_t at = s.find("\"" + key + "\"");
-            if (at != std::string::npos) {
-                int L = 0, G = 0;
-                if (sscanf(s.c_str() + s.find('[', at), "[%d, %d]", &L, &G) == 2 && L >= c->leaf_min && L <= 64 &&
-                    (G == 8 || G == 16 || G == 32 || G == 64)) {
-                    c->leaf_size = L;
-                    c->group_size = G;
-                    return SPH_OK;
-                }
-            }
+            body = ss.str();
         }
     }
-    // the node-node gravity favours larger leaves (its particle sums fill more lanes)
-    const bool fmm = c->cfg.G != 0.0 && c->cfg.gravity_scheme == SPH_GRAVITY_FMM;
-    const std::vector<int> leaves = fmm ? std::vector<int>{16, 24, 32, 48, 64} : std::vector<int>{8, 12, 16, 24, 32};
-    const int groups[] = {16, 32, 64};
-    double best = 1e300;
-    int bL = c->leaf_size, bG = c->group_size;
+    const std::string qkey = "\"" + key + "\"";
+    const size_t at = body.find(qkey);
+    int cL = 0, cG = 0, cW = -1;
+    bool cached = false;
+    if (at != std::string::npos && body.find('[', at) != std::string::npos) {
+        const int got = sscanf(body.c_str() + body.find('[', at), "[%d, %d, %d]", &cL, &cG, &cW);
+        cached = got >= 2 && cL >= c->leaf_min && cL <= 64 && (cG == 8 || cG == 16 || cG == 32 || cG == 64);
+        if (got < 3 || cW < 0 || cW > 32) cW = -1;
+    }
+    if (cached && cW >= 0) {
+        c->leaf_size = cL;
+        c->group_size = cG;
+        c->waves = cW;
+        return SPH_OK;
+    }
     sph_particles q = *p;
     q.ax = q.ay = q.az = q.dudt = nullptr;
     hipEvent_t e0, e1;
     HIPCHK(c, hipEventCreate(&e0));
     HIPCHK(c, hipEventCreate(&e1));
-    for (int L : leaves) {
-        if (L < c->leaf_min) continue;
-        for (int G : groups) {
-            c->leaf_size = L;
-            c->group_size = G;
-            st = step_impl(c, &q, dt, 1, 0, nullptr, false);  // load, prime, warm up, capture
-            if (st != SPH_OK) continue;
-            HIPCHK(c, hipEventRecord(e0, c->stream));
-            st = step_impl(c, &q, dt, 3, SPH_STEP_RESUME, nullptr, false);
-            HIPCHK(c, hipEventRecord(e1, c->stream));
-            HIPCHK(c, hipEventSynchronize(e1));
-            if (st != SPH_OK) continue;
-            float ms = 0.f;
-            HIPCHK(c, hipEventElapsedTime(&ms, e0, e1));
-            if (ms < best) {
-                best = ms;
-                bL = L;
-                bG = G;
+    // milliseconds of 3 steps (after a load, prime, warm-up and capture), or a negative value
+    auto time_steps = [&](int L, int G, int W) -> double {
+        c->leaf_size = L;
+        c->group_size = G;
+        c->waves = W;
+        if (step_impl(c, &q, dt, 1, 0, nullptr, false) != SPH_OK) return -1.0;
+        if (hipEventRecord(e0, c->stream) != hipSuccess) return -1.0;
+        if (step_impl(c, &q, dt, 3, SPH_STEP_RESUME, nullptr, false) != SPH_OK) return -1.0;
+        if (hipEventRecord(e1, c->stream) != hipSuccess || hipEventSynchronize(e1) != hipSuccess) return -1.0;
+        float ms = 0.f;
+        if (hipEventElapsedTime(&ms, e0, e1) != hipSuccess) return -1.0;
+        return ms;
+    };
+    double best = 1e300;
+    int bL = c->leaf_size, bG = c->group_size;
+    if (cached) {
+        bL = cL;
+        bG = cG;
+        const double ms = time_steps(bL, bG, 0);
+        if (ms >= 0.0) best = ms;
+    } else {
+        // the node-node gravity favours larger leaves (its particle sums fill more lanes)
+        const bool fmm = c->cfg.G != 0.0 && c->cfg.gravity_scheme == SPH_GRAVITY_FMM;
+        const std::vector<int> leaves =
+            fmm ? std::vector<int>{16, 24, 32, 48, 64} : std::vector<int>{8, 12, 16, 24, 32};
+        const int groups[] = {16, 32, 64};
+        for (int L : leaves) {
+            if (L < c->leaf_min) continue;
+            for (int G : groups) {
+                const double ms = time_steps(L, G, 0);
+                if (ms >= 0.0 && ms < best) {
+                    best = ms;
+                    bL = L;
+                    bG = G;
+                }
+            }
+        }
+    }
+    // waves per CU for the chosen sizes; a cap must win by more than 1% over the default
+    int bW = 0;
+    if (best < 1e300) {
+        double bw = best;
+        for (int W : {4, 8, 12, 16, 24}) {
+            const double ms = time_steps(bL, bG, W);
+            if (ms >= 0.0 && ms < 0.99 * bw) {
+                bw = ms;
+                bW = W;
             }
         }
     }
@@ -754,23 +797,22 @@ sph_status sph_autotune(sph_ctx* c, const sph_particles* p, double dt, const cha
     (void)hipEventDestroy(e1);
     c->leaf_size = bL;
     c->group_size = bG;
+    c->waves = bW;
     c->resident_ok = false;
     c->tab = Tables();
-    if (cache) {
-        std::string body;
-        {
-            std::ifstream f(cache);
-            if (f) {
-                std::stringstream ss;
-                ss << f.rdbuf();
-                body = ss.str();
-            }
-        }
-        const size_t close = body.rfind('}');
+    if (cache && best < 1e300) {
         char entry[256];
-        snprintf(entry, sizeof entry, "\"%s\": [%d, %d]", key.c_str(), bL, bG);
-        if (close == std::string::npos || body.find('"') == std::string::npos) body = std::string("{\n  ") + entry + "\n}\n";
-        else body = body.substr(0, close) + ",\n  " + entry + "\n}\n";
+        snprintf(entry, sizeof entry, "%s: [%d, %d, %d]", qkey.c_str(), bL, bG, bW);
+        if (at != std::string::npos) {  // replace the entry of this key
+            const size_t end = body.find(']', at);
+            body = body.substr(0, at) + entry + (end == std::string::npos ? std::string() : body.substr(end + 1));
+        } else {
+            const size_t close = body.rfind('}');
+            if (close == std::string::npos || body.find('"') == std::string::npos)
+                body = std::string("{\n  ") + entry + "\n}\n";
+            else
+                body = body.substr(0, close) + ",\n  " + entry + "\n}\n";
+        }
         std::ofstream o(cache);
         o << body;
     }

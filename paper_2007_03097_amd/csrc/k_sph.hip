@@ -201,11 +201,11 @@ void launch_density(hipStream_t s, const DevPtrs& d, const Dims& dm, int fp32c, 
                     const double* u_eos, int kin) {
     if (dm.n <= 0) return;
     if (fp32c)
-        hipLaunchKernelGGL(k_density<true>, dim3(dm.group_grid), dim3(PAIR_THREADS), 0, s, d.ctl, d.group,
+        hipLaunchKernelGGL(k_density<true>, dim3(dm.pair_grid), dim3(PAIR_THREADS), 0, s, d.ctl, d.group,
                            dm.group_size, dm.nbr_cap, d.nbr, d.nbr_cnt, d.uni, d.ucnt, d.pos4, d.vel4, d.m, u_eos,
                            kin, gamma, h_coeff, d.rho, d.P, d.cs, d.hnext, d.thr4, d.thrf);
     else
-        hipLaunchKernelGGL(k_density<false>, dim3(dm.group_grid), dim3(PAIR_THREADS), 0, s, d.ctl, d.group,
+        hipLaunchKernelGGL(k_density<false>, dim3(dm.pair_grid), dim3(PAIR_THREADS), 0, s, d.ctl, d.group,
                            dm.group_size, dm.nbr_cap, d.nbr, d.nbr_cnt, d.uni, d.ucnt, d.pos4, d.vel4, d.m, u_eos,
                            kin, gamma, h_coeff, d.rho, d.P, d.cs, d.hnext, d.thr4, d.thrf);
 }
@@ -396,7 +396,7 @@ void launch_forces(hipStream_t s, const DevPtrs& d, const Dims& dm, int fp32c, d
                    double eps_av, int thermo) {
     if (dm.n <= 0) return;
     auto go = [&](auto kern) {
-        hipLaunchKernelGGL(kern, dim3(dm.group_grid), dim3(PAIR_THREADS), 0, s, d.ctl, d.group, dm.group_size,
+        hipLaunchKernelGGL(kern, dim3(dm.pair_grid), dim3(PAIR_THREADS), 0, s, d.ctl, d.group, dm.group_size,
                            dm.nbr_cap, d.nbr, d.nbr_cnt, d.uni, d.ucnt, d.pos4, d.vel4, d.thr4, d.velf, d.thrf, alpha,
                            beta, eps_av, d.ax, d.ay, d.az, d.du);
     };

@@ -15,10 +15,11 @@ def make_ctx(n_cap, seg_cap=1, **cfg):
 
 
 def tuned(ctx, pa, dt=1e-4):
-    """Leaf and group sizes the benchmark uses for this workload (the package's tuning file)."""
+    """Leaf and group sizes (and waves per CU) the benchmark uses for this workload (the
+    package's tuning file); returns (leaf, group)."""
     import paper_2007_03097_amd as sph
     sph.sph_autotune(ctx.h, pa, dt, sph.TUNING_CACHE)
-    return sph.sph_get_tuning(ctx.h)
+    return sph.sph_get_tuning(ctx.h)[:2]
 
 
 def parts(ps, with_accel=False):

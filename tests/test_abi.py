@@ -52,7 +52,8 @@ def test_host_validation_without_gpu():
         sph.sph_create(cfg, 10, 513)
     with pytest.raises(sph.SPHError):  # the octree's node indices would overflow 32 bits
         sph.sph_create(cfg, 600_000_000, 1)
-    for bad in (dict(gravity_scheme=2), dict(key_curve=5), dict(energy_form=-1)):
+    for bad in (dict(gravity_scheme=2), dict(key_curve=5), dict(energy_form=-1), dict(waves_per_cu=-1),
+                dict(waves_per_cu=33)):
         with pytest.raises(sph.SPHError):
             sph.sph_create(sph.sph_config_default(**bad), 10, 1)
     lib = _abi.load()

@@ -220,6 +220,28 @@ def test_lattice_pins_on_gpu():
     assert np.all(du == 0)
 
 
+def test_waves_per_cu_does_not_change_results(orc):
+    """A capped persistent grid reorders which workgroup takes which group, nothing else:
+    lists, density, forces and a leapfrog step are bit-identical to the uncapped grid."""
+    import paper_2007_03097_amd as sph
+    ps = sod_tube(8)
+    out = {}
+    for w in (0, 1, 4):
+        ctx = make_ctx(ps.n, adaptive_h=1, group_size=64, waves_per_cu=w)
+        assert sph.sph_get_tuning(ctx.h)[2] == w
+        pa = parts(ps)
+        gpu_keys_order(ctx, pa)
+        off, idx = gpu_neighbors(ctx, ps.n)
+        rho, P, c, hn = gpu_density(ctx, ps.n)
+        ax, ay, az, du = gpu_forces(ctx, ps.n)
+        pb = parts(ps)
+        sph.sph_step(ctx.h, pb, 1e-4, 3, 0)
+        out[w] = [off, idx, rho, ax, ay, az, du] + [pb[k].cpu().numpy() for k in ("x", "vx", "u", "h")]
+    for w in (1, 4):
+        for a, b in zip(out[0], out[w]):
+            assert np.array_equal(a, b)
+
+
 # ---------------------------------------------------------------------------- gravity
 def test_gravity_off_gives_zeros():
     """G = 0: the tree carries no node masses or moments and sph_compute_gravity returns zeros."""
@@ -724,14 +746,22 @@ def test_autotune_keeps_results_and_caches(tmp_path):
     before = {k: pa[k].cpu().numpy().copy() for k in ("x", "vx", "u", "h")}
     cache = str(tmp_path / "tune.json")
     sph.sph_autotune(ctx.h, pa, 4e-4, cache)
-    leaf, group = sph.sph_get_tuning(ctx.h)
-    assert leaf in (8, 12, 16, 24, 32) and group in (16, 32, 64)
+    leaf, group, waves = sph.sph_get_tuning(ctx.h)
+    assert leaf in (8, 12, 16, 24, 32) and group in (16, 32, 64) and waves in (0, 4, 8, 12, 16, 24)
     for k, v in before.items():
         assert np.array_equal(pa[k].cpu().numpy(), v)
-    assert f"[{leaf}, {group}]" in open(cache).read()
+    assert f"[{leaf}, {group}, {waves}]" in open(cache).read()
     ctx2 = make_ctx(ps.n, adaptive_h=1)
     sph.sph_autotune(ctx2.h, pa, 4e-4, cache)
-    assert sph.sph_get_tuning(ctx2.h) == (leaf, group)
+    assert sph.sph_get_tuning(ctx2.h) == (leaf, group, waves)
+    # an entry with sizes only keeps them and gains its waves per CU, in place
+    key = open(cache).read().split('"')[1]
+    open(cache, "w").write('{\n  "%s": [%d, %d]\n}\n' % (key, leaf, group))
+    ctx4 = make_ctx(ps.n, adaptive_h=1)
+    sph.sph_autotune(ctx4.h, pa, 4e-4, cache)
+    l4, g4, w4 = sph.sph_get_tuning(ctx4.h)
+    assert (l4, g4) == (leaf, group) and open(cache).read().count(key) == 1
+    assert f"[{leaf}, {group}, {w4}]" in open(cache).read()
     k1, o1 = gpu_keys_order(ctx2, pa)
     off1, idx1 = gpu_neighbors(ctx2, ps.n)
     ctx3 = make_ctx(ps.n, leaf_size=8, group_size=64)
