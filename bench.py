@@ -27,8 +27,8 @@ sys.path.insert(0, ROOT)
 
 FP64_PEAK_TFLOPS = 78.6     # MI355X FP64 vector, 256 CU x 64 lanes x 2 flop x 2.4 GHz
 HBM_PEAK_GBS = 8000.0
-# leaf / group sizes chosen by sph_autotune on MI355X, keyed by workload; missing keys are
-# tuned on the spot (and appended to that file)
+# leaf size, group size and waves per CU chosen by sph_autotune on MI355X, keyed by workload;
+# missing keys are tuned on the spot (and appended to that file)
 TUNING_CACHE = os.path.join(ROOT, "paper_2007_03097_amd", "tuning_gfx950.json")  # = paper_2007_03097_amd.TUNING_CACHE
 
 # Algorithmic operation counts per true pair (see the design notes): one flop per IEEE
@@ -75,7 +75,7 @@ def run_gpu(ps, prec, steps, warmup, reps, autotune=True, energy_form=0, key_cur
     pa = sph.ParticleArrays.from_numpy(ps)
     dt = dt_for(ps)
     if autotune:
-        sph.sph_autotune(ctx.h, pa, dt, TUNING_CACHE)    # leaf and group size by timed steps (untimed here)
+        sph.sph_autotune(ctx.h, pa, dt, TUNING_CACHE)    # leaf size, group size, waves per CU (untimed here)
     sph.sph_step(ctx.h, pa, dt, max(warmup, 1), 0)       # load, prime, warm up, capture graphs
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -397,7 +397,7 @@ def main():
     ap.add_argument("--reps", type=int, default=20, help="repetitions of the per-kernel timing")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-extra", action="store_true", help="skip the polytrope and ensemble workloads")
-    ap.add_argument("--no-autotune", action="store_true", help="keep the default leaf and group sizes")
+    ap.add_argument("--no-autotune", action="store_true", help="keep the default leaf size, group size and grids")
     ap.add_argument("--sweep", action="store_true",
                     help="instead of the benchmark: gravity time/accuracy vs theta and time vs N (one JSON line)")
     ap.add_argument("--polytrope", action="store_true",
