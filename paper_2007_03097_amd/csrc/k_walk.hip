@@ -73,7 +73,8 @@ __device__ __forceinline__ float4 offset_rec(const double4& p, const Screen& S) 
     return make_float4((float)(p.x - S.o[0]), (float)(p.y - S.o[1]), (float)(p.z - S.o[2]), (float)p.w);
 }
 
-// Screen of one pair: returns 1 (hit), 0 (miss) or -1 (undecided).
+// Screen of one pair: sets `bit` in hits when the pair is a neighbour for certain and in
+// undecided when the screen cannot tell (neither for a certain miss).
 __device__ __forceinline__ void screen_pair(const float4& a, const float4& s, float me, u32 bit, u32& hits,
                                             u32& undecided) {
     const float dx = a.x - s.x, dy = a.y - s.y, dz = a.z - s.z;
