@@ -264,6 +264,28 @@ def test_gravity_theta0_equals_direct(orc):
     assert rel_err(phi, dp, np.abs(dp)) <= TOL
 
 
+@pytest.mark.parametrize("case", ["polytrope", "clustered"])
+def test_gravity_fp32c_against_fp64(case, capsys):
+    """FP32C quadrupole gravity (FP32 offsets from each group's first target, Kahan tile sums)
+    against the FP64 walk on the same tree and groups: both take their opening decisions in
+    FP64, so they differ by FP32 rounding only (observed: g median 3e-8, max 1e-6; phi max 1e-7)."""
+    ps = polytrope_n1(16384, seed=6) if case == "polytrope" else _clustered(6000, seed=14)
+    res = {}
+    for prec in (0, 1):
+        ctx = make_ctx(ps.n, theta=0.5, G=1.0, soft_eps=0.01, precision=prec, leaf_size=16, group_size=32)
+        gpu_keys_order(ctx, parts(ps))
+        res[prec] = gpu_gravity(ctx, ps.n)
+    g64 = np.stack(res[0][:3], axis=1)
+    g32 = np.stack(res[1][:3], axis=1)
+    d = np.linalg.norm(g32 - g64, axis=1) / np.linalg.norm(g64, axis=1)
+    dp = np.abs(res[1][3] - res[0][3]) / np.abs(res[0][3])
+    with capsys.disabled():
+        print(f"\nFP32C vs FP64 gravity ({case}): g median {np.median(d):.2e} max {d.max():.2e}; "
+              f"phi median {np.median(dp):.2e} max {dp.max():.2e}")
+    assert np.median(d) <= 2e-7 and d.max() <= 1e-5
+    assert np.median(dp) <= 1e-7 and dp.max() <= 1e-6
+
+
 @pytest.mark.parametrize("prec", [0, 1])
 def test_gravity_theta_half(orc, prec, capsys):
     """theta = 0.5 quadrupole tree gravity: RMS relative error <= 1e-3 against the direct sum;
