@@ -28,7 +28,8 @@ static_assert(GW_STACK > 2 * DFS_HEADROOM, "room for wide rounds above the headr
 struct GravStage {
     union {
         struct {
-            double4 c0[64], c1[64], c2[64];  // (M, com), (Ixx, Iyy, Izz, tr I), (Ixy, Ixz, Iyz, -)
+            // (M, com), (3 Ixx, 3 Iyy, 3 Izz, 3/2 tr I), (3 Ixy, 3 Ixz, 3 Iyz, 1/2 tr I)
+            double4 c0[64], c1[64], c2[64];
         } cell;
         struct {
             double4 pm[64];  // (x, y, z, m)
@@ -69,41 +70,25 @@ struct TargetSums {
     }
 };
 
-// Monopole + quadrupole of cell (a = (M, com), b = (Ixx, Iyy, Izz, tr I), d = (Ixy, Ixz, Iyz)).
-template <bool FP32C>
+// Monopole + quadrupole of a staged cell, with the expansion's constants folded into the
+// record at staging: a = (M, com), b = (3 Ixx, 3 Iyy, 3 Izz, 3/2 tr I), d = (3 Ixy, 3 Ixz,
+// 3 Iyz, 1/2 tr I).  With Q = 3 I: g += -M R/s^3 + Q.R/s^5 - (5/2) (R.Q.R) R/s^7 + (3/2) tr(I) R/s^5
+// and phi -= M/s + (1/2) R.Q.R/s^5 - (1/2) tr(I)/s^3.
 __device__ __forceinline__ void cell_term(const double4 me, const double4 a, const double4 b, const double4 d,
                                           double e2, TargetSums& S) {
-    if (!FP32C) {
-        const double Rx = me.x - a.y, Ry = me.y - a.z, Rz = me.z - a.w;
-        const double IRx = fma(b.x, Rx, fma(d.x, Ry, d.y * Rz));
-        const double IRy = fma(d.x, Rx, fma(b.y, Ry, d.z * Rz));
-        const double IRz = fma(d.y, Rx, fma(d.z, Ry, b.z * Rz));
-        const double RIR = fma(Rx, IRx, fma(Ry, IRy, Rz * IRz));
-        const double s2 = fma(Rx, Rx, fma(Ry, Ry, fma(Rz, Rz, e2)));
-        const double i1 = rsq_nr1(s2);
-        const double i2 = i1 * i1, i3 = i1 * i2, i5 = i3 * i2, i7 = i5 * i2;
-        const double cR = -a.x * i3 + 1.5 * b.w * i5 - 7.5 * RIR * i7;
-        S.gx = fma(cR, Rx, fma(3.0 * i5, IRx, S.gx));
-        S.gy = fma(cR, Ry, fma(3.0 * i5, IRy, S.gy));
-        S.gz = fma(cR, Rz, fma(3.0 * i5, IRz, S.gz));
-        S.ph -= a.x * i1 + 1.5 * RIR * i5 - 0.5 * b.w * i3;
-    } else {
-        const float Rx = (float)(me.x - a.y), Ry = (float)(me.y - a.z), Rz = (float)(me.z - a.w);
-        const float bx = (float)b.x, by = (float)b.y, bz = (float)b.z, tr = (float)b.w;
-        const float dxy = (float)d.x, dxz = (float)d.y, dyz = (float)d.z, M = (float)a.x;
-        const float IRx = fmaf(bx, Rx, fmaf(dxy, Ry, dxz * Rz));
-        const float IRy = fmaf(dxy, Rx, fmaf(by, Ry, dyz * Rz));
-        const float IRz = fmaf(dxz, Rx, fmaf(dyz, Ry, bz * Rz));
-        const float RIR = fmaf(Rx, IRx, fmaf(Ry, IRy, Rz * IRz));
-        const float s2 = fmaf(Rx, Rx, fmaf(Ry, Ry, fmaf(Rz, Rz, (float)e2)));
-        const float i1 = __builtin_amdgcn_rsqf(s2);
-        const float i2 = i1 * i1, i3 = i1 * i2, i5 = i3 * i2, i7 = i5 * i2;
-        const float cR = -M * i3 + 1.5f * tr * i5 - 7.5f * RIR * i7;
-        S.tx = fmaf(cR, Rx, fmaf(3.0f * i5, IRx, S.tx));
-        S.ty = fmaf(cR, Ry, fmaf(3.0f * i5, IRy, S.ty));
-        S.tz = fmaf(cR, Rz, fmaf(3.0f * i5, IRz, S.tz));
-        S.tph -= M * i1 + 1.5f * RIR * i5 - 0.5f * tr * i3;
-    }
+    const double Rx = me.x - a.y, Ry = me.y - a.z, Rz = me.z - a.w;
+    const double QRx = fma(b.x, Rx, fma(d.x, Ry, d.y * Rz));
+    const double QRy = fma(d.x, Rx, fma(b.y, Ry, d.z * Rz));
+    const double QRz = fma(d.y, Rx, fma(d.z, Ry, b.z * Rz));
+    const double RQR = fma(Rx, QRx, fma(Ry, QRy, Rz * QRz));
+    const double s2 = fma(Rx, Rx, fma(Ry, Ry, fma(Rz, Rz, e2)));
+    const double i1 = rsq_nr1(s2);
+    const double i2 = i1 * i1, i3 = i1 * i2, i5 = i3 * i2, i7 = i5 * i2;
+    const double cR = fma(b.w, i5, fma(-2.5 * RQR, i7, -a.x * i3));
+    S.gx = fma(cR, Rx, fma(i5, QRx, S.gx));
+    S.gy = fma(cR, Ry, fma(i5, QRy, S.gy));
+    S.gz = fma(cR, Rz, fma(i5, QRz, S.gz));
+    S.ph -= fma(a.x, i1, fma(0.5 * RQR, i5, -d.w * i3));
 }
 
 // Softened particle term of source sb = (x, y, z, m).
@@ -138,18 +123,18 @@ __device__ __forceinline__ void part_term(const double4 me, const double4 sb, do
 __device__ __forceinline__ void cell_term_f(const float4 me, const float4 a, const float4 b, const float4 d, float e2,
                                             TargetSums& S) {
     const float Rx = me.x - a.y, Ry = me.y - a.z, Rz = me.z - a.w;
-    const float IRx = fmaf(b.x, Rx, fmaf(d.x, Ry, d.y * Rz));
-    const float IRy = fmaf(d.x, Rx, fmaf(b.y, Ry, d.z * Rz));
-    const float IRz = fmaf(d.y, Rx, fmaf(d.z, Ry, b.z * Rz));
-    const float RIR = fmaf(Rx, IRx, fmaf(Ry, IRy, Rz * IRz));
+    const float QRx = fmaf(b.x, Rx, fmaf(d.x, Ry, d.y * Rz));
+    const float QRy = fmaf(d.x, Rx, fmaf(b.y, Ry, d.z * Rz));
+    const float QRz = fmaf(d.y, Rx, fmaf(d.z, Ry, b.z * Rz));
+    const float RQR = fmaf(Rx, QRx, fmaf(Ry, QRy, Rz * QRz));
     const float s2 = fmaf(Rx, Rx, fmaf(Ry, Ry, fmaf(Rz, Rz, e2)));
     const float i1 = __builtin_amdgcn_rsqf(s2);
     const float i2 = i1 * i1, i3 = i1 * i2, i5 = i3 * i2, i7 = i5 * i2;
-    const float cR = -a.x * i3 + 1.5f * b.w * i5 - 7.5f * RIR * i7;
-    S.tx = fmaf(cR, Rx, fmaf(3.0f * i5, IRx, S.tx));
-    S.ty = fmaf(cR, Ry, fmaf(3.0f * i5, IRy, S.ty));
-    S.tz = fmaf(cR, Rz, fmaf(3.0f * i5, IRz, S.tz));
-    S.tph -= a.x * i1 + 1.5f * RIR * i5 - 0.5f * b.w * i3;
+    const float cR = fmaf(b.w, i5, fmaf(-2.5f * RQR, i7, -a.x * i3));
+    S.tx = fmaf(cR, Rx, fmaf(i5, QRx, S.tx));
+    S.ty = fmaf(cR, Ry, fmaf(i5, QRy, S.ty));
+    S.tz = fmaf(cR, Rz, fmaf(i5, QRz, S.tz));
+    S.tph -= fmaf(a.x, i1, fmaf(0.5f * RQR, i5, -d.w * i3));
 }
 
 __device__ __forceinline__ void part_term_f(const float4 me, const float4 sb, float e2, TargetSums& S) {
@@ -191,12 +176,14 @@ __device__ void eval_cells(int ncell, const int* cells, GravStage& St, const dou
             if (FP32C) {
                 St.cellf.c0[lane] = make_float4((float)c0.x, (float)(c0.y - T.o[0]), (float)(c0.z - T.o[1]),
                                                 (float)(c0.w - T.o[2]));
-                St.cellf.c1[lane] = make_float4((float)c1.x, (float)c1.y, (float)c1.z, (float)c1.w);
-                St.cellf.c2[lane] = make_float4((float)c2.x, (float)c2.y, (float)c2.z, 0.0f);
-            } else {
+                St.cellf.c1[lane] = make_float4((float)(3.0 * c1.x), (float)(3.0 * c1.y), (float)(3.0 * c1.z),
+                                                (float)(1.5 * c1.w));
+                St.cellf.c2[lane] = make_float4((float)(3.0 * c2.x), (float)(3.0 * c2.y), (float)(3.0 * c2.z),
+                                                (float)(0.5 * c1.w));
+            } else {  // the expansion's constants folded in (see cell_term)
                 St.cell.c0[lane] = c0;
-                St.cell.c1[lane] = c1;
-                St.cell.c2[lane] = c2;
+                St.cell.c1[lane] = make_double4(3.0 * c1.x, 3.0 * c1.y, 3.0 * c1.z, 1.5 * c1.w);
+                St.cell.c2[lane] = make_double4(3.0 * c2.x, 3.0 * c2.y, 3.0 * c2.z, 0.5 * c1.w);
             }
         }
         __syncthreads();
@@ -214,8 +201,8 @@ __device__ void eval_cells(int ncell, const int* cells, GravStage& St, const dou
         } else {
             for (int k = T.phi; k < cn; k += T.P) {
                 const double4 a = St.cell.c0[k], b = St.cell.c1[k], d = St.cell.c2[k];
-                cell_term<false>(T.a, a, b, d, e2, A);
-                cell_term<false>(T.b, a, b, d, e2, B);
+                cell_term(T.a, a, b, d, e2, A);
+                cell_term(T.b, a, b, d, e2, B);
             }
         }
     }
