@@ -432,12 +432,12 @@ void orc_dedt(const double* x, const double* y, const double* z, const double* v
  *   phi_a = -G sum_{b != a} m_b / sqrt(r_ab^2 + eps^2).                                   */
 void orc_gravity_direct(int64_t n, const double* x, const double* y, const double* z, const double* m,
                         double G, double eps, int64_t ntgt, const int64_t* tgt, double* gx, double* gy,
-                        double* gz, double* phi)
+                        double* gz, double* phi, double* sg)
 {
 #pragma omp parallel for schedule(dynamic, 16)
     for (int64_t t = 0; t < ntgt; ++t) {
         int64_t a = tgt ? tgt[t] : t;
-        double sx = 0, sy = 0, sz = 0, sp = 0;
+        double sx = 0, sy = 0, sz = 0, sp = 0, sa = 0;
         for (int64_t b = 0; b < n; ++b) {
             if (b == a) continue;
             double dx = x[a] - x[b], dy = y[a] - y[b], dz = z[a] - z[b];
@@ -448,9 +448,11 @@ void orc_gravity_direct(int64_t n, const double* x, const double* y, const doubl
             sy -= m[b] * dy * inv3;
             sz -= m[b] * dz * inv3;
             sp -= m[b] * inv;
+            if (sg) sa += m[b] * sqrt(dx * dx + dy * dy + dz * dz) * inv3;
         }
         gx[t] = G * sx; gy[t] = G * sy; gz[t] = G * sz;
         if (phi) phi[t] = G * sp;
+        if (sg) sg[t] = fabs(G) * sa;   /* absolute-sum scale: sum of the terms' magnitudes */
     }
 }
 

@@ -60,7 +60,7 @@ def lib():
         L.orc_density.argtypes = [_d, _d, _d, _d, _d, _d, DBL, DBL, I64, _i64, _i64, _i64, _d, _d, _d, _d]
         L.orc_forces.argtypes = [_d] * 11 + [DBL, DBL, DBL, I64, _i64, _i64, _i64] + [_d] * 6
         L.orc_dedt.argtypes = [_d] * 11 + [DBL, DBL, DBL, I64, _i64, _i64, _i64] + [_d] * 2
-        L.orc_gravity_direct.argtypes = [I64, _d, _d, _d, _d, DBL, DBL, I64, _i64, _d, _d, _d, _d]
+        L.orc_gravity_direct.argtypes = [I64, _d, _d, _d, _d, DBL, DBL, I64, _i64, _d, _d, _d, _d, _d]
         L.orc_moments.argtypes = [I64, I64, _i64, _d, _d, _d, _d, _d]
         L.orc_quad_field.argtypes = [_d, DBL, DBL, DBL, DBL, DBL, _d, _d]
         L.orc_tree_gravity.argtypes = ([I64, I64, _i32, _i32, _i64, _i64, _d, _d, _d, _d, DBL, DBL, DBL, DBL,
@@ -230,14 +230,17 @@ def dedt(ps_or_arrays, rho, P, c, csr, alpha=1.0, beta=2.0, eps_av=0.01, targets
     return de, se
 
 
-def gravity_direct(x, y, z, m, G=1.0, eps=0.0, targets=None):
+def gravity_direct(x, y, z, m, G=1.0, eps=0.0, targets=None, scale=False):
+    """Direct softened sums (eq. (10) with every cell opened): gx, gy, gz, phi, and with
+    scale=True also the absolute-sum scale |G| sum_b m_b |r_ab| / s_ab^3 of each target."""
     x, y, z, m = _f64(x), _f64(y), _f64(z), _f64(m)
     tg = _ii(targets)
     nt = x.size if tg is None else tg.size
     gx, gy, gz, phi = (np.empty(nt) for _ in range(4))
+    sg = np.empty(nt) if scale else None
     lib().orc_gravity_direct(x.size, _p(x), _p(y), _p(z), _p(m), G, eps, nt, _p(tg, _i64), _p(gx), _p(gy),
-                             _p(gz), _p(phi))
-    return gx, gy, gz, phi
+                             _p(gz), _p(phi), _p(sg))
+    return (gx, gy, gz, phi, sg) if scale else (gx, gy, gz, phi)
 
 
 def moments(x, y, z, m, idx=None):
@@ -310,39 +313,45 @@ class Params:
 
 
 def accelerations(st: dict, prm: Params, vel=None, u=None, seg=None):
-    """Hydro (+ direct gravity) accelerations for the whole set.  Returns
-    (ax, ay, az, dudt, rho, P, c, h_next).  u overrides the state's thermal energy in the EOS.
-    Thermokinetic: the fourth value is de/dt of eq. (8), plus v . g with gravity (the work of
-    gravity on e = u + v^2/2)."""
+    """Hydro (+ direct gravity) accelerations for the whole set, as a dict: ax, ay, az, dudt,
+    rho, P, c, h_next, and the absolute-sum scales Sa (of the acceleration) and Su (of dudt):
+    each the sum of its terms' magnitudes, gravity's included.  u overrides the state's thermal
+    energy in the EOS.  Thermokinetic: dudt is de/dt of eq. (8), plus v . g with gravity (the
+    work of gravity on e = u + v^2/2)."""
     csr = neighbors(st["x"], st["y"], st["z"], st["h"], seg=seg)
     d = dict(st)
     if u is not None:
         d["u"] = u
     rho, P, c, hn = density(d, csr, prm.gamma, prm.h_coeff)
-    ax, ay, az, du, _, _ = forces(d, rho, P, c, csr, prm.alpha, prm.beta, prm.eps_av, vel=vel)
+    ax, ay, az, du, Sa, Su = forces(d, rho, P, c, csr, prm.alpha, prm.beta, prm.eps_av, vel=vel)
     if prm.thermokinetic:
-        du, _ = dedt(d, rho, P, c, csr, prm.alpha, prm.beta, prm.eps_av, vel=vel)
+        du, Su = dedt(d, rho, P, c, csr, prm.alpha, prm.beta, prm.eps_av, vel=vel)
     if prm.G != 0.0:
-        gx, gy, gz, _ = gravity_direct(st["x"], st["y"], st["z"], st["m"], prm.G, prm.soft_eps)
+        gx, gy, gz, _, sg = gravity_direct(st["x"], st["y"], st["z"], st["m"], prm.G, prm.soft_eps, scale=True)
         ax, ay, az = ax + gx, ay + gy, az + gz
+        Sa = Sa + sg
         if prm.thermokinetic:
             v = vel if vel is not None else (st["vx"], st["vy"], st["vz"])
             du = du + (v[0] * gx + v[1] * gy + v[2] * gz)
-    return ax, ay, az, du, rho, P, c, hn
+            Su = Su + np.sqrt(v[0] ** 2 + v[1] ** 2 + v[2] ** 2) * sg
+    return dict(ax=ax, ay=ay, az=az, dudt=du, rho=rho, P=P, c=c, h_next=hn, Sa=Sa, Su=Su)
 
 
 def prime(st: dict, prm: Params, seg=None):
-    """Accelerations at t = 0 and, for adaptive h, h <- h_coeff (m / rho)^(1/3)."""
+    """Accelerations at t = 0 and, for adaptive h, h <- h_coeff (m / rho)^(1/3).  The result
+    also carries rho, cs (the sound speed) and the scales Sa, Su of that pass."""
     st = {k: np.array(v, dtype=np.float64) for k, v in st.items()}
-    ax, ay, az, du, rho, P, c, hn = accelerations(st, prm, seg=seg)
-    st.update(ax=ax, ay=ay, az=az, dudt=du)
+    r = accelerations(st, prm, seg=seg)
+    st.update(ax=r["ax"], ay=r["ay"], az=r["az"], dudt=r["dudt"], rho=r["rho"], cs=r["c"], Sa=r["Sa"], Su=r["Su"])
     if prm.adaptive_h:
-        st["h"] = hn
+        st["h"] = r["h_next"]
     return st
 
 
-def kdk_step(st: dict, dt: float, prm: Params, seg=None):
-    """One step from a primed state (dict with x..u, ax, ay, az, dudt)."""
+def kdk_step(st: dict, dt, prm: Params, seg=None):
+    """One step from a primed state (dict with x..u, ax, ay, az, dudt).  dt is a number, or an
+    array of one step size per particle (independent sets stepping by their own dt).  The
+    result also carries rho, cs and the scales Sa, Su of the step's force pass."""
     if prm.thermokinetic:
         return _kdk_step_thermokinetic(st, dt, prm, seg)
     s = {k: np.array(v, dtype=np.float64) for k, v in st.items()}
@@ -352,16 +361,16 @@ def kdk_step(st: dict, dt: float, prm: Params, seg=None):
     s["x"], s["y"], s["z"] = s["x"] + dt * vhx, s["y"] + dt * vhy, s["z"] + dt * vhz
     vpx, vpy, vpz = vhx + half * s["ax"], vhy + half * s["ay"], vhz + half * s["az"]
     up = uh + half * s["dudt"]
-    ax, ay, az, du, rho, P, c, hn = accelerations(s, prm, vel=(vpx, vpy, vpz), u=up, seg=seg)
-    s["vx"], s["vy"], s["vz"] = vhx + half * ax, vhy + half * ay, vhz + half * az
-    s["u"] = uh + half * du
-    s.update(ax=ax, ay=ay, az=az, dudt=du, rho=rho)
+    r = accelerations(s, prm, vel=(vpx, vpy, vpz), u=up, seg=seg)
+    s["vx"], s["vy"], s["vz"] = vhx + half * r["ax"], vhy + half * r["ay"], vhz + half * r["az"]
+    s["u"] = uh + half * r["dudt"]
+    s.update(ax=r["ax"], ay=r["ay"], az=r["az"], dudt=r["dudt"], rho=r["rho"], cs=r["c"], Sa=r["Sa"], Su=r["Su"])
     if prm.adaptive_h:
-        s["h"] = hn
+        s["h"] = r["h_next"]
     return s
 
 
-def _kdk_step_thermokinetic(st: dict, dt: float, prm: Params, seg=None):
+def _kdk_step_thermokinetic(st: dict, dt, prm: Params, seg=None):
     """The same kick-drift-kick with the total energy e = u + v^2/2 in place of u:
     e' = e + dt/2 de; predictor e^ = e' + dt/2 de and u^ = e^ - |v^|^2/2 for the EOS;
     e = e' + dt/2 de_new; the returned state holds u = e - |v|^2/2."""
@@ -374,14 +383,28 @@ def _kdk_step_thermokinetic(st: dict, dt: float, prm: Params, seg=None):
     vpx, vpy, vpz = vhx + half * s["ax"], vhy + half * s["ay"], vhz + half * s["az"]
     ep = eh + half * s["dudt"]
     up = ep - 0.5 * (vpx ** 2 + vpy ** 2 + vpz ** 2)
-    ax, ay, az, de, rho, P, c, hn = accelerations(s, prm, vel=(vpx, vpy, vpz), u=up, seg=seg)
-    s["vx"], s["vy"], s["vz"] = vhx + half * ax, vhy + half * ay, vhz + half * az
-    e = eh + half * de
+    r = accelerations(s, prm, vel=(vpx, vpy, vpz), u=up, seg=seg)
+    s["vx"], s["vy"], s["vz"] = vhx + half * r["ax"], vhy + half * r["ay"], vhz + half * r["az"]
+    e = eh + half * r["dudt"]
     s["u"] = e - 0.5 * (s["vx"] ** 2 + s["vy"] ** 2 + s["vz"] ** 2)
-    s.update(ax=ax, ay=ay, az=az, dudt=de, rho=rho)
+    s.update(ax=r["ax"], ay=r["ay"], az=r["az"], dudt=r["dudt"], rho=r["rho"], cs=r["c"], Sa=r["Sa"], Su=r["Su"])
     if prm.adaptive_h:
-        s["h"] = hn
+        s["h"] = r["h_next"]
     return s
+
+
+def dt_bound(st: dict, eps=0.0, seg_offsets=None):
+    """Time-step bound of a state that carries h, cs and the accelerations: per set, the
+    minimum over its particles of min(h/c, sqrt(eps/|a|)); the second term only for eps > 0
+    and |a| > 0.  One value per set (seg_offsets), or one for the whole state."""
+    b = st["h"] / st["cs"]
+    if eps > 0.0:
+        a = np.sqrt(st["ax"] ** 2 + st["ay"] ** 2 + st["az"] ** 2)
+        with np.errstate(divide="ignore"):
+            g = np.where(a > 0.0, np.sqrt(eps / np.where(a > 0.0, a, 1.0)), np.inf)
+        b = np.minimum(b, g)
+    so = [0, b.size] if seg_offsets is None else list(seg_offsets)
+    return np.array([b[so[i]:so[i + 1]].min() if so[i + 1] > so[i] else np.inf for i in range(len(so) - 1)])
 
 
 def diagnostics(st: dict, phi=None):

@@ -176,36 +176,29 @@ def test_octree_matches_level_construction(orc, cap, min_level):
 
 
 # ---------------------------------------------------------------------------- neighbours
-def _lattice_sum(hfac):
-    """Closed lattice sum for an infinite cubic lattice with h = hfac dx (dx = 1, m = 1):
-    sum over integer vectors n with |n| < 2 hfac of w(|n|/hfac) / (pi hfac^3), and the
-    number of such vectors."""
-    R = int(math.ceil(2 * hfac)) + 1
-    s, cnt = 0.0, 0
-    for i in range(-R, R + 1):
-        for j in range(-R, R + 1):
-            for k in range(-R, R + 1):
-                r = math.sqrt(i * i + j * j + k * k)
-                q = r / hfac
-                if q < 2.0:
-                    cnt += 1
-                    s += (1 - 1.5 * q * q + 0.75 * q ** 3 if q < 1 else 0.25 * (2 - q) ** 3) / (math.pi * hfac ** 3)
-    return s, cnt
+# Closed lattice sums of an infinite cubic lattice with h = hfac dx (m = dx^3 = rho0 = 1):
+# rho/rho0 = sum over integer vectors n with |n| < 2 hfac of w(|n|/hfac) / (pi hfac^3), self
+# included, and the number of such vectors.  The values were computed independently of this
+# repository's code (high-precision sums of the M4 kernel); the short ones carry 5 digits.
+LATTICE_SUMS = {1.0: (0.99997, 27, 5e-6), 1.2: (1.000809548358436, 57, 1e-13), 1.3: (0.99726, 81, 5e-6),
+                1.5: (1.00179, 93, 5e-6)}
 
 
-def test_lattice_density_and_neighbour_count(orc):
+@pytest.mark.parametrize("hfac", sorted(LATTICE_SUMS))
+def test_lattice_density_and_neighbour_count(orc, hfac):
     """A perfect lattice recovers rho0 up to the closed lattice sum; interior particles have
-    exactly as many neighbours as integer vectors inside radius 2.4 (57, self included)."""
+    exactly as many neighbours as integer vectors inside radius 2 hfac (self included)."""
     ps = lattice_box(16, jitter=0.0, v_sigma=0.0)
     dx = 1.0 / 16
+    ps.h = np.full(ps.n, hfac * dx)
     csr = orc.neighbors(ps.x, ps.y, ps.z, ps.h)
     rho, P, c, hn = orc.density(ps.fields(), csr)
-    inner = ((ps.x > 2.4 * dx) & (ps.x < 1 - 2.4 * dx) & (ps.y > 2.4 * dx) & (ps.y < 1 - 2.4 * dx)
-             & (ps.z > 2.4 * dx) & (ps.z < 1 - 2.4 * dx))
-    ref, cnt = _lattice_sum(1.2)
-    assert cnt == 57
-    assert (np.diff(csr[0])[inner] == 57).all()
-    assert np.allclose(rho[inner], ref, rtol=1e-13, atol=0)
+    e = 2 * hfac * dx
+    inner = ((ps.x > e) & (ps.x < 1 - e) & (ps.y > e) & (ps.y < 1 - e) & (ps.z > e) & (ps.z < 1 - e))
+    ref, cnt, rtol = LATTICE_SUMS[hfac]
+    assert inner.sum() > 0
+    assert (np.diff(csr[0])[inner] == cnt).all()
+    assert np.allclose(rho[inner], ref, rtol=rtol, atol=0)
 
 
 def test_neighbours_match_kdtree(orc):
@@ -666,3 +659,102 @@ def test_kdk_momentum_and_energy_order(orc):
         errs.append(abs((E1[6] + E1[7]) - (E0[6] + E0[7])))
         assert np.abs(E1[:3] - E0[:3]).max() < 1e-15
     assert 7.0 < errs[0] / errs[1] < 20.0 and 7.0 < errs[1] / errs[2] < 20.0
+
+
+# ---------------------------------------------------------------------------- diagnostics, time step
+def test_diagnostics_rigid_rotation_closed_form(orc):
+    """Rigid rotation v = w z_hat x r of a cell-centred n^3 lattice with spacing dx and equal
+    masses m: L_z = w m sum (x^2 + y^2) = w m 2 n^2 dx^2 (n^3/3 - n/12) (the 1D sum of
+    ((i + 1/2) dx)^2), L_x = L_y = 0, P = 0 about the lattice centre, E_kin = w L_z / 2."""
+    n, dx, w, m = 10, 0.1, 0.7, 0.3
+    c = (np.arange(n) + 0.5) * dx - 0.5 * n * dx   # centred on the origin
+    X, Y, Z = (a.ravel() for a in np.meshgrid(c, c, c, indexing="ij"))
+    st = dict(x=X, y=Y, z=Z, vx=-w * Y, vy=w * X, vz=np.zeros_like(X), m=np.full(X.size, m), u=np.ones(X.size))
+    d = orc.diagnostics(st)
+    s1 = dx * dx * (n ** 3 / 12.0 - n / 12.0)         # sum_i (i + 1/2 - n/2)^2 dx^2
+    Lz = w * m * 2 * n * n * s1
+    assert np.allclose(d[:3], 0.0, atol=1e-13)
+    assert np.allclose(d[3:5], 0.0, atol=1e-13)
+    assert abs(d[5] - Lz) <= 1e-13 * Lz
+    assert abs(d[6] - 0.5 * w * Lz) <= 1e-13 * Lz
+    assert d[7] == pytest.approx(m * X.size, rel=1e-15)
+    # L about a shifted origin picks up r0 x P = 0 (P = 0), so it is unchanged
+    st2 = dict(st, x=X + 3.0, vx=st["vx"], vy=st["vy"])
+    st2["vx"] = -w * Y
+    st2["vy"] = w * X
+    assert abs(orc.diagnostics(st2)[5] - Lz) <= 1e-12 * Lz
+
+
+def test_diagnostics_two_body_potential_energy(orc):
+    """E_grav = sum m phi / 2 of two softened point masses is -G m1 m2 / sqrt(r^2 + eps^2)."""
+    G, eps, m1, m2, r = 1.3, 0.05, 0.4, 0.9, 0.37
+    x, y, z = np.array([0.1, 0.1 + r]), np.zeros(2), np.zeros(2)
+    m = np.array([m1, m2])
+    _, _, _, phi = orc.gravity_direct(x, y, z, m, G, eps)
+    st = dict(x=x, y=y, z=z, vx=np.zeros(2), vy=np.zeros(2), vz=np.zeros(2), m=m, u=np.zeros(2))
+    eg = orc.diagnostics(st, phi)[8]
+    assert eg == pytest.approx(-G * m1 * m2 / math.sqrt(r * r + eps * eps), rel=1e-15)
+
+
+def test_gravity_absolute_sum_scale(orc):
+    """The direct sum's absolute-sum scale: for two bodies it is |g|; for a body midway between
+    two equal masses the pulls cancel (g = 0) while the scale is twice one pull."""
+    G, eps = 1.0, 0.01
+    x, y, z = np.array([0.0, 0.5]), np.zeros(2), np.zeros(2)
+    m = np.array([1.0, 2.0])
+    gx, gy, gz, phi, sg = orc.gravity_direct(x, y, z, m, G, eps, scale=True)
+    assert np.allclose(sg, np.abs(gx), rtol=1e-15)
+    x3 = np.array([-1.0, 0.0, 1.0])
+    gx, _, _, _, sg = orc.gravity_direct(x3, np.zeros(3), np.zeros(3), np.ones(3), G, eps, scale=True)
+    one = G * 1.0 / (1.0 + eps * eps) ** 1.5
+    assert abs(gx[1]) <= 1e-16 and sg[1] == pytest.approx(2 * one, rel=1e-14)
+
+
+def test_dt_bound_closed_forms(orc):
+    """Time-step bound min(h/c, sqrt(eps/|a|)): the sound speed c = sqrt(gamma (gamma - 1) u)
+    does not depend on rho, so a jittered lattice with one h and one u gives exactly
+    h / sqrt(gamma (gamma - 1) u) (10/9 for u = 1); two sets with their own u give one value
+    each; with gravity, two distant bodies (no hydro neighbours) are limited by the
+    free-fall term sqrt(eps / |a|) with |a| = G m r / (r^2 + eps^2)^(3/2)."""
+    prm = orc.Params()
+    ps = lattice_box(8, seed=5)
+    st = orc.prime(ps.fields(), prm)
+    assert orc.dt_bound(st)[0] == pytest.approx(ps.h[0] / math.sqrt(10.0 / 9.0), rel=1e-14)
+    # two sets: the second one hotter (u = 4 -> c doubles, bound halves)
+    a, b = lattice_box(6, seed=6), lattice_box(6, seed=7)
+    xs = {k: np.concatenate([getattr(a, k), getattr(b, k) + (5.0 if k == "x" else 0.0)])
+          for k in ("x", "y", "z", "vx", "vy", "vz", "m", "h", "u")}
+    xs["u"][a.n:] = 4.0
+    so = [0, a.n, a.n + b.n]
+    st2 = orc.prime(xs, prm, seg=orc.seg_ids(a.n + b.n, so))
+    bd = orc.dt_bound(st2, seg_offsets=so)
+    assert bd[0] == pytest.approx(a.h[0] / math.sqrt(10.0 / 9.0), rel=1e-14)
+    assert bd[1] == pytest.approx(b.h[0] / math.sqrt(40.0 / 9.0), rel=1e-14)
+    # gravity: two bodies 0.5 apart, h = 0.2 (no hydro pairs: r > h_a + h_b), softening 0.01
+    G, eps, r = 1.0, 0.01, 0.5
+    two = dict(x=np.array([0.0, r]), y=np.zeros(2), z=np.zeros(2), vx=np.zeros(2), vy=np.zeros(2), vz=np.zeros(2),
+               m=np.array([0.5, 0.5]), h=np.full(2, 0.2), u=np.full(2, 1.0))
+    st3 = orc.prime(two, orc.Params(G=G, soft_eps=eps))
+    acc = G * 0.5 * r / (r * r + eps * eps) ** 1.5
+    assert orc.dt_bound(st3, eps)[0] == pytest.approx(math.sqrt(eps / acc), rel=1e-14)
+    assert math.sqrt(eps / acc) < 0.2 / math.sqrt(10.0 / 9.0)   # the gravity term decides
+    assert orc.dt_bound(st3, 0.0)[0] == pytest.approx(0.2 / math.sqrt(10.0 / 9.0), rel=1e-14)
+
+
+def test_kdk_per_set_step_sizes(orc):
+    """Independent sets stepped with their own dt (one value per particle) evolve exactly as
+    each set stepped alone with its scalar dt."""
+    prm = orc.Params()
+    a, b = lattice_box(6, seed=8, v_sigma=0.1), lattice_box(5, seed=9, v_sigma=0.1)
+    fa, fb = a.fields(), b.fields()
+    both = {k: np.concatenate([fa[k], fb[k]]) for k in fa}   # overlapping, but separate sets
+    so = [0, a.n, a.n + b.n]
+    seg = orc.seg_ids(a.n + b.n, so)
+    st = orc.prime(both, prm, seg=seg)
+    dts = np.concatenate([np.full(a.n, 0.01), np.full(b.n, 0.004)])
+    s2 = orc.kdk_step(st, dts, prm, seg=seg)
+    ra = orc.kdk_step(orc.prime(fa, prm), 0.01, prm)
+    rb = orc.kdk_step(orc.prime(fb, prm), 0.004, prm)
+    for k in ("x", "vx", "u", "h", "ax", "dudt"):
+        assert np.array_equal(s2[k][:a.n], ra[k]), k
+        assert np.array_equal(s2[k][a.n:], rb[k]), k
