@@ -330,9 +330,12 @@ void orc_density(const double* x, const double* y, const double* z, const double
 
 /* Momentum (eq. (6), g = 0) and internal energy (eq. (5)) with Monaghan viscosity over a
  * CSR neighbour list (self entries skipped).  rho, P, c are indexed by particle.  Also
- * returns the absolute-sum scales used for the relative tolerance:
+ * returns the absolute-sum scales used for the relative tolerance, each the sum of the
+ * magnitudes of the elementary products the sum expands into (the dot product v . grad W
+ * counted as its three products, whose rounding does not shrink when v is orthogonal to
+ * grad W):
  *   Sa_a = sum_b m_b |(P_a/rho_a^2 + P_b/rho_b^2) + Pi_ab| |grad_a W_ab|
- *   Su_a = sum_b m_b |P_a/rho_a^2 + Pi_ab/2| |v_ab . grad_a W_ab|                       */
+ *   Su_a = sum_b m_b |P_a/rho_a^2 + Pi_ab/2| sum_d |v_ab,d (grad_a W_ab)_d|                */
 void orc_forces(const double* x, const double* y, const double* z, const double* vx, const double* vy,
                 const double* vz, const double* h, const double* m, const double* rho, const double* P,
                 const double* c, double alpha, double beta, double eps_av, int64_t ntgt, const int64_t* tgt,
@@ -370,7 +373,7 @@ void orc_forces(const double* x, const double* y, const double* z, const double*
             double vg = wx * gx + wy * gy + wz * gz;
             du += m[b] * (pa + 0.5 * Pi) * vg;
             sa += m[b] * fabs(term) * sqrt(gx * gx + gy * gy + gz * gz);
-            su += m[b] * fabs(pa + 0.5 * Pi) * fabs(vg);
+            su += m[b] * fabs(pa + 0.5 * Pi) * (fabs(wx * gx) + fabs(wy * gy) + fabs(wz * gz));
         }
         ax[t] = fx; ay[t] = fy; az[t] = fz; dudt[t] = du;
         if (Sa) Sa[t] = sa;
@@ -383,8 +386,8 @@ void orc_forces(const double* x, const double* y, const double* z, const double*
  * e_a = u_a + v_a^2 / 2 evolves as
  *   de_a/dt = -sum_{b != a} m_b (P_a v_b / rho_a^2 + P_b v_a / rho_b^2
  *                                + (v_a + v_b)/2 Pi_ab) . grad_a W_ab,
- * with W, h_ab and Pi_ab exactly as in orc_forces.  Se: the absolute-sum scale of the
- * three terms (for relative error bounds).                                             */
+ * with W, h_ab and Pi_ab exactly as in orc_forces.  Se: the absolute-sum scale (for
+ * relative error bounds), each dot product counted as its three products.              */
 void orc_dedt(const double* x, const double* y, const double* z, const double* vx, const double* vy,
               const double* vz, const double* h, const double* m, const double* rho, const double* P,
               const double* c, double alpha, double beta, double eps_av, int64_t ntgt, const int64_t* tgt,
@@ -418,7 +421,9 @@ void orc_dedt(const double* x, const double* y, const double* z, const double* v
             double vbg = vx[b] * gx + vy[b] * gy + vz[b] * gz;   /* v_b . grad_a W_ab */
             double t1 = pa * vbg, t2 = pb * vag, t3 = 0.5 * Pi * (vag + vbg);
             de -= m[b] * (t1 + t2 + t3);
-            se += m[b] * (fabs(t1) + fabs(t2) + fabs(t3));
+            double avag = fabs(vx[a] * gx) + fabs(vy[a] * gy) + fabs(vz[a] * gz);
+            double avbg = fabs(vx[b] * gx) + fabs(vy[b] * gy) + fabs(vz[b] * gz);
+            se += m[b] * (fabs(pa) * avbg + fabs(pb) * avag + fabs(0.5 * Pi) * (avag + avbg));
         }
         dedt[t] = de;
         if (Se) Se[t] = se;

@@ -105,3 +105,62 @@ def vec_rel_err(g3, r3, scale):
     d = np.sqrt(sum((a - b) ** 2 for a, b in zip(g3, r3)))
     scale = np.where(scale > 0, scale, 1e-300)
     return float(np.max(d / scale)) if d.size else 0.0
+
+
+def state_from(pa):
+    """The state sph_step wrote back (caller order), as numpy arrays."""
+    st = {k: to_np(pa[k]).copy() for k in ("x", "y", "z", "vx", "vy", "vz", "m", "h", "u")}
+    for k in ("ax", "ay", "az", "dudt"):
+        if pa[k] is not None:
+            st[k] = to_np(pa[k]).copy()
+    return st
+
+
+STEP_FIELDS = ("x", "y", "z", "vx", "vy", "vz", "u", "h", "ax", "ay", "az", "dudt")
+
+
+def step_scales(start, ref, dt, thermo=False):
+    """Per-particle scale of each field after one kick-drift-kick step from `start` (the
+    shared starting state, with its accelerations) to the oracle's `ref` (which carries the
+    absolute-sum scales Sa, Su of its force pass): the sum of the magnitudes of what enters the
+    field's update, so an error in the accelerations of size tol * Sa moves the field by at
+    most about tol times this scale.
+      x:  |x0| + |dt v'|,  v' = v0 + dt/2 a0
+      v:  |v'| + dt/2 (Sa0 + Sa)            (Sa0 when the start carries it)
+      u:  |u'| + dt/2 (Su0 + Su),  u' = u0 + dt/2 du0
+          (thermokinetic: e' = e0 + dt/2 de0 and u = e - v^2/2 adds |v| S_v + v^2/2)
+      a, du/dt: Sa, Su;  h: h."""
+    half = 0.5 * dt
+    sa0 = start.get("Sa", 0.0)
+    su0 = start.get("Su", 0.0)
+    vh = [start[v] + half * start[a] for v, a in (("vx", "ax"), ("vy", "ay"), ("vz", "az"))]
+    sc = {}
+    for k, v in zip(("x", "y", "z"), vh):
+        sc[k] = np.abs(start[k]) + np.abs(dt * v)
+    for k, v in zip(("vx", "vy", "vz"), vh):
+        sc[k] = np.abs(v) + half * (sa0 + ref["Sa"])
+    if thermo:
+        e0 = start["u"] + 0.5 * (start["vx"] ** 2 + start["vy"] ** 2 + start["vz"] ** 2)
+        eh = e0 + half * start["dudt"]
+        vmag = np.sqrt(ref["vx"] ** 2 + ref["vy"] ** 2 + ref["vz"] ** 2)
+        sv = np.sqrt(sum(v * v for v in vh)) + half * (sa0 + ref["Sa"])
+        sc["u"] = np.abs(eh) + half * (su0 + ref["Su"]) + vmag * sv + 0.5 * vmag ** 2
+    else:
+        uh = start["u"] + half * start["dudt"]
+        sc["u"] = np.abs(uh) + half * (su0 + ref["Su"])
+    sc["h"] = np.abs(ref["h"])
+    for k in ("ax", "ay", "az"):
+        sc[k] = ref["Sa"]
+    sc["dudt"] = ref["Su"]
+    return sc
+
+
+def step_errors(got, ref, start, dt, thermo=False):
+    """|got - ref| / scale per particle and field (see step_scales); 0/0 counts as 0."""
+    sc = step_scales(start, ref, dt, thermo)
+    out = {}
+    for k in STEP_FIELDS:
+        d = np.abs(got[k] - ref[k])
+        s = sc[k]
+        out[k] = np.where(s > 0, d / np.where(s > 0, s, 1.0), np.where(d > 0, np.inf, 0.0))
+    return out

@@ -19,7 +19,7 @@ def test_library_exports_every_declared_symbol():
     from paper_2007_03097_amd import _abi
     lib = _abi.load()
     decl = _declared()
-    assert len(decl) == 17
+    assert len(decl) >= 19
     for name in decl:
         assert hasattr(lib, name), name
     assert sorted(_abi.EXPORTS) == decl
@@ -64,6 +64,15 @@ def test_host_validation_without_gpu():
     assert lib.sph_build_tree(h, ctypes.byref(p), None, None, None) in (_abi.SPH_E_ARG, _abi.SPH_E_NOMEM)
     assert lib.sph_compute_forces(h, None, None, None, None, None, None, None) in (_abi.SPH_E_STATE, _abi.SPH_E_ARG)
     assert lib.sph_step(h, None, -1.0, 1, 0, None) == _abi.SPH_E_ARG
+    # per-set step sizes must be positive (checked before anything is launched)
+    bad_dt = (ctypes.c_double * 1)(0.0)
+    p.seg_dt = ctypes.cast(bad_dt, ctypes.POINTER(ctypes.c_double))
+    assert lib.sph_step(h, ctypes.byref(p), 1e-3, 1, 0, None) == _abi.SPH_E_ARG
+    assert b"seg_dt" in lib.sph_last_error(h)
+    bound = (ctypes.c_double * 1)()
+    assert lib.sph_timestep(h, bound) == _abi.SPH_E_STATE   # no resident state yet
+    assert lib.sph_timestep(None, bound) == _abi.SPH_E_ARG
+    assert lib.sph_key_order(h, None, None) == _abi.SPH_E_STATE
     assert lib.sph_last_error(h)
     assert lib.sph_destroy(None) == 0
     sph.sph_destroy(h)

@@ -71,6 +71,77 @@ def test_sod_full_size_sampled(orc):
     assert np.all(np.abs(du[tg] - r_du) <= 1e-12 * Su + 1e-300)
 
 
+def test_sod_full_size_evolved_sampled(orc, capsys):
+    """The tube after five resident steps (graph replays, the benchmark's dt and tuning), when
+    the pressure jump has set the gas moving and the viscosity and du/dt are active: on the
+    returned state, neighbour sets bit-exact and FP64 density within 1e-12 for 2048 sampled
+    targets plus the interface region, forces (layered) within 1e-12 of each target's
+    absolute-sum scale; FP32C density and forces on the same state within 2e-6 (median and max
+    printed per field)."""
+    import torch
+    import paper_2007_03097_amd as sph
+    ps = sod_tube(56)
+    n = ps.n
+    ctx = make_ctx(n, adaptive_h=1)
+    pa = parts(ps, with_accel=True)
+    tuned(ctx, pa)
+    sph.sph_step(ctx.h, pa, 1e-12, 0, 0)                 # prime
+    dt = 0.25 * sph.sph_timestep(ctx.h, 1)[0]
+    pa = parts(ps, with_accel=True)
+    sph.sph_step(ctx.h, pa, dt, 5, 0)
+    ev = ps.copy()
+    for k in ("x", "y", "z", "vx", "vy", "vz", "h", "u"):
+        setattr(ev, k, to_np(pa[k]).copy())
+    vmax = np.sqrt(ev.vx ** 2 + ev.vy ** 2 + ev.vz ** 2).max()
+    print(f"\nevolved tube: dt {dt:.3e}, 5 steps, max |v| {vmax:.3e}", flush=True)
+    assert vmax > 1e-3
+    rng = np.random.default_rng(6)
+    tg = np.sort(rng.choice(n, 2048, replace=False))
+    tg = np.unique(np.concatenate([tg, np.nonzero(np.abs(ev.x - 0.5) < 0.01)[0][::41]]))
+    roff, ridx = orc.neighbors(ev.x, ev.y, ev.z, ev.h, targets=tg)
+    results = {}
+    for prec in (0, 1):
+        c2 = make_ctx(n, adaptive_h=1, precision=prec)
+        pe = parts(ev)
+        tuned(c2, pe)
+        gpu_keys_order(c2, pe)
+        if prec == 0:
+            off = torch.zeros(n + 1, dtype=torch.int64, device="cuda")
+            total = sph.sph_find_neighbors(c2.h, off, None, 0)
+            idx = torch.zeros(total, dtype=torch.int32, device="cuda")
+            sph.sph_find_neighbors(c2.h, off, idx, total)
+            off, idx = to_np(off), to_np(idx)
+            for j, a in enumerate(tg):
+                assert np.array_equal(idx[off[a]:off[a + 1]], ridx[roff[j]:roff[j + 1]]), a
+        rho, P, c, hn = gpu_density(c2, n)
+        outs = [torch.zeros(n, dtype=torch.float64, device="cuda") for _ in range(4)]
+        sph.sph_compute_forces(c2.h, *outs)
+        results[prec] = (rho, P, c, hn, [to_np(x) for x in outs])
+        c2.close()
+    rho, P, c, hn, (ax, ay, az, du) = results[0]
+    r_rho, r_P, r_c, r_hn = orc.density(ev.fields(), (roff, ridx), targets=tg)
+    assert rel_err(rho[tg], r_rho, r_rho) <= 1e-12
+    assert rel_err(hn[tg], r_hn, r_hn) <= 1e-12
+    r_ax, r_ay, r_az, r_du, Sa, Su = orc.forces(ev.fields(), rho, P, c, (roff, ridx), targets=tg)
+    d = np.sqrt((ax[tg] - r_ax) ** 2 + (ay[tg] - r_ay) ** 2 + (az[tg] - r_az) ** 2)
+    assert np.all(d <= 1e-12 * Sa)
+    assert np.all(np.abs(du[tg] - r_du) <= 1e-12 * Su + 1e-300)
+    # the viscosity really acts on this state: without it the sampled forces change
+    n_ax, _, _, n_du, _, _ = orc.forces(ev.fields(), rho, P, c, (roff, ridx), alpha=0.0, beta=0.0, targets=tg)
+    assert np.abs(n_ax - r_ax).max() > 1e-6 * np.abs(r_ax).max() and np.abs(r_du).max() > 0.0
+    # FP32C on the same state against the oracle (its density by brute force, its forces given
+    # the FP64 density field that passed above)
+    f_rho, _, _, f_hn, (fx, fy, fz, fdu) = results[1]
+    e = dict(rho=np.abs(f_rho[tg] - r_rho) / r_rho, h_next=np.abs(f_hn[tg] - r_hn) / r_hn,
+             a=np.sqrt((fx[tg] - r_ax) ** 2 + (fy[tg] - r_ay) ** 2 + (fz[tg] - r_az) ** 2) / Sa,
+             du=np.abs(fdu[tg] - r_du) / np.where(Su > 0, Su, 1.0))
+    with capsys.disabled():
+        print("evolved tube FP32C vs oracle median/p99/max: " + "  ".join(
+            f"{k} {np.median(v):.1e}/{np.percentile(v, 99):.1e}/{v.max():.1e}" for k, v in e.items()), flush=True)
+    for k, v in e.items():
+        assert np.median(v) <= 2e-7 and v.max() <= 2e-6, k
+
+
 def test_polytrope_4m_gravity_sampled(orc, capsys):
     n = 4194304
     ps = polytrope_n1(n, seed=1003)

@@ -14,7 +14,7 @@ from workloads import ensemble, fig1_points, lattice_box, polytrope_n1, sod_tube
 from workloads.generators import ParticleSet
 
 from gpu_helpers import (gpu_density, gpu_forces, gpu_gravity, gpu_keys_order, gpu_neighbors, gpu_tree, make_ctx,
-                         parts, rel_err, vec_rel_err)
+                         parts, rel_err, step_errors, vec_rel_err)
 
 pytestmark = pytest.mark.gpu
 
@@ -475,18 +475,22 @@ def test_fmm_rejects_segments():
 
 # ---------------------------------------------------------------------------- leapfrog
 def _state_from(ps, pa):
-    from gpu_helpers import to_np
-    st = {k: to_np(pa[k]).copy() for k in ("x", "y", "z", "vx", "vy", "vz", "m", "h", "u")}
-    for k in ("ax", "ay", "az", "dudt"):
-        if pa[k] is not None:
-            st[k] = to_np(pa[k]).copy()
-    return st
+    from gpu_helpers import state_from
+    return state_from(pa)
+
+
+def _assert_step(got, ref, start, dt, step, thermo=False, tol=TOL):
+    """Every particle of every field within tol of its own scale (gpu_helpers.step_scales)."""
+    err = step_errors(got, ref, start, dt, thermo)
+    for k, e in err.items():
+        assert e.max() <= tol, (step, k, float(e.max()), int(np.argmax(e)))
 
 
 @pytest.mark.parametrize("case,adaptive,dt", [("lattice4096", 0, 0.0178), ("sod_small", 1, 4.0e-4)])
 def test_step_lockstep(orc, case, adaptive, dt):
     """KDK steps in lockstep: each GPU step starts from the GPU state, and the oracle takes
-    one step from that same state; fields agree to 1e-12 of their scale."""
+    one step from that same state; every particle of x, v, u, h, a and du/dt agrees to 1e-12 of
+    its own scale (the absolute-sum scale of the accelerations, carried through the kicks)."""
     import paper_2007_03097_amd as sph
     ps = CASES[case]()
     ctx = make_ctx(ps.n, adaptive_h=adaptive)
@@ -496,14 +500,10 @@ def test_step_lockstep(orc, case, adaptive, dt):
     flags = 0
     for step in range(3):
         start = st if step == 0 else _state_from(ps, pa)
-        if step > 0:
-            start = dict(start)
         sph.sph_step(ctx.h, pa, dt, 1, flags)
         got = _state_from(ps, pa)
-        ref = orc.kdk_step(start if step > 0 else st, dt, prm)
-        for k in ("x", "y", "z", "vx", "vy", "vz", "u", "h", "ax", "ay", "az", "dudt"):
-            scale = max(np.abs(ref[k]).max(), 1e-300)
-            assert np.abs(got[k] - ref[k]).max() <= 1e-11 * scale, (step, k)
+        ref = orc.kdk_step(start, dt, prm)
+        _assert_step(got, ref, start, dt, step)
         flags = sph.SPH_STEP_PRIMED
 
 
@@ -547,8 +547,8 @@ def test_hilbert_batched_and_physics(orc):
 
 
 def test_hilbert_step_lockstep(orc):
-    """Leapfrog steps with Hilbert ordering agree with the oracle (the curve changes only the
-    summation order)."""
+    """Leapfrog steps with Hilbert ordering agree with the oracle per particle to 1e-12 of each
+    field's scale (the curve changes only the summation order)."""
     import paper_2007_03097_amd as sph
     ps = CASES["sod_small"]()
     ctx = make_ctx(ps.n, adaptive_h=1, key_curve=sph.SPH_CURVE_HILBERT)
@@ -561,9 +561,7 @@ def test_hilbert_step_lockstep(orc):
         sph.sph_step(ctx.h, pa, 4.0e-4, 1, flags)
         got = _state_from(ps, pa)
         ref = orc.kdk_step(start, 4.0e-4, prm)
-        for k in ("x", "vx", "u", "h", "ax", "dudt"):
-            scale = max(np.abs(ref[k]).max(), 1e-300)
-            assert np.abs(got[k] - ref[k]).max() <= 1e-11 * scale, (step, k)
+        _assert_step(got, ref, start, 4.0e-4, step)
         flags = sph.SPH_STEP_PRIMED
 
 
@@ -607,8 +605,9 @@ def test_thermokinetic_rate(orc, case, prec):
                                                        ("polytrope", 1, 2.0e-3, 1.0, 1)])
 def test_thermokinetic_step_lockstep(orc, case, adaptive, dt, G, scheme):
     """Thermokinetic KDK steps in lockstep with the oracle (each GPU step starts from the GPU
-    state); with gravity (theta = 0: the direct sum, through either gravity scheme) de/dt
-    includes the work v.g."""
+    state), every particle within 1e-12 of its scale; with gravity (theta = 0: the direct sum,
+    through either gravity scheme) de/dt includes the work v.g and the scales include the
+    gravitational terms."""
     import paper_2007_03097_amd as sph
     ps = CASES[case]()
     if case == "lattice4096":
@@ -625,9 +624,7 @@ def test_thermokinetic_step_lockstep(orc, case, adaptive, dt, G, scheme):
         sph.sph_step(ctx.h, pa, dt, 1, flags)
         got = _state_from(ps, pa)
         ref = orc.kdk_step(start, dt, prm)
-        for k in ("x", "y", "z", "vx", "vy", "vz", "u", "h", "ax", "ay", "az", "dudt"):
-            scale = max(np.abs(ref[k]).max(), 1e-300)
-            assert np.abs(got[k] - ref[k]).max() <= 1e-11 * scale, (step, k)
+        _assert_step(got, ref, start, dt, step, thermo=True)
         flags = sph.SPH_STEP_PRIMED
 
 
@@ -680,9 +677,11 @@ def test_step_diagnostics_vs_oracle(orc):
         st = orc.kdk_step(st, 0.0178, prm)
     r1 = orc.diagnostics(st)
     assert np.abs(d1[:3] - d0[:3]).max() < 1e-14
-    assert np.abs(d0 - r0).max() < 1e-13
+    assert np.abs(d0[:9] - r0).max() < 1e-13
     assert np.abs(d1[:6] - r1[:6]).max() < 1e-12
     assert abs(d1[6] - r1[6]) < 1e-10 * r1[6] and abs(d1[7] - r1[7]) < 1e-12 * r1[7]
+    # the time-step bound (entry 9) of the free-running state follows the oracle's
+    assert abs(d1[9] - orc.dt_bound(st)[0]) < 1e-10 * d1[9]
 
 
 # ---------------------------------------------------------------------------- batched ensembles
