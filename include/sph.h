@@ -122,6 +122,8 @@ typedef struct {
     double *ax, *ay, *az, *dudt;  /* device, sph_step only: accelerations and du/dt (de/dt
                                      in the thermokinetic form) of the current state (read
                                      when SPH_STEP_PRIMED, written on return when non-NULL)  */
+    const double* seg_dt;         /* host, sph_step only: n_seg step sizes (each > 0), set s
+                                     stepping by seg_dt[s]; NULL = every set steps by dt     */
 } sph_particles;
 
 /* Flags of sph_step. */
@@ -214,7 +216,7 @@ sph_status sph_compute_forces(sph_ctx* ctx, const double* rho, const double* P, 
  * Outputs: device double[n] in caller order; any may be NULL (not copied out). */
 sph_status sph_compute_gravity(sph_ctx* ctx, double* gx, double* gy, double* gz, double* phi);
 
-/* nsteps kick-drift-kick leapfrog steps of size dt (> 0):
+/* nsteps kick-drift-kick leapfrog steps of size dt (> 0; per set when ps->seg_dt is given):
  *   v' = v + dt/2 a;  u' = u + dt/2 du;  x += dt v';  predictors v^ = v' + dt/2 a, u^ = u' + dt/2 du;
  *   rebuild keys, tree and neighbours; density, EOS(u^), forces with v^ (+ gravity if G != 0);
  *   v = v' + dt/2 a_new;  u = u' + dt/2 du_new;  adaptive_h: h = h_coeff (m/rho)^(1/3).
@@ -225,10 +227,32 @@ sph_status sph_compute_gravity(sph_ctx* ctx, double* gx, double* gy, double* gz,
  * with adaptive_h, h is reset from that density).  The state stays on the device in key
  * order between steps; on return x, v, u, h (and ax..dudt when given) are written back in
  * caller order.  Synchronous.
- *   diag_host host double[9] or NULL: Px, Py, Pz, Lx, Ly, Lz, E_kin, E_th, E_grav of the
- *   final state (FP64 sums in a fixed order). */
+ *   diag_host host double[10] or NULL: Px, Py, Pz, Lx, Ly, Lz, E_kin, E_th, E_grav of the
+ *   final state (FP64 sums in a fixed order; E_grav = sum m phi / 2 with the last gravity
+ *   pass's potential), then the smallest time-step bound over all sets (see sph_timestep;
+ *   NaN when no density pass has run on the state, i.e. nsteps = 0 with SPH_STEP_PRIMED). */
 sph_status sph_step(sph_ctx* ctx, sph_particles* ps, double dt, int32_t nsteps, uint32_t flags,
                     double* diag_host);
+
+/* Time-step bound of the state the last sph_step left on the device (the step criterion of
+ * the configurations: a Courant-type h/c limit and, with self-gravity, the free-fall limit of
+ * the softening length): per set s, bound_host[s] = min over its particles of
+ * min(h_a/c_a, sqrt(soft_eps/|a_a|)), the second term only when G != 0 and soft_eps > 0 and
+ * |a_a| > 0.  h is the current smoothing length, c the sound speed of the last density pass
+ * (at the step's predicted state), a the last accelerations (gravity included).  The caller
+ * scales it by its Courant factor (0.25 in the configurations).  An empty set gives +inf.
+ *   bound_host host double[n_seg].  Synchronous.
+ * SPH_E_STATE without a previous sph_step, or when no density pass has run on the state. */
+sph_status sph_timestep(sph_ctx* ctx, double* bound_host);
+
+/* Keys and key order of the set the context holds (test and inspection path): after
+ * sph_build_tree, its keys and order; after sph_step, the keys of the step's last key sort
+ * (computed at the returned positions with each set's box of those positions) and the order
+ * of the resident state.  Synchronous.
+ *   keys_out  device uint64[n] in caller order, or NULL.
+ *   order_out device int64[n]: caller index of the i-th particle in key order, or NULL.
+ * SPH_E_STATE without a previous sph_build_tree or sph_step. */
+sph_status sph_key_order(sph_ctx* ctx, uint64_t* keys_out, int64_t* order_out);
 
 /* Times sph_step over candidate leaf_size x group_size settings on ps (which it leaves
  * unchanged), then over waves_per_cu for the fastest pair, keeps the fastest in the context

@@ -25,7 +25,7 @@ STATUS_NAMES = {0: "SPH_OK", -1: "SPH_E_ARG", -2: "SPH_E_STATE", -3: "SPH_E_NOME
 EXPORTS = ["sph_config_default", "sph_create", "sph_destroy", "sph_workspace_size", "sph_set_workspace",
            "sph_build_tree", "sph_tree_nodes", "sph_find_neighbors", "sph_compute_density", "sph_compute_forces",
            "sph_compute_gravity", "sph_step", "sph_autotune", "sph_get_tuning", "sph_sync", "sph_last_error",
-           "sph_peak_probe"]
+           "sph_peak_probe", "sph_timestep", "sph_key_order"]
 
 
 class sph_config(ctypes.Structure):
@@ -43,7 +43,8 @@ _dp = ctypes.c_void_p  # device pointers are passed as integers
 class sph_particles(ctypes.Structure):
     _fields_ = [("n", ctypes.c_int64), ("n_seg", ctypes.c_int32), ("seg_offsets", ctypes.POINTER(ctypes.c_int64)),
                 ("x", _dp), ("y", _dp), ("z", _dp), ("vx", _dp), ("vy", _dp), ("vz", _dp), ("m", _dp), ("h", _dp),
-                ("u", _dp), ("ax", _dp), ("ay", _dp), ("az", _dp), ("dudt", _dp)]
+                ("u", _dp), ("ax", _dp), ("ay", _dp), ("az", _dp), ("dudt", _dp),
+                ("seg_dt", ctypes.POINTER(ctypes.c_double))]
 
 
 class SPHError(RuntimeError):
@@ -87,6 +88,8 @@ def load() -> ctypes.CDLL:
     L.sph_last_error.argtypes = [ctx_p]
     L.sph_last_error.restype = ctypes.c_char_p
     L.sph_peak_probe.argtypes = [i32, _dp, i64, i32, ctypes.c_void_p]
+    L.sph_timestep.argtypes = [ctx_p, P(dbl)]
+    L.sph_key_order.argtypes = [ctx_p, _dp, _dp]
     for name in EXPORTS:
         if name not in ("sph_config_default", "sph_last_error"):
             getattr(L, name).restype = ctypes.c_int

@@ -46,11 +46,13 @@ def _check(ctx, status):
 class ParticleArrays:
     """Device arrays (float64, caller order) of a particle set plus optional segments."""
 
-    def __init__(self, x, y, z, vx, vy, vz, m, h, u, seg_offsets=None, ax=None, ay=None, az=None, dudt=None):
+    def __init__(self, x, y, z, vx, vy, vz, m, h, u, seg_offsets=None, ax=None, ay=None, az=None, dudt=None,
+                 seg_dt=None):
         import torch
         self.t = dict(x=x, y=y, z=z, vx=vx, vy=vy, vz=vz, m=m, h=h, u=u, ax=ax, ay=ay, az=az, dudt=dudt)
         self.n = int(x.shape[0])
         self.seg = None if seg_offsets is None else np.ascontiguousarray(seg_offsets, dtype=np.int64)
+        self.seg_dt = None if seg_dt is None else np.ascontiguousarray(seg_dt, dtype=np.float64)
         self._dtype = torch.float64
 
     @classmethod
@@ -74,6 +76,11 @@ class ParticleArrays:
         for k in FIELDS + ACCEL:
             p = _ptr(self.t[k], self._dtype)
             setattr(s, k, p.value if p is not None else None)
+        if self.seg_dt is not None:
+            self._seg_dt_c = self.seg_dt.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+            s.seg_dt = self._seg_dt_c
+        else:
+            s.seg_dt = None
         return s
 
     def __getitem__(self, k):
@@ -155,7 +162,8 @@ def sph_compute_gravity(ctx, gx, gy, gz, phi=None):
 
 
 def sph_step(ctx, parts: ParticleArrays | None, dt: float, nsteps: int, flags: int = 0) -> np.ndarray:
-    diag = np.zeros(9)
+    """Returns the 10 diagnostics (momenta, angular momenta, energies, time-step bound)."""
+    diag = np.zeros(10)
     s = parts.struct() if parts is not None else None
     _check(ctx, _lib().sph_step(ctx, ctypes.byref(s) if s is not None else None, float(dt), int(nsteps), int(flags),
                                 diag.ctypes.data_as(ctypes.POINTER(ctypes.c_double))))
@@ -177,6 +185,20 @@ def sph_get_tuning(ctx):
     a, b, w = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
     _check(ctx, _lib().sph_get_tuning(ctx, ctypes.byref(a), ctypes.byref(b), ctypes.byref(w)))
     return int(a.value), int(b.value), int(w.value)
+
+
+def sph_timestep(ctx, n_seg: int = 1) -> np.ndarray:
+    """Time-step bound min(h/c, sqrt(eps/|a|)) of each set of the resident state."""
+    out = np.zeros(n_seg)
+    _check(ctx, _lib().sph_timestep(ctx, out.ctypes.data_as(ctypes.POINTER(ctypes.c_double))))
+    return out
+
+
+def sph_key_order(ctx, keys_out=None, order_out=None):
+    import torch
+    if keys_out is not None and keys_out.element_size() != 8:
+        raise TypeError("keys_out must have 8-byte elements (int64 or uint64)")
+    _check(ctx, _lib().sph_key_order(ctx, _ptr(keys_out), _ptr(order_out, torch.int64)))
 
 
 def sph_sync(ctx):

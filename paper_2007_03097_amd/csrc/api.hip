@@ -27,7 +27,7 @@ struct Tables {
     int n_seg = 0;
     int gsz = 0;
     std::vector<int64_t> seg;  // offsets
-    int version = 0;           // bumped whenever the device tables change
+    int version = 0;           // identifies the device tables; never reused within a context
 };
 
 }  // namespace
@@ -46,6 +46,9 @@ struct sph_ctx {
     DevPtrs d[2]{};           // pointer sets: d[p] has the resident state in buffer set p
     Dims dm{};
     Tables tab;
+    int tab_gen = 0;          // last table version handed out (only ever increases)
+    std::vector<double> seg_dt;  // step size per segment of the current sph_step call
+    bool cs_ok = false;       // the resident sound speeds belong to the resident state
     hipStream_t stream = nullptr;
     hipStream_t cap_stream = nullptr;
     bool tree_ok = false, lists_ok = false, dens_ok = false, resident_ok = false;
@@ -53,7 +56,6 @@ struct sph_ctx {
     // graphs
     hipGraphExec_t gexec[2] = {nullptr, nullptr};
     hipGraph_t graph[2] = {nullptr, nullptr};
-    double g_dt = 0.0;
     int64_t g_n = -1;
     int g_leaf = 0, g_gsz = 0, g_waves = -1, g_tabv = -1;
     bool use_graph = true;
@@ -276,7 +278,7 @@ static sph_status prepare(sph_ctx* c, const sph_particles* p) {
         c->tab.n = p->n;
         c->tab.n_seg = n_seg;
         c->tab.seg = seg;
-        c->tab.version++;
+        c->tab.version = ++c->tab_gen;
     }
     return SPH_OK;
 }
@@ -301,13 +303,23 @@ static sph_status read_err(sph_ctx* c) {
     return fail(c, SPH_E_DEVICE, "device error word 0x%x", e);
 }
 
+// Forgets the captured step graphs (they hold workspace pointers and table sizes by value).
+static void drop_graphs(sph_ctx* c) {
+    for (int p = 0; p < 2; ++p) {
+        if (c->gexec[p]) { (void)hipGraphExecDestroy(c->gexec[p]); c->gexec[p] = nullptr; }
+        if (c->graph[p]) { (void)hipGraphDestroy(c->graph[p]); c->graph[p] = nullptr; }
+    }
+    c->g_tabv = -1;
+    c->g_n = -1;
+}
+
 // keys (caller order) -> sort -> key-ordered snapshot in buffer set 0 -> octree
 static sph_status build_from_caller(sph_ctx* c, const sph_particles* p, const double* box_host, uint64_t* keys_out,
                                     int64_t* order_out) {
     sph_status st = prepare(c, p);
     if (st != SPH_OK) return st;
     c->parity = 0;
-    c->tree_ok = c->lists_ok = c->dens_ok = c->resident_ok = false;
+    c->tree_ok = c->lists_ok = c->dens_ok = c->resident_ok = c->cs_ok = false;
     const DevPtrs& d = c->d[0];
     const Dims& dm = c->dm;
     if (dm.n == 0) {
@@ -440,7 +452,8 @@ sph_status sph_set_workspace(sph_ctx* c, void* ptr, size_t bytes) {
     HIPCHK(c, hipMemcpyAsync(c->d[0].ctl, &zero, sizeof zero, hipMemcpyHostToDevice, c->stream));
     HIPCHK(c, hipStreamSynchronize(c->stream));
     c->tab = Tables();
-    c->tree_ok = c->lists_ok = c->dens_ok = c->resident_ok = false;
+    drop_graphs(c);
+    c->tree_ok = c->lists_ok = c->dens_ok = c->resident_ok = c->cs_ok = false;
     return SPH_OK;
 }
 
@@ -593,22 +606,24 @@ static void step_launches(sph_ctx* c, hipStream_t s, int p) {
     const DevPtrs& a = c->d[p];
     const DevPtrs& b = c->d[1 - p];
     const int n = c->dm.n;
-    const double dt = c->g_dt;
     launch_box_init(s, a, c->dm);
-    launch_kick_drift(s, a, c->dm, dt);   // also merges the new box
+    launch_kick_drift(s, a, c->dm);       // also merges the new box
     launch_step_keys(s, a, c->dm);        // also derives L and S
     radix_sort(s, a, n);
     launch_step_permute(s, a, n);         // also writes the pair records
     build_octree(s, b, c->dm);
     accel_pass(c, s, b, b.up, c->cfg.energy_form == SPH_ENERGY_THERMOKINETIC);
-    launch_kick(s, b, n, dt, c->cfg.adaptive_h);
+    launch_kick(s, b, c->dm, c->cfg.adaptive_h);
 }
 
-static sph_status run_steps(sph_ctx* c, double dt, int nsteps) {
+// The kernels read each segment's step size from the control block, so a change of dt
+// needs no new graph.
+static sph_status run_steps(sph_ctx* c, int nsteps) {
     if (nsteps <= 0 || c->dm.n == 0) return SPH_OK;
-    const bool regraph = c->g_dt != dt || c->g_n != c->dm.n || c->g_leaf != c->leaf_size ||
-                         c->g_gsz != c->group_size || c->g_waves != c->waves || c->g_tabv != c->tab.version;
-    c->g_dt = dt;
+    HIPCHK(c, hipMemcpyAsync(c->d[0].ctl->seg_dt, c->seg_dt.data(), sizeof(double) * c->seg_dt.size(),
+                             hipMemcpyHostToDevice, c->stream));
+    const bool regraph = c->g_n != c->dm.n || c->g_leaf != c->leaf_size || c->g_gsz != c->group_size ||
+                         c->g_waves != c->waves || c->g_tabv != c->tab.version;
     if (!c->use_graph) {
         for (int k = 0; k < nsteps; ++k) {
             step_launches(c, c->stream, c->parity);
@@ -620,9 +635,8 @@ static sph_status run_steps(sph_ctx* c, double dt, int nsteps) {
     if (regraph || !c->gexec[0] || !c->gexec[1]) {
         if (!c->cap_stream) HIPCHK(c, hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking));
         HIPCHK(c, hipStreamSynchronize(c->stream));
+        drop_graphs(c);
         for (int p = 0; p < 2; ++p) {
-            if (c->gexec[p]) { (void)hipGraphExecDestroy(c->gexec[p]); c->gexec[p] = nullptr; }
-            if (c->graph[p]) { (void)hipGraphDestroy(c->graph[p]); c->graph[p] = nullptr; }
             HIPCHK(c, hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeThreadLocal));
             step_launches(c, c->cap_stream, p);
             HIPCHK(c, hipStreamEndCapture(c->cap_stream, &c->graph[p]));
@@ -645,6 +659,15 @@ static sph_status step_impl(sph_ctx* c, sph_particles* p, double dt, int32_t nst
                             bool write_back) {
     if (!(dt > 0.0) || !std::isfinite(dt)) return fail(c, SPH_E_ARG, "dt must be > 0");
     if (nsteps < 0) return fail(c, SPH_E_ARG, "nsteps must be >= 0");
+    if (p && p->seg_dt) {
+        const int ns = (flags & SPH_STEP_RESUME) ? c->dm.n_seg : p->n_seg;
+        if ((flags & SPH_STEP_RESUME) && p->n_seg != ns)
+            return fail(c, SPH_E_ARG, "SPH_STEP_RESUME with a different number of sets");
+        if (ns < 1 || ns > c->seg_cap) return fail(c, SPH_E_ARG, "n_seg = %d outside 1..%d", ns, c->seg_cap);
+        for (int s = 0; s < ns; ++s)
+            if (!(p->seg_dt[s] > 0.0) || !std::isfinite(p->seg_dt[s]))
+                return fail(c, SPH_E_ARG, "seg_dt[%d] must be > 0", s);
+    }
     sph_status st;
     if (flags & SPH_STEP_RESUME) {
         if (!c->resident_ok) return fail(c, SPH_E_STATE, "SPH_STEP_RESUME without a previous sph_step");
@@ -667,6 +690,7 @@ static sph_status step_impl(sph_ctx* c, sph_particles* p, double dt, int32_t nst
             } else {
                 accel_pass(c, c->stream, d, d.u, 0);
                 if (c->cfg.adaptive_h) launch_set_hnext(c->stream, d, n);
+                c->cs_ok = true;
             }
             if (c->cfg.energy_form == SPH_ENERGY_THERMOKINETIC) launch_add_kinetic(c->stream, d, n);
         }
@@ -674,23 +698,62 @@ static sph_status step_impl(sph_ctx* c, sph_particles* p, double dt, int32_t nst
         c->resident_ok = true;
     }
     c->tree_ok = c->lists_ok = c->dens_ok = false;
-    st = run_steps(c, dt, nsteps);
+    c->seg_dt.assign(c->dm.n_seg, dt);
+    if (p && p->seg_dt) c->seg_dt.assign(p->seg_dt, p->seg_dt + c->dm.n_seg);
+    st = run_steps(c, nsteps);
     if (st != SPH_OK) return st;
+    if (nsteps > 0 && c->dm.n > 0) c->cs_ok = true;
     const DevPtrs& d = c->d[c->parity];
     const int n = c->dm.n;
     if (diag) {
-        launch_diag(c->stream, d, n, c->cfg.G != 0.0, c->cfg.energy_form == SPH_ENERGY_THERMOKINETIC);
-        HIPCHK(c, hipMemcpyAsync(diag, d.ctl->diag, 9 * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+        launch_diag(c->stream, d, c->dm, c->cfg.G != 0.0, c->cfg.energy_form == SPH_ENERGY_THERMOKINETIC,
+                    c->cfg.G != 0.0 ? c->cfg.soft_eps : 0.0);
+        HIPCHK(c, hipMemcpyAsync(diag, d.ctl->diag, 10 * sizeof(double), hipMemcpyDeviceToHost, c->stream));
     }
     if (write_back && p && p->x && n > 0)
         launch_write_back(c->stream, d, n, p->x, p->y, p->z, p->vx, p->vy, p->vz, p->h, p->u, p->ax, p->ay, p->az,
                           p->dudt, c->cfg.energy_form == SPH_ENERGY_THERMOKINETIC);
     HIPCHK(c, hipGetLastError());
     HIPCHK(c, hipStreamSynchronize(c->stream));
+    if (diag && !c->cs_ok) diag[9] = NAN;  // no density pass on this state yet
     return read_err(c);
 }
 
 extern "C" {
+
+sph_status sph_timestep(sph_ctx* c, double* bound_host) {
+    if (!c || !bound_host) return SPH_E_ARG;
+    if (!c->resident_ok) return fail(c, SPH_E_STATE, "sph_timestep needs the state of a previous sph_step");
+    if (!c->cs_ok) return fail(c, SPH_E_STATE, "sph_timestep: no density pass on the resident state yet");
+    const int ns = c->dm.n_seg;
+    if (c->dm.n == 0) {
+        for (int s = 0; s < ns; ++s) bound_host[s] = INFINITY;
+        return SPH_OK;
+    }
+    const DevPtrs& d = c->d[c->parity];
+    launch_dt_bound(c->stream, d, c->dm, c->cfg.G != 0.0 ? c->cfg.soft_eps : 0.0);
+    std::vector<u64> enc(ns);
+    HIPCHK(c, hipMemcpyAsync(enc.data(), d.ctl->dtb_enc, sizeof(u64) * ns, hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    for (int s = 0; s < ns; ++s) {  // the ordered-integer encoding of k_dt_bound, inverted
+        const u64 e = enc[s];
+        const u64 b = (e >> 63) ? (e & 0x7fffffffffffffffull) : ~e;
+        double v;
+        memcpy(&v, &b, sizeof v);
+        bound_host[s] = v;
+    }
+    return read_err(c);
+}
+
+sph_status sph_key_order(sph_ctx* c, uint64_t* keys_out, int64_t* order_out) {
+    if (!c) return SPH_E_ARG;
+    if (!c->tree_ok && !c->resident_ok)
+        return fail(c, SPH_E_STATE, "sph_key_order needs a previous sph_build_tree or sph_step");
+    launch_resident_export(c->stream, c->d[c->parity], c->dm.n, (u64*)keys_out, order_out);
+    HIPCHK(c, hipGetLastError());
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    return read_err(c);
+}
 
 sph_status sph_step(sph_ctx* c, sph_particles* p, double dt, int32_t nsteps, uint32_t flags, double* diag_host) {
     if (!c) return SPH_E_ARG;
@@ -798,8 +861,9 @@ sph_status sph_autotune(sph_ctx* c, const sph_particles* p, double dt, const cha
     c->leaf_size = bL;
     c->group_size = bG;
     c->waves = bW;
-    c->resident_ok = false;
+    c->resident_ok = c->cs_ok = false;
     c->tab = Tables();
+    drop_graphs(c);
     if (cache && best < 1e300) {
         char entry[256];
         snprintf(entry, sizeof entry, "%s: [%d, %d, %d]", qkey.c_str(), bL, bG, bW);

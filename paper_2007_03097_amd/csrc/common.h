@@ -37,6 +37,8 @@ struct DevCtl {
     double scale[512];            // 2^B / L per segment (0 when L == 0)
     double side[512];             // L (root cell side) per segment
     double diag[16];              // step diagnostics
+    double seg_dt[512];           // step size of each segment (read by the kick kernels)
+    u64 dtb_enc[512];             // per segment: ordered-integer min of the time-step bound
 };
 
 // Device pointers of one context.  All arrays are carved out of the caller's workspace.
@@ -361,15 +363,17 @@ void launch_scatter_caller(hipStream_t s, const DevPtrs& d, int n, const double*
 void launch_fill_zero(hipStream_t s, int n, double* dst);
 void launch_gather_caller(hipStream_t s, const DevPtrs& d, int n, const double* src_caller, double* dst);
 void launch_box_init(hipStream_t s, const DevPtrs& d, const Dims& dm);
-void launch_kick_drift(hipStream_t s, const DevPtrs& d, const Dims& dm, double dt);
+void launch_kick_drift(hipStream_t s, const DevPtrs& d, const Dims& dm);
 void launch_step_keys(hipStream_t s, const DevPtrs& d, const Dims& dm);
 void launch_step_permute(hipStream_t s, const DevPtrs& d, int n);
-void launch_kick(hipStream_t s, const DevPtrs& d, int n, double dt, int adaptive_h);
+void launch_kick(hipStream_t s, const DevPtrs& d, const Dims& dm, int adaptive_h);
 void launch_set_hnext(hipStream_t s, const DevPtrs& d, int n);
-void launch_diag(hipStream_t s, const DevPtrs& d, int n, int with_phi, int kinetic_in_u);
+void launch_diag(hipStream_t s, const DevPtrs& d, const Dims& dm, int with_phi, int kinetic_in_u, double eps_grav);
 void launch_write_back(hipStream_t s, const DevPtrs& d, int n, double* x, double* y, double* z, double* vx,
                        double* vy, double* vz, double* h, double* u, double* ax, double* ay, double* az,
                        double* du, int kinetic_in_u);
+void launch_dt_bound(hipStream_t s, const DevPtrs& d, const Dims& dm, double eps_grav);
+void launch_resident_export(hipStream_t s, const DevPtrs& d, int n, u64* keys_caller, int64_t* order);
 void launch_add_kinetic(hipStream_t s, const DevPtrs& d, int n);
 void launch_load_accel(hipStream_t s, const DevPtrs& d, int n, const double* ax, const double* ay,
                        const double* az, const double* du);

@@ -19,9 +19,11 @@
 // contraction (each target has its own irregular list), so they run on the vector ALUs,
 // not on the matrix cores.
 //
-// FP32C: positions enter as FP32 offsets from the group's first particle (each offset
-// formed in FP64, then rounded), so a pair's difference is one FP32 subtraction of two
-// nearby offsets; everything else of the pair term is FP32, summed per thread with Kahan
+// FP32C: positions, and in the force pass velocities, enter as FP32 offsets from the group's
+// first particle (each offset formed in FP64, then rounded), so a pair's difference is one
+// FP32 subtraction of two nearby offsets rather than of two rounded absolute values (whose
+// rounding would dominate r_ab in a compact group, and v_ab in a smooth flow); everything
+// else of the pair term is FP32, summed per thread with Kahan
 // compensation (its error stays within about 2u times the sum of the terms' magnitudes,
 // whatever their signs); the partial sums combine in FP64 and results are stored in FP64.
 #include "common.h"
@@ -89,6 +91,10 @@ struct DensAcc<true> {
 // FP32 offset record of a position from the group origin o: (x - o, y - o, z - o, h).
 __device__ __forceinline__ float4 offset_rec(const double4 p, const double4 o) {
     return make_float4((float)(p.x - o.x), (float)(p.y - o.y), (float)(p.z - o.z), (float)p.w);
+}
+// FP32 velocity record relative to the group origin's velocity vo: (v - vo, m).
+__device__ __forceinline__ float4 vel_offset(const double4 v, const double4 vo) {
+    return make_float4((float)(v.x - vo.x), (float)(v.y - vo.y), (float)(v.z - vo.z), (float)v.w);
 }
 
 // Density sources staged in LDS: FP64 (x, y, z, h) and m, or FP32 offset records and m.
@@ -310,12 +316,17 @@ __global__ void __launch_bounds__(PAIR_THREADS) k_forces(
             }
             fx = sx; fy = sy; fz = sz; fu = su;
         } else {
-            const float4 mv = tv ? velf[q] : make_float4(0, 0, 0, 0);
+            // velocities as FP32 offsets from the group origin's (each formed in FP64): v_ab is
+            // then one subtraction of two nearby offsets, without the cancellation of two
+            // rounded absolute velocities in a smooth flow
+            const double4 vo = vel4[g.x];
+            const float4 mv = tv ? vel_offset(vel4[q], vo) : make_float4(0, 0, 0, 0);
             const float4 mt = tv ? thrf[q] : make_float4(1, 0, 0, 1);
             const double4 org = pos4[g.x];  // group origin
             const float4 mef = offset_rec(tv ? me : org, org);
             const float alf = (float)alpha, bef = (float)beta, epf = (float)eps_av;
             const float ipi = (float)M_1_PI_D;
+            const float3 vof = make_float3((float)vo.x, (float)vo.y, (float)vo.z);
             Kahan sx, sy, sz, su;
             for (int c0 = 0; c0 < nu; c0 += FORCE_CHUNK_F) {
                 const int cn = nu - c0 < FORCE_CHUNK_F ? nu - c0 : FORCE_CHUNK_F;
@@ -323,7 +334,7 @@ __global__ void __launch_bounds__(PAIR_THREADS) k_forces(
                 for (int i = tid; i < cn; i += PAIR_THREADS) {
                     const int b = un[c0 + i];
                     reinterpret_cast<float4*>(S.pos)[i] = offset_rec(pos4[b], org);
-                    reinterpret_cast<float4*>(S.vel)[i] = velf[b];
+                    reinterpret_cast<float4*>(S.vel)[i] = vel_offset(vel4[b], vo);
                     reinterpret_cast<float4*>(S.thr)[i] = thrf[b];
                 }
                 __syncthreads();
@@ -355,9 +366,9 @@ __global__ void __launch_bounds__(PAIR_THREADS) k_forces(
                     sx.add(-term * dx);
                     sy.add(-term * dy);
                     sz.add(-term * dz);
-                    if (THERMO) {
-                        const float var = fmaf(mv.x, dx, fmaf(mv.y, dy, mv.z * dz));
-                        const float vbr = fmaf(vb.x, dx, fmaf(vb.y, dy, vb.z * dz));
+                    if (THERMO) {  // eq. (8) takes the absolute velocities: origin + offsets
+                        const float var = fmaf(vof.x + mv.x, dx, fmaf(vof.y + mv.y, dy, (vof.z + mv.z) * dz));
+                        const float vbr = fmaf(vof.x + vb.x, dx, fmaf(vof.y + vb.y, dy, (vof.z + vb.z) * dz));
                         su.add(-vb.w * gw * fmaf(mt.y, vbr, fmaf(tb.y, var, 0.5f * Pi * (var + vbr))));
                     } else {
                         su.add(vb.w * fmaf(0.5f, Pi, mt.y) * gw * vr);

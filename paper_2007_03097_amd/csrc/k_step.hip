@@ -29,14 +29,15 @@ void launch_gather_caller(hipStream_t s, const DevPtrs& d, int n, const double* 
 }
 
 // v' = v + dt/2 a; u' = u + dt/2 du; x += dt v'; predictors v^ = v' + dt/2 a, u^ = u' + dt/2 du.
-// One block per chunk (chunks never cross a segment); the new positions' box is merged
-// into the segment's box on the way.
-__global__ void __launch_bounds__(256) k_kick_drift(DevCtl* ctl, const int4* __restrict__ chunk, double dt, double* x,
+// One block per chunk (chunks never cross a segment; dt is the segment's step size); the new
+// positions' box is merged into the segment's box on the way.
+__global__ void __launch_bounds__(256) k_kick_drift(DevCtl* ctl, const int4* __restrict__ chunk, double* x,
                                                     double* y, double* z, double* vx, double* vy, double* vz, double* u,
                                                     const double* __restrict__ ax, const double* __restrict__ ay,
                                                     const double* __restrict__ az, const double* __restrict__ du,
                                                     double* vpx, double* vpy, double* vpz, double* up) {
     const int4 ch = chunk[blockIdx.x];
+    const double dt = ctl->seg_dt[ch.z];
     const double half = 0.5 * dt;
     double lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
     for (int q = ch.x + threadIdx.x; q < ch.y; q += blockDim.x) {
@@ -58,9 +59,9 @@ __global__ void __launch_bounds__(256) k_kick_drift(DevCtl* ctl, const int4* __r
     }
     box_block_merge(ctl, ch.z, lo, hi, ch.y > ch.x);
 }
-void launch_kick_drift(hipStream_t s, const DevPtrs& d, const Dims& dm, double dt) {
+void launch_kick_drift(hipStream_t s, const DevPtrs& d, const Dims& dm) {
     if (dm.n_chunks > 0)
-        hipLaunchKernelGGL(k_kick_drift, dim3(dm.n_chunks), dim3(256), 0, s, d.ctl, d.chunk, dt, d.x, d.y, d.z, d.vx,
+        hipLaunchKernelGGL(k_kick_drift, dim3(dm.n_chunks), dim3(256), 0, s, d.ctl, d.chunk, d.x, d.y, d.z, d.vx,
                            d.vy, d.vz, d.u, d.ax, d.ay, d.az, d.du, d.vpx, d.vpy, d.vpz, d.up);
 }
 
@@ -86,23 +87,27 @@ void launch_step_permute(hipStream_t s, const DevPtrs& d, int n) {
     if (n > 0) hipLaunchKernelGGL(k_step_permute, g256(n), dim3(256), 0, s, n, d.val_a, d);
 }
 
-// v = v' + dt/2 a_new;  u = u' + dt/2 du_new;  optional lagged h update.
-__global__ void k_kick(int n, double dt, double* vx, double* vy, double* vz, double* u, const double* __restrict__ ax,
-                       const double* __restrict__ ay, const double* __restrict__ az, const double* __restrict__ du,
-                       double* h, const double* __restrict__ hnext, int adaptive) {
-    const int q = blockIdx.x * blockDim.x + threadIdx.x;
-    if (q >= n) return;
-    const double half = 0.5 * dt;
-    vx[q] = vx[q] + half * ax[q];
-    vy[q] = vy[q] + half * ay[q];
-    vz[q] = vz[q] + half * az[q];
-    u[q] = u[q] + half * du[q];
-    if (adaptive) h[q] = hnext[q];
+// v = v' + dt/2 a_new;  u = u' + dt/2 du_new;  optional lagged h update.  One block per
+// chunk, dt the segment's step size.
+__global__ void __launch_bounds__(256) k_kick(const DevCtl* __restrict__ ctl, const int4* __restrict__ chunk,
+                                              double* vx, double* vy, double* vz, double* u,
+                                              const double* __restrict__ ax, const double* __restrict__ ay,
+                                              const double* __restrict__ az, const double* __restrict__ du, double* h,
+                                              const double* __restrict__ hnext, int adaptive) {
+    const int4 ch = chunk[blockIdx.x];
+    const double half = 0.5 * ctl->seg_dt[ch.z];
+    for (int q = ch.x + threadIdx.x; q < ch.y; q += blockDim.x) {
+        vx[q] = vx[q] + half * ax[q];
+        vy[q] = vy[q] + half * ay[q];
+        vz[q] = vz[q] + half * az[q];
+        u[q] = u[q] + half * du[q];
+        if (adaptive) h[q] = hnext[q];
+    }
 }
-void launch_kick(hipStream_t s, const DevPtrs& d, int n, double dt, int adaptive_h) {
-    if (n > 0)
-        hipLaunchKernelGGL(k_kick, g256(n), dim3(256), 0, s, n, dt, d.vx, d.vy, d.vz, d.u, d.ax, d.ay, d.az, d.du, d.h,
-                           d.hnext, adaptive_h);
+void launch_kick(hipStream_t s, const DevPtrs& d, const Dims& dm, int adaptive_h) {
+    if (dm.n_chunks > 0)
+        hipLaunchKernelGGL(k_kick, dim3(dm.n_chunks), dim3(256), 0, s, d.ctl, d.chunk, d.vx, d.vy, d.vz, d.u, d.ax,
+                           d.ay, d.az, d.du, d.h, d.hnext, adaptive_h);
 }
 
 __global__ void k_set_hnext(int n, double* h, const double* __restrict__ hnext) {
@@ -143,17 +148,23 @@ __global__ void __launch_bounds__(256) k_diag1(int n, const double* __restrict__
     if (threadIdx.x < 9) part[blockIdx.x * 16 + threadIdx.x] = ((red[0][threadIdx.x] + red[1][threadIdx.x]) +
                                                                 red[2][threadIdx.x]) + red[3][threadIdx.x];
 }
-__global__ void k_diag2(const double* __restrict__ part, DevCtl* ctl) {
+__global__ void k_diag2(const double* __restrict__ part, DevCtl* ctl, int n_seg) {
     if (threadIdx.x < 9) {
         double s = 0.0;
         for (int b = 0; b < DIAG_BLOCKS; ++b) s += part[b * 16 + threadIdx.x];
         ctl->diag[threadIdx.x] = s;
+    } else if (threadIdx.x == 9) {  // smallest time-step bound over the segments
+        double b = INFINITY;
+        for (int k = 0; k < n_seg; ++k) b = fmin(b, dec_double(ctl->dtb_enc[k]));
+        ctl->diag[9] = b;
     }
 }
-void launch_diag(hipStream_t s, const DevPtrs& d, int n, int with_phi, int kin) {
-    hipLaunchKernelGGL(k_diag1, dim3(DIAG_BLOCKS), dim3(256), 0, s, n, d.x, d.y, d.z, d.vx, d.vy, d.vz, d.m, d.u,
+// Diagnostics of the resident state plus (diag[9]) the time-step bound of k_dt_bound.
+void launch_diag(hipStream_t s, const DevPtrs& d, const Dims& dm, int with_phi, int kin, double eps_grav) {
+    launch_dt_bound(s, d, dm, eps_grav);
+    hipLaunchKernelGGL(k_diag1, dim3(DIAG_BLOCKS), dim3(256), 0, s, dm.n, d.x, d.y, d.z, d.vx, d.vy, d.vz, d.m, d.u,
                        with_phi ? d.phi : nullptr, kin, d.diag_part);
-    hipLaunchKernelGGL(k_diag2, dim3(1), dim3(64), 0, s, d.diag_part, d.ctl);
+    hipLaunchKernelGGL(k_diag2, dim3(1), dim3(64), 0, s, d.diag_part, d.ctl, dm.n_seg);
 }
 
 // Resident key-ordered state -> caller order (kin: the resident u is e = u + v^2/2).
@@ -200,4 +211,58 @@ __global__ void k_load_accel(int n, const u32* __restrict__ id, const double* __
 void launch_load_accel(hipStream_t s, const DevPtrs& d, int n, const double* ax, const double* ay, const double* az,
                        const double* du) {
     if (n > 0) hipLaunchKernelGGL(k_load_accel, g256(n), dim3(256), 0, s, n, d.id, ax, ay, az, du, d.ax, d.ay, d.az, d.du);
+}
+
+// Time-step bound of the resident state, per segment: min over its particles of
+// min(h/c, sqrt(eps/|a|)) (the second term only when eps > 0, i.e. with self-gravity and
+// softening; |a| = 0 gives no bound).  h is the current smoothing length, c the sound speed
+// of the last density pass, a the last accelerations.  A minimum is exact in any order, so
+// the chunks merge into the segment's value with atomics on the ordered-integer encoding.
+__global__ void k_dt_bound_init(DevCtl* ctl, int n_seg) {
+    const int s = blockIdx.x * blockDim.x + threadIdx.x;
+    if (s < n_seg) ctl->dtb_enc[s] = enc_double(INFINITY);
+}
+__global__ void __launch_bounds__(256) k_dt_bound(DevCtl* ctl, const int4* __restrict__ chunk,
+                                                  const double* __restrict__ h, const double* __restrict__ cs,
+                                                  const double* __restrict__ ax, const double* __restrict__ ay,
+                                                  const double* __restrict__ az, double eps) {
+    const int4 ch = chunk[blockIdx.x];
+    double b = INFINITY;
+    for (int q = ch.x + threadIdx.x; q < ch.y; q += blockDim.x) {
+        double v = h[q] / cs[q];
+        if (eps > 0.0) {
+            const double a0 = ax[q], a1 = ay[q], a2 = az[q];
+            const double a = sqrt(a0 * a0 + a1 * a1 + a2 * a2);
+            if (a > 0.0) v = fmin(v, sqrt(eps / a));
+        }
+        b = fmin(b, v);
+    }
+    b = wave_min(b);
+    __shared__ double red[4];
+    if (lane_id() == 0) red[threadIdx.x >> 6] = b;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        const double m = fmin(fmin(red[0], red[1]), fmin(red[2], red[3]));
+        if (ch.y > ch.x) atomicMin(&ctl->dtb_enc[ch.z], enc_double(m));
+    }
+}
+void launch_dt_bound(hipStream_t s, const DevPtrs& d, const Dims& dm, double eps_grav) {
+    hipLaunchKernelGGL(k_dt_bound_init, dim3((dm.n_seg + 255) / 256), dim3(256), 0, s, d.ctl, dm.n_seg);
+    if (dm.n_chunks > 0)
+        hipLaunchKernelGGL(k_dt_bound, dim3(dm.n_chunks), dim3(256), 0, s, d.ctl, d.chunk, d.h, d.cs, d.ax, d.ay, d.az,
+                           eps_grav);
+}
+
+// Keys (caller order) and key order of the resident state: the sorted keys of the last key
+// sort, and the caller index of each sorted position.
+__global__ void k_resident_export(int n, const u32* __restrict__ id, const u64* __restrict__ skey, u64* keys,
+                                  int64_t* order) {
+    const int q = blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= n) return;
+    const u32 i = id[q];
+    if (keys) keys[i] = skey[q];
+    if (order) order[q] = (int64_t)i;
+}
+void launch_resident_export(hipStream_t s, const DevPtrs& d, int n, u64* keys_caller, int64_t* order) {
+    if (n > 0) hipLaunchKernelGGL(k_resident_export, g256(n), dim3(256), 0, s, n, d.id, d.key_a, keys_caller, order);
 }
