@@ -19,10 +19,11 @@
 // contraction (each target has its own irregular list), so they run on the vector ALUs,
 // not on the matrix cores.
 //
-// FP32C: positions, and in the force pass velocities, enter as FP32 offsets from the group's
-// first particle (each offset formed in FP64, then rounded), so a pair's difference is one
-// FP32 subtraction of two nearby offsets rather than of two rounded absolute values (whose
-// rounding would dominate r_ab in a compact group, and v_ab in a smooth flow); everything
+// FP32C: in the density pass positions enter as FP32 offsets from the group's first particle
+// (each offset formed in FP64, then rounded), so a pair's difference is one FP32 subtraction
+// of two nearby offsets; the force pass forms r_ab, v_ab and the support-edge margin
+// (h_a + h_b)^2 - r^2 in FP64 and rounds them once (their rounding in FP32 would dominate the
+// terms near the edge of the support and in smooth flows); everything
 // else of the pair term is FP32, summed per thread with Kahan
 // compensation (its error stays within about 2u times the sum of the terms' magnitudes,
 // whatever their signs); the partial sums combine in FP64 and results are stored in FP64.
@@ -92,10 +93,7 @@ struct DensAcc<true> {
 __device__ __forceinline__ float4 offset_rec(const double4 p, const double4 o) {
     return make_float4((float)(p.x - o.x), (float)(p.y - o.y), (float)(p.z - o.z), (float)p.w);
 }
-// FP32 velocity record relative to the group origin's velocity vo: (v - vo, m).
-__device__ __forceinline__ float4 vel_offset(const double4 v, const double4 vo) {
-    return make_float4((float)(v.x - vo.x), (float)(v.y - vo.y), (float)(v.z - vo.z), (float)v.w);
-}
+
 
 // Density sources staged in LDS: FP64 (x, y, z, h) and m, or FP32 offset records and m.
 template <bool FP32C>
@@ -228,8 +226,8 @@ struct ForceSrc<false> {
 };
 template <>
 struct ForceSrc<true> {
-    float4 pos[FORCE_CHUNK_F];  // offsets from the group origin, h
-    float4 vel[FORCE_CHUNK_F];
+    double4 pos[FORCE_CHUNK_F];  // x, y, z, h and predicted v, m in FP64: the pair's differences
+    double4 vel[FORCE_CHUNK_F];  // and its support-edge margin are formed in FP64
     float4 thr[FORCE_CHUNK_F];
 };
 static_assert(sizeof(ForceSrc<true>) >= 4 * PAIR_THREADS * sizeof(double), "the reduction reuses the staging");
@@ -316,25 +314,18 @@ __global__ void __launch_bounds__(PAIR_THREADS) k_forces(
             }
             fx = sx; fy = sy; fz = sz; fu = su;
         } else {
-            // velocities as FP32 offsets from the group origin's (each formed in FP64): v_ab is
-            // then one subtraction of two nearby offsets, without the cancellation of two
-            // rounded absolute velocities in a smooth flow
-            const double4 vo = vel4[g.x];
-            const float4 mv = tv ? vel_offset(vel4[q], vo) : make_float4(0, 0, 0, 0);
+            const double4 mv = tv ? vel4[q] : make_double4(0, 0, 0, 0);
             const float4 mt = tv ? thrf[q] : make_float4(1, 0, 0, 1);
-            const double4 org = pos4[g.x];  // group origin
-            const float4 mef = offset_rec(tv ? me : org, org);
             const float alf = (float)alpha, bef = (float)beta, epf = (float)eps_av;
             const float ipi = (float)M_1_PI_D;
-            const float3 vof = make_float3((float)vo.x, (float)vo.y, (float)vo.z);
             Kahan sx, sy, sz, su;
             for (int c0 = 0; c0 < nu; c0 += FORCE_CHUNK_F) {
                 const int cn = nu - c0 < FORCE_CHUNK_F ? nu - c0 : FORCE_CHUNK_F;
                 __syncthreads();
                 for (int i = tid; i < cn; i += PAIR_THREADS) {
                     const int b = un[c0 + i];
-                    reinterpret_cast<float4*>(S.pos)[i] = offset_rec(pos4[b], org);
-                    reinterpret_cast<float4*>(S.vel)[i] = vel_offset(vel4[b], vo);
+                    S.pos[i] = pos4[b];
+                    S.vel[i] = vel4[b];
                     reinterpret_cast<float4*>(S.thr)[i] = thrf[b];
                 }
                 __syncthreads();
@@ -343,18 +334,31 @@ __global__ void __launch_bounds__(PAIR_THREADS) k_forces(
                     const int kn = k + PL;
                     const int en = kn < cnt ? lst[kn * g.y] : INT_MAX;
                     const int j = e - c0;
-                    const float4 sb = reinterpret_cast<const float4*>(S.pos)[j];
-                    const float4 vb = reinterpret_cast<const float4*>(S.vel)[j];
+                    const double4 sb = S.pos[j];
+                    const double4 vb = S.vel[j];
                     const float4 tb = reinterpret_cast<const float4*>(S.thr)[j];
-                    const float dx = mef.x - sb.x, dy = mef.y - sb.y, dz = mef.z - sb.z;
-                    const float r2 = fmaf(dx, dx, fmaf(dy, dy, dz * dz));
+                    // the pair's separation, relative velocity and margin to the support edge
+                    // in FP64, rounded once to FP32: D = (h_a + h_b)^2 - r^2 has no
+                    // cancellation, so 2 - q = D/((T + r) h_ab) keeps FP32 relative accuracy as
+                    // q -> 2 (2 - q formed from an FP32 q loses digits there), and r_ab, v_ab
+                    // keep it however large the positions and velocities are against their
+                    // differences; the rest of the pair term is FP32
+                    const double ex = me.x - sb.x, ey = me.y - sb.y, ez = me.z - sb.z;
+                    const double r2d = fma(ex, ex, fma(ey, ey, ez * ez));
+                    const double Td = me.w + sb.w;
+                    const float Dm = (float)fma(Td, Td, -r2d);
+                    const float dx = (float)ex, dy = (float)ey, dz = (float)ez;
+                    const float r2 = (float)r2d;
                     const float r = __builtin_amdgcn_sqrtf(r2);
-                    const float hab = 0.5f * (mt.w + tb.w);
+                    const float T = (float)Td;
+                    const float hab = 0.5f * T;
                     const float ih = __builtin_amdgcn_rcpf(hab);
                     const float ih2 = ih * ih;
                     const float qq = r * ih;
-                    const float gw = m4_gf(qq, __builtin_amdgcn_rcpf(qq)) * (ih2 * ih2 * ih) * ipi;
-                    const float wx = mv.x - vb.x, wy = mv.y - vb.y, wz = mv.z - vb.z;
+                    const float tq = Dm * __builtin_amdgcn_rcpf((T + r) * hab);
+                    const float gq = qq < 1.0f ? fmaf(2.25f, qq, -3.0f) : -0.75f * (tq * tq) * __builtin_amdgcn_rcpf(qq);
+                    const float gw = gq * (ih2 * ih2 * ih) * ipi;
+                    const float wx = (float)(mv.x - vb.x), wy = (float)(mv.y - vb.y), wz = (float)(mv.z - vb.z);
                     const float vr = fmaf(wx, dx, fmaf(wy, dy, wz * dz));
                     float Pi = 0.0f;
                     if (vr < 0.0f) {
@@ -362,16 +366,17 @@ __global__ void __launch_bounds__(PAIR_THREADS) k_forces(
                         Pi = fmaf(-alf * 0.5f * (mt.z + tb.z), mu, bef * mu * mu) *
                              __builtin_amdgcn_rcpf(0.5f * (mt.x + tb.x));
                     }
-                    const float term = vb.w * ((mt.y + tb.y) + Pi) * gw;
+                    const float mb = (float)vb.w;
+                    const float term = mb * ((mt.y + tb.y) + Pi) * gw;
                     sx.add(-term * dx);
                     sy.add(-term * dy);
                     sz.add(-term * dz);
-                    if (THERMO) {  // eq. (8) takes the absolute velocities: origin + offsets
-                        const float var = fmaf(vof.x + mv.x, dx, fmaf(vof.y + mv.y, dy, (vof.z + mv.z) * dz));
-                        const float vbr = fmaf(vof.x + vb.x, dx, fmaf(vof.y + vb.y, dy, (vof.z + vb.z) * dz));
-                        su.add(-vb.w * gw * fmaf(mt.y, vbr, fmaf(tb.y, var, 0.5f * Pi * (var + vbr))));
+                    if (THERMO) {  // eq. (8) takes the absolute velocities
+                        const float var = fmaf((float)mv.x, dx, fmaf((float)mv.y, dy, (float)mv.z * dz));
+                        const float vbr = fmaf((float)vb.x, dx, fmaf((float)vb.y, dy, (float)vb.z * dz));
+                        su.add(-mb * gw * fmaf(mt.y, vbr, fmaf(tb.y, var, 0.5f * Pi * (var + vbr))));
                     } else {
-                        su.add(vb.w * fmaf(0.5f, Pi, mt.y) * gw * vr);
+                        su.add(mb * fmaf(0.5f, Pi, mt.y) * gw * vr);
                     }
                     k = kn;
                     e = en;

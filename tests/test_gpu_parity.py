@@ -593,10 +593,10 @@ def test_thermokinetic_rate(orc, case, prec):
     if prec == 0:
         assert e_de.max() <= TOL and e_a.max() <= TOL
     else:
-        # FP32C: 2e-7 typical; up to ~1e-5 where one pair near the support edge dominates the
-        # sum (2 - q from an FP32 distance loses digits as q -> 2; the thermal form does the same)
+        # FP32C: the stated budget, also where one pair near the support edge dominates a
+        # sum (the force pass forms the edge margin and the pair's differences in FP64)
         for e in (e_de, e_a):
-            assert np.median(e) <= 2e-7 and e.max() <= 3e-5
+            assert np.median(e) <= 2e-7 and e.max() <= 2e-6
 
 
 @pytest.mark.parametrize("case,adaptive,dt,G,scheme", [("lattice4096", 0, 0.0178, 0.0, 0),
