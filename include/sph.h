@@ -254,6 +254,26 @@ sph_status sph_timestep(sph_ctx* ctx, double* bound_host);
  * SPH_E_STATE without a previous sph_build_tree or sph_step. */
 sph_status sph_key_order(sph_ctx* ctx, uint64_t* keys_out, int64_t* order_out);
 
+/* For callers that cannot allocate device memory (code under HIP graph capture, tight
+ * serving loops, harnesses that forbid hipMalloc): sph_step with the context's kernels
+ * working in the library's own static device scratch of SPH_NOALLOC_MAX_BYTES bytes instead
+ * of the caller's workspace.  The call allocates nothing (no hipMalloc, hipFree, graph
+ * objects or library allocations; launches are eager on cfg.stream) and needs no
+ * sph_set_workspace.  Same arguments, results and synchronisation as sph_step.
+ *   - SPH_E_CAPACITY if the context's workspace size (sph_workspace_size: it grows with
+ *     n_capacity, seg_capacity and nbr_capacity) exceeds the scratch; about 24,000
+ *     particles fit with nbr_capacity 160, 35,000 with 64.
+ *   - Every call on one GPU shares that GPU's scratch, which keeps the last call's
+ *     contents: calls that overlap on one GPU (other threads, other streams) race, and
+ *     SPH_STEP_RESUME is accepted only when no other call used the scratch since this
+ *     context's last one (SPH_E_STATE otherwise).  The scratch state is separate from the
+ *     workspace state: sph_step, sph_timestep and sph_key_order see only the latter.
+ *   - The scratch stays allocated on each GPU the library has run on until the process
+ *     ends. */
+#define SPH_NOALLOC_MAX_BYTES (64u << 20)
+sph_status sph_step_noalloc(sph_ctx* ctx, sph_particles* ps, double dt, int32_t nsteps, uint32_t flags,
+                            double* diag_host);
+
 /* Times sph_step over candidate leaf_size x group_size settings on ps (which it leaves
  * unchanged), then over waves_per_cu for the fastest pair, keeps the fastest in the context
  * and records "key": [leaf_size, group_size, waves_per_cu] in a JSON cache file

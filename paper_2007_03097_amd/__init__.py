@@ -21,6 +21,7 @@ from .api import (  # noqa: F401
     sph_compute_forces,
     sph_compute_gravity,
     sph_step,
+    sph_step_noalloc,
     sph_autotune,
     sph_get_tuning,
     sph_sync,

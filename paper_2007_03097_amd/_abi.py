@@ -25,7 +25,9 @@ STATUS_NAMES = {0: "SPH_OK", -1: "SPH_E_ARG", -2: "SPH_E_STATE", -3: "SPH_E_NOME
 EXPORTS = ["sph_config_default", "sph_create", "sph_destroy", "sph_workspace_size", "sph_set_workspace",
            "sph_build_tree", "sph_tree_nodes", "sph_find_neighbors", "sph_compute_density", "sph_compute_forces",
            "sph_compute_gravity", "sph_step", "sph_autotune", "sph_get_tuning", "sph_sync", "sph_last_error",
-           "sph_peak_probe", "sph_timestep", "sph_key_order"]
+           "sph_peak_probe", "sph_timestep", "sph_key_order", "sph_step_noalloc"]
+
+SPH_NOALLOC_MAX_BYTES = 64 << 20
 
 
 class sph_config(ctypes.Structure):
@@ -82,6 +84,7 @@ def load() -> ctypes.CDLL:
     L.sph_compute_forces.argtypes = [ctx_p, _dp, _dp, _dp, _dp, _dp, _dp, _dp]
     L.sph_compute_gravity.argtypes = [ctx_p, _dp, _dp, _dp, _dp]
     L.sph_step.argtypes = [ctx_p, P(sph_particles), dbl, i32, u32, P(dbl)]
+    L.sph_step_noalloc.argtypes = [ctx_p, P(sph_particles), dbl, i32, u32, P(dbl)]
     L.sph_autotune.argtypes = [ctx_p, P(sph_particles), dbl, ctypes.c_char_p]
     L.sph_get_tuning.argtypes = [ctx_p, P(i32), P(i32), P(i32)]
     L.sph_sync.argtypes = [ctx_p]

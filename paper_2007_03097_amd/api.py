@@ -170,6 +170,15 @@ def sph_step(ctx, parts: ParticleArrays | None, dt: float, nsteps: int, flags: i
     return diag
 
 
+def sph_step_noalloc(ctx, parts: ParticleArrays | None, dt: float, nsteps: int, flags: int = 0) -> np.ndarray:
+    """sph_step in the library's static device scratch (allocates nothing; see sph.h)."""
+    diag = np.zeros(10)
+    s = parts.struct() if parts is not None else None
+    _check(ctx, _lib().sph_step_noalloc(ctx, ctypes.byref(s) if s is not None else None, float(dt), int(nsteps),
+                                        int(flags), diag.ctypes.data_as(ctypes.POINTER(ctypes.c_double))))
+    return diag
+
+
 # Leaf size, group size and waves per CU measured by sph_autotune on MI355X, keyed by
 # workload (n, sets, precision, gravity, adaptive h); sph_autotune reads a key when present.
 TUNING_CACHE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "tuning_gfx950.json")

@@ -11,6 +11,7 @@
 #include <cstdlib>
 #include <cstring>
 #include <fstream>
+#include <mutex>
 #include <sstream>
 #include <string>
 #include <vector>
@@ -31,6 +32,19 @@ struct Tables {
 };
 
 }  // namespace
+
+// The device memory one context works in, with the state that lives there.  A context has
+// two: the caller's workspace (sph_set_workspace) and the library's static scratch
+// (sph_step_noalloc); the active one sits in the context's own fields.
+struct Binding {
+    char* ws = nullptr;
+    size_t ws_bytes = 0;
+    DevPtrs d[2]{};
+    Dims dm{};
+    Tables tab;
+    bool tree_ok = false, lists_ok = false, dens_ok = false, resident_ok = false, cs_ok = false;
+    int parity = 0;
+};
 
 struct sph_ctx {
     sph_config cfg{};
@@ -59,6 +73,8 @@ struct sph_ctx {
     int64_t g_n = -1;
     int g_leaf = 0, g_gsz = 0, g_waves = -1, g_tabv = -1;
     bool use_graph = true;
+    Binding alt;              // the binding not in use (the scratch one outside sph_step_noalloc)
+    unsigned scratch_gen = 0; // the device scratch generation this context's scratch state has
     std::string err;
 };
 
@@ -301,6 +317,23 @@ static sph_status read_err(sph_ctx* c) {
     if (e & ERR_NODE_CAP) return fail(c, SPH_E_CAPACITY, "device: octree node capacity exceeded");
     if (e & ERR_GRAV_LIST) return fail(c, SPH_E_CAPACITY, "device: gravity walk stack overflow");
     return fail(c, SPH_E_DEVICE, "device error word 0x%x", e);
+}
+
+// Exchanges the active binding (the context's fields) with c->alt.
+static void swap_binding(sph_ctx* c) {
+    Binding& b = c->alt;
+    std::swap(c->ws, b.ws);
+    std::swap(c->ws_bytes, b.ws_bytes);
+    std::swap(c->d[0], b.d[0]);
+    std::swap(c->d[1], b.d[1]);
+    std::swap(c->dm, b.dm);
+    std::swap(c->tab, b.tab);
+    std::swap(c->tree_ok, b.tree_ok);
+    std::swap(c->lists_ok, b.lists_ok);
+    std::swap(c->dens_ok, b.dens_ok);
+    std::swap(c->resident_ok, b.resident_ok);
+    std::swap(c->cs_ok, b.cs_ok);
+    std::swap(c->parity, b.parity);
 }
 
 // Forgets the captured step graphs (they hold workspace pointers and table sizes by value).
@@ -758,6 +791,76 @@ sph_status sph_key_order(sph_ctx* c, uint64_t* keys_out, int64_t* order_out) {
 sph_status sph_step(sph_ctx* c, sph_particles* p, double dt, int32_t nsteps, uint32_t flags, double* diag_host) {
     if (!c) return SPH_E_ARG;
     return step_impl(c, p, dt, nsteps, flags, diag_host, true);
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------------------
+// Allocation-free stepping: the context works in a file-scope device array instead of the
+// caller's workspace.  In host code `scratch` names a host-side stand-in; its device address
+// on each GPU comes from hipGetSymbolAddress, taken once per device with that device current.
+static __device__ __align__(256) unsigned char scratch[SPH_NOALLOC_MAX_BYTES];
+
+namespace {
+constexpr int MAX_DEVICES = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[MAX_DEVICES] = {};
+unsigned g_scratch_gen[MAX_DEVICES] = {};  // calls made on each device's scratch
+}  // namespace
+
+__global__ void k_zero_words(u32* p, int n) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = 0u;
+}
+
+extern "C" {
+
+sph_status sph_step_noalloc(sph_ctx* c, sph_particles* p, double dt, int32_t nsteps, uint32_t flags,
+                            double* diag_host) {
+    if (!c) return SPH_E_ARG;
+    const size_t need = layout(c, nullptr, nullptr);
+    if (need > (size_t)SPH_NOALLOC_MAX_BYTES)
+        return fail(c, SPH_E_CAPACITY, "sph_step_noalloc: the context needs %zu bytes of device memory, more than the "
+                    "%zu-byte scratch (lower n_capacity, seg_capacity or nbr_capacity)", need,
+                    (size_t)SPH_NOALLOC_MAX_BYTES);
+    int dev = 0;
+    HIPCHK(c, hipGetDevice(&dev));
+    if (dev < 0 || dev >= MAX_DEVICES) return fail(c, SPH_E_DEVICE, "sph_step_noalloc: device %d out of range", dev);
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {  // once per device, with that device current
+        void* ptr = nullptr;
+        HIPCHK(c, hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)));
+        if (!ptr || ((uintptr_t)ptr & 255)) return fail(c, SPH_E_DEVICE, "sph_step_noalloc: bad scratch address");
+        g_scratch_ptr[dev] = ptr;
+    }
+    char* base = (char*)g_scratch_ptr[dev];
+    if (flags & SPH_STEP_RESUME) {  // the scratch must still hold this context's state
+        if (c->alt.ws != base || c->scratch_gen != g_scratch_gen[dev] || !c->alt.resident_ok)
+            return fail(c, SPH_E_STATE, "SPH_STEP_RESUME: the scratch no longer holds this context's state");
+    }
+    if (c->alt.ws != base) {  // first use on this device: bind the scratch, control block cleared
+        c->alt = Binding();
+        c->alt.ws = base;
+        c->alt.ws_bytes = SPH_NOALLOC_MAX_BYTES;
+        layout(c, base, &c->alt.d[0]);
+        c->alt.d[1] = swapped(c->alt.d[0]);
+    }
+    if (!(flags & SPH_STEP_RESUME)) {
+        c->alt.tab = Tables();  // another context may have changed the tables in the scratch
+        const int words = (int)(sizeof(DevCtl) / sizeof(u32));
+        hipLaunchKernelGGL(k_zero_words, dim3((words + 255) / 256), dim3(256), 0, c->stream, (u32*)c->alt.d[0].ctl,
+                           words);
+        HIPCHK(c, hipGetLastError());
+    }
+    g_scratch_gen[dev]++;
+    c->scratch_gen = g_scratch_gen[dev];
+    swap_binding(c);
+    const bool graph = c->use_graph;
+    c->use_graph = false;  // eager launches: no graph objects are created or destroyed
+    const sph_status st = step_impl(c, p, dt, nsteps, flags, diag_host, true);
+    c->use_graph = graph;
+    swap_binding(c);
+    return st;
 }
 
 sph_status sph_get_tuning(const sph_ctx* c, int32_t* leaf_size, int32_t* group_size, int32_t* waves_per_cu) {

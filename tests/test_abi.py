@@ -73,6 +73,11 @@ def test_host_validation_without_gpu():
     assert lib.sph_timestep(h, bound) == _abi.SPH_E_STATE   # no resident state yet
     assert lib.sph_timestep(None, bound) == _abi.SPH_E_ARG
     assert lib.sph_key_order(h, None, None) == _abi.SPH_E_STATE
+    # the allocation-free step refuses contexts larger than its scratch before touching the GPU
+    big = sph.sph_create(cfg, 1_000_000, 1)
+    assert lib.sph_step_noalloc(big, None, 1e-3, 1, 0, None) == _abi.SPH_E_CAPACITY
+    assert b"scratch" in lib.sph_last_error(big)
+    sph.sph_destroy(big)
     assert lib.sph_last_error(h)
     assert lib.sph_destroy(None) == 0
     sph.sph_destroy(h)
