@@ -436,6 +436,7 @@ __global__ void __launch_bounds__(RS_THREADS) k_rs_scatter(const u64* __restrict
         const u32 before = ok ? wcnt[w][dg] : 0u;
         rank[r] = before + (u32)__popcll(peers & lt);
         const bool leader = ok && ((peers & lt) == 0ull);
+        __builtin_amdgcn_wave_barrier();  // every lane has read its count before a leader updates it
         if (leader) wcnt[w][dg] = before + (u32)__popcll(peers);
     }
     __syncthreads();

@@ -262,6 +262,7 @@ __global__ void __launch_bounds__(LS_THREADS) k_lsort_scatter(const DevCtl* __re
             }
             const int before = ok ? wcnt[w][dg] : 0;
             rank[r] = before + __popcll(peers & lt);
+            __builtin_amdgcn_wave_barrier();  // every lane has read its count before a leader updates it
             if (ok && (peers & lt) == 0ull) wcnt[w][dg] = before + __popcll(peers);
         }
         __syncthreads();
