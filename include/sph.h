@@ -65,8 +65,10 @@ typedef struct {
     int32_t adaptive_h;  /* sph_step: 1 = update h from the density after each step (lagged) */
     double G;            /* gravitational constant; 0 disables gravity in sph_step           */
     double soft_eps;     /* Plummer softening length (>= 0)                                  */
-    double theta;        /* opening angle in [0, 1]: a cell of side s at distance d from the
-                            target group's box is accepted when s < theta d; 0 = direct sum  */
+    double theta;        /* opening angle in [0, 1]: a cell whose radius b about its centre of
+                            mass (to the farthest corner of its particle box) and distance d
+                            from the target group's box satisfy b < theta d is accepted;
+                            0 = direct sum                                                 */
     int32_t leaf_size;   /* octree leaf capacity, 1..64 (0 = 16)                             */
     int32_t group_size;  /* target particles per walk group: 8, 16, 32 or 64 (0 = 32)        */
     int32_t nbr_capacity;/* maximum neighbours per particle, 16..4096 (0 = 160)              */
@@ -83,7 +85,7 @@ typedef struct {
                             level-l octree cell, so the tree cells, neighbour sets and
                             sums are the same; the sorted order and keys_out differ.    */
     int32_t gravity_scheme; /* SPH_GRAVITY_QUADRUPOLE: particle-cell walk with monopole +
-                            quadrupole cells and the cell-side test above (default).
+                            quadrupole cells and the opening test above (default).
                             SPH_GRAVITY_FMM: the paper's symmetric node-node scheme (Sec.
                             2.2.2, eq. (10), after Dehnen 2000): node pairs accepted when
                             r_A + r_B < theta |c_A - c_B| (r = sqrt(3)/2 side, c = cell

@@ -509,13 +509,15 @@ void orc_quad_field(const double* mom10, double px, double py, double pz, double
 
 /* Tree gravity reference: the same octree as orc_octree (pre-order node list over particles
  * in sorted order), walked once per target group [gstart[g], gstart[g] + gcount[g]).
- * A cell B is accepted for the whole group when its side s_B = L / 2^level is below
- * theta * d, d being the distance from B's centre of mass to the group's bounding box, and
- * B's particle box does not touch the group's box (the paper's MAC = 1 limit: nodes that do
- * not intersect, Sec. 3.4).  Accepted cells contribute through orc_quad_field; unaccepted
+ * A cell B is accepted for the whole group when its radius b_B about its centre of mass is
+ * below theta * d, d being the distance from that centre of mass to the group's bounding
+ * box, and B's particle box does not touch the group's box (the paper's MAC = 1 limit: nodes
+ * that do not intersect, Sec. 3.4).  b_B is the distance from the centre of mass to the
+ * farthest corner of B's particle box (an upper bound of its largest particle distance; the
+ * paper's opening test compares node radii with the distance, Sec. 2.2.2).  Accepted cells contribute through orc_quad_field; unaccepted
  * leaves through softened particle sums with the target itself excluded; unaccepted
  * internal cells are opened.  theta = 0 opens everything (exact direct sum, Sec. 2.2.2).
- * L is the root cell side (the largest extent used by the key quantisation).             */
+ * L (the root cell side) is not used by this opening test; it stays in the interface.      */
 void orc_tree_gravity(int64_t n, int64_t n_nodes, const int32_t* nlevel, const int32_t* nleaf,
                       const int64_t* nstart, const int64_t* ncount, const double* x, const double* y,
                       const double* z, const double* m, double L, double theta, double G, double eps,
@@ -549,7 +551,11 @@ void orc_tree_gravity(int64_t n, int64_t n_nodes, const int32_t* nlevel, const i
             int64_t node = st[--sp];
             const double* nb = nbox + 6 * node;
             const double* mo = mom + 10 * node;
-            double side = ldexp(L, -nlevel[node]);
+            double b2 = 0.0;   /* b_B^2 */
+            for (int d = 0; d < 3; ++d) {
+                double u = fmax(mo[1 + d] - nb[d], nb[3 + d] - mo[1 + d]);
+                b2 += u * u;
+            }
             double d2 = 0.0;
             for (int d = 0; d < 3; ++d) {
                 double q = mo[1 + d];
@@ -559,7 +565,7 @@ void orc_tree_gravity(int64_t n, int64_t n_nodes, const int32_t* nlevel, const i
             int apart = 0;
             for (int d = 0; d < 3; ++d)
                 if (nb[d] > gb[3 + d] || nb[3 + d] < gb[d]) apart = 1;
-            if (apart && side * side < theta * theta * d2) {
+            if (apart && b2 < theta * theta * d2) {
                 for (int64_t a = g0; a < g1; ++a) {
                     double g3[3], p;
                     orc_quad_field(mo, x[a], y[a], z[a], G, eps, g3, &p);

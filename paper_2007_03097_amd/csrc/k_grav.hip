@@ -2,9 +2,11 @@
 // and quadrupole moments).
 //
 // One wavefront per target group, two targets per lane.  The wide walk tests up to 64 nodes at once against the
-// group's box: a cell B of side s_B is accepted for the whole group when its particle box
-// does not touch the group box and s_B < theta d, d being the distance from B's centre of
-// mass to the group box (theta = 0 opens everything: the exact direct sum).  Accepted
+// group's box: a cell B is accepted for the whole group when its particle box does not touch
+// the group box and b_B < theta d, b_B being the distance from B's centre of mass to the
+// farthest corner of its particle box (B's radius about the centre of mass) and d the
+// distance from the centre of mass to the group box (theta = 0 opens everything: the exact
+// direct sum).  Accepted
 // cells act through the second-order expansion of the softened potential about their
 // centre of mass (monopole + quadrupole; the dipole vanishes there):
 //   phi += -G [M/s + (3/2) R.I.R/s^5 - (1/2) tr(I)/s^3]
@@ -443,8 +445,10 @@ __global__ void __launch_bounds__(64) k_gravity(DevCtl* ctl, const int4* __restr
                 }
                 const bool apart =
                     a.x > hi[0] || b.x < lo[0] || a.y > hi[1] || b.y < lo[1] || a.z > hi[2] || b.z < lo[2];
-                const double side = b.w;
-                if (apart && side * side < th2 * d2) kind = 1;
+                const double ux = fmax(com[0] - a.x, b.x - com[0]), uy = fmax(com[1] - a.y, b.y - com[1]),
+                             uz = fmax(com[2] - a.z, b.z - com[2]);
+                const double b2 = (ux * ux + uy * uy) + uz * uz;  // radius^2 about the centre of mass
+                if (apart && b2 < th2 * d2) kind = 1;
                 else kind = tp.w ? 2 : 3;
             }
             const u64 bc = __ballot(kind == 1), bl = __ballot(kind == 2);
