@@ -62,10 +62,12 @@ struct Screen {
 // Each lane serves two targets of the group, tp and tp + TP (TP = group_size / 2), and a
 // block of B = TP staged sources; the P = 64 / TP lanes with the same tp cover the tile.
 // One LDS read of a source feeds two pair tests.
+template <int TP_>
 struct LaneTargets {
+    static constexpr int TP = TP_, P = 64 / TP_;
     float4 a, b;    // targets tp and tp + TP: FP32 offsets from the origin, h
     bool va, vb;    // they exist
-    int tp, phi, TP, P;
+    int tp, phi;
     int cnt_a, cnt_b;
 };
 
@@ -73,18 +75,32 @@ __device__ __forceinline__ float4 offset_rec(const double4& p, const Screen& S) 
     return make_float4((float)(p.x - S.o[0]), (float)(p.y - S.o[1]), (float)(p.z - S.o[2]), (float)p.w);
 }
 
-// Screen of one pair: sets `bit` in hits when the pair is a neighbour for certain and in
-// undecided when the screen cannot tell (neither for a certain miss).
-__device__ __forceinline__ void screen_pair(const float4& a, const float4& s, float me, u32 bit, u32& hits,
-                                            u32& undecided) {
+// Margin of the screen for target a against a tile whose sources have |h| <= hm:
+// M' = fma(fl(fl(|h_a| + hm)^2), 2^-19, me) is at least the margin fma(t2', 2^-19, me) of
+// each of those pairs (t2' = fl(fl(h_a + h_b)^2), every operation monotone), so deciding
+// with M' keeps the screen's guarantee and only leaves a few more pairs undecided.  A NaN
+// h makes M' NaN and every pair of the target undecided.
+__device__ __forceinline__ float tile_margin(float ha, float hm, float me) {
+    const float tt = fabsf(ha) + hm;
+    return fmaf(tt * tt, 0x1p-19f, me);
+}
+
+// d' = t2' - r2' of one pair (the screen value; see fp32_screen above).
+__device__ __forceinline__ float screen_d(const float4& a, const float4& s) {
     const float dx = a.x - s.x, dy = a.y - s.y, dz = a.z - s.z;
     const float r2 = fmaf(dx, dx, fmaf(dy, dy, dz * dz));
     const float tt = a.w + s.w;
-    const float t2 = tt * tt;
-    const float M = fmaf(t2, 0x1p-19f, me);
-    const float d = t2 - r2;
-    if (d > M) hits |= bit;
-    if (!(fabsf(d) > M)) undecided |= bit;
+    return tt * tt - r2;
+}
+
+// Largest |h| of the tn (>= 1) sources of the tile at ring positions head .., over the wave:
+// the bits of a non-negative float order as unsigned integers (a NaN above every number).
+__device__ __forceinline__ float tile_hmax(const float4* tile, int head, int tn) {
+    const int lane = lane_id();
+    u32 v = lane < tn ? __float_as_uint(fabsf(tile[(head + lane) & (TILE_RING - 1)].w)) : 0u;
+#pragma unroll
+    for (int d = 32; d >= 1; d >>= 1) v = max(v, (u32)__shfl_xor((int)v, d, 64));
+    return __uint_as_float(v);
 }
 
 // The exact FP64 predicate for the pairs the screen left undecided (bit i = tile source i).
@@ -104,7 +120,8 @@ __device__ void resolve_exact(u32 q, const double4& A, int head, int j0, const i
 
 // Slots for one target's hits: the P lanes of the target take consecutive slot ranges in
 // phi order, each in ascending source order; the entry is the source's index in the union.
-__device__ __forceinline__ void append_hits(u32 bits, int t, int& cnt, const LaneTargets& L, u64 ub, int ucnt,
+template <int TP>
+__device__ __forceinline__ void append_hits(u32 bits, int t, int& cnt, const LaneTargets<TP>& L, u64 ub, int ucnt,
                                             int gy, int cap, int* mylist) {
     const int lane = lane_id();
     const int mine = __popc(bits);
@@ -130,23 +147,44 @@ __device__ __forceinline__ void append_hits(u32 bits, int t, int& cnt, const Lan
 // for the 64 (or, at the end, fewer) filtered sources at ring positions head .. head+tn-1
 // (FP32 screen, FP64 for the undecided pairs); hits go to the group's union and to the
 // targets' lists.
-__device__ __forceinline__ void test_tile(int head, int tn, const float4* tile, const int* tsrc, LaneTargets& L,
+template <int TP>
+__device__ __forceinline__ void test_tile(int head, int tn, const float4* tile, const int* tsrc, LaneTargets<TP>& L,
                                           float me, const double4* __restrict__ pos4, int gx, int gy, int cap,
                                           int* mylist, int* myuni, int ulim, int& ucnt) {
     const int lane = lane_id();
-    const int j0 = L.phi * L.TP;
-    const int je = tn - j0 < L.TP ? tn - j0 : L.TP;
-    u32 ba = 0, bb = 0, qa = 0, qb = 0;
-    for (int it = 0; it < je; ++it) {
-        const float4 s = tile[(head + j0 + it) & (TILE_RING - 1)];
-        screen_pair(L.a, s, me, 1u << it, ba, qa);
-        screen_pair(L.b, s, me, 1u << it, bb, qb);
+    const int j0 = L.phi * TP;
+    const int je = min(max(tn - j0, 0), TP);  // sources of this lane's block
+    const u32 valid = je >= 32 ? 0xffffffffu : (1u << je) - 1u;
+    const float hm = tile_hmax(tile, head, tn);
+    const float Ma = tile_margin(L.a.w, hm, me), Mb = tile_margin(L.b.w, hm, me);
+    // head is a multiple of 64, so the block's TP ring entries are contiguous; entries past
+    // the block's end are stale records whose bits are masked off below
+    const float4* blk = tile + ((head + j0) & (TILE_RING - 1));
+    u32 ba = 0, bb = 0;
+    u64 und = 0;  // lanes with an undecided pair
+#pragma unroll 4
+    for (int it = 0; it < TP; ++it) {
+        const float4 s = blk[it];
+        const float da = screen_d(L.a, s), db = screen_d(L.b, s);
+        ba |= (da > Ma ? 1u : 0u) << it;
+        bb |= (db > Mb ? 1u : 0u) << it;
+        und |= __builtin_amdgcn_ballot_w64(!(fabsf(da) > Ma) || !(fabsf(db) > Mb));
     }
-    if (!L.va) ba = qa = 0u;
-    if (!L.vb) bb = qb = 0u;
-    if (__ballot((qa | qb) != 0u)) {
+    ba &= L.va ? valid : 0u;
+    bb &= L.vb ? valid : 0u;
+    if (und) {  // rare: the lanes concerned redo their block's undecided pairs in FP64
+        u32 qa = 0, qb = 0;
+        if ((und >> lane) & 1ull) {
+            for (int it = 0; it < je; ++it) {
+                const float4 s = blk[it];
+                if (!(fabsf(screen_d(L.a, s)) > Ma)) qa |= 1u << it;
+                if (!(fabsf(screen_d(L.b, s)) > Mb)) qb |= 1u << it;
+            }
+            if (!L.va) qa = 0u;
+            if (!L.vb) qb = 0u;
+        }
         if (qa) resolve_exact(qa, pos4[gx + L.tp], head, j0, tsrc, pos4, ba);
-        if (qb) resolve_exact(qb, pos4[gx + L.tp + L.TP], head, j0, tsrc, pos4, bb);
+        if (qb) resolve_exact(qb, pos4[gx + L.tp + TP], head, j0, tsrc, pos4, bb);
     }
     // union of the tile, bit j = ring entry head + j
     u64 ub = (u64)(ba | bb) << j0;
@@ -166,9 +204,10 @@ __device__ __forceinline__ void test_tile(int head, int tn, const float4* tile, 
 // test (gap^2 < (hmax_group + h_b)^2), so no true neighbour is dropped; survivors enter an
 // LDS ring and are matched 64 at a time.  Sources left in the ring (< 64) are matched by
 // the caller's final flush.
+template <int TP>
 __device__ void match_candidates(int nc, int* cand, int* coff, float4* tile, int* tsrc, int& head, int& tail,
                                  const GroupBox& gb, const Screen& S, const int4* __restrict__ topo,
-                                 const double4* __restrict__ pos4, LaneTargets& L, int gx, int gy, int cap,
+                                 const double4* __restrict__ pos4, LaneTargets<TP>& L, int gx, int gy, int cap,
                                  int* mylist, int* myuni, int ulim, int& ucnt) {
     const int lane = lane_id();
     const u64 lt = lanemask_lt();
@@ -230,6 +269,7 @@ __device__ void match_candidates(int nc, int* cand, int* coff, float4* tile, int
     }
 }
 
+template <int TP>
 __global__ void __launch_bounds__(64) k_nbr_lists(DevCtl* ctl, const int4* __restrict__ group, int gsz, int cap,
                                                   const int4* __restrict__ topo, const double4* __restrict__ nbox_lo,
                                                   const double4* __restrict__ nbox_hi, const double4* __restrict__ pos4,
@@ -243,9 +283,7 @@ __global__ void __launch_bounds__(64) k_nbr_lists(DevCtl* ctl, const int4* __res
     __shared__ int tsrc[TILE_RING];
     const int lane = lane_id();
     const u64 lt = lanemask_lt();
-    LaneTargets L;
-    L.TP = gsz >> 1;
-    L.P = 64 / L.TP;
+    LaneTargets<TP> L;
     L.tp = lane & (L.TP - 1);
     L.phi = lane / L.TP;
     int g0, g1, gstep;
@@ -363,8 +401,16 @@ __global__ void __launch_bounds__(64) k_nbr_lists(DevCtl* ctl, const int4* __res
 
 void launch_nbr_lists(hipStream_t s, const DevPtrs& d, const Dims& dm) {
     if (dm.n <= 0) return;
-    hipLaunchKernelGGL(k_nbr_lists, dim3(dm.group_grid), dim3(64), 0, s, d.ctl, d.group, dm.group_size, dm.nbr_cap,
-                       d.topo, d.nbox_lo, d.nbox_hi, d.pos4, d.nbr, d.nbr_cnt, d.nbr_base, d.uni, d.ucnt);
+    auto go = [&](auto kern) {
+        hipLaunchKernelGGL(kern, dim3(dm.group_grid), dim3(64), 0, s, d.ctl, d.group, dm.group_size, dm.nbr_cap,
+                           d.topo, d.nbox_lo, d.nbox_hi, d.pos4, d.nbr, d.nbr_cnt, d.nbr_base, d.uni, d.ucnt);
+    };
+    switch (dm.group_size) {  // validated at context creation: 8, 16, 32 or 64
+        case 8: go(k_nbr_lists<4>); break;
+        case 16: go(k_nbr_lists<8>); break;
+        case 32: go(k_nbr_lists<16>); break;
+        default: go(k_nbr_lists<32>); break;
+    }
 }
 
 // ---- CSR export in caller order (test and inspection path)
