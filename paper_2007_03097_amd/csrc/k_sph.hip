@@ -95,19 +95,37 @@ __device__ __forceinline__ float4 offset_rec(const double4 p, const double4 o) {
 }
 
 
+// An array of 32-byte records kept as two arrays of their 16-byte halves.  Read with 16-byte
+// loads at random indices, records 32 bytes apart put the first half of every record in the
+// same half of the LDS banks (a two-way conflict at least); at a 16-byte stride the halves of
+// different records spread over all banks.
+template <int N>
+struct Split4 {
+    double2 lo[N], hi[N];
+    __device__ __forceinline__ void put(int i, const double4& v) {
+        lo[i] = make_double2(v.x, v.y);
+        hi[i] = make_double2(v.z, v.w);
+    }
+    __device__ __forceinline__ double4 get(int i) const {
+        const double2 a = lo[i], b = hi[i];
+        return make_double4(a.x, a.y, b.x, b.y);
+    }
+};
+
 // Density sources staged in LDS: FP64 (x, y, z, h) and m, or FP32 offset records and m.
 template <bool FP32C>
 struct DensSrc;
 template <>
 struct DensSrc<false> {
-    double4 pos[DENS_CHUNK];
+    Split4<DENS_CHUNK> pos;
     double mass[DENS_CHUNK];
     using Rec = double4;
     using Mass = double;
     __device__ __forceinline__ void put(int i, const double4 p, double mb, const double4&) {
-        pos[i] = p;
+        pos.put(i, p);
         mass[i] = mb;
     }
+    __device__ __forceinline__ double4 rec(int i) const { return pos.get(i); }
     __device__ __forceinline__ static double4 target(const double4 p, const double4&) { return p; }
 };
 template <>
@@ -120,6 +138,7 @@ struct DensSrc<true> {
         pos[i] = offset_rec(p, o);
         mass[i] = (float)mb;
     }
+    __device__ __forceinline__ float4 rec(int i) const { return pos[i]; }
     __device__ __forceinline__ static float4 target(const double4 p, const double4& o) { return offset_rec(p, o); }
 };
 static_assert(sizeof(DensSrc<true>) >= PAIR_THREADS * sizeof(double), "the reduction reuses the staging");
@@ -166,7 +185,7 @@ __global__ void __launch_bounds__(PAIR_THREADS) k_density(
             while (e < ce) {
                 const int kn = k + 4 * PL;
                 const int en = kn < cnt ? lst[kn * g.y] : INT_MAX;
-                acc.add(me, S.pos[e - c0], S.mass[e - c0]);
+                acc.add(me, S.rec(e - c0), S.mass[e - c0]);
                 k += PL;
                 e = e1;
                 e1 = e2;
@@ -175,7 +194,7 @@ __global__ void __launch_bounds__(PAIR_THREADS) k_density(
             }
         }
         __syncthreads();
-        double* red = reinterpret_cast<double*>(S.pos);
+        double* red = reinterpret_cast<double*>(&S);
         red[tid] = acc.value();
         __syncthreads();
         if (tv && phi == 0) {
@@ -220,16 +239,14 @@ template <bool FP32C>
 struct ForceSrc;
 template <>
 struct ForceSrc<false> {
-    double4 pos[FORCE_CHUNK];
-    double4 vel[FORCE_CHUNK];
-    double4 thr[FORCE_CHUNK];
+    Split4<FORCE_CHUNK> pos, vel, thr;
 };
 template <>
 struct ForceSrc<true> {
-    double4 pos[FORCE_CHUNK_F];  // x, y, z, h and predicted v, m in FP64: the pair's differences
-    double4 vel[FORCE_CHUNK_F];  // and its support-edge margin are formed in FP64
-    float4 thr[FORCE_CHUNK_F];
+    Split4<FORCE_CHUNK_F> pos, vel;  // x, y, z, h and predicted v, m in FP64: the pair's differences
+    float4 thr[FORCE_CHUNK_F];       // and its support-edge margin are formed in FP64
 };
+static_assert(sizeof(ForceSrc<false>) >= 4 * PAIR_THREADS * sizeof(double), "the reduction reuses the staging");
 static_assert(sizeof(ForceSrc<true>) >= 4 * PAIR_THREADS * sizeof(double), "the reduction reuses the staging");
 
 template <bool FP32C, bool THERMO>
@@ -256,7 +273,7 @@ __global__ void __launch_bounds__(PAIR_THREADS) k_forces(
         int k = phi;
         int e = k < cnt ? lst[k * g.y] : INT_MAX;
         double fx, fy, fz, fu;
-        if (!FP32C) {
+        if constexpr (!FP32C) {
             const double4 mv = tv ? vel4[q] : make_double4(0, 0, 0, 0);
             const double4 mt = tv ? thr4[q] : make_double4(1, 0, 0, 0);
             double sx = 0, sy = 0, sz = 0, su = 0;
@@ -265,9 +282,9 @@ __global__ void __launch_bounds__(PAIR_THREADS) k_forces(
                 __syncthreads();
                 for (int i = tid; i < cn; i += PAIR_THREADS) {
                     const int b = un[c0 + i];
-                    reinterpret_cast<double4*>(S.pos)[i] = pos4[b];
-                    reinterpret_cast<double4*>(S.vel)[i] = vel4[b];
-                    reinterpret_cast<double4*>(S.thr)[i] = thr4[b];
+                    S.pos.put(i, pos4[b]);
+                    S.vel.put(i, vel4[b]);
+                    S.thr.put(i, thr4[b]);
                 }
                 __syncthreads();
                 const int ce = c0 + cn;
@@ -275,9 +292,9 @@ __global__ void __launch_bounds__(PAIR_THREADS) k_forces(
                     const int kn = k + PL;
                     const int en = kn < cnt ? lst[kn * g.y] : INT_MAX;
                     const int j = e - c0;
-                    const double4 sb = reinterpret_cast<const double4*>(S.pos)[j];
-                    const double4 vb = reinterpret_cast<const double4*>(S.vel)[j];
-                    const double4 tb = reinterpret_cast<const double4*>(S.thr)[j];
+                    const double4 sb = S.pos.get(j);
+                    const double4 vb = S.vel.get(j);
+                    const double4 tb = S.thr.get(j);
                     const double dx = me.x - sb.x, dy = me.y - sb.y, dz = me.z - sb.z;
                     const double r2 = fma(dx, dx, fma(dy, dy, dz * dz));
                     double ir;
@@ -324,9 +341,9 @@ __global__ void __launch_bounds__(PAIR_THREADS) k_forces(
                 __syncthreads();
                 for (int i = tid; i < cn; i += PAIR_THREADS) {
                     const int b = un[c0 + i];
-                    S.pos[i] = pos4[b];
-                    S.vel[i] = vel4[b];
-                    reinterpret_cast<float4*>(S.thr)[i] = thrf[b];
+                    S.pos.put(i, pos4[b]);
+                    S.vel.put(i, vel4[b]);
+                    S.thr[i] = thrf[b];
                 }
                 __syncthreads();
                 const int ce = c0 + cn;
@@ -334,9 +351,9 @@ __global__ void __launch_bounds__(PAIR_THREADS) k_forces(
                     const int kn = k + PL;
                     const int en = kn < cnt ? lst[kn * g.y] : INT_MAX;
                     const int j = e - c0;
-                    const double4 sb = S.pos[j];
-                    const double4 vb = S.vel[j];
-                    const float4 tb = reinterpret_cast<const float4*>(S.thr)[j];
+                    const double4 sb = S.pos.get(j);
+                    const double4 vb = S.vel.get(j);
+                    const float4 tb = S.thr[j];
                     // the pair's separation, relative velocity and margin to the support edge
                     // in FP64, rounded once to FP32: D = (h_a + h_b)^2 - r^2 has no
                     // cancellation, so 2 - q = D/((T + r) h_ab) keeps FP32 relative accuracy as
@@ -385,7 +402,7 @@ __global__ void __launch_bounds__(PAIR_THREADS) k_forces(
             fx = sx.value(); fy = sy.value(); fz = sz.value(); fu = su.value();
         }
         __syncthreads();
-        double* red = reinterpret_cast<double*>(S.pos);  // 4 x 256 doubles
+        double* red = reinterpret_cast<double*>(&S);  // 4 x 256 doubles
         red[tid] = fx;
         red[PAIR_THREADS + tid] = fy;
         red[2 * PAIR_THREADS + tid] = fz;
