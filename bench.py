@@ -563,12 +563,12 @@ def main():
     if not args.no_extra:
         from workloads import polytrope_n1
         pp = polytrope_n1(4194304, seed=1003)
-        extra["polytrope_4m_gravity"] = {"n_particles": pp.n, "fp64": run_polytrope(pp, 5, 0),
-                                         "fp32c": run_polytrope(pp, 5, 1)}
-        extra["polytrope_4m_fmm_gravity"] = {"n_particles": pp.n, "fp64": run_polytrope(pp, 5, 0, scheme=1),
-                                             "fp32c": run_polytrope(pp, 5, 1, scheme=1)}
+        extra["polytrope_4m_gravity"] = {"n_particles": pp.n, "fp64": run_polytrope(pp, 10, 0),
+                                         "fp32c": run_polytrope(pp, 10, 1)}
+        extra["polytrope_4m_fmm_gravity"] = {"n_particles": pp.n, "fp64": run_polytrope(pp, 10, 0, scheme=1),
+                                             "fp32c": run_polytrope(pp, 10, 1, scheme=1)}
         del pp
-        extra["ensemble_256"] = run_ensemble(5)
+        extra["ensemble_256"] = run_ensemble(10)
         tk = {}
         for prec, key in ((0, "fp64"), (1, "fp32c")):
             r = run_gpu(ps, prec, args.steps, args.warmup, 2, not args.no_autotune, energy_form=1)
@@ -584,8 +584,8 @@ def main():
         extra["hilbert_keys_tube"] = hk
         from workloads import evrard
         pe = evrard(16777216, seed=1005)
-        extra["evrard_16m_fp32c"] = dict(run_polytrope(pe, 3, 1, 0, eps=0.005, sizes=(32, 64), cap=256),
-                                         n_particles=pe.n, timed_steps=3)
+        extra["evrard_16m_fp32c"] = dict(run_polytrope(pe, 20, 1, 0, eps=0.005, sizes=(32, 64), cap=256),
+                                         n_particles=pe.n, timed_steps=20)
         del pe
     # FP32C error per field on the benchmark workload's evolved state (after the timed steps)
     ev = ps.copy()
