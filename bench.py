@@ -223,14 +223,22 @@ def run_polytrope(ps, steps, prec, scheme=0, eps=0.01, sizes=None, cap=2048):
     e1.record()
     torch.cuda.synchronize()
     grav_ms = e0.elapsed_time(e1) / 3
+    grav = None
+    if scheme == 0:   # terms of the particle-cell walk, counted on the device during the last pass
+        cells, pp = sph.sph_gravity_counts(ctx.h)
+        grav = {"cells_per_particle": cells / n, "pairs_per_particle": pp / n,
+                "cell_terms_per_s": cells / (grav_ms * 1e-3), "pair_terms_per_s": pp / (grav_ms * 1e-3)}
     leaf, group, waves = sph.sph_get_tuning(ctx.h)
     ctx.close()
     del g
     torch.cuda.empty_cache()
-    return dict(ms_per_step=wall / steps * 1e3, steps_per_s=steps / wall, value=pairs * steps / wall, dt=dt,
-                leaf_size=leaf, group_size=group, waves_per_cu=waves, gravity_ms=grav_ms,
-                lists_ms=t_list * 1e3, pass_rate=pairs / (t_dens + t_force),
-                passes=pass_rooflines(n, total, total - n, t_dens, t_force))
+    out = dict(ms_per_step=wall / steps * 1e3, steps_per_s=steps / wall, value=pairs * steps / wall, dt=dt,
+               leaf_size=leaf, group_size=group, waves_per_cu=waves, gravity_ms=grav_ms,
+               lists_ms=t_list * 1e3, pass_rate=pairs / (t_dens + t_force),
+               passes=pass_rooflines(n, total, total - n, t_dens, t_force))
+    if grav:
+        out["gravity_terms"] = grav
+    return out
 
 
 def run_ensemble(steps):

@@ -218,6 +218,14 @@ sph_status sph_compute_forces(sph_ctx* ctx, const double* rho, const double* P, 
  * Outputs: device double[n] in caller order; any may be NULL (not copied out). */
 sph_status sph_compute_gravity(sph_ctx* ctx, double* gx, double* gy, double* gz, double* phi);
 
+/* Work of the last particle-cell gravity pass (Sec. 2.2.2; the tree code's cost, Sec. 3.4),
+ * from sph_compute_gravity or the last step that evaluated gravity: *cells_host = cell terms
+ * evaluated (each accepted cell times the targets of its group), *pairs_host = particle-
+ * particle terms (each unaccepted leaf's particles times the group's targets, the targets'
+ * own pairs taken out).  At theta = 0 these are 0 and n (n - 1) for one set.  Synchronises the
+ * stream.  SPH_E_STATE when gravity is off or uses the node-node scheme (not counted). */
+sph_status sph_gravity_counts(sph_ctx* ctx, int64_t* cells_host, int64_t* pairs_host);
+
 /* nsteps kick-drift-kick leapfrog steps of size dt (> 0; per set when ps->seg_dt is given):
  *   v' = v + dt/2 a;  u' = u + dt/2 du;  x += dt v';  predictors v^ = v' + dt/2 a, u^ = u' + dt/2 du;
  *   rebuild keys, tree and neighbours; density, EOS(u^), forces with v^ (+ gravity if G != 0);

@@ -517,13 +517,16 @@ void orc_quad_field(const double* mom10, double px, double py, double pz, double
  * paper's opening test compares node radii with the distance, Sec. 2.2.2).  Accepted cells contribute through orc_quad_field; unaccepted
  * leaves through softened particle sums with the target itself excluded; unaccepted
  * internal cells are opened.  theta = 0 opens everything (exact direct sum, Sec. 2.2.2).
- * L (the root cell side) is not used by this opening test; it stays in the interface.      */
+ * L (the root cell side) is not used by this opening test; it stays in the interface.
+ * counts (nullable): [0] cell terms evaluated (accepted cells times their group's targets),
+ * [1] particle-particle terms (each target's own pair excluded).                          */
 void orc_tree_gravity(int64_t n, int64_t n_nodes, const int32_t* nlevel, const int32_t* nleaf,
                       const int64_t* nstart, const int64_t* ncount, const double* x, const double* y,
                       const double* z, const double* m, double L, double theta, double G, double eps,
                       int64_t ngroups, const int64_t* gstart, const int64_t* gcount, double* gx, double* gy,
-                      double* gz, double* phi)
+                      double* gz, double* phi, int64_t* counts)
 {
+    int64_t n_cells = 0, n_pairs = 0;
     int64_t* child = (int64_t*)malloc(sizeof(int64_t) * 8 * (size_t)n_nodes);
     int32_t* nch = (int32_t*)calloc((size_t)n_nodes, sizeof(int32_t));
     double* mom = (double*)malloc(sizeof(double) * 10 * (size_t)n_nodes);
@@ -539,7 +542,7 @@ void orc_tree_gravity(int64_t n, int64_t n_nodes, const int32_t* nlevel, const i
         orc_bbox(nstart[j], nstart[j] + ncount[j], x, y, z, nbox + 6 * j);
     }
     for (int64_t a = 0; a < n; ++a) { gx[a] = gy[a] = gz[a] = phi[a] = 0.0; }
-#pragma omp parallel for schedule(dynamic, 1)
+#pragma omp parallel for schedule(dynamic, 1) reduction(+ : n_cells, n_pairs)
     for (int64_t g = 0; g < ngroups; ++g) {
         int64_t g0 = gstart[g], g1 = g0 + gcount[g];
         double gb[6];
@@ -570,12 +573,14 @@ void orc_tree_gravity(int64_t n, int64_t n_nodes, const int32_t* nlevel, const i
                     double g3[3], p;
                     orc_quad_field(mo, x[a], y[a], z[a], G, eps, g3, &p);
                     gx[a] += g3[0]; gy[a] += g3[1]; gz[a] += g3[2]; phi[a] += p;
+                    ++n_cells;
                 }
             } else if (nleaf[node]) {
                 int64_t b0 = nstart[node], b1 = b0 + ncount[node];
                 for (int64_t a = g0; a < g1; ++a)
                     for (int64_t b = b0; b < b1; ++b) {
                         if (b == a) continue;
+                        ++n_pairs;
                         double dx = x[a] - x[b], dy = y[a] - y[b], dz = z[a] - z[b];
                         double inv = 1.0 / sqrt(dx * dx + dy * dy + dz * dz + eps * eps);
                         double inv3 = inv * inv * inv;
@@ -590,6 +595,7 @@ void orc_tree_gravity(int64_t n, int64_t n_nodes, const int32_t* nlevel, const i
         }
     }
     free(child); free(nch); free(mom); free(nbox);
+    if (counts) { counts[0] = n_cells; counts[1] = n_pairs; }
 }
 
 /* ------------------------------------------------------------------------------------ */

@@ -64,7 +64,7 @@ def lib():
         L.orc_moments.argtypes = [I64, I64, _i64, _d, _d, _d, _d, _d]
         L.orc_quad_field.argtypes = [_d, DBL, DBL, DBL, DBL, DBL, _d, _d]
         L.orc_tree_gravity.argtypes = ([I64, I64, _i32, _i32, _i64, _i64, _d, _d, _d, _d, DBL, DBL, DBL, DBL,
-                                        I64, _i64, _i64, _d, _d, _d, _d])
+                                        I64, _i64, _i64, _d, _d, _d, _d, _i64])
         L.orc_fmm_gravity.argtypes = ([I64, I64, _i32, _i32, _i64, _i64, _d, _d, _d, _d, _d, DBL, ctypes.c_int, DBL,
                                        DBL, DBL, _d, _d, _d, _d, _d, _d, _i64])
         L.orc_fmm_gravity.restype = ctypes.c_int
@@ -260,8 +260,9 @@ def quad_field(mom10, p, G=1.0, eps=0.0):
     return g, float(phi[0])
 
 
-def tree_gravity(xs, ys, zs, ms, tree, L, theta, G, eps, gstart, gcount):
-    """Tree gravity over particles already in sorted order; tree from octree()."""
+def tree_gravity(xs, ys, zs, ms, tree, L, theta, G, eps, gstart, gcount, counts=False):
+    """Tree gravity over particles already in sorted order; tree from octree().  counts=True
+    also returns (cell terms, particle-particle terms) evaluated."""
     xs, ys, zs, ms = _f64(xs), _f64(ys), _f64(zs), _f64(ms)
     n = xs.size
     lev = np.ascontiguousarray(tree["level"], np.int32)
@@ -269,9 +270,12 @@ def tree_gravity(xs, ys, zs, ms, tree, L, theta, G, eps, gstart, gcount):
     st, ct = _ii(tree["start"]), _ii(tree["count"])
     gs, gc = _ii(gstart), _ii(gcount)
     gx, gy, gz, phi = (np.empty(n) for _ in range(4))
+    cnt = np.zeros(2, np.int64)
     lib().orc_tree_gravity(n, lev.size, _p(lev, _i32), _p(leaf, _i32), _p(st, _i64), _p(ct, _i64), _p(xs), _p(ys),
                            _p(zs), _p(ms), L, theta, G, eps, gs.size, _p(gs, _i64), _p(gc, _i64), _p(gx), _p(gy),
-                           _p(gz), _p(phi))
+                           _p(gz), _p(phi), _p(cnt, _i64))
+    if counts:
+        return gx, gy, gz, phi, (int(cnt[0]), int(cnt[1]))
     return gx, gy, gz, phi
 
 

@@ -29,6 +29,7 @@ from .api import (  # noqa: F401
     sph_peak_probe,
     sph_timestep,
     sph_key_order,
+    sph_gravity_counts,
 )
 from ._abi import (SPH_CURVE_HILBERT, SPH_CURVE_MORTON, SPH_ENERGY_THERMAL, SPH_ENERGY_THERMOKINETIC, SPH_FP32C, SPH_FP64, SPH_STEP_PRIMED,  # noqa: F401
                    SPH_GRAVITY_FMM, SPH_GRAVITY_QUADRUPOLE, SPH_STEP_RESUME)

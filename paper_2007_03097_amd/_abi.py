@@ -25,7 +25,7 @@ STATUS_NAMES = {0: "SPH_OK", -1: "SPH_E_ARG", -2: "SPH_E_STATE", -3: "SPH_E_NOME
 EXPORTS = ["sph_config_default", "sph_create", "sph_destroy", "sph_workspace_size", "sph_set_workspace",
            "sph_build_tree", "sph_tree_nodes", "sph_find_neighbors", "sph_compute_density", "sph_compute_forces",
            "sph_compute_gravity", "sph_step", "sph_autotune", "sph_get_tuning", "sph_sync", "sph_last_error",
-           "sph_peak_probe", "sph_timestep", "sph_key_order", "sph_step_noalloc"]
+           "sph_peak_probe", "sph_timestep", "sph_key_order", "sph_step_noalloc", "sph_gravity_counts"]
 
 SPH_NOALLOC_MAX_BYTES = 64 << 20
 
@@ -93,6 +93,7 @@ def load() -> ctypes.CDLL:
     L.sph_peak_probe.argtypes = [i32, _dp, i64, i32, ctypes.c_void_p]
     L.sph_timestep.argtypes = [ctx_p, P(dbl)]
     L.sph_key_order.argtypes = [ctx_p, _dp, _dp]
+    L.sph_gravity_counts.argtypes = [ctx_p, P(i64), P(i64)]
     for name in EXPORTS:
         if name not in ("sph_config_default", "sph_last_error"):
             getattr(L, name).restype = ctypes.c_int

@@ -203,6 +203,13 @@ def sph_timestep(ctx, n_seg: int = 1) -> np.ndarray:
     return out
 
 
+def sph_gravity_counts(ctx):
+    """(cell terms, particle-particle terms) of the last particle-cell gravity pass."""
+    c, p = ctypes.c_int64(), ctypes.c_int64()
+    _check(ctx, _lib().sph_gravity_counts(ctx, ctypes.byref(c), ctypes.byref(p)))
+    return int(c.value), int(p.value)
+
+
 def sph_key_order(ctx, keys_out=None, order_out=None):
     import torch
     if keys_out is not None and keys_out.element_size() != 8:

@@ -778,6 +778,18 @@ sph_status sph_timestep(sph_ctx* c, double* bound_host) {
     return read_err(c);
 }
 
+sph_status sph_gravity_counts(sph_ctx* c, int64_t* cells_host, int64_t* pairs_host) {
+    if (!c || !cells_host || !pairs_host) return SPH_E_ARG;
+    if (c->cfg.G == 0.0 || c->cfg.gravity_scheme == SPH_GRAVITY_FMM)
+        return fail(c, SPH_E_STATE, "sph_gravity_counts: no particle-cell gravity pass in this context");
+    u64 v[2] = {0, 0};
+    HIPCHK(c, hipMemcpyAsync(v, &c->d[0].ctl->grav_cells, sizeof v, hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    *cells_host = (int64_t)v[0];
+    *pairs_host = (int64_t)v[1] - (v[1] > 0 ? (int64_t)c->dm.n : 0);  // the targets' own pairs
+    return read_err(c);
+}
+
 sph_status sph_key_order(sph_ctx* c, uint64_t* keys_out, int64_t* order_out) {
     if (!c) return SPH_E_ARG;
     if (!c->tree_ok && !c->resident_ok)

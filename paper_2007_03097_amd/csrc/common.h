@@ -39,6 +39,8 @@ struct DevCtl {
     double diag[16];              // step diagnostics
     double seg_dt[512];           // step size of each segment (read by the kick kernels)
     u64 dtb_enc[512];             // per segment: ordered-integer min of the time-step bound
+    u64 grav_cells;               // last quadrupole gravity pass: particle-cell terms evaluated
+    u64 grav_pairs;               // and particle-particle terms, each target's own pair included
 };
 
 // Device pointers of one context.  All arrays are carved out of the caller's workspace.

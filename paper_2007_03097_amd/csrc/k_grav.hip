@@ -350,6 +350,27 @@ __device__ void eval_leaves1(int nleaf, int* leaves, Stage& St, const int4* __re
     });
 }
 
+// Terms one flush of the lists evaluates: ncell cells and the particles of nleaf leaves, each
+// against the group's ng targets (added to the pass's counters; leaves still unstaged).
+__device__ __forceinline__ void count_terms(DevCtl* ctl, int ncell, int nleaf, const int* leaves,
+                                            const int4* __restrict__ topo, int ng) {
+    u64 np = 0;
+    for (int i = lane_id(); i < nleaf; i += 64) np += (u64)topo[leaves[i]].y;
+#pragma unroll
+    for (int d = 32; d >= 1; d >>= 1) np += __shfl_xor(np, d, 64);
+    if (lane_id() == 0) {
+        atomicAdd(&ctl->grav_cells, (u64)ncell * (u64)ng);
+        atomicAdd(&ctl->grav_pairs, np * (u64)ng);
+    }
+}
+
+__global__ void k_zero_grav_counts(DevCtl* ctl) {
+    if (threadIdx.x == 0) {
+        ctl->grav_cells = 0;
+        ctl->grav_pairs = 0;
+    }
+}
+
 template <bool FP32C>
 __device__ void eval_lists(int ncell, int nleaf, const int* cells, int* leaves, GravStage& St,
                            const int4* __restrict__ topo, const double4* __restrict__ mom0,
@@ -419,6 +440,7 @@ __global__ void __launch_bounds__(64) k_gravity(DevCtl* ctl, const int4* __restr
                 break;
             }
             if (nc + 64 > GW_CELLS || nl + 64 > GW_LEAVES) {
+                count_terms(ctl, nc, nl, leaves, topo, g.y);
                 eval_lists<FP32C>(nc, nl, cells, leaves, St, topo, mom0, mom1, mom2, pos4, m, T, eps, A, B);
                 nc = nl = 0;
                 __syncthreads();
@@ -468,6 +490,7 @@ __global__ void __launch_bounds__(64) k_gravity(DevCtl* ctl, const int4* __restr
             __syncthreads();
         }
         __syncthreads();
+        count_terms(ctl, nc, nl, leaves, topo, g.y);
         eval_lists<FP32C>(nc, nl, cells, leaves, St, topo, mom0, mom1, mom2, pos4, m, T, eps, A, B);
         // per target: lanes tp + TP*phi combine in a fixed butterfly order
         double r[8];
@@ -517,6 +540,7 @@ void launch_gravity(hipStream_t s, const DevPtrs& d, const Dims& dm, int fp32c, 
     double* gy = accumulate ? d.ay : d.gy;
     double* gz = accumulate ? d.az : d.gz;
     double* de = (accumulate && thermo) ? d.du : nullptr;
+    hipLaunchKernelGGL(k_zero_grav_counts, dim3(1), dim3(64), 0, s, d.ctl);
     if (fp32c)
         hipLaunchKernelGGL(k_gravity<true>, dim3(dm.group_grid), dim3(64), 0, s, d.ctl, d.group, dm.group_size, d.topo,
                            d.nbox_lo, d.nbox_hi, d.mom0, d.mom1, d.mom2, d.pos4, d.m, G, eps, theta, accumulate, gx, gy,

@@ -19,7 +19,7 @@ def test_library_exports_every_declared_symbol():
     from paper_2007_03097_amd import _abi
     lib = _abi.load()
     decl = _declared()
-    assert len(decl) >= 19
+    assert len(decl) >= 20
     for name in decl:
         assert hasattr(lib, name), name
     assert sorted(_abi.EXPORTS) == decl
@@ -73,6 +73,9 @@ def test_host_validation_without_gpu():
     assert lib.sph_timestep(h, bound) == _abi.SPH_E_STATE   # no resident state yet
     assert lib.sph_timestep(None, bound) == _abi.SPH_E_ARG
     assert lib.sph_key_order(h, None, None) == _abi.SPH_E_STATE
+    c1, c2 = ctypes.c_int64(), ctypes.c_int64()
+    assert lib.sph_gravity_counts(h, ctypes.byref(c1), ctypes.byref(c2)) == _abi.SPH_E_STATE   # gravity off
+    assert lib.sph_gravity_counts(None, ctypes.byref(c1), ctypes.byref(c2)) == _abi.SPH_E_ARG
     # the allocation-free step refuses contexts larger than its scratch before touching the GPU
     big = sph.sph_create(cfg, 1_000_000, 1)
     assert lib.sph_step_noalloc(big, None, 1e-3, 1, 0, None) == _abi.SPH_E_CAPACITY

@@ -262,6 +262,8 @@ def test_gravity_theta0_equals_direct(orc):
     scale = np.abs(dp) / 1.0
     assert vec_rel_err((gx, gy, gz), (dx, dy, dz), np.full_like(gm, gm.max())) <= TOL
     assert rel_err(phi, dp, np.abs(dp)) <= TOL
+    import paper_2007_03097_amd as sph
+    assert sph.sph_gravity_counts(ctx.h) == (0, ps.n * (ps.n - 1))   # every ordered pair once
 
 
 @pytest.mark.parametrize("case", ["polytrope", "clustered"])
@@ -312,8 +314,11 @@ def test_gravity_theta_half(orc, prec, capsys):
             for j in range(0, int(c0), 32):
                 gs.append(s0 + j)
                 gc.append(min(32, int(c0) - j))
-        tx, ty, tz, tp = orc.tree_gravity(ps.x[o], ps.y[o], ps.z[o], ps.m[o], t, L, 0.5, 1.0, 0.01, np.array(gs),
-                                          np.array(gc))
+        tx, ty, tz, tp, cnt = orc.tree_gravity(ps.x[o], ps.y[o], ps.z[o], ps.m[o], t, L, 0.5, 1.0, 0.01,
+                                               np.array(gs), np.array(gc), counts=True)
+        import paper_2007_03097_amd as sph
+        gcnt = sph.sph_gravity_counts(ctx.h)   # the same walk's terms (borderline flips aside)
+        assert abs(gcnt[0] - cnt[0]) <= 1e-3 * cnt[0] and abs(gcnt[1] - cnt[1]) <= 1e-3 * cnt[1]
         ref = np.empty((ps.n, 3))
         ref[o] = np.stack([tx, ty, tz], axis=1)
         d = np.linalg.norm(np.stack([gx, gy, gz], axis=1) - ref, axis=1) / gd

@@ -758,3 +758,15 @@ def test_kdk_per_set_step_sizes(orc):
     for k in ("x", "vx", "u", "h", "ax", "dudt"):
         assert np.array_equal(s2[k][:a.n], ra[k]), k
         assert np.array_equal(s2[k][a.n:], rb[k]), k
+
+
+def test_tree_gravity_counts_closed_form(orc):
+    """Counted terms: at theta = 0 no cell is accepted and every ordered pair is summed once
+    (n (n - 1), the direct sum); at theta = 0.5 accepted cells replace part of the pairs."""
+    ps = polytrope_n1(3000, seed=11)
+    o, t, L, gs, gc = _sorted_tree(orc, ps, 8, 32)
+    xs, ys, zs, ms = ps.x[o], ps.y[o], ps.z[o], ps.m[o]
+    *_, (nc, npair) = orc.tree_gravity(xs, ys, zs, ms, t, L, 0.0, 1.0, 0.01, gs, gc, counts=True)
+    assert nc == 0 and npair == ps.n * (ps.n - 1)
+    *_, (nc, npair) = orc.tree_gravity(xs, ys, zs, ms, t, L, 0.5, 1.0, 0.01, gs, gc, counts=True)
+    assert nc > 0 and 0 < npair < ps.n * (ps.n - 1)
