@@ -11,9 +11,10 @@
 // with the M4 cubic spline, W = w(q)/(pi h^3), grad_a W_ab = r_ab g(q)/(pi h^5), g = w'(q)/q.
 //
 // One 256-thread workgroup per target group, in a persistent, XCD-aware loop.  The group's
-// source union (built with the lists) is staged in LDS in chunks; target t is served by
-// 256/group_size threads that take every (256/group_size)-th entry of its list -- entries
-// are ascending union indices, so each thread walks its entries once across the chunks --
+// source union (built with the lists) is staged in LDS in chunks; each of the group's n_g
+// targets is served by PL = 256/n_g threads that take every PL-th entry of its list --
+// entries are ascending union indices, so each thread walks its entries once across the
+// chunks --
 // and read the source records from LDS.  The partial sums of a target are added in a
 // fixed order, so results are bitwise reproducible.  The pair sums are not a dense
 // contraction (each target has its own irregular list), so they run on the vector ALUs,
@@ -153,12 +154,15 @@ __global__ void __launch_bounds__(PAIR_THREADS) k_density(
     float4* __restrict__ thrf) {
     __shared__ DensSrc<FP32C> S;
     const int tid = threadIdx.x;
-    const int t = tid & (gsz - 1), phi = tid / gsz, PL = PAIR_THREADS / gsz;
     int g0, g1, gstep;
     group_range(ctl->n_groups, g0, g1, gstep);
     for (int gi = g0; gi < g1; gi += gstep) {
         const int4 g = group[gi];
-        const bool tv = t < g.y;
+        // PL = 256 / n_g threads per target, so a group with few targets still fills the
+        // workgroup; thread tid serves target tid mod n_g (the last 256 mod n_g threads idle)
+        const int PL = PAIR_THREADS / g.y;
+        const int t = tid % g.y, phi = tid / g.y;
+        const bool tv = phi < PL;
         const int q = g.x + t;
         const double4 org = pos4[g.x];  // group origin (FP32C offsets)
         const double4 mp = tv ? pos4[q] : make_double4(org.x, org.y, org.z, 1);
@@ -199,7 +203,7 @@ __global__ void __launch_bounds__(PAIR_THREADS) k_density(
         __syncthreads();
         if (tv && phi == 0) {
             double sum = red[t];
-            for (int f = 1; f < PL; ++f) sum += red[t + gsz * f];
+            for (int f = 1; f < PL; ++f) sum += red[t + g.y * f];
             const double r_ = sum * M_1_PI_D;
             double ue = u_eos[q];
             const double4 mpos = mp;
@@ -258,12 +262,15 @@ __global__ void __launch_bounds__(PAIR_THREADS) k_forces(
     double* __restrict__ ax, double* __restrict__ ay, double* __restrict__ az, double* __restrict__ du) {
     __shared__ ForceSrc<FP32C> S;
     const int tid = threadIdx.x;
-    const int t = tid & (gsz - 1), phi = tid / gsz, PL = PAIR_THREADS / gsz;
     int g0, g1, gstep;
     group_range(ctl->n_groups, g0, g1, gstep);
     for (int gi = g0; gi < g1; gi += gstep) {
         const int4 g = group[gi];
-        const bool tv = t < g.y;
+        // PL = 256 / n_g threads per target, so a group with few targets still fills the
+        // workgroup; thread tid serves target tid mod n_g (the last 256 mod n_g threads idle)
+        const int PL = PAIR_THREADS / g.y;
+        const int t = tid % g.y, phi = tid / g.y;
+        const bool tv = phi < PL;
         const int q = g.x + t;
         const double4 me = tv ? pos4[q] : make_double4(0, 0, 0, 1);
         const int cnt = tv ? nbr_cnt[q] : 0;
@@ -411,7 +418,7 @@ __global__ void __launch_bounds__(PAIR_THREADS) k_forces(
         if (tv && phi == 0) {
             double s0 = red[t], s1 = red[PAIR_THREADS + t], s2 = red[2 * PAIR_THREADS + t], s3 = red[3 * PAIR_THREADS + t];
             for (int f = 1; f < PL; ++f) {
-                const int i = t + gsz * f;
+                const int i = t + g.y * f;
                 s0 += red[i];
                 s1 += red[PAIR_THREADS + i];
                 s2 += red[2 * PAIR_THREADS + i];
