@@ -397,14 +397,18 @@ __global__ void __launch_bounds__(64) k_gravity(DevCtl* ctl, const int4* __restr
     __shared__ GravStage St;
     const int lane = lane_id();
     GravTargets T;
-    T.TP = gsz >> 1;
-    T.P = 64 / T.TP;
-    T.tp = lane & (T.TP - 1);
-    T.phi = lane / T.TP;
     int g0, g1, gstep;
     group_range(ctl->n_groups, g0, g1, gstep);
     for (int gi = g0; gi < g1; gi += gstep) {
         const int4 g = group[gi];
+        // TP target pairs per wave, the fewest (a power of two) that hold the group's targets:
+        // the P = 64 / TP lanes of a pair split each staged tile, so a group with few
+        // targets keeps every lane busy
+        T.TP = 1;
+        while (2 * T.TP < g.y && T.TP < (gsz >> 1)) T.TP <<= 1;
+        T.P = 64 / T.TP;
+        T.tp = lane & (T.TP - 1);
+        T.phi = lane / T.TP;
         T.qa = g.x + T.tp;
         T.qb = g.x + T.tp + T.TP;
         T.va = T.tp < g.y;
