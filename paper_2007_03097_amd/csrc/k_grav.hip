@@ -19,6 +19,9 @@
 
 constexpr int GW_STACK = 768;
 constexpr int GW_CELLS = 512;
+// FP32C: fewer cells per list flush, so that its walk's LDS (with the FP32 staging) stays
+// within four workgroups per SIMD
+constexpr int GW_CELLS_F = 448;
 constexpr int GW_LEAVES = 256;
 // Stack headroom kept free of wide rounds: popping one entry at a time (depth first), the
 // stack grows by at most 7 per tree level below the popped node, so rounds of 64 entries
@@ -26,8 +29,13 @@ constexpr int GW_LEAVES = 256;
 constexpr int DFS_HEADROOM = 7 * MAX_LEVEL + 8;
 static_assert(GW_STACK > 2 * DFS_HEADROOM, "room for wide rounds above the headroom");
 
-// LDS staging of one evaluation: cell moments in the cell phase, particles in the leaf phase.
-struct GravStage {
+// LDS staging of one evaluation: cell moments in the cell phase, particles in the leaf phase
+// (FP32C stages FP32 records, half the size, which keeps its walk's LDS within four
+// workgroups per SIMD).
+template <bool FP32C>
+struct GravStage;
+template <>
+struct GravStage<false> {
     union {
         struct {
             // (M, com), (3 Ixx, 3 Iyy, 3 Izz, 3/2 tr I), (3 Ixy, 3 Ixz, 3 Iyz, 1/2 tr I)
@@ -37,15 +45,25 @@ struct GravStage {
             double4 pm[64];  // (x, y, z, m)
             int src[64];     // particle index (self test without softening)
         } part;
-        struct {             // FP32C: the same with positions as offsets from the group origin
+    };
+    int loff[GW_LEAVES + 1];  // particle offsets of the staged leaves
+};
+template <>
+struct GravStage<true> {
+    union {
+        struct {             // positions as offsets from the group origin
             float4 c0[64], c1[64], c2[64];
         } cellf;
         struct {
             float4 pm[64];
             int src[64];
         } partf;
+        struct {
+            double4 pm[64];
+            int src[64];
+        } part;
     };
-    int loff[GW_LEAVES + 1];  // particle offsets of the staged leaves
+    int loff[GW_LEAVES + 1];
 };
 
 // Kahan-compensated FP32 sum of FP32 partial sums (one add per staged tile).
@@ -165,7 +183,7 @@ struct GravTargets {
 // Accepted cells (monopole + quadrupole) for the lane's targets, staged 64 at a time (one
 // lane loads one cell).
 template <bool FP32C>
-__device__ void eval_cells(int ncell, const int* cells, GravStage& St, const double4* __restrict__ mom0,
+__device__ void eval_cells(int ncell, const int* cells, GravStage<FP32C>& St, const double4* __restrict__ mom0,
                            const double4* __restrict__ mom1, const double4* __restrict__ mom2, const GravTargets& T,
                            double e2, TargetSums& A, TargetSums& B) {
     const int lane = lane_id();
@@ -175,7 +193,7 @@ __device__ void eval_cells(int ncell, const int* cells, GravStage& St, const dou
         if (k0 + lane < ncell) {
             const int c = cells[k0 + lane];
             const double4 c0 = mom0[c], c1 = mom1[c], c2 = mom2[c];
-            if (FP32C) {
+            if constexpr (FP32C) {
                 St.cellf.c0[lane] = make_float4((float)c0.x, (float)(c0.y - T.o[0]), (float)(c0.z - T.o[1]),
                                                 (float)(c0.w - T.o[2]));
                 St.cellf.c1[lane] = make_float4((float)(3.0 * c1.x), (float)(3.0 * c1.y), (float)(3.0 * c1.z),
@@ -191,7 +209,7 @@ __device__ void eval_cells(int ncell, const int* cells, GravStage& St, const dou
         __syncthreads();
         const int cn = ncell - k0 < 64 ? ncell - k0 : 64;
         if (!any) continue;
-        if (FP32C) {
+        if constexpr (FP32C) {
             const float e2f = (float)e2;
             for (int k = T.phi; k < cn; k += T.P) {
                 const float4 a = St.cellf.c0[k], b = St.cellf.c1[k], d = St.cellf.c2[k];
@@ -270,12 +288,12 @@ __device__ void stage_leaves(int nleaf, int* leaves, Stage& St, const int4* __re
 // With softening the self pair is evaluated like any other (it adds no force) and its
 // potential term -m_q/eps is taken out by the caller.
 template <bool FP32C>
-__device__ void eval_leaves(int nleaf, int* leaves, GravStage& St, const int4* __restrict__ topo,
+__device__ void eval_leaves(int nleaf, int* leaves, GravStage<FP32C>& St, const int4* __restrict__ topo,
                             const double4* __restrict__ pos4, const double* __restrict__ m, const GravTargets& T,
                             double e2, TargetSums& A, TargetSums& B) {
     const bool any = T.va || T.vb;
     const bool soft = e2 > 0.0;
-    if (FP32C) {
+    if constexpr (FP32C) {
         const float e2f = (float)e2;
         stage_leaves_put(
             nleaf, leaves, St, topo, pos4, m,
@@ -372,7 +390,7 @@ __global__ void k_zero_grav_counts(DevCtl* ctl) {
 }
 
 template <bool FP32C>
-__device__ void eval_lists(int ncell, int nleaf, const int* cells, int* leaves, GravStage& St,
+__device__ void eval_lists(int ncell, int nleaf, const int* cells, int* leaves, GravStage<FP32C>& St,
                            const int4* __restrict__ topo, const double4* __restrict__ mom0,
                            const double4* __restrict__ mom1, const double4* __restrict__ mom2,
                            const double4* __restrict__ pos4, const double* __restrict__ m, const GravTargets& T,
@@ -392,9 +410,10 @@ __global__ void __launch_bounds__(64) k_gravity(DevCtl* ctl, const int4* __restr
                                                 double* __restrict__ gzo, double* __restrict__ pho,
                                                 const double4* __restrict__ vel4, double* __restrict__ deo) {
     __shared__ int stack[GW_STACK];
-    __shared__ int cells[GW_CELLS];
+    constexpr int NCELLS = FP32C ? GW_CELLS_F : GW_CELLS;
+    __shared__ int cells[NCELLS];
     __shared__ int leaves[GW_LEAVES];
-    __shared__ GravStage St;
+    __shared__ GravStage<FP32C> St;
     const int lane = lane_id();
     GravTargets T;
     int g0, g1, gstep;
@@ -443,7 +462,7 @@ __global__ void __launch_bounds__(64) k_gravity(DevCtl* ctl, const int4* __restr
                 if (lane == 0) set_err(ctl, ERR_GRAV_LIST);
                 break;
             }
-            if (nc + 64 > GW_CELLS || nl + 64 > GW_LEAVES) {
+            if (nc + 64 > NCELLS || nl + 64 > GW_LEAVES) {
                 count_terms(ctl, nc, nl, leaves, topo, g.y);
                 eval_lists<FP32C>(nc, nl, cells, leaves, St, topo, mom0, mom1, mom2, pos4, m, T, eps, A, B);
                 nc = nl = 0;
