@@ -182,9 +182,12 @@ sph_status sph_tree_nodes(sph_ctx* ctx, int64_t capacity, uint64_t* key, int32_t
  * sorted by ascending caller index.  Synchronous.
  *   offsets_out device int64[n + 1];  idx_out device int32[capacity].
  *   *total_host receives the number of entries; SPH_E_CAPACITY (nothing written to
- *   idx_out) if it exceeds capacity.  Either output may be NULL to only count.  With all
- *   three of offsets_out, idx_out and total_host NULL the call only (re)builds the device
- *   lists, asynchronously (used to time the list kernel). */
+ *   idx_out) if it exceeds capacity.  SPH_E_CAPACITY also when a particle has more than
+ *   nbr_capacity neighbours, or when the source union of a walk group (the particles that
+ *   are a neighbour of at least one of its group_size targets) exceeds 65,536 particles:
+ *   the device lists hold 16-bit indices into that union.  Either output may be NULL to
+ *   only count.  With all three of offsets_out, idx_out and total_host NULL the call only
+ *   (re)builds the device lists, asynchronously (used to time the list kernel). */
 sph_status sph_find_neighbors(sph_ctx* ctx, int64_t* offsets_out, int32_t* idx_out, int64_t capacity,
                               int64_t* total_host);
 
@@ -271,8 +274,8 @@ sph_status sph_key_order(sph_ctx* ctx, uint64_t* keys_out, int64_t* order_out);
  * objects or library allocations; launches are eager on cfg.stream) and needs no
  * sph_set_workspace.  Same arguments, results and synchronisation as sph_step.
  *   - SPH_E_CAPACITY if the context's workspace size (sph_workspace_size: it grows with
- *     n_capacity, seg_capacity and nbr_capacity) exceeds the scratch; about 24,000
- *     particles fit with nbr_capacity 160, 35,000 with 64.
+ *     n_capacity, seg_capacity and nbr_capacity) exceeds the scratch; about 27,000
+ *     particles fit with nbr_capacity 160, 36,000 with 64.
  *   - Every call on one GPU shares that GPU's scratch, which keeps the last call's
  *     contents: calls that overlap on one GPU (other threads, other streams) race, and
  *     SPH_STEP_RESUME is accepted only when no other call used the scratch since this

@@ -174,7 +174,7 @@ static size_t layout(const sph_ctx* c, char* base, DevPtrs* out) {
     d.gcell = cv.take<int>(N + 1);
     d.gnch = cv.take<u32>(N + 1);
     d.goff = cv.take<u32>(N + 1);
-    d.nbr = cv.take<int>(NBR);
+    d.nbr = cv.take<u16>(NBR);
     d.nbr_cnt = cv.take<int>(N);
     d.nbr_base = cv.take<int>(N);
     d.uni = cv.take<int>(NBR);
@@ -314,6 +314,8 @@ static sph_status read_err(sph_ctx* c) {
                     (e & ERR_NONPOSITIVE) ? "h <= 0 or m <= 0" : "");
     if (e & ERR_NBR_CAP) return fail(c, SPH_E_CAPACITY, "device: neighbour list overflow (%d > nbr_capacity %d)", nmax, c->nbr_cap);
     if (e & ERR_WALK_STACK) return fail(c, SPH_E_CAPACITY, "device: tree-walk stack or candidate list overflow");
+    if (e & ERR_UNION_CAP)
+        return fail(c, SPH_E_CAPACITY, "device: a walk group's source union exceeds %d particles", UNION_MAX);
     if (e & ERR_NODE_CAP) return fail(c, SPH_E_CAPACITY, "device: octree node capacity exceeded");
     if (e & ERR_GRAV_LIST) return fail(c, SPH_E_CAPACITY, "device: gravity walk stack overflow");
     return fail(c, SPH_E_DEVICE, "device error word 0x%x", e);

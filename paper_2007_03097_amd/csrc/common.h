@@ -7,6 +7,7 @@
 
 typedef unsigned long long u64;
 typedef unsigned int u32;
+typedef unsigned short u16;
 
 // ---------------------------------------------------------------------------------------
 // Sticky device error bits (read back by sph_sync / synchronous calls).
@@ -17,7 +18,12 @@ enum : u32 {
     ERR_WALK_STACK = 8u,     // tree-walk stack or candidate list overflow
     ERR_NODE_CAP = 16u,      // octree node capacity exceeded
     ERR_GRAV_LIST = 32u,     // gravity walk stack overflow
+    ERR_UNION_CAP = 64u,     // a walk group's source union exceeds UNION_MAX particles
 };
+
+// List entries are 16-bit indices into their group's source union, so a union holds at most
+// this many particles (unions of a few thousand are typical).
+constexpr int UNION_MAX = 65536;
 
 constexpr int MAX_LEVEL = 21;   // 21 three-bit digits below the sentinel bit 63
 constexpr double M_1_PI_D = 0.318309886183790671537767526745028724;
@@ -96,7 +102,7 @@ struct DevPtrs {
     int* gcell;                   // n_cap + 1: first sorted position of each group cell, then n
     u32* gnch;                    // n_cap + 1: groups per group cell
     u32* goff;                    // n_cap + 1
-    int* nbr;                     // n_cap * nbr_cap: list slots, indices into the group's union
+    u16* nbr;                     // n_cap * nbr_cap: list slots, indices into the group's union
     int* nbr_cnt;                 // n_cap
     int* nbr_base;                // n_cap: group whose lists hold the particle (-1 = none)
     int* uni;                     // n_cap * nbr_cap: per group, particles of its source union

@@ -146,7 +146,7 @@ static_assert(sizeof(DensSrc<true>) >= PAIR_THREADS * sizeof(double), "the reduc
 
 template <bool FP32C>
 __global__ void __launch_bounds__(PAIR_THREADS) k_density(
-    const DevCtl* __restrict__ ctl, const int4* __restrict__ group, int gsz, int cap, const int* __restrict__ nbr,
+    const DevCtl* __restrict__ ctl, const int4* __restrict__ group, int gsz, int cap, const u16* __restrict__ nbr,
     const int* __restrict__ nbr_cnt, const int* __restrict__ uni, const int* __restrict__ ucnt,
     const double4* __restrict__ pos4, const double4* __restrict__ vel4, const double* __restrict__ m,
     const double* __restrict__ u_eos, int kin, double gamma, double h_coeff, double* __restrict__ rho,
@@ -168,7 +168,7 @@ __global__ void __launch_bounds__(PAIR_THREADS) k_density(
         const double4 mp = tv ? pos4[q] : make_double4(org.x, org.y, org.z, 1);
         const typename DensSrc<FP32C>::Rec me = DensSrc<FP32C>::target(mp, org);
         const int cnt = tv ? nbr_cnt[q] : 0;
-        const int* lst = nbr + (size_t)g.x * cap + t;
+        const u16* lst = nbr + (size_t)g.x * cap + t;
         const int* un = uni + (size_t)g.x * cap;
         const int nu = ucnt[gi];
         DensAcc<FP32C> acc;
@@ -255,7 +255,7 @@ static_assert(sizeof(ForceSrc<true>) >= 4 * PAIR_THREADS * sizeof(double), "the 
 
 template <bool FP32C, bool THERMO>
 __global__ void __launch_bounds__(PAIR_THREADS) k_forces(
-    const DevCtl* __restrict__ ctl, const int4* __restrict__ group, int gsz, int cap, const int* __restrict__ nbr,
+    const DevCtl* __restrict__ ctl, const int4* __restrict__ group, int gsz, int cap, const u16* __restrict__ nbr,
     const int* __restrict__ nbr_cnt, const int* __restrict__ uni, const int* __restrict__ ucnt,
     const double4* __restrict__ pos4, const double4* __restrict__ vel4, const double4* __restrict__ thr4,
     const float4* __restrict__ velf, const float4* __restrict__ thrf, double alpha, double beta, double eps_av,
@@ -274,7 +274,7 @@ __global__ void __launch_bounds__(PAIR_THREADS) k_forces(
         const int q = g.x + t;
         const double4 me = tv ? pos4[q] : make_double4(0, 0, 0, 1);
         const int cnt = tv ? nbr_cnt[q] : 0;
-        const int* lst = nbr + (size_t)g.x * cap + t;
+        const u16* lst = nbr + (size_t)g.x * cap + t;
         const int* un = uni + (size_t)g.x * cap;
         const int nu = ucnt[gi];
         int k = phi;

@@ -26,9 +26,9 @@
 //     and write, for each hit, the source's index in U.
 // Outputs per group (n_g targets starting at sorted position s):
 //   uni[s*cap + i], i < ucnt[group]: particle index of the i-th member of U;
-//   nbr[s*cap + k*n_g + t]: slot k of target t, an index into U, ascending in k; the blocks
-//   of all groups tile exactly n * cap words, and consumers reading slot k of consecutive
-//   targets read consecutive words.
+//   nbr[s*cap + k*n_g + t]: slot k of target t, a 16-bit index into U (|U| <= UNION_MAX),
+//   ascending in k; the blocks of all groups tile exactly n * cap entries, and consumers
+//   reading slot k of consecutive targets read consecutive entries.
 // The pair kernels stage U in LDS and read their sources there.
 #include "common.h"
 
@@ -122,7 +122,7 @@ __device__ void resolve_exact(u32 q, const double4& A, int head, int j0, const i
 // phi order, each in ascending source order; the entry is the source's index in the union.
 template <int TP>
 __device__ __forceinline__ void append_hits(u32 bits, int t, int& cnt, const LaneTargets<TP>& L, u64 ub, int ucnt,
-                                            int gy, int cap, int* mylist) {
+                                            int gy, int cap, u16* mylist) {
     const int lane = lane_id();
     const int mine = __popc(bits);
     int incl = mine;
@@ -137,7 +137,8 @@ __device__ __forceinline__ void append_hits(u32 bits, int t, int& cnt, const Lan
         const int it = __ffs(bits) - 1;
         bits &= bits - 1;
         const int j = j0 + it;
-        if (slot < cap) mylist[slot * gy + t] = ucnt + __popcll(ub & ((1ull << j) - 1ull));
+        // past UNION_MAX (an overflow the kernel reports) entries stay at the last index, in bounds
+        if (slot < cap) mylist[slot * gy + t] = (u16)min(ucnt + __popcll(ub & ((1ull << j) - 1ull)), UNION_MAX - 1);
         ++slot;
     }
     cnt += tot;
@@ -150,7 +151,7 @@ __device__ __forceinline__ void append_hits(u32 bits, int t, int& cnt, const Lan
 template <int TP>
 __device__ __forceinline__ void test_tile(int head, int tn, const float4* tile, const int* tsrc, LaneTargets<TP>& L,
                                           float me, const double4* __restrict__ pos4, int gx, int gy, int cap,
-                                          int* mylist, int* myuni, int ulim, int& ucnt) {
+                                          u16* mylist, int* myuni, int ulim, int& ucnt) {
     const int lane = lane_id();
     const int j0 = L.phi * TP;
     const int je = min(max(tn - j0, 0), TP);  // sources of this lane's block
@@ -208,7 +209,7 @@ template <int TP>
 __device__ void match_candidates(int nc, int* cand, int* coff, float4* tile, int* tsrc, int& head, int& tail,
                                  const GroupBox& gb, const Screen& S, const int4* __restrict__ topo,
                                  const double4* __restrict__ pos4, LaneTargets<TP>& L, int gx, int gy, int cap,
-                                 int* mylist, int* myuni, int ulim, int& ucnt) {
+                                 u16* mylist, int* myuni, int ulim, int& ucnt) {
     const int lane = lane_id();
     const u64 lt = lanemask_lt();
     int carry = 0;
@@ -273,7 +274,7 @@ template <int TP>
 __global__ void __launch_bounds__(64) k_nbr_lists(DevCtl* ctl, const int4* __restrict__ group, int gsz, int cap,
                                                   const int4* __restrict__ topo, const double4* __restrict__ nbox_lo,
                                                   const double4* __restrict__ nbox_hi, const double4* __restrict__ pos4,
-                                                  int* __restrict__ nbr, int* __restrict__ nbr_cnt,
+                                                  u16* __restrict__ nbr, int* __restrict__ nbr_cnt,
                                                   int* __restrict__ list_base, int* __restrict__ uni,
                                                   int* __restrict__ ucnt_out) {
     __shared__ int stack[WALK_STACK];
@@ -318,9 +319,9 @@ __global__ void __launch_bounds__(64) k_nbr_lists(DevCtl* ctl, const int4* __res
         const double* lo = gb.lo;
         const double* hi = gb.hi;
         const double hg = gb.hg;
-        int* mylist = nbr + (size_t)g.x * (size_t)cap;
+        u16* mylist = nbr + (size_t)g.x * (size_t)cap;
         int* myuni = uni + (size_t)g.x * (size_t)cap;
-        const int ulim = g.y * cap;
+        const int ulim = min(g.y * cap, UNION_MAX);
         int ucnt = 0, head = 0, tail = 0;
         const int root = g.z < 0 ? 0 : ctl->level_off[3] + g.z;
         __syncthreads();
@@ -382,7 +383,10 @@ __global__ void __launch_bounds__(64) k_nbr_lists(DevCtl* ctl, const int4* __res
             __syncthreads();
         } else if (lane == 0)
             set_err(ctl, ERR_WALK_STACK);
-        if (lane == 0) ucnt_out[gi] = overflow ? 0 : (ucnt < ulim ? ucnt : ulim);
+        if (lane == 0) {
+            ucnt_out[gi] = overflow ? 0 : (ucnt < ulim ? ucnt : ulim);
+            if (ucnt > UNION_MAX) set_err(ctl, ERR_UNION_CAP);
+        }
         if (L.phi == 0) {
             for (int s = 0; s < 2; ++s) {
                 if (!(s ? L.vb : L.va)) continue;
@@ -425,14 +429,14 @@ void launch_csr_count(hipStream_t s, const DevPtrs& d, const Dims& dm, int64_t* 
 }
 
 __global__ void k_csr_fill(int n, int gsz, int cap, const int4* __restrict__ group, const u32* __restrict__ id,
-                           const int* __restrict__ cnt, const int* __restrict__ gidx, const int* __restrict__ nbr,
+                           const int* __restrict__ cnt, const int* __restrict__ gidx, const u16* __restrict__ nbr,
                            const int* __restrict__ uni, const int64_t* __restrict__ off, int32_t* idx) {
     const int q = blockIdx.x * blockDim.x + threadIdx.x;
     if (q >= n) return;
     const int c = cnt[q], g = gidx[q];
     if (g < 0) return;
     const int4 gr = group[g];
-    const int* lst = nbr + (size_t)gr.x * cap + (q - gr.x);
+    const u16* lst = nbr + (size_t)gr.x * cap + (q - gr.x);
     const int* un = uni + (size_t)gr.x * cap;
     int32_t* out = idx + off[id[q]];
     for (int k = 0; k < c; ++k) {   // insertion sort by caller index while copying
