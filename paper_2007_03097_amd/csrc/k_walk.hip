@@ -45,13 +45,14 @@ struct GroupBox {
 // FP32 screen of the exact predicate.  Coordinates are offsets from the group origin o (the
 // group's first target), each formed in FP64 and rounded to FP32; h is rounded to FP32.
 // With u = 2^-24 and E the largest per-axis offset of a target from o, the screen values
-//   r2' = fma(dx', dx', fma(dy', dy', dz' dz')),  t2' = fl(fl(h_a' + h_b')^2)
-// (dx' = fl(x_a' - x_b') ...) differ from the exact r^2 and t^2 = (h_a + h_b)^2 by at most
-// 3.6u E^2 + 10.7u r^2 and 5.1u t^2 (offset errors grow with |x - o| <= E + |dx|), and the
-// FP64 expressions differ from them by O(2^-53).  Hence with
+//   r2' = fma(dx', dx', fma(dy', dy', dz' dz')),  t' = fl(h_a' + h_b')
+// (dx' = fl(x_a' - x_b') ...) give r2' and t'^2 within 3.6u E^2 + 10.7u r^2 and 4.1u t^2 of the
+// exact r^2 and t^2 = (h_a + h_b)^2 (offset errors grow with |x - o| <= E + |dx|), and the
+// FP64 expressions differ from them by O(2^-53).  The screen value d' = fma(t', t', -r2')
+// rounds once, so with t2' = fl(t'^2) and
 //   M = 2^-21 E^2 + 2^-19 t2' + 2^-100   (about twice the bound; the last term covers FP32
 //                                          underflow)
-// the FP64 predicate holds when d' = t2' - r2' > M and fails when d' < -M.  Pairs with
+// the FP64 predicate holds when d' > M and fails when d' < -M.  Pairs with
 // |d'| <= M, and any NaN or overflow, are undecided and take the FP64 expression.  FP32
 // arithmetic issues at twice the FP64 rate on this GPU and the staged records halve.
 struct Screen {
@@ -85,12 +86,12 @@ __device__ __forceinline__ float tile_margin(float ha, float hm, float me) {
     return fmaf(tt * tt, 0x1p-19f, me);
 }
 
-// d' = t2' - r2' of one pair (the screen value; see fp32_screen above).
+// d' = fma(t', t', -r2') of one pair (the screen value; see fp32_screen above).
 __device__ __forceinline__ float screen_d(const float4& a, const float4& s) {
     const float dx = a.x - s.x, dy = a.y - s.y, dz = a.z - s.z;
     const float r2 = fmaf(dx, dx, fmaf(dy, dy, dz * dz));
     const float tt = a.w + s.w;
-    return tt * tt - r2;
+    return fmaf(tt, tt, -r2);
 }
 
 // Largest |h| of the tn (>= 1) sources of the tile at ring positions head .., over the wave:
@@ -163,13 +164,15 @@ __device__ __forceinline__ void test_tile(int head, int tn, const float4* tile, 
     const float4* blk = tile + ((head + j0) & (TILE_RING - 1));
     u32 ba = 0, bb = 0;
     u64 und = 0;  // lanes with an undecided pair
+    // sources in descending order, each decision shifted in at bit 0, so that bit it ends up
+    // holding source it; one ballot per comparison keeps the undecided masks in scalar registers
 #pragma unroll 4
-    for (int it = 0; it < TP; ++it) {
+    for (int it = TP - 1; it >= 0; --it) {
         const float4 s = blk[it];
         const float da = screen_d(L.a, s), db = screen_d(L.b, s);
-        ba |= (da > Ma ? 1u : 0u) << it;
-        bb |= (db > Mb ? 1u : 0u) << it;
-        und |= __builtin_amdgcn_ballot_w64(!(fabsf(da) > Ma) || !(fabsf(db) > Mb));
+        ba = ba + ba + (da > Ma ? 1u : 0u);
+        bb = bb + bb + (db > Mb ? 1u : 0u);
+        und |= __builtin_amdgcn_ballot_w64(!(fabsf(da) > Ma)) | __builtin_amdgcn_ballot_w64(!(fabsf(db) > Mb));
     }
     ba &= L.va ? valid : 0u;
     bb &= L.vb ? valid : 0u;
@@ -270,8 +273,10 @@ __device__ void match_candidates(int nc, int* cand, int* coff, float4* tile, int
     }
 }
 
+// 96 VGPRs (five waves per SIMD, no spills) against 110 (four) unconstrained: the walk's
+// dependent loads need the extra wave more than the screen needs the registers.
 template <int TP>
-__global__ void __launch_bounds__(64) k_nbr_lists(DevCtl* ctl, const int4* __restrict__ group, int gsz, int cap,
+__global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(5))) k_nbr_lists(DevCtl* ctl, const int4* __restrict__ group, int gsz, int cap,
                                                   const int4* __restrict__ topo, const double4* __restrict__ nbox_lo,
                                                   const double4* __restrict__ nbox_hi, const double4* __restrict__ pos4,
                                                   u16* __restrict__ nbr, int* __restrict__ nbr_cnt,

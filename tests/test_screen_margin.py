@@ -1,9 +1,9 @@
 """The neighbour kernel's FP32 screen, emulated on the CPU: whenever the screen decides a pair
 (|d'| > M), its decision equals the FP64 predicate fl(fl(fl(dx dx) + fl(dy dy)) + fl(dz dz)) <
 fl(t t).  Screen: offsets from the group origin o formed in FP64 and rounded to FP32,
-r2' = fma(dx', dx', fma(dy', dy', dz' dz')), t2' = fl(fl(h_a' + h_b')^2), d' = t2' - r2',
-M = fma(t2', 2^-19, me), me = 2^-21 E^2 + 2^-100 rounded up, E the largest per-axis offset of a
-target from o.  The kernel decides with the tile margin M' = fma(fl(fl(|h_a'| + hm)^2), 2^-19, me),
+r2' = fma(dx', dx', fma(dy', dy', dz' dz')), t' = fl(h_a' + h_b'), d' = fma(t', t', -r2'),
+M = fma(t2', 2^-19, me) with t2' = fl(t'^2), me = 2^-21 E^2 + 2^-100 rounded up, E the largest
+per-axis offset of a target from o.  The kernel decides with the tile margin M' = fma(fl(fl(|h_a'| + hm)^2), 2^-19, me),
 hm the largest |h'| of the tile's 64 sources, which is at least M for each of the tile's pairs.
 The fused operations are emulated by one FP64 evaluation rounded to FP32 (the FP32 product is
 exact in FP64)."""
@@ -34,7 +34,7 @@ def _screen(ta, sb, ha, hb, o, E, tile=0):
         Mt = _fma32((tx * tx).astype(f32), np.full_like(t2, f32(2.0 ** -19)), np.full_like(t2, me))
         assert np.all(Mt >= M)  # the tile margin bounds every pair's own margin
         M = Mt
-    dd = (t2 - r2).astype(f32)
+    dd = _fma32(tt, tt, -r2)
     hit = dd > M
     undecided = ~(np.abs(dd) > M)
     return hit, undecided
