@@ -14,14 +14,12 @@
 // with R = r_a - R_B, s^2 = |R|^2 + eps^2, I = sum m y y^T about R_B.  Unaccepted leaves
 // contribute softened particle sums with the target itself skipped.  Cell and leaf lists
 // live in LDS and are evaluated whenever they fill, so the walk needs no global scratch;
-// the evaluation stages cell moments and leaf particles through LDS 64 at a time.
+// the evaluation stages cell moments (32 at a time in FP64, 64 in FP32C) and leaf particles
+// (64 at a time) through LDS.
 #include "common.h"
 
 constexpr int GW_STACK = 768;
-constexpr int GW_CELLS = 512;
-// FP32C: fewer cells per list flush, so that its walk's LDS (with the FP32 staging) stays
-// within four workgroups per SIMD
-constexpr int GW_CELLS_F = 448;
+constexpr int GW_CELLS = 448;
 constexpr int GW_LEAVES = 256;
 // Stack headroom kept free of wide rounds: popping one entry at a time (depth first), the
 // stack grows by at most 7 per tree level below the popped node, so rounds of 64 entries
@@ -29,9 +27,9 @@ constexpr int GW_LEAVES = 256;
 constexpr int DFS_HEADROOM = 7 * MAX_LEVEL + 8;
 static_assert(GW_STACK > 2 * DFS_HEADROOM, "room for wide rounds above the headroom");
 
-// LDS staging of one evaluation: cell moments in the cell phase, particles in the leaf phase
-// (FP32C stages FP32 records, half the size, which keeps its walk's LDS within four
-// workgroups per SIMD).
+// LDS staging of one evaluation: cell moments in the cell phase, particles in the leaf phase.
+// FP32C stages FP32 records, 64 cells per round; FP64 stages 32 cells of 96 bytes per round.
+// Either way the walk's LDS stays near 10 KB per workgroup (16 workgroups per CU).
 template <bool FP32C>
 struct GravStage;
 template <>
@@ -39,7 +37,7 @@ struct GravStage<false> {
     union {
         struct {
             // (M, com), (3 Ixx, 3 Iyy, 3 Izz, 3/2 tr I), (3 Ixy, 3 Ixz, 3 Iyz, 1/2 tr I)
-            double4 c0[64], c1[64], c2[64];
+            double4 c0[32], c1[32], c2[32];
         } cell;
         struct {
             double4 pm[64];  // (x, y, z, m)
@@ -180,7 +178,7 @@ struct GravTargets {
     int tp, phi, TP, P;
 };
 
-// Accepted cells (monopole + quadrupole) for the lane's targets, staged 64 at a time (one
+// Accepted cells (monopole + quadrupole) for the lane's targets, staged CS at a time (one
 // lane loads one cell).
 template <bool FP32C>
 __device__ void eval_cells(int ncell, const int* cells, GravStage<FP32C>& St, const double4* __restrict__ mom0,
@@ -188,9 +186,10 @@ __device__ void eval_cells(int ncell, const int* cells, GravStage<FP32C>& St, co
                            double e2, TargetSums& A, TargetSums& B) {
     const int lane = lane_id();
     const bool any = T.va || T.vb;
-    for (int k0 = 0; k0 < ncell; k0 += 64) {
+    constexpr int CS = FP32C ? 64 : 32;  // cells staged per round
+    for (int k0 = 0; k0 < ncell; k0 += CS) {
         __syncthreads();
-        if (k0 + lane < ncell) {
+        if (lane < CS && k0 + lane < ncell) {
             const int c = cells[k0 + lane];
             const double4 c0 = mom0[c], c1 = mom1[c], c2 = mom2[c];
             if constexpr (FP32C) {
@@ -207,7 +206,7 @@ __device__ void eval_cells(int ncell, const int* cells, GravStage<FP32C>& St, co
             }
         }
         __syncthreads();
-        const int cn = ncell - k0 < 64 ? ncell - k0 : 64;
+        const int cn = ncell - k0 < CS ? ncell - k0 : CS;
         if (!any) continue;
         if constexpr (FP32C) {
             const float e2f = (float)e2;
@@ -410,8 +409,7 @@ __global__ void __launch_bounds__(64) k_gravity(DevCtl* ctl, const int4* __restr
                                                 double* __restrict__ gzo, double* __restrict__ pho,
                                                 const double4* __restrict__ vel4, double* __restrict__ deo) {
     __shared__ int stack[GW_STACK];
-    constexpr int NCELLS = FP32C ? GW_CELLS_F : GW_CELLS;
-    __shared__ int cells[NCELLS];
+    __shared__ int cells[GW_CELLS];
     __shared__ int leaves[GW_LEAVES];
     __shared__ GravStage<FP32C> St;
     const int lane = lane_id();
@@ -462,7 +460,7 @@ __global__ void __launch_bounds__(64) k_gravity(DevCtl* ctl, const int4* __restr
                 if (lane == 0) set_err(ctl, ERR_GRAV_LIST);
                 break;
             }
-            if (nc + 64 > NCELLS || nl + 64 > GW_LEAVES) {
+            if (nc + 64 > GW_CELLS || nl + 64 > GW_LEAVES) {
                 count_terms(ctl, nc, nl, leaves, topo, g.y);
                 eval_lists<FP32C>(nc, nl, cells, leaves, St, topo, mom0, mom1, mom2, pos4, m, T, eps, A, B);
                 nc = nl = 0;
