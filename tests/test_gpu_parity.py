@@ -753,6 +753,49 @@ def test_error_paths():
     assert e.value.status == -1
 
 
+def _halo_and_blobs(n_blob=1100, seed=41):
+    """64 'halo' particles alone in the octree cell [0, 0.5]^3 of the root [0, 1]^3, on an
+    8 x 8 grid at x = 0.495, each reaching only its own blob of n_blob particles just across
+    x = 0.5: every halo particle has n_blob + 1 neighbours, while the 64 halo particles
+    together reach 64 (n_blob + 1) particles."""
+    rng = np.random.default_rng(seed)
+    g = 0.05 * np.arange(1, 9)
+    hy, hz = (a.ravel() for a in np.meshgrid(g, g, indexing="ij"))
+    hx = np.full(64, 0.495)
+    d = rng.normal(size=(64, n_blob, 3))
+    d *= (0.002 * rng.random((64, n_blob, 1)) ** (1 / 3)) / np.linalg.norm(d, axis=2, keepdims=True)
+    bx = 0.505 + d[..., 0]
+    by = hy[:, None] + d[..., 1]
+    bz = hz[:, None] + d[..., 2]
+    x = np.concatenate([hx, bx.ravel()])
+    y = np.concatenate([hy, by.ravel()])
+    z = np.concatenate([hz, bz.ravel()])
+    n = x.size
+    h = np.concatenate([np.full(64, 0.0125), np.full(64 * n_blob, 1e-4)])
+    zero = np.zeros(n)
+    return ParticleSet(x, y, z, zero, zero.copy(), zero.copy(), np.full(n, 1.0 / n), h, np.ones(n))
+
+
+def test_union_limit():
+    """List entries are 16-bit indices into a group's source union: a group whose union
+    exceeds 65,536 particles is a capacity error (not a wrapped index), and the same set with
+    smaller groups is listed correctly (each halo particle's list is itself and its blob)."""
+    import paper_2007_03097_amd as sph
+    ps = _halo_and_blobs()
+    box = np.array([0.0, 0.0, 0.0, 1.0, 1.0, 1.0])
+    ctx = make_ctx(ps.n, leaf_size=16, group_size=64, nbr_capacity=2048)
+    gpu_keys_order(ctx, parts(ps), box=box)
+    with pytest.raises(sph.SPHError) as e:
+        gpu_neighbors(ctx, ps.n)
+    assert e.value.status == -4 and "union" in str(e.value)
+    ctx2 = make_ctx(ps.n, leaf_size=16, group_size=32, nbr_capacity=2048)
+    gpu_keys_order(ctx2, parts(ps), box=box)
+    off, idx = gpu_neighbors(ctx2, ps.n)
+    for a in range(64):
+        row = idx[off[a]:off[a + 1]]
+        assert row.tolist() == [a] + list(range(64 + 1100 * a, 64 + 1100 * (a + 1)))
+
+
 def test_empty_set():
     ps = uniform_random(0, seed=1)
     ctx = make_ctx(1)
