@@ -50,15 +50,42 @@ __device__ __forceinline__ int window_level(const signed char* c, int ci, int wi
     return L > MAX_LEVEL ? MAX_LEVEL : L;
 }
 
+// window_level with the leaf capacity W known at compile time: the running minima MR(k) stay
+// in registers (the same values, the same pairing of ML(t) with MR(W - t)).
+template <int W>
+__device__ __forceinline__ int window_level_w(const signed char* c, int ci) {
+    int mr[W];
+    int m = 127;
+#pragma unroll
+    for (int k = 1; k <= W; ++k) {
+        const int v = c[ci + k];
+        m = v < m ? v : m;
+        mr[k - 1] = m;
+    }
+    int best = 127, ml = 127;
+#pragma unroll
+    for (int t = 0; t < W; ++t) {
+        const int v = c[ci - t];
+        ml = v < ml ? v : ml;
+        const int r = mr[W - 1 - t];
+        const int x = ml > r ? ml : r;
+        best = x < best ? x : best;
+    }
+    const int L = best + 1;
+    return L > MAX_LEVEL ? MAX_LEVEL : L;
+}
+
 // Per sorted position: lcp, leaf level (leaf capacity win) and the node / leaf-start counts
 // for the pre-order scan.  Also clears the per-level node counters (block 0) and the
-// group-cell flags of every position, which later kernels of the build fill in.
+// group-cell flags of every position, which later kernels of the build fill in.  W > 0: the
+// leaf capacity is W (= win) and the window runs in registers; W = 0: any win, through LDS.
+template <int W>
 __global__ void __launch_bounds__(TB) k_leaf_levels(const u64* __restrict__ key, int n, int win, int min_level,
                                                     signed char* lcp, unsigned char* lvl, u64* scan_in, DevCtl* ctl,
                                                     u32* gflag) {
     if (blockIdx.x == 0 && threadIdx.x < 24) ctl->level_count[threadIdx.x] = 0;
     __shared__ signed char c[TB + 2 * MAX_WIN + 2];
-    __shared__ signed char mrow[TB * MAX_WIN];
+    __shared__ signed char mrow[W > 0 ? 1 : TB * MAX_WIN];
     const int b0 = blockIdx.x * TB;
     const int lo = b0 - win;                      // c[j] holds position lo + j
     const int cnt = TB + 2 * win + 1;
@@ -72,7 +99,9 @@ __global__ void __launch_bounds__(TB) k_leaf_levels(const u64* __restrict__ key,
     const int i = b0 + threadIdx.x;
     if (i >= n) return;
     const int ci = i - lo;
-    int L = window_level(c, ci, win, mrow + threadIdx.x);
+    int L;
+    if constexpr (W > 0) L = window_level_w<W>(c, ci);
+    else L = window_level(c, ci, win, mrow + threadIdx.x);
     if (L < min_level) L = min_level;
     const int cc = c[ci];
     const int nodes = L > cc ? L - cc : 0;
@@ -500,8 +529,19 @@ static int grid_cap(int n, int bs, int cap) {
 void build_octree(hipStream_t s, const DevPtrs& d, const Dims& dm) {
     const int n = dm.n;
     if (n <= 0) return;
-    hipLaunchKernelGGL(k_leaf_levels, dim3((n + TB - 1) / TB), dim3(TB), 0, s, d.key_a, n, dm.leaf_size, dm.min_level,
-                       d.lcp, d.lvl, d.scan_in, d.ctl, d.gflag);
+    auto levels = [&](auto kern) {
+        hipLaunchKernelGGL(kern, dim3((n + TB - 1) / TB), dim3(TB), 0, s, d.key_a, n, dm.leaf_size, dm.min_level, d.lcp,
+                           d.lvl, d.scan_in, d.ctl, d.gflag);
+    };
+    switch (dm.leaf_size) {  // the autotuner's leaf sizes and the node-node scheme's 64
+        case 8: levels(k_leaf_levels<8>); break;
+        case 12: levels(k_leaf_levels<12>); break;
+        case 16: levels(k_leaf_levels<16>); break;
+        case 24: levels(k_leaf_levels<24>); break;
+        case 32: levels(k_leaf_levels<32>); break;
+        case 64: levels(k_leaf_levels<64>); break;
+        default: levels(k_leaf_levels<0>); break;
+    }
     scan_u64(s, d.scan_in, d.scan_out, n, d.scan_tmp);
     hipLaunchKernelGGL(k_emit_nodes, dim3(grid_cap(n, 256, 512)), dim3(256), 0, s, n, d.lcp, d.lvl, d.scan_out,
                        d.pre_level, d.pre_leaf, d.pre_start, d.leaf_start, d.leaf_pre, d.ctl, dm.node_cap);

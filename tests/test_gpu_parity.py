@@ -118,8 +118,10 @@ def test_fig1_tree_on_gpu(orc):
 
 
 @pytest.mark.parametrize("case", ["random_varh", "duplicates", "clustered", "polytrope", "n1", "n2"])
-@pytest.mark.parametrize("leaf", [1, 5, 16, 64])
+@pytest.mark.parametrize("leaf", [1, 5, 8, 12, 16, 24, 32, 64])
 def test_octree_matches_oracle(orc, case, leaf):
+    """Leaf sizes 8-32 and 64 take the leaf-level kernel's compile-time windows, 1 and 5 the
+    general one."""
     ps = CASES[case]()
     ctx = make_ctx(ps.n, leaf_size=leaf)
     k, o = gpu_keys_order(ctx, parts(ps))
