@@ -168,6 +168,13 @@ __device__ __forceinline__ double wave_max(double v) {
     for (int d = 32; d >= 1; d >>= 1) v = fmax(v, __shfl_xor(v, d, 64));
     return v;
 }
+// A value every active lane holds (a wave reduction's result) moved to scalar registers, so
+// that it costs no vector registers where it is only read.
+__device__ __forceinline__ double uniform_d(double v) {
+    const u64 b = (u64)__double_as_longlong(v);
+    const u32 lo = __builtin_amdgcn_readfirstlane((u32)b), hi = __builtin_amdgcn_readfirstlane((u32)(b >> 32));
+    return __longlong_as_double((long long)(((u64)hi << 32) | lo));
+}
 
 // Sum over the 64/gsz lanes that serve one target (lanes t, t+gsz, ...), fixed order.
 __device__ __forceinline__ double lanes_sum_d(double v, int gsz) {

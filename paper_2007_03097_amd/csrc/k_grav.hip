@@ -447,6 +447,10 @@ __global__ void __launch_bounds__(64) k_gravity(DevCtl* ctl, const int4* __restr
         hi[0] = wave_max(fmax(T.va ? T.a.x : -INFINITY, T.vb ? T.b.x : -INFINITY));
         hi[1] = wave_max(fmax(T.va ? T.a.y : -INFINITY, T.vb ? T.b.y : -INFINITY));
         hi[2] = wave_max(fmax(T.va ? T.a.z : -INFINITY, T.vb ? T.b.z : -INFINITY));
+        for (int c = 0; c < 3; ++c) {  // the group box in scalar registers
+            lo[c] = uniform_d(lo[c]);
+            hi[c] = uniform_d(hi[c]);
+        }
         const double th2 = theta * theta;
         const u64 lt = lanemask_lt();
         TargetSums A, B;
