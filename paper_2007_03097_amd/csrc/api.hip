@@ -145,7 +145,6 @@ static size_t layout(const sph_ctx* c, char* base, DevPtrs* out) {
     d.pos4 = cv.take<double4>(N);
     d.vel4 = cv.take<double4>(N);
     d.thr4 = cv.take<double4>(N);
-    d.velf = cv.take<float4>(N);
     d.thrf = cv.take<float4>(N);
     d.lcp = cv.take<signed char>(N + 1);
     d.lvl = cv.take<unsigned char>(N);

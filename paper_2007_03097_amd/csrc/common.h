@@ -71,8 +71,7 @@ struct DevPtrs {
     double4* pos4;                // x, y, z, h (Morton order)
     double4* vel4;                // vx(pred), vy, vz, m
     double4* thr4;                // rho, P/rho^2, c, u
-    float4* velf;                 // FP32 copies for the compensated path: vx, vy, vz, m
-    float4* thrf;                 //   rho, P/rho^2, c, h
+    float4* thrf;                 // FP32 copy for the compensated path: rho, P/rho^2, c, h
     // tree
     signed char* lcp;             // n_cap + 1: shared leading digits with the previous key
     unsigned char* lvl;           // n_cap: leaf level of each sorted position

@@ -544,7 +544,6 @@ __global__ void __launch_bounds__(256) k_gather_input(int n, const u32* __restri
     d.m[q] = pm; d.h[q] = ph; d.u[q] = pu;
     d.pos4[q] = make_double4(px, py, pz, ph);
     d.vel4[q] = make_double4(wx, wy, wz, pm);
-    d.velf[q] = make_float4((float)wx, (float)wy, (float)wz, (float)pm);
     if (order_out) order_out[q] = (int64_t)i;
 }
 

@@ -238,7 +238,7 @@ void launch_density(hipStream_t s, const DevPtrs& d, const Dims& dm, int fp32c, 
 }
 
 // Source records in LDS for the force sums: FP64 (x, h), (v, m), (rho, P/rho^2, c), or
-// FP32C (x, h) in FP64 and (v, m), (rho, P/rho^2, c, h) in FP32.
+// FP32C (x, h) and (v, m) in FP64 and (rho, P/rho^2, c, h) in FP32.
 template <bool FP32C>
 struct ForceSrc;
 template <>
@@ -258,7 +258,7 @@ __global__ void __launch_bounds__(PAIR_THREADS) k_forces(
     const DevCtl* __restrict__ ctl, const int4* __restrict__ group, int gsz, int cap, const u16* __restrict__ nbr,
     const int* __restrict__ nbr_cnt, const int* __restrict__ uni, const int* __restrict__ ucnt,
     const double4* __restrict__ pos4, const double4* __restrict__ vel4, const double4* __restrict__ thr4,
-    const float4* __restrict__ velf, const float4* __restrict__ thrf, double alpha, double beta, double eps_av,
+    const float4* __restrict__ thrf, double alpha, double beta, double eps_av,
     double* __restrict__ ax, double* __restrict__ ay, double* __restrict__ az, double* __restrict__ du) {
     __shared__ ForceSrc<FP32C> S;
     const int tid = threadIdx.x;
@@ -437,7 +437,7 @@ void launch_forces(hipStream_t s, const DevPtrs& d, const Dims& dm, int fp32c, d
     if (dm.n <= 0) return;
     auto go = [&](auto kern) {
         hipLaunchKernelGGL(kern, dim3(dm.pair_grid), dim3(PAIR_THREADS), 0, s, d.ctl, d.group, dm.group_size,
-                           dm.nbr_cap, d.nbr, d.nbr_cnt, d.uni, d.ucnt, d.pos4, d.vel4, d.thr4, d.velf, d.thrf, alpha,
+                           dm.nbr_cap, d.nbr, d.nbr_cnt, d.uni, d.ucnt, d.pos4, d.vel4, d.thr4, d.thrf, alpha,
                            beta, eps_av, d.ax, d.ay, d.az, d.du);
     };
     if (fp32c) {

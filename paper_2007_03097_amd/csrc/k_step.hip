@@ -67,7 +67,8 @@ void launch_kick_drift(hipStream_t s, const DevPtrs& d, const Dims& dm) {
 
 // New key order: q <- old position val[q] (the sort carried the positions); the second
 // buffer set receives the data, and the pair kernels' records pos4 = (x, h),
-// vel4 = (predicted v, m) are written too.
+// vel4 = (predicted v, m) are written too.  The predicted velocities enter vel4 only: the
+// next kick-drift writes them anew before anything reads them.
 __global__ void k_step_permute(int n, const u32* __restrict__ val, DevPtrs d) {
     const int q = blockIdx.x * blockDim.x + threadIdx.x;
     if (q >= n) return;
@@ -78,10 +79,9 @@ __global__ void k_step_permute(int n, const u32* __restrict__ val, DevPtrs d) {
     d.x2[q] = px; d.y2[q] = py; d.z2[q] = pz;
     d.vx2[q] = d.vx[p]; d.vy2[q] = d.vy[p]; d.vz2[q] = d.vz[p];
     d.u2[q] = d.u[p]; d.m2[q] = mm; d.h2[q] = hh;
-    d.vpx2[q] = wx; d.vpy2[q] = wy; d.vpz2[q] = wz; d.up2[q] = d.up[p];
+    d.up2[q] = d.up[p];
     d.pos4[q] = make_double4(px, py, pz, hh);
     d.vel4[q] = make_double4(wx, wy, wz, mm);
-    d.velf[q] = make_float4((float)wx, (float)wy, (float)wz, (float)mm);
 }
 void launch_step_permute(hipStream_t s, const DevPtrs& d, int n) {
     if (n > 0) hipLaunchKernelGGL(k_step_permute, g256(n), dim3(256), 0, s, n, d.val_a, d);
