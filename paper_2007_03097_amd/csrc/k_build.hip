@@ -183,11 +183,11 @@ void launch_keys(hipStream_t s, const DevPtrs& d, const Dims& dm, const double* 
 // Step-loop keys: positions are in the previous key order; write the key at the caller
 // index (so the sort input is again in caller order) and remember where each caller
 // index sat.
+// (the positions, velocities and energies it keys were checked for non-finite values by the
+// kick-drift that wrote them)
 __global__ void __launch_bounds__(256) k_step_keys(DevCtl* ctl, const int4* chunk, int batched, int curve,
                                                     const double* __restrict__ x, const double* __restrict__ y,
-                                                    const double* __restrict__ z, const double* __restrict__ vx,
-                                                    const double* __restrict__ vy, const double* __restrict__ vz,
-                                                    const double* __restrict__ u, const u32* __restrict__ id,
+                                                    const double* __restrict__ z, const u32* __restrict__ id,
                                                     u64* key, u32* val) {
     const int4 ch = chunk[blockIdx.x];
     // the segment's box from the merged encodings, L and S = 2^B / L (one IEEE division);
@@ -208,23 +208,18 @@ __global__ void __launch_bounds__(256) k_step_keys(DevCtl* ctl, const int4* chun
             ctl->side[ch.z] = L;
         }
     }
-    u32 bad = 0;
     for (int p = ch.x + threadIdx.x; p < ch.y; p += blockDim.x) {
-        double px = x[p], py = y[p], pz = z[p];
-        if (!isfinite(px) || !isfinite(py) || !isfinite(pz) || !isfinite(vx[p]) || !isfinite(vy[p]) ||
-            !isfinite(vz[p]) || !isfinite(u[p]))
-            bad |= ERR_NONFINITE;
+        const double px = x[p], py = y[p], pz = z[p];
         const u32 i = id[p];  // keys go to caller order, so the stable sort orders ties by ID
         key[i] = make_key(px, py, pz, box, S, ch.z, batched, curve);
         val[i] = (u32)p;      // the sort carries each particle's current position
     }
-    if (bad) set_err(ctl, bad);
 }
 
 void launch_step_keys(hipStream_t s, const DevPtrs& d, const Dims& dm) {
     if (dm.n_chunks > 0)
         hipLaunchKernelGGL(k_step_keys, dim3(dm.n_chunks), dim3(256), 0, s, d.ctl, d.chunk, dm.batched, dm.curve, d.x, d.y,
-                           d.z, d.vx, d.vy, d.vz, d.u, d.id, d.key_a, d.val_a);
+                           d.z, d.id, d.key_a, d.val_a);
 }
 
 // ---------------------------------------------------------------------------------------

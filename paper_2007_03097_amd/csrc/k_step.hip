@@ -30,7 +30,8 @@ void launch_gather_caller(hipStream_t s, const DevPtrs& d, int n, const double* 
 
 // v' = v + dt/2 a; u' = u + dt/2 du; x += dt v'; predictors v^ = v' + dt/2 a, u^ = u' + dt/2 du.
 // One block per chunk (chunks never cross a segment; dt is the segment's step size); the new
-// positions' box is merged into the segment's box on the way.
+// positions' box is merged into the segment's box on the way, and non-finite new x, v' or u'
+// raise the sticky error.
 __global__ void __launch_bounds__(256) k_kick_drift(DevCtl* ctl, const int4* __restrict__ chunk, double* x,
                                                     double* y, double* z, double* vx, double* vy, double* vz, double* u,
                                                     const double* __restrict__ ax, const double* __restrict__ ay,
@@ -40,6 +41,7 @@ __global__ void __launch_bounds__(256) k_kick_drift(DevCtl* ctl, const int4* __r
     const double dt = ctl->seg_dt[ch.z];
     const double half = 0.5 * dt;
     double lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
+    bool bad = false;
     for (int q = ch.x + threadIdx.x; q < ch.y; q += blockDim.x) {
         const double a0 = ax[q], a1 = ay[q], a2 = az[q], d0 = du[q];
         const double hx = vx[q] + half * a0, hy = vy[q] + half * a1, hz = vz[q] + half * a2;
@@ -56,7 +58,10 @@ __global__ void __launch_bounds__(256) k_kick_drift(DevCtl* ctl, const int4* __r
         up[q] = uh + half * d0;
         lo[0] = fmin(lo[0], nx); lo[1] = fmin(lo[1], ny); lo[2] = fmin(lo[2], nz);
         hi[0] = fmax(hi[0], nx); hi[1] = fmax(hi[1], ny); hi[2] = fmax(hi[2], nz);
+        bad |= !isfinite(nx) || !isfinite(ny) || !isfinite(nz) || !isfinite(hx) || !isfinite(hy) ||
+               !isfinite(hz) || !isfinite(uh);
     }
+    if (bad) set_err(ctl, ERR_NONFINITE);
     box_block_merge(ctl, ch.z, lo, hi, ch.y > ch.x);
 }
 void launch_kick_drift(hipStream_t s, const DevPtrs& d, const Dims& dm) {

@@ -223,3 +223,21 @@ def test_same_size_new_layout_recaptures_the_step(monkeypatch, tmp_path):
     ref = _step_fresh(b, 2, True, monkeypatch, leaf_size=lf, group_size=gs, **cap)
     for k in got:
         assert np.array_equal(got[k], ref[k]), k
+
+
+def test_step_reports_a_state_turned_nonfinite(monkeypatch):
+    """A state that turns non-finite during the steps is reported: one particle with negative
+    thermal energy has a NaN sound speed, so its viscous pairs (and the accelerations) are NaN,
+    and the kick-drift that applies them raises SPH_E_NONFINITE, with graphs and without."""
+    import paper_2007_03097_amd as sph
+    for no_graph in ("0", "1"):
+        monkeypatch.setenv("SPH_NO_GRAPH", no_graph)
+        ps = lattice_box(8, seed=3, v_sigma=0.1)
+        ps.u[100] = -1.0
+        ctx = make_ctx(ps.n)
+        with pytest.raises(sph.SPHError) as e:
+            sph.sph_step(ctx.h, parts(ps), 1e-4, 2, 0)
+        assert e.value.status == -6
+        ok = lattice_box(8, seed=3, v_sigma=0.1)
+        ctx2 = make_ctx(ok.n)
+        sph.sph_step(ctx2.h, parts(ok), 1e-4, 2, 0)  # the same set with u > 0 steps cleanly
