@@ -170,9 +170,7 @@ static size_t layout(const sph_ctx* c, char* base, DevPtrs* out) {
     d.group = cv.take<int4>(GC);
     d.gflag = cv.take<u32>(N + 1);
     d.gscan = cv.take<u32>(N + 1);
-    d.gcell = cv.take<int>(N + 1);
-    d.gnch = cv.take<u32>(N + 1);
-    d.goff = cv.take<u32>(N + 1);
+    d.gsize = cv.take<u32>(N + 1);
     d.nbr = cv.take<u16>(NBR);
     d.nbr_cnt = cv.take<int>(N);
     d.nbr_base = cv.take<int>(N);

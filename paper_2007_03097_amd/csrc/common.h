@@ -34,7 +34,6 @@ struct DevCtl {
     int n_nodes;
     int n_leaves;
     int nbr_max;                  // largest neighbour count seen (for overflow reports)
-    int n_gcells;                 // group cells (octree cells of at most 4 * group_size)
     int n_groups;                 // target groups
     int level_count[24];          // nodes per level
     int level_off[24];            // exclusive prefix of level_count
@@ -96,11 +95,9 @@ struct DevPtrs {
     double4* mom2;                // node_cap: Ixy, Ixz, Iyz, cell (bits; node-node gravity only)
     // groups and neighbour lists
     int4* group;                  // group_cap: {start, count, segment root rank (-1 = root), 0}
-    u32* gflag;                   // n_cap + 1: 1 where a group cell starts
+    u32* gflag;                   // n_cap + 1: 1 where a target group starts
     u32* gscan;                   // n_cap + 1
-    int* gcell;                   // n_cap + 1: first sorted position of each group cell, then n
-    u32* gnch;                    // n_cap + 1: groups per group cell
-    u32* goff;                    // n_cap + 1
+    u32* gsize;                   // n_cap + 1: size of the target group starting at a flagged position
     u16* nbr;                     // n_cap * nbr_cap: list slots, indices into the group's union
     int* nbr_cnt;                 // n_cap
     int* nbr_base;                // n_cap: group whose lists hold the particle (-1 = none)

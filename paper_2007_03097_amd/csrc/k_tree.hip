@@ -116,10 +116,12 @@ __global__ void __launch_bounds__(TB) k_leaf_levels(const u64* __restrict__ key,
 }
 
 // Group cells: the largest nodes holding at most gcap particles (at or below min_level),
-// plus leaves that hold more (runs of equal keys).  They partition the sorted particles;
-// their first positions are flagged.
-__global__ void k_gcell_flags(const DevCtl* __restrict__ ctl, int gcap, int min_level, const int4* __restrict__ topo,
-                              const int* __restrict__ parent, const int2* __restrict__ range, u32* gflag) {
+// plus leaves that hold more (runs of equal keys).  They partition the sorted particles.
+// Each is cut into target groups of at most gsz consecutive particles: the first position
+// of every group is flagged and the group's size recorded there.
+__global__ void k_group_starts(const DevCtl* __restrict__ ctl, int gcap, int gsz, int min_level,
+                               const int4* __restrict__ topo, const int* __restrict__ parent,
+                               const int2* __restrict__ range, u32* gflag, u32* gsize) {
     const int nn = ctl->n_nodes;
     for (int b = blockIdx.x * blockDim.x + threadIdx.x; b < nn; b += gridDim.x * blockDim.x) {
         const int4 tp = topo[b];
@@ -128,42 +130,25 @@ __global__ void k_gcell_flags(const DevCtl* __restrict__ ctl, int gcap, int min_
         const int p = parent[b];
         bool pfits = false;
         if (p >= 0) pfits = range[p].y <= gcap && topo[p].z >= min_level;
-        if (!pfits) gflag[range[b].x] = 1u;
+        if (pfits) continue;
+        const int2 r = range[b];
+        const int e = r.x + r.y;
+        for (int k = r.x; k < e; k += gsz) {
+            gflag[k] = 1u;
+            gsize[k] = (u32)min(gsz, e - k);
+        }
     }
 }
 
-// Group cells -> target groups of at most gsz consecutive particles inside one cell.
-__global__ void k_gcells(int n, const u32* __restrict__ gflag, const u32* __restrict__ gscan, int* gcell,
-                         DevCtl* ctl) {
+// Target groups in sorted order: group gscan[i] starts at each flagged position i.
+__global__ void k_emit_groups(int n, int batched, DevCtl* ctl, const u32* __restrict__ gflag,
+                              const u32* __restrict__ gscan, const u32* __restrict__ gsize,
+                              const u64* __restrict__ key, const int* __restrict__ seg_root_rank, int4* group) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < n && gflag[i]) gcell[gscan[i]] = i;
-    if (i == 0) {
-        const int nc = (int)gscan[n];
-        ctl->n_gcells = nc;
-        gcell[nc] = n;
-    }
-}
-
-__global__ void k_gcell_chunks(int n, int gsz, const DevCtl* __restrict__ ctl, const int* __restrict__ gcell,
-                               u32* gnch) {
-    const int j = blockIdx.x * blockDim.x + threadIdx.x;
-    if (j >= n) return;
-    const int nc = ctl->n_gcells;
-    gnch[j] = j < nc ? (u32)((gcell[j + 1] - gcell[j] + gsz - 1) / gsz) : 0u;
-}
-
-__global__ void k_emit_groups(int n, int gsz, int batched, DevCtl* ctl, const int* __restrict__ gcell,
-                              const u32* __restrict__ gnch, const u32* __restrict__ goff, const u64* __restrict__ key,
-                              const int* __restrict__ seg_root_rank, int4* group) {
-    const int j = blockIdx.x * blockDim.x + threadIdx.x;
-    if (j == 0) ctl->n_groups = (int)goff[n];
-    if (j >= ctl->n_gcells) return;
-    const int s = gcell[j], e = gcell[j + 1];
-    const int rank = batched ? seg_root_rank[(int)((key[s] >> 54) & 511ull)] : -1;
-    const u32 base = goff[j];
-    for (u32 k = 0; k < gnch[j]; ++k) {
-        const int b = s + (int)k * gsz;
-        group[base + k] = make_int4(b, min(gsz, e - b), rank, 0);
+    if (i == 0) ctl->n_groups = (int)gscan[n];
+    if (i < n && gflag[i]) {
+        const int rank = batched ? seg_root_rank[(int)((key[i] >> 54) & 511ull)] : -1;
+        group[gscan[i]] = make_int4(i, (int)gsize[i], rank, 0);
     }
 }
 
@@ -564,15 +549,11 @@ void build_octree(hipStream_t s, const DevPtrs& d, const Dims& dm) {
     hipLaunchKernelGGL(k_top_moments, dim3(1), dim3(1024), 0, s, A);
     // target groups: cells of at most 4 * group_size particles, cut into runs of group_size
     const int gcap = 4 * dm.group_size;
-    hipLaunchKernelGGL(k_gcell_flags, dim3(g), dim3(256), 0, s, d.ctl, gcap, dm.min_level, d.topo, d.parent, d.range,
-                       d.gflag);
+    hipLaunchKernelGGL(k_group_starts, dim3(g), dim3(256), 0, s, d.ctl, gcap, dm.group_size, dm.min_level, d.topo,
+                       d.parent, d.range, d.gflag, d.gsize);
     scan_u32_total(s, d.gflag, d.gscan, n, d.scan_tmp);
-    hipLaunchKernelGGL(k_gcells, dim3((n + 255) / 256), dim3(256), 0, s, n, d.gflag, d.gscan, d.gcell, d.ctl);
-    hipLaunchKernelGGL(k_gcell_chunks, dim3((n + 255) / 256), dim3(256), 0, s, n, dm.group_size, d.ctl, d.gcell,
-                       d.gnch);
-    scan_u32_total(s, d.gnch, d.goff, n, d.scan_tmp);
-    hipLaunchKernelGGL(k_emit_groups, dim3((n + 255) / 256), dim3(256), 0, s, n, dm.group_size, dm.batched, d.ctl,
-                       d.gcell, d.gnch, d.goff, d.key_a, d.seg_root_rank, d.group);
+    hipLaunchKernelGGL(k_emit_groups, dim3((n + 255) / 256), dim3(256), 0, s, n, dm.batched, d.ctl, d.gflag, d.gscan,
+                       d.gsize, d.key_a, d.seg_root_rank, d.group);
 }
 
 // Export (test path): node keys etc. in breadth-first order.
