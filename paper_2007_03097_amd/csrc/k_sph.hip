@@ -172,29 +172,65 @@ __global__ void __launch_bounds__(PAIR_THREADS) k_density(
         const int* un = uni + (size_t)g.x * cap;
         const int nu = ucnt[gi];
         DensAcc<FP32C> acc;
-        int k = phi;
-        int e = k < cnt ? lst[k * g.y] : INT_MAX;
-        int e1 = k + PL < cnt ? lst[(k + PL) * g.y] : INT_MAX;
-        int e2 = k + 2 * PL < cnt ? lst[(k + 2 * PL) * g.y] : INT_MAX;
-        int e3 = k + 3 * PL < cnt ? lst[(k + 3 * PL) * g.y] : INT_MAX;
-        for (int c0 = 0; c0 < nu; c0 += DENS_CHUNK) {
-            const int cn = nu - c0 < DENS_CHUNK ? nu - c0 : DENS_CHUNK;
+        auto stage = [&](int c0, int cn) {  // union members c0 .. c0 + cn - 1 into LDS
             __syncthreads();
             for (int i = tid; i < cn; i += PAIR_THREADS) {
                 const int b = un[c0 + i];
                 S.put(i, pos4[b], m[b], org);
             }
             __syncthreads();
-            const int ce = c0 + cn;
-            while (e < ce) {
-                const int kn = k + 4 * PL;
-                const int en = kn < cnt ? lst[kn * g.y] : INT_MAX;
-                acc.add(me, S.rec(e - c0), S.mass[e - c0]);
-                k += PL;
-                e = e1;
-                e1 = e2;
-                e2 = e3;
-                e3 = en;
+        };
+        if constexpr (FP32C) {
+            // The thread's entries k = phi, phi + PL, ... are read in batches of four, one batch
+            // ahead of the batch being summed; every load goes to a register that is consumed only
+            // after the next batch's loads are issued, and leaving a staged round keeps no loaded
+            // value (the next round reloads from its slot), so no load is waited for early.  Slots
+            // are clamped into the list (slot 0 of an empty list exists too); k < cnt decides.
+            const int kmax = cnt > 0 ? cnt - 1 : 0;
+            auto entry = [&](int kk) -> int { return lst[min(kk, kmax) * g.y]; };
+            int k = phi;
+            for (int c0 = 0; c0 < nu; c0 += DENS_CHUNK) {
+                const int cn = nu - c0 < DENS_CHUNK ? nu - c0 : DENS_CHUNK;
+                stage(c0, cn);
+                const int ce = c0 + cn;
+                auto take = [&](int r) {  // sums entry r if it is in the list and in this round
+                    if (!(k < cnt && r < ce)) return false;
+                    acc.add(me, S.rec(r - c0), S.mass[r - c0]);
+                    k += PL;
+                    return true;
+                };
+                int a0 = entry(k), a1 = entry(k + PL), a2 = entry(k + 2 * PL), a3 = entry(k + 3 * PL);
+                while (true) {
+                    const int b0 = entry(k + 4 * PL), b1 = entry(k + 5 * PL), b2 = entry(k + 6 * PL),
+                              b3 = entry(k + 7 * PL);
+                    if (!take(a0) || !take(a1) || !take(a2) || !take(a3)) break;
+                    a0 = entry(k + 4 * PL);
+                    a1 = entry(k + 5 * PL);
+                    a2 = entry(k + 6 * PL);
+                    a3 = entry(k + 7 * PL);
+                    if (!take(b0) || !take(b1) || !take(b2) || !take(b3)) break;
+                }
+            }
+        } else {  // the longer FP64 term hides a four-deep rotation's waits (batches measured slower)
+            int k = phi;
+            int e = k < cnt ? lst[k * g.y] : INT_MAX;
+            int e1 = k + PL < cnt ? lst[(k + PL) * g.y] : INT_MAX;
+            int e2 = k + 2 * PL < cnt ? lst[(k + 2 * PL) * g.y] : INT_MAX;
+            int e3 = k + 3 * PL < cnt ? lst[(k + 3 * PL) * g.y] : INT_MAX;
+            for (int c0 = 0; c0 < nu; c0 += DENS_CHUNK) {
+                const int cn = nu - c0 < DENS_CHUNK ? nu - c0 : DENS_CHUNK;
+                stage(c0, cn);
+                const int ce = c0 + cn;
+                while (e < ce) {
+                    const int kn = k + 4 * PL;
+                    const int en = kn < cnt ? lst[kn * g.y] : INT_MAX;
+                    acc.add(me, S.rec(e - c0), S.mass[e - c0]);
+                    k += PL;
+                    e = e1;
+                    e1 = e2;
+                    e2 = e3;
+                    e3 = en;
+                }
             }
         }
         __syncthreads();
@@ -278,9 +314,9 @@ __global__ void __launch_bounds__(PAIR_THREADS) k_forces(
         const int* un = uni + (size_t)g.x * cap;
         const int nu = ucnt[gi];
         int k = phi;
-        int e = k < cnt ? lst[k * g.y] : INT_MAX;
         double fx, fy, fz, fu;
         if constexpr (!FP32C) {
+            int e = k < cnt ? lst[k * g.y] : INT_MAX;
             const double4 mv = tv ? vel4[q] : make_double4(0, 0, 0, 0);
             const double4 mt = tv ? thr4[q] : make_double4(1, 0, 0, 0);
             double sx = 0, sy = 0, sz = 0, su = 0;
@@ -343,6 +379,9 @@ __global__ void __launch_bounds__(PAIR_THREADS) k_forces(
             const float alf = (float)alpha, bef = (float)beta, epf = (float)eps_av;
             const float ipi = (float)M_1_PI_D;
             Kahan sx, sy, sz, su;
+            // entries read in batches of four, one batch ahead (as in the FP32C density pass)
+            const int kmax = cnt > 0 ? cnt - 1 : 0;
+            auto entry = [&](int kk) -> int { return lst[min(kk, kmax) * g.y]; };
             for (int c0 = 0; c0 < nu; c0 += FORCE_CHUNK_F) {
                 const int cn = nu - c0 < FORCE_CHUNK_F ? nu - c0 : FORCE_CHUNK_F;
                 __syncthreads();
@@ -354,10 +393,9 @@ __global__ void __launch_bounds__(PAIR_THREADS) k_forces(
                 }
                 __syncthreads();
                 const int ce = c0 + cn;
-                while (e < ce) {
-                    const int kn = k + PL;
-                    const int en = kn < cnt ? lst[kn * g.y] : INT_MAX;
-                    const int j = e - c0;
+                auto take = [&](int ent) {
+                    if (!(k < cnt && ent < ce)) return false;
+                    const int j = ent - c0;
                     const double4 sb = S.pos.get(j);
                     const double4 vb = S.vel.get(j);
                     const float4 tb = S.thr[j];
@@ -402,8 +440,19 @@ __global__ void __launch_bounds__(PAIR_THREADS) k_forces(
                     } else {
                         su.add(mb * fmaf(0.5f, Pi, mt.y) * gw * vr);
                     }
-                    k = kn;
-                    e = en;
+                    k += PL;
+                    return true;
+                };
+                int a0 = entry(k), a1 = entry(k + PL), a2 = entry(k + 2 * PL), a3 = entry(k + 3 * PL);
+                while (true) {
+                    const int b0 = entry(k + 4 * PL), b1 = entry(k + 5 * PL), b2 = entry(k + 6 * PL),
+                              b3 = entry(k + 7 * PL);
+                    if (!take(a0) || !take(a1) || !take(a2) || !take(a3)) break;
+                    a0 = entry(k + 4 * PL);
+                    a1 = entry(k + 5 * PL);
+                    a2 = entry(k + 6 * PL);
+                    a3 = entry(k + 7 * PL);
+                    if (!take(b0) || !take(b1) || !take(b2) || !take(b3)) break;
                 }
             }
             fx = sx.value(); fy = sy.value(); fz = sz.value(); fu = su.value();
