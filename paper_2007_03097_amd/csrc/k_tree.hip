@@ -447,8 +447,10 @@ __device__ __forceinline__ void node_moments(const MomArgs& A, int b) {
 // internal node), so the runs are found top-down, then the levels are done deepest first
 // with the wavefront's own results as inputs.  The levels between the cut and the top
 // block go one launch each; large sets cut deeper, so that centrally concentrated ones do
-// not leave a few waves with very deep subtrees.
-constexpr int TOP_LEVELS = 5;
+// not leave a few waves with very deep subtrees.  The top block is one workgroup on one CU:
+// it takes levels 3 .. 0 only, since a sparse outer shell (the polytrope's) puts thousands of
+// nodes and leaves at level 4, which a grid-wide launch handles faster.
+constexpr int TOP_LEVELS = 4;
 static int subtree_cut(int n) { return n >= (1 << 21) ? 9 : 6; }
 __global__ void __launch_bounds__(64) k_subtree_moments(MomArgs A, int cut) {
     __shared__ int run_lo[MAX_LEVEL + 1], run_hi[MAX_LEVEL + 1];
