@@ -67,9 +67,9 @@ struct sph_ctx {
     hipStream_t cap_stream = nullptr;
     bool tree_ok = false, lists_ok = false, dens_ok = false, resident_ok = false;
     int parity = 0;
-    // graphs
-    hipGraphExec_t gexec[2] = {nullptr, nullptr};
-    hipGraph_t graph[2] = {nullptr, nullptr};
+    // step graphs [k][p]: from buffer set p, k = 0 the first step of a run, k = 1 a later one
+    hipGraphExec_t gexec[2][2] = {{nullptr, nullptr}, {nullptr, nullptr}};
+    hipGraph_t graph[2][2] = {{nullptr, nullptr}, {nullptr, nullptr}};
     int64_t g_n = -1;
     int g_leaf = 0, g_gsz = 0, g_waves = -1, g_tabv = -1;
     bool use_graph = true;
@@ -337,10 +337,11 @@ static void swap_binding(sph_ctx* c) {
 
 // Forgets the captured step graphs (they hold workspace pointers and table sizes by value).
 static void drop_graphs(sph_ctx* c) {
-    for (int p = 0; p < 2; ++p) {
-        if (c->gexec[p]) { (void)hipGraphExecDestroy(c->gexec[p]); c->gexec[p] = nullptr; }
-        if (c->graph[p]) { (void)hipGraphDestroy(c->graph[p]); c->graph[p] = nullptr; }
-    }
+    for (int k = 0; k < 2; ++k)
+        for (int p = 0; p < 2; ++p) {
+            if (c->gexec[k][p]) { (void)hipGraphExecDestroy(c->gexec[k][p]); c->gexec[k][p] = nullptr; }
+            if (c->graph[k][p]) { (void)hipGraphDestroy(c->graph[k][p]); c->graph[k][p] = nullptr; }
+        }
     c->g_tabv = -1;
     c->g_n = -1;
 }
@@ -454,10 +455,7 @@ sph_status sph_create(const sph_config* cfg, int64_t n_capacity, int32_t seg_cap
 sph_status sph_destroy(sph_ctx* c) {
     if (!c) return SPH_OK;
     if (c->ws) (void)hipStreamSynchronize(c->stream);
-    for (int p = 0; p < 2; ++p) {
-        if (c->gexec[p]) (void)hipGraphExecDestroy(c->gexec[p]);
-        if (c->graph[p]) (void)hipGraphDestroy(c->graph[p]);
-    }
+    drop_graphs(c);
     if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
     delete c;
     return SPH_OK;
@@ -633,20 +631,24 @@ static void accel_pass(sph_ctx* c, hipStream_t s, const DevPtrs& d, const double
     if (c->cfg.G != 0.0) gravity_pass(c, s, d, 1, thermo);
 }
 
-// One KDK step from buffer set p into buffer set 1 - p.
-static void step_launches(sph_ctx* c, hipStream_t s, int p) {
+// One KDK step from buffer set p into buffer set 1 - p, without its closing half kick: a run
+// of steps applies each closing kick at the start of the next step (the kick-drift's PRE form,
+// the same accelerations and roundings) and the last one after the run (close_run).
+static void step_launches(sph_ctx* c, hipStream_t s, int p, bool later) {
     const DevPtrs& a = c->d[p];
     const DevPtrs& b = c->d[1 - p];
     const int n = c->dm.n;
     launch_box_init(s, a, c->dm);
-    launch_kick_drift(s, a, c->dm);       // also merges the new box
+    launch_kick_drift(s, a, c->dm, later, c->cfg.adaptive_h);  // also merges the new box
     launch_step_keys(s, a, c->dm);        // also derives L and S
     radix_sort(s, a, n);
     launch_step_permute(s, a, n);         // also writes the pair records
     build_octree(s, b, c->dm);
     accel_pass(c, s, b, b.up, c->cfg.energy_form == SPH_ENERGY_THERMOKINETIC);
-    launch_kick(s, b, c->dm, c->cfg.adaptive_h);
 }
+
+// The last step's closing half kick (and lagged h update), on the resident state.
+static void close_run(sph_ctx* c, hipStream_t s) { launch_kick(s, c->d[c->parity], c->dm, c->cfg.adaptive_h); }
 
 // The kernels read each segment's step size from the control block, so a change of dt
 // needs no new graph.
@@ -658,22 +660,24 @@ static sph_status run_steps(sph_ctx* c, int nsteps) {
                          c->g_waves != c->waves || c->g_tabv != c->tab.version;
     if (!c->use_graph) {
         for (int k = 0; k < nsteps; ++k) {
-            step_launches(c, c->stream, c->parity);
+            step_launches(c, c->stream, c->parity, k > 0);
             c->parity ^= 1;
         }
+        close_run(c, c->stream);
         HIPCHK(c, hipGetLastError());
         return SPH_OK;
     }
-    if (regraph || !c->gexec[0] || !c->gexec[1]) {
+    if (regraph || !c->gexec[0][0] || !c->gexec[0][1] || !c->gexec[1][0] || !c->gexec[1][1]) {
         if (!c->cap_stream) HIPCHK(c, hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking));
         HIPCHK(c, hipStreamSynchronize(c->stream));
         drop_graphs(c);
-        for (int p = 0; p < 2; ++p) {
-            HIPCHK(c, hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeThreadLocal));
-            step_launches(c, c->cap_stream, p);
-            HIPCHK(c, hipStreamEndCapture(c->cap_stream, &c->graph[p]));
-            HIPCHK(c, hipGraphInstantiate(&c->gexec[p], c->graph[p], nullptr, nullptr, 0));
-        }
+        for (int k = 0; k < 2; ++k)
+            for (int p = 0; p < 2; ++p) {
+                HIPCHK(c, hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeThreadLocal));
+                step_launches(c, c->cap_stream, p, k > 0);
+                HIPCHK(c, hipStreamEndCapture(c->cap_stream, &c->graph[k][p]));
+                HIPCHK(c, hipGraphInstantiate(&c->gexec[k][p], c->graph[k][p], nullptr, nullptr, 0));
+            }
         c->g_n = c->dm.n;
         c->g_tabv = c->tab.version;
         c->g_leaf = c->leaf_size;
@@ -681,9 +685,11 @@ static sph_status run_steps(sph_ctx* c, int nsteps) {
         c->g_waves = c->waves;
     }
     for (int k = 0; k < nsteps; ++k) {
-        HIPCHK(c, hipGraphLaunch(c->gexec[c->parity], c->stream));
+        HIPCHK(c, hipGraphLaunch(c->gexec[k > 0][c->parity], c->stream));
         c->parity ^= 1;
     }
+    close_run(c, c->stream);
+    HIPCHK(c, hipGetLastError());
     return SPH_OK;
 }
 

@@ -374,7 +374,7 @@ void launch_scatter_caller(hipStream_t s, const DevPtrs& d, int n, const double*
 void launch_fill_zero(hipStream_t s, int n, double* dst);
 void launch_gather_caller(hipStream_t s, const DevPtrs& d, int n, const double* src_caller, double* dst);
 void launch_box_init(hipStream_t s, const DevPtrs& d, const Dims& dm);
-void launch_kick_drift(hipStream_t s, const DevPtrs& d, const Dims& dm);
+void launch_kick_drift(hipStream_t s, const DevPtrs& d, const Dims& dm, bool pre_kick, int adaptive_h);
 void launch_step_keys(hipStream_t s, const DevPtrs& d, const Dims& dm);
 void launch_step_permute(hipStream_t s, const DevPtrs& d, int n);
 void launch_kick(hipStream_t s, const DevPtrs& d, const Dims& dm, int adaptive_h);

@@ -31,12 +31,17 @@ void launch_gather_caller(hipStream_t s, const DevPtrs& d, int n, const double* 
 // v' = v + dt/2 a; u' = u + dt/2 du; x += dt v'; predictors v^ = v' + dt/2 a, u^ = u' + dt/2 du.
 // One block per chunk (chunks never cross a segment; dt is the segment's step size); the new
 // positions' box is merged into the segment's box on the way, and non-finite new x, v' or u'
-// raise the sticky error.
+// raise the sticky error.  PRE: inside a run of steps, the previous step's closing half kick
+// v = v + dt/2 a, u = u + dt/2 du (the same accelerations: the two kicks of the leapfrog's
+// joint) and its lagged h update are applied here first, in registers, with the same roundings
+// as in a separate pass.
+template <bool PRE>
 __global__ void __launch_bounds__(256) k_kick_drift(DevCtl* ctl, const int4* __restrict__ chunk, double* x,
                                                     double* y, double* z, double* vx, double* vy, double* vz, double* u,
                                                     const double* __restrict__ ax, const double* __restrict__ ay,
                                                     const double* __restrict__ az, const double* __restrict__ du,
-                                                    double* vpx, double* vpy, double* vpz, double* up) {
+                                                    double* vpx, double* vpy, double* vpz, double* up, double* h,
+                                                    const double* __restrict__ hnext, int adaptive) {
     const int4 ch = chunk[blockIdx.x];
     const double dt = ctl->seg_dt[ch.z];
     const double half = 0.5 * dt;
@@ -44,8 +49,16 @@ __global__ void __launch_bounds__(256) k_kick_drift(DevCtl* ctl, const int4* __r
     bool bad = false;
     for (int q = ch.x + threadIdx.x; q < ch.y; q += blockDim.x) {
         const double a0 = ax[q], a1 = ay[q], a2 = az[q], d0 = du[q];
-        const double hx = vx[q] + half * a0, hy = vy[q] + half * a1, hz = vz[q] + half * a2;
-        const double uh = u[q] + half * d0;
+        double v0 = vx[q], v1 = vy[q], v2 = vz[q], e0 = u[q];
+        if constexpr (PRE) {
+            v0 = v0 + half * a0;
+            v1 = v1 + half * a1;
+            v2 = v2 + half * a2;
+            e0 = e0 + half * d0;
+            if (adaptive) h[q] = hnext[q];
+        }
+        const double hx = v0 + half * a0, hy = v1 + half * a1, hz = v2 + half * a2;
+        const double uh = e0 + half * d0;
         const double nx = x[q] + dt * hx, ny = y[q] + dt * hy, nz = z[q] + dt * hz;
         x[q] = nx;
         y[q] = ny;
@@ -64,10 +77,14 @@ __global__ void __launch_bounds__(256) k_kick_drift(DevCtl* ctl, const int4* __r
     if (bad) set_err(ctl, ERR_NONFINITE);
     box_block_merge(ctl, ch.z, lo, hi, ch.y > ch.x);
 }
-void launch_kick_drift(hipStream_t s, const DevPtrs& d, const Dims& dm) {
-    if (dm.n_chunks > 0)
-        hipLaunchKernelGGL(k_kick_drift, dim3(dm.n_chunks), dim3(256), 0, s, d.ctl, d.chunk, d.x, d.y, d.z, d.vx,
-                           d.vy, d.vz, d.u, d.ax, d.ay, d.az, d.du, d.vpx, d.vpy, d.vpz, d.up);
+void launch_kick_drift(hipStream_t s, const DevPtrs& d, const Dims& dm, bool pre_kick, int adaptive_h) {
+    if (dm.n_chunks <= 0) return;
+    auto go = [&](auto kern) {
+        hipLaunchKernelGGL(kern, dim3(dm.n_chunks), dim3(256), 0, s, d.ctl, d.chunk, d.x, d.y, d.z, d.vx, d.vy, d.vz,
+                           d.u, d.ax, d.ay, d.az, d.du, d.vpx, d.vpy, d.vpz, d.up, d.h, d.hnext, adaptive_h);
+    };
+    if (pre_kick) go(k_kick_drift<true>);
+    else go(k_kick_drift<false>);
 }
 
 // New key order: q <- old position val[q] (the sort carried the positions); the second
