@@ -638,7 +638,7 @@ static void step_launches(sph_ctx* c, hipStream_t s, int p, bool later) {
     const DevPtrs& a = c->d[p];
     const DevPtrs& b = c->d[1 - p];
     const int n = c->dm.n;
-    launch_box_init(s, a, c->dm);
+    if (!later) launch_box_init(s, a, c->dm);  // later steps: the previous permute reset the box
     launch_kick_drift(s, a, c->dm, later, c->cfg.adaptive_h);  // also merges the new box
     launch_step_keys(s, a, c->dm);        // also derives L and S
     radix_sort(s, a, n);

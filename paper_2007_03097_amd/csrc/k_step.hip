@@ -90,8 +90,14 @@ void launch_kick_drift(hipStream_t s, const DevPtrs& d, const Dims& dm, bool pre
 // New key order: q <- old position val[q] (the sort carried the positions); the second
 // buffer set receives the data, and the pair kernels' records pos4 = (x, h),
 // vel4 = (predicted v, m) are written too.  The predicted velocities enter vel4 only: the
-// next kick-drift writes them anew before anything reads them.
+// next kick-drift writes them anew before anything reads them.  The step's keys are made, so
+// block 0 also resets the box accumulators of every set for the next step's kick-drift (a run's
+// first step resets them itself: other calls may use them in between).
 __global__ void k_step_permute(int n, const u32* __restrict__ val, DevPtrs d) {
+    if (blockIdx.x == 0) {
+        constexpr int NB = (int)(sizeof(d.ctl->box_enc) / sizeof(u64));
+        for (int i = threadIdx.x; i < NB; i += blockDim.x) d.ctl->box_enc[i] = (i % 6) < 3 ? ~0ull : 0ull;
+    }
     const int q = blockIdx.x * blockDim.x + threadIdx.x;
     if (q >= n) return;
     const u32 p = val[q];
