@@ -269,10 +269,14 @@ static sph_status prepare(sph_ctx* c, const sph_particles* p) {
             chunks.push_back(make_int4((int)b, (int)std::min<int64_t>(seg[s + 1], b + CHUNK), s, b == seg[s]));
     }
     dm.n_chunks = (int)chunks.size();
-    {   // persistent grids of the per-group kernels: multiples of 8 (one share per XCD); with
-        // waves_per_cu, at most that many wavefronts per CU (one-wave and four-wave workgroups)
+    {   // grids of the per-group kernels: multiples of 8 (one share per XCD), one workgroup per
+        // expected group (groups average over half of group_size); the kernels loop over any
+        // groups beyond that.  Groups differ widely in cost, and the hardware dispatcher, which
+        // starts a workgroup wherever one ends, balances them better than a resident-sized grid
+        // with a fixed share per workgroup.  With waves_per_cu, at most that many wavefronts
+        // per CU (one-wave and four-wave workgroups).
         const int64_t est = p->n / std::max(1, c->group_size / 2) + 8;
-        const int64_t units = std::min<int64_t>(1024, (est + 7) / 8);
+        const int64_t units = (est + 7) / 8;
         int64_t u1 = units, u4 = units;
         if (c->waves > 0) {
             u1 = std::min<int64_t>(units, (int64_t)c->waves * 256 / 8);
