@@ -791,9 +791,14 @@ sph_status sph_gravity_counts(sph_ctx* c, int64_t* cells_host, int64_t* pairs_ho
     if (!c || !cells_host || !pairs_host) return SPH_E_ARG;
     if (c->cfg.G == 0.0 || c->cfg.gravity_scheme == SPH_GRAVITY_FMM)
         return fail(c, SPH_E_STATE, "sph_gravity_counts: no particle-cell gravity pass in this context");
-    u64 v[2] = {0, 0};
-    HIPCHK(c, hipMemcpyAsync(v, &c->d[0].ctl->grav_cells, sizeof v, hipMemcpyDeviceToHost, c->stream));
+    u64 slots[GRAV_SLOTS][16];
+    HIPCHK(c, hipMemcpyAsync(slots, c->d[0].ctl->grav_cnt, sizeof slots, hipMemcpyDeviceToHost, c->stream));
     HIPCHK(c, hipStreamSynchronize(c->stream));
+    u64 v[2] = {0, 0};
+    for (int s = 0; s < GRAV_SLOTS; ++s) {
+        v[0] += slots[s][0];
+        v[1] += slots[s][1];
+    }
     *cells_host = (int64_t)v[0];
     *pairs_host = (int64_t)v[1] - (v[1] > 0 ? (int64_t)c->dm.n : 0);  // the targets' own pairs
     return read_err(c);

@@ -29,6 +29,9 @@ constexpr int MAX_LEVEL = 21;   // 21 three-bit digits below the sentinel bit 63
 constexpr double M_1_PI_D = 0.318309886183790671537767526745028724;
 
 // Small control block living in device memory.
+// Counter slots of the gravity pass's term counts, one 128-byte line each.
+constexpr int GRAV_SLOTS = 64;
+
 struct DevCtl {
     u32 err;
     int n_nodes;
@@ -44,8 +47,10 @@ struct DevCtl {
     double diag[16];              // step diagnostics
     double seg_dt[512];           // step size of each segment (read by the kick kernels)
     u64 dtb_enc[512];             // per segment: ordered-integer min of the time-step bound
-    u64 grav_cells;               // last quadrupole gravity pass: particle-cell terms evaluated
-    u64 grav_pairs;               // and particle-particle terms, each target's own pair included
+    // last quadrupole gravity pass: particle-cell terms ([s][0]) and particle-particle terms
+    // ([s][1], each target's own pair included) evaluated, summed over the slots s; a group
+    // adds its counts to slot (group % GRAV_SLOTS), so the atomics spread over 64 lines
+    u64 grav_cnt[GRAV_SLOTS][16];
 };
 
 // Device pointers of one context.  All arrays are carved out of the caller's workspace.
