@@ -610,6 +610,7 @@ sph_status sph_compute_gravity(sph_ctx* c, double* gx, double* gy, double* gz, d
         return SPH_OK;
     }
     const DevPtrs& d = c->d[c->parity];
+    launch_fill_i32(c->stream, &d.ctl->skip_phi, 0, 1);  // this pass returns the potential
     gravity_pass(c, c->stream, d, 0, 0);
     launch_scatter_caller(c->stream, d, n, d.gx, gx);
     launch_scatter_caller(c->stream, d, n, d.gy, gy);
@@ -662,8 +663,18 @@ static sph_status run_steps(sph_ctx* c, int nsteps) {
                              hipMemcpyHostToDevice, c->stream));
     const bool regraph = c->g_n != c->dm.n || c->g_leaf != c->leaf_size || c->g_gsz != c->group_size ||
                          c->g_waves != c->waves || c->g_tabv != c->tab.version;
+    // Only the last step's potential is read (by the diagnostics of the final state): the
+    // quadrupole pass skips it before that.  Set on the stream between the steps, so the
+    // captured step graphs are the same for every step.
+    int* skip_phi = &c->d[0].ctl->skip_phi;
+    const bool thin = c->cfg.G != 0.0 && c->cfg.gravity_scheme != SPH_GRAVITY_FMM && nsteps > 1;
+    auto phi_flag = [&](int k) {
+        if (thin && k == 0) launch_fill_i32(c->stream, skip_phi, 1, 1);
+        if (thin && k == nsteps - 1) launch_fill_i32(c->stream, skip_phi, 0, 1);
+    };
     if (!c->use_graph) {
         for (int k = 0; k < nsteps; ++k) {
+            phi_flag(k);
             step_launches(c, c->stream, c->parity, k > 0);
             c->parity ^= 1;
         }
@@ -689,6 +700,7 @@ static sph_status run_steps(sph_ctx* c, int nsteps) {
         c->g_waves = c->waves;
     }
     for (int k = 0; k < nsteps; ++k) {
+        phi_flag(k);
         HIPCHK(c, hipGraphLaunch(c->gexec[k > 0][c->parity], c->stream));
         c->parity ^= 1;
     }
@@ -726,6 +738,7 @@ static sph_status step_impl(sph_ctx* c, sph_particles* p, double dt, int32_t nst
         if (st != SPH_OK) return st;
         const DevPtrs& d = c->d[0];
         const int n = c->dm.n;
+        launch_fill_i32(c->stream, &d.ctl->skip_phi, 0, 1);  // the primed state's potential too
         if (n > 0) {
             if (flags & SPH_STEP_PRIMED) {
                 launch_load_accel(c->stream, d, n, p->ax, p->ay, p->az, p->dudt);

@@ -92,6 +92,7 @@ struct TargetSums {
 // record at staging: a = (M, com), b = (3 Ixx, 3 Iyy, 3 Izz, 3/2 tr I), d = (3 Ixy, 3 Ixz,
 // 3 Iyz, 1/2 tr I).  With Q = 3 I: g += -M R/s^3 + Q.R/s^5 - (5/2) (R.Q.R) R/s^7 + (3/2) tr(I) R/s^5
 // and phi -= M/s + (1/2) R.Q.R/s^5 - (1/2) tr(I)/s^3.
+template <bool PH = true>
 __device__ __forceinline__ void cell_term(const double4 me, const double4 a, const double4 b, const double4 d,
                                           double e2, TargetSums& S) {
     const double Rx = me.x - a.y, Ry = me.y - a.z, Rz = me.z - a.w;
@@ -106,11 +107,11 @@ __device__ __forceinline__ void cell_term(const double4 me, const double4 a, con
     S.gx = fma(cR, Rx, fma(i5, QRx, S.gx));
     S.gy = fma(cR, Ry, fma(i5, QRy, S.gy));
     S.gz = fma(cR, Rz, fma(i5, QRz, S.gz));
-    S.ph -= fma(a.x, i1, fma(0.5 * RQR, i5, -d.w * i3));
+    if constexpr (PH) S.ph -= fma(a.x, i1, fma(0.5 * RQR, i5, -d.w * i3));
 }
 
 // Softened particle term of source sb = (x, y, z, m).
-template <bool FP32C>
+template <bool FP32C, bool PH = true>
 __device__ __forceinline__ void part_term(const double4 me, const double4 sb, double e2, TargetSums& S) {
     if (!FP32C) {
         const double dx = me.x - sb.x, dy = me.y - sb.y, dz = me.z - sb.z;
@@ -120,7 +121,7 @@ __device__ __forceinline__ void part_term(const double4 me, const double4 sb, do
         S.gx = fma(-mi3, dx, S.gx);
         S.gy = fma(-mi3, dy, S.gy);
         S.gz = fma(-mi3, dz, S.gz);
-        S.ph = fma(-sb.w, i1, S.ph);
+        if constexpr (PH) S.ph = fma(-sb.w, i1, S.ph);
     } else {
         const float dx = (float)(me.x - sb.x), dy = (float)(me.y - sb.y), dz = (float)(me.z - sb.z);
         const float s2 = fmaf(dx, dx, fmaf(dy, dy, fmaf(dz, dz, (float)e2)));
@@ -130,7 +131,7 @@ __device__ __forceinline__ void part_term(const double4 me, const double4 sb, do
         S.tx = fmaf(-mi3, dx, S.tx);
         S.ty = fmaf(-mi3, dy, S.ty);
         S.tz = fmaf(-mi3, dz, S.tz);
-        S.tph = fmaf(-mb, i1, S.tph);
+        if constexpr (PH) S.tph = fmaf(-mb, i1, S.tph);
     }
 }
 
@@ -138,6 +139,7 @@ __device__ __forceinline__ void part_term(const double4 me, const double4 sb, do
 // source particle) are FP32 offsets from the group's first target, each formed in FP64 and
 // rounded once, so one FP32 subtraction gives R (its error is within u (|r_a - o| + |R_B - o|),
 // small against |R| for accepted cells, and softened for near particle pairs).
+template <bool PH = true>
 __device__ __forceinline__ void cell_term_f(const float4 me, const float4 a, const float4 b, const float4 d, float e2,
                                             TargetSums& S) {
     const float Rx = me.x - a.y, Ry = me.y - a.z, Rz = me.z - a.w;
@@ -152,9 +154,10 @@ __device__ __forceinline__ void cell_term_f(const float4 me, const float4 a, con
     S.tx = fmaf(cR, Rx, fmaf(i5, QRx, S.tx));
     S.ty = fmaf(cR, Ry, fmaf(i5, QRy, S.ty));
     S.tz = fmaf(cR, Rz, fmaf(i5, QRz, S.tz));
-    S.tph -= fmaf(a.x, i1, fmaf(0.5f * RQR, i5, -d.w * i3));
+    if constexpr (PH) S.tph -= fmaf(a.x, i1, fmaf(0.5f * RQR, i5, -d.w * i3));
 }
 
+template <bool PH = true>
 __device__ __forceinline__ void part_term_f(const float4 me, const float4 sb, float e2, TargetSums& S) {
     const float dx = me.x - sb.x, dy = me.y - sb.y, dz = me.z - sb.z;
     const float s2 = fmaf(dx, dx, fmaf(dy, dy, fmaf(dz, dz, e2)));
@@ -163,7 +166,7 @@ __device__ __forceinline__ void part_term_f(const float4 me, const float4 sb, fl
     S.tx = fmaf(-mi3, dx, S.tx);
     S.ty = fmaf(-mi3, dy, S.ty);
     S.tz = fmaf(-mi3, dz, S.tz);
-    S.tph = fmaf(-sb.w, i1, S.tph);
+    if constexpr (PH) S.tph = fmaf(-sb.w, i1, S.tph);
 }
 
 // Two targets per lane: tp and tp + TP (TP = group_size / 2); the P = 64 / TP lanes with
@@ -180,10 +183,16 @@ struct GravTargets {
 
 // Accepted cells (monopole + quadrupole) for the lane's targets, staged CS at a time (one
 // lane loads one cell).
+// A compile-time flag passed as a value, to select a template from a run-time branch.
+template <bool B>
+struct BoolC {
+    static constexpr bool value = B;
+};
+
 template <bool FP32C>
 __device__ void eval_cells(int ncell, const int* cells, GravStage<FP32C>& St, const double4* __restrict__ mom0,
                            const double4* __restrict__ mom1, const double4* __restrict__ mom2, const GravTargets& T,
-                           double e2, TargetSums& A, TargetSums& B) {
+                           double e2, bool phi, TargetSums& A, TargetSums& B) {
     const int lane = lane_id();
     const bool any = T.va || T.vb;
     constexpr int CS = FP32C ? 64 : 32;  // cells staged per round
@@ -208,22 +217,27 @@ __device__ void eval_cells(int ncell, const int* cells, GravStage<FP32C>& St, co
         __syncthreads();
         const int cn = ncell - k0 < CS ? ncell - k0 : CS;
         if (!any) continue;
-        if constexpr (FP32C) {
-            const float e2f = (float)e2;
-            for (int k = T.phi; k < cn; k += T.P) {
-                const float4 a = St.cellf.c0[k], b = St.cellf.c1[k], d = St.cellf.c2[k];
-                cell_term_f(T.fa, a, b, d, e2f, A);
-                cell_term_f(T.fb, a, b, d, e2f, B);
+        auto run = [&](auto ph) {
+            constexpr bool PH = decltype(ph)::value;
+            if constexpr (FP32C) {
+                const float e2f = (float)e2;
+                for (int k = T.phi; k < cn; k += T.P) {
+                    const float4 a = St.cellf.c0[k], b = St.cellf.c1[k], d = St.cellf.c2[k];
+                    cell_term_f<PH>(T.fa, a, b, d, e2f, A);
+                    cell_term_f<PH>(T.fb, a, b, d, e2f, B);
+                }
+                A.flush_tile();
+                B.flush_tile();
+            } else {
+                for (int k = T.phi; k < cn; k += T.P) {
+                    const double4 a = St.cell.c0[k], b = St.cell.c1[k], d = St.cell.c2[k];
+                    cell_term<PH>(T.a, a, b, d, e2, A);
+                    cell_term<PH>(T.b, a, b, d, e2, B);
+                }
             }
-            A.flush_tile();
-            B.flush_tile();
-        } else {
-            for (int k = T.phi; k < cn; k += T.P) {
-                const double4 a = St.cell.c0[k], b = St.cell.c1[k], d = St.cell.c2[k];
-                cell_term(T.a, a, b, d, e2, A);
-                cell_term(T.b, a, b, d, e2, B);
-            }
-        }
+        };
+        if (phi) run(BoolC<true>());
+        else run(BoolC<false>());
     }
 }
 
@@ -289,29 +303,34 @@ __device__ void stage_leaves(int nleaf, int* leaves, Stage& St, const int4* __re
 template <bool FP32C>
 __device__ void eval_leaves(int nleaf, int* leaves, GravStage<FP32C>& St, const int4* __restrict__ topo,
                             const double4* __restrict__ pos4, const double* __restrict__ m, const GravTargets& T,
-                            double e2, TargetSums& A, TargetSums& B) {
+                            double e2, bool phi, TargetSums& A, TargetSums& B) {
     const bool any = T.va || T.vb;
     const bool soft = e2 > 0.0;
     if constexpr (FP32C) {
         const float e2f = (float)e2;
+        auto run = [&](int tn, auto ph) {
+            constexpr bool PH = decltype(ph)::value;
+            if (soft) {
+                for (int j = T.phi; j < tn; j += T.P) {
+                    const float4 sb = St.partf.pm[j];
+                    part_term_f<PH>(T.fa, sb, e2f, A);
+                    part_term_f<PH>(T.fb, sb, e2f, B);
+                }
+            } else {
+                for (int j = T.phi; j < tn; j += T.P) {
+                    const float4 sb = St.partf.pm[j];
+                    const int s = St.partf.src[j];
+                    if (s != T.qa) part_term_f<PH>(T.fa, sb, e2f, A);
+                    if (s != T.qb) part_term_f<PH>(T.fb, sb, e2f, B);
+                }
+            }
+        };
         stage_leaves_put(
             nleaf, leaves, St, topo, pos4, m,
             [&](int tn) {
                 if (!any) return;
-                if (soft) {
-                    for (int j = T.phi; j < tn; j += T.P) {
-                        const float4 sb = St.partf.pm[j];
-                        part_term_f(T.fa, sb, e2f, A);
-                        part_term_f(T.fb, sb, e2f, B);
-                    }
-                } else {
-                    for (int j = T.phi; j < tn; j += T.P) {
-                        const float4 sb = St.partf.pm[j];
-                        const int s = St.partf.src[j];
-                        if (s != T.qa) part_term_f(T.fa, sb, e2f, A);
-                        if (s != T.qb) part_term_f(T.fb, sb, e2f, B);
-                    }
-                }
+                if (phi) run(tn, BoolC<true>());
+                else run(tn, BoolC<false>());
                 A.flush_tile();
                 B.flush_tile();
             },
@@ -322,22 +341,27 @@ __device__ void eval_leaves(int nleaf, int* leaves, GravStage<FP32C>& St, const 
             });
         return;
     }
-    stage_leaves(nleaf, leaves, St, topo, pos4, m, [&](int tn) {
-        if (!any) return;
+    auto run = [&](int tn, auto ph) {
+        constexpr bool PH = decltype(ph)::value;
         if (soft) {
             for (int j = T.phi; j < tn; j += T.P) {
                 const double4 sb = St.part.pm[j];
-                part_term<false>(T.a, sb, e2, A);
-                part_term<false>(T.b, sb, e2, B);
+                part_term<false, PH>(T.a, sb, e2, A);
+                part_term<false, PH>(T.b, sb, e2, B);
             }
         } else {
             for (int j = T.phi; j < tn; j += T.P) {
                 const double4 sb = St.part.pm[j];
                 const int s = St.part.src[j];
-                if (s != T.qa) part_term<false>(T.a, sb, e2, A);
-                if (s != T.qb) part_term<false>(T.b, sb, e2, B);
+                if (s != T.qa) part_term<false, PH>(T.a, sb, e2, A);
+                if (s != T.qb) part_term<false, PH>(T.b, sb, e2, B);
             }
         }
+    };
+    stage_leaves(nleaf, leaves, St, topo, pos4, m, [&](int tn) {
+        if (!any) return;
+        if (phi) run(tn, BoolC<true>());
+        else run(tn, BoolC<false>());
     });
 }
 
@@ -395,9 +419,9 @@ __device__ void eval_lists(int ncell, int nleaf, const int* cells, int* leaves, 
                            const int4* __restrict__ topo, const double4* __restrict__ mom0,
                            const double4* __restrict__ mom1, const double4* __restrict__ mom2,
                            const double4* __restrict__ pos4, const double* __restrict__ m, const GravTargets& T,
-                           double eps, TargetSums& A, TargetSums& B) {
-    eval_cells<FP32C>(ncell, cells, St, mom0, mom1, mom2, T, eps * eps, A, B);
-    eval_leaves<FP32C>(nleaf, leaves, St, topo, pos4, m, T, eps * eps, A, B);
+                           double eps, bool phi, TargetSums& A, TargetSums& B) {
+    eval_cells<FP32C>(ncell, cells, St, mom0, mom1, mom2, T, eps * eps, phi, A, B);
+    eval_leaves<FP32C>(nleaf, leaves, St, topo, pos4, m, T, eps * eps, phi, A, B);
 }
 
 template <bool FP32C>
@@ -416,6 +440,9 @@ __global__ void __launch_bounds__(64) k_gravity(DevCtl* ctl, const int4* __restr
     __shared__ GravStage<FP32C> St;
     const int lane = lane_id();
     GravTargets T;
+    // the potential is evaluated (and written) unless the step sequence has switched it off:
+    // inside a run of steps only the last step's value is read (by the energy diagnostic)
+    const bool phi = pho != nullptr && ctl->skip_phi == 0;
     int g0, g1, gstep;
     group_range(ctl->n_groups, g0, g1, gstep);
     for (int gi = g0; gi < g1; gi += gstep) {
@@ -469,7 +496,7 @@ __global__ void __launch_bounds__(64) k_gravity(DevCtl* ctl, const int4* __restr
             }
             if (nc + 64 > GW_CELLS || nl + 64 > GW_LEAVES) {
                 count_terms(nc, nl, leaves, topo, g.y, n_cells, n_pairs);
-                eval_lists<FP32C>(nc, nl, cells, leaves, St, topo, mom0, mom1, mom2, pos4, m, T, eps, A, B);
+                eval_lists<FP32C>(nc, nl, cells, leaves, St, topo, mom0, mom1, mom2, pos4, m, T, eps, phi, A, B);
                 nc = nl = 0;
                 __syncthreads();
             }
@@ -519,7 +546,7 @@ __global__ void __launch_bounds__(64) k_gravity(DevCtl* ctl, const int4* __restr
         }
         __syncthreads();
         count_terms(nc, nl, leaves, topo, g.y, n_cells, n_pairs);
-        eval_lists<FP32C>(nc, nl, cells, leaves, St, topo, mom0, mom1, mom2, pos4, m, T, eps, A, B);
+        eval_lists<FP32C>(nc, nl, cells, leaves, St, topo, mom0, mom1, mom2, pos4, m, T, eps, phi, A, B);
         // per target: lanes tp + TP*phi combine in a fixed butterfly order
         double r[8];
         r[0] = FP32C ? A.kx.value() : A.gx;
@@ -555,7 +582,7 @@ __global__ void __launch_bounds__(64) k_gravity(DevCtl* ctl, const int4* __restr
                     gyo[q] = gy;
                     gzo[q] = gz;
                 }
-                if (pho) pho[q] = ph;
+                if (phi) pho[q] = ph;
             }
         }
         if (lane == 0) {  // last, so that no later memory wait of the group holds for it
