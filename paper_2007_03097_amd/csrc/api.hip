@@ -664,10 +664,10 @@ static sph_status run_steps(sph_ctx* c, int nsteps) {
     const bool regraph = c->g_n != c->dm.n || c->g_leaf != c->leaf_size || c->g_gsz != c->group_size ||
                          c->g_waves != c->waves || c->g_tabv != c->tab.version;
     // Only the last step's potential is read (by the diagnostics of the final state): the
-    // quadrupole pass skips it before that.  Set on the stream between the steps, so the
+    // gravity passes skip it before that.  Set on the stream between the steps, so the
     // captured step graphs are the same for every step.
     int* skip_phi = &c->d[0].ctl->skip_phi;
-    const bool thin = c->cfg.G != 0.0 && c->cfg.gravity_scheme != SPH_GRAVITY_FMM && nsteps > 1;
+    const bool thin = c->cfg.G != 0.0 && nsteps > 1;
     auto phi_flag = [&](int k) {
         if (thin && k == 0) launch_fill_i32(c->stream, skip_phi, 1, 1);
         if (thin && k == nsteps - 1) launch_fill_i32(c->stream, skip_phi, 0, 1);

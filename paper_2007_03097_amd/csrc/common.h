@@ -51,7 +51,7 @@ struct DevCtl {
     // ([s][1], each target's own pair included) evaluated, summed over the slots s; a group
     // adds its counts to slot (group % GRAV_SLOTS), so the atomics spread over 64 lines
     u64 grav_cnt[GRAV_SLOTS][16];
-    int skip_phi;                 // nonzero: the quadrupole gravity pass leaves phi unevaluated
+    int skip_phi;                 // nonzero: the gravity passes leave phi unevaluated
 };
 
 // Device pointers of one context.  All arrays are carved out of the caller's workspace.

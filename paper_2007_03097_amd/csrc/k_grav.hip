@@ -377,16 +377,21 @@ struct LaneTarget {
 template <bool FP32C, typename Stage>
 __device__ void eval_leaves1(int nleaf, int* leaves, Stage& St, const int4* __restrict__ topo,
                              const double4* __restrict__ pos4, const double* __restrict__ m, const LaneTarget& T,
-                             double e2, TargetSums& A) {
+                             double e2, bool phi, TargetSums& A) {
     const bool soft = e2 > 0.0;
-    stage_leaves(nleaf, leaves, St, topo, pos4, m, [&](int tn) {
-        if (!T.v) return;
+    auto run = [&](int tn, auto ph) {
+        constexpr bool PH = decltype(ph)::value;
         if (soft) {
-            for (int j = T.ph; j < tn; j += T.P) part_term<FP32C>(T.a, St.part.pm[j], e2, A);
+            for (int j = T.ph; j < tn; j += T.P) part_term<FP32C, PH>(T.a, St.part.pm[j], e2, A);
         } else {
             for (int j = T.ph; j < tn; j += T.P)
-                if (St.part.src[j] != T.q) part_term<FP32C>(T.a, St.part.pm[j], e2, A);
+                if (St.part.src[j] != T.q) part_term<FP32C, PH>(T.a, St.part.pm[j], e2, A);
         }
+    };
+    stage_leaves(nleaf, leaves, St, topo, pos4, m, [&](int tn) {
+        if (!T.v) return;
+        if (phi) run(tn, BoolC<true>());
+        else run(tn, BoolC<false>());
         if (FP32C) A.flush_tile();
     });
 }
@@ -708,6 +713,7 @@ __device__ __forceinline__ bool fmm_accept(int la, const int* ca, int lb, const 
 // Accepted pairs (tnode[k], depth tdep[k]): lane k evaluates pair k, k + 64, ... and keeps
 // its own partial sums of the field (fg) and of the potential referred to the leaf's
 // centre of mass (fc); the caller sums them across the wave.
+template <bool PH>
 __device__ __forceinline__ void fmm_eval_terms(int nt, const int* tnode, const unsigned char* tdep, const FmmPath& P,
                                                int D, const double4* __restrict__ mom0, double e2, double& fgx,
                                                double& fgy, double& fgz, double& fc) {
@@ -724,7 +730,7 @@ __device__ __forceinline__ void fmm_eval_terms(int nt, const int* tnode, const u
         fgx += gx;
         fgy += gy;
         fgz += gz;
-        fc -= mi1 + fma(gx, cl.y - cx.y, fma(gy, cl.z - cx.z, gz * (cl.w - cx.w)));
+        if constexpr (PH) fc -= mi1 + fma(gx, cl.y - cx.y, fma(gy, cl.z - cx.z, gz * (cl.w - cx.w)));
     }
 }
 
@@ -740,6 +746,7 @@ __global__ void __launch_bounds__(64) k_fmm(DevCtl* ctl, const int* __restrict__
                                             const double4* __restrict__ vel4, double* __restrict__ deo) {
     __shared__ int stk[FM_STACK];
     __shared__ unsigned char sdep[FM_STACK];
+    const bool phi = pho != nullptr && ctl->skip_phi == 0;  // as in k_gravity
     __shared__ int tnode[FM_TERMS];
     __shared__ unsigned char tdep[FM_TERMS];
     __shared__ int leaves[FM_LEAVES];
@@ -810,12 +817,13 @@ __global__ void __launch_bounds__(64) k_fmm(DevCtl* ctl, const int* __restrict__
                     break;
                 }
                 if (nt + 64 > FM_TERMS) {
-                    fmm_eval_terms(nt, tnode, tdep, Pth, D, mom0, e2, fgx, fgy, fgz, fc);
+                    if (phi) fmm_eval_terms<true>(nt, tnode, tdep, Pth, D, mom0, e2, fgx, fgy, fgz, fc);
+                    else fmm_eval_terms<false>(nt, tnode, tdep, Pth, D, mom0, e2, fgx, fgy, fgz, fc);
                     nt = 0;
                     __syncthreads();
                 }
                 if (nl + 64 > FM_LEAVES) {
-                    eval_leaves1<FP32C>(nl, leaves, St, topo, pos4, m, T, e2, A);
+                    eval_leaves1<FP32C>(nl, leaves, St, topo, pos4, m, T, e2, phi, A);
                     nl = 0;
                     __syncthreads();
                 }
@@ -876,8 +884,9 @@ __global__ void __launch_bounds__(64) k_fmm(DevCtl* ctl, const int* __restrict__
                 __syncthreads();
             }
             __syncthreads();
-            fmm_eval_terms(nt, tnode, tdep, Pth, D, mom0, e2, fgx, fgy, fgz, fc);
-            eval_leaves1<FP32C>(nl, leaves, St, topo, pos4, m, T, e2, A);
+            if (phi) fmm_eval_terms<true>(nt, tnode, tdep, Pth, D, mom0, e2, fgx, fgy, fgz, fc);
+            else fmm_eval_terms<false>(nt, tnode, tdep, Pth, D, mom0, e2, fgx, fgy, fgz, fc);
+            eval_leaves1<FP32C>(nl, leaves, St, topo, pos4, m, T, e2, phi, A);
             fgx = lanes_sum_d(fgx, 1);
             fgy = lanes_sum_d(fgy, 1);
             fgz = lanes_sum_d(fgz, 1);
@@ -919,7 +928,7 @@ __global__ void __launch_bounds__(64) k_fmm(DevCtl* ctl, const int* __restrict__
                         gyo[q] = gy;
                         gzo[q] = gz;
                     }
-                    if (pho) pho[q] = ph;
+                    if (phi) pho[q] = ph;
                 }
             }
         }

@@ -272,16 +272,17 @@ def test_run_of_steps_equals_single_steps(monkeypatch, no_graph):
 
 @pytest.mark.parametrize("no_graph", [False, True])
 def test_run_with_gravity_keeps_the_final_potential(monkeypatch, no_graph):
-    """Inside a run of steps only the last step's quadrupole gravity pass evaluates the potential,
-    which nothing but the energy diagnostic reads: the state and the diagnostics (E_grav
-    included) after one call of three steps are bit for bit those of three calls of one step,
-    in both precisions, and a gravity pass through the API after the run returns the potential
-    again (equal to that of a fresh context on the same particles)."""
+    """Inside a run of steps only the last step's gravity pass evaluates the potential, which
+    nothing but the energy diagnostic reads: the state and the diagnostics (E_grav included)
+    after one call of three steps are bit for bit those of three calls of one step, in both
+    precisions and with both gravity schemes, and a gravity pass through the API after the run
+    returns the potential again (equal to that of a fresh context on the same particles)."""
     import paper_2007_03097_amd as sph
     monkeypatch.setenv("SPH_NO_GRAPH", "1" if no_graph else "0")
     ps = polytrope_n1(3000, seed=23)
-    for prec in (0, 1):
-        cfg = dict(G=1.0, soft_eps=0.01, theta=0.5, adaptive_h=1, nbr_capacity=1024, precision=prec)
+    for prec, scheme in ((0, 0), (1, 0), (0, 1), (1, 1)):
+        cfg = dict(G=1.0, soft_eps=0.01, theta=0.5, adaptive_h=1, nbr_capacity=1024, precision=prec,
+                   gravity_scheme=scheme)
         runs, diags = [], []
         for split in (False, True):
             ctx = make_ctx(ps.n, **cfg)
@@ -299,12 +300,12 @@ def test_run_with_gravity_keeps_the_final_potential(monkeypatch, no_graph):
                 ref = gpu_gravity(fresh, ps.n)
                 fresh.close()
                 for a, b in zip(after, ref):
-                    assert np.array_equal(a, b), prec
+                    assert np.array_equal(a, b), (prec, scheme)
                 assert np.all(ref[3] < 0.0)  # the potential was evaluated
             runs.append(state_from(pa))
             diags.append(np.asarray(d, dtype=np.float64))
             ctx.close()
         for k in STEP_FIELDS:
-            assert np.array_equal(runs[0][k], runs[1][k]), (prec, k)
-        assert np.array_equal(diags[0], diags[1], equal_nan=True), prec
+            assert np.array_equal(runs[0][k], runs[1][k]), (prec, scheme, k)
+        assert np.array_equal(diags[0], diags[1], equal_nan=True), (prec, scheme)
         assert np.isfinite(diags[0][8]) and diags[0][8] < 0.0  # E_grav of the final state
