@@ -28,10 +28,10 @@ constexpr int UNION_MAX = 65536;
 constexpr int MAX_LEVEL = 21;   // 21 three-bit digits below the sentinel bit 63
 constexpr double M_1_PI_D = 0.318309886183790671537767526745028724;
 
-// Small control block living in device memory.
 // Counter slots of the gravity pass's term counts, one 128-byte line each.
 constexpr int GRAV_SLOTS = 64;
 
+// Control block living in device memory.
 struct DevCtl {
     u32 err;
     int n_nodes;
