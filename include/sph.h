@@ -93,12 +93,13 @@ typedef struct {
                             first order in the potential (field constant across a node);
                             linear and angular momentum are conserved to rounding.  One set
                             only (n_seg == 1).                                       */
-    int32_t waves_per_cu; /* wavefronts per compute unit of the persistent per-group
+    int32_t waves_per_cu; /* wavefronts per compute unit of the per-group
                             kernels (neighbour walk, density, forces, gravity): their grids
                             hold at most waves_per_cu x 256 wavefronts (256 CUs), fewer when
                             there are fewer groups; 1..32, or 0 (default) for one workgroup
-                            per group up to 8192 workgroups, as many resident per CU as
-                            registers and LDS allow.  Results do not depend on it.     */
+                            per expected group (n over half the group size), as many
+                            resident per CU as registers and LDS allow.  Results do not
+                            depend on it.                                             */
 } sph_config;
 
 /* Values of sph_config.energy_form. */

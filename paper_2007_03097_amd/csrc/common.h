@@ -125,7 +125,7 @@ struct Dims {
     int leaf_size;
     int group_size;
     int nbr_cap;
-    int group_grid;   // persistent grid (multiple of 8) of the one-wave per-group kernels
+    int group_grid;   // grid (multiple of 8) of the one-wave per-group kernels
     int pair_grid;    // the same for the four-wave pair kernels (density, forces)
     int n_chunks;
     int node_cap;

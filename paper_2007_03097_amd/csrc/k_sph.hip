@@ -10,7 +10,7 @@
 //                       mu = h_ab v_ab . r_ab / (r^2 + eps h_ab^2)
 // with the M4 cubic spline, W = w(q)/(pi h^3), grad_a W_ab = r_ab g(q)/(pi h^5), g = w'(q)/q.
 //
-// One 256-thread workgroup per target group, in a persistent, XCD-aware loop.  The group's
+// One 256-thread workgroup per target group, in an XCD-aware loop over the groups.  The group's
 // source union (built with the lists) is staged in LDS in chunks; each of the group's n_g
 // targets is served by PL = 256/n_g threads that take every PL-th entry of its list --
 // entries are ascending union indices, so each thread walks its entries once across the

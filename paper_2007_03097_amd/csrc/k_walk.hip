@@ -3,7 +3,8 @@
 // particle).
 //
 // One wavefront per target group (at most group_size consecutive particles of one compact
-// octree cell), in a persistent, XCD-aware loop over the groups.
+// octree cell), in an XCD-aware loop over the groups (one group per workgroup at the
+// default grid, which holds a workgroup per expected group).
 //  1. Group box and largest h by wave reductions.
 //  2. Wide tree walk: up to 64 nodes are tested at once, one per lane, against the group
 //     box.  A node survives when the squared gap between the boxes, summed in the same
